@@ -1,0 +1,153 @@
+"""FP64 oracle of the JDE forward pass (test infrastructure only).
+
+The paper describes the model as a Darknet-53 backbone with detection done the
+YOLOv3 way, an FPN in which higher-level features are upsampled and fused with
+lower-level ones, and prediction heads on three layers (Sec. 3.1).  The exact
+head layout is not given; the reading used here (and by the product) is:
+
+* backbone: stem 3x3 conv, then five stages of [3x3 stride-2 conv, residual
+  blocks x + leaky(conv3x3(leaky(conv1x1(x))))]; C3/C4/C5 are the stage 3/4/5
+  outputs (strides 8/16/32);
+* each head: five convs (1x1, 3x3, 1x1, 3x3, 1x1) to a feature F, a det branch
+  (3x3 then a linear 1x1 to 6 outputs per anchor) and a linear 3x3 emb branch;
+* a lateral 1x1 from F, nearest x2 upsample, concat [upsampled, skip] feeds the
+  next finer head.
+
+Every non-output conv is conv + folded batch-norm bias, then leaky ReLU 0.1;
+the residual add comes after the activation.  Output convs are linear + bias.
+"""
+
+import numpy as np
+
+LEAKY_SLOPE = 0.1
+BN_EPS = 1e-5
+
+
+def conv2d(x, w, b, stride):
+    """Direct convolution, zero padding k//2.
+
+    out[n, y, x, co] = b[co] + sum_{r, s, ci} in[n, y*st + r - p, x*st + s - p, ci] * w[co, r, s, ci]
+
+    x: [N, H, W, Cin] FP64 NHWC.  w: [Cout, k, k, Cin].  b: [Cout] or None.
+    The sum over ci of each tap is one matmul; taps are added in (r, s) order.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    n, h, wd, cin = x.shape
+    cout, k, k2, cin_w = w.shape
+    assert k == k2 and cin == cin_w, (x.shape, w.shape)
+    p = k // 2
+    ho = (h + 2 * p - k) // stride + 1
+    wo = (wd + 2 * p - k) // stride + 1
+    xp = np.pad(x, ((0, 0), (p, p), (p, p), (0, 0)))
+    out = np.zeros((n * ho * wo, cout))
+    for r in range(k):
+        for s in range(k):
+            tap = xp[:, r:r + stride * (ho - 1) + 1:stride, s:s + stride * (wo - 1) + 1:stride, :]
+            out += tap.reshape(-1, cin) @ w[:, r, s, :].T
+    out = out.reshape(n, ho, wo, cout)
+    if b is not None:
+        out = out + np.asarray(b, dtype=np.float64)
+    return out
+
+
+def leaky(x):
+    """Leaky ReLU with slope 0.1 (x > 0 ? x : 0.1 x)."""
+    return np.where(x > 0, x, LEAKY_SLOPE * x)
+
+
+def upsample2x(x):
+    """Nearest x2: up[n, y, x, c] = in[n, y // 2, x // 2, c]."""
+    return x.repeat(2, axis=1).repeat(2, axis=2)
+
+
+def concat(a, b):
+    """Channel concat in the order [a, b]."""
+    return np.concatenate([a, b], axis=3)
+
+
+def ingest(frames):
+    """[N, 3, H, W] pixels -> [N, H, W, 3] FP64 (layout change only)."""
+    return np.ascontiguousarray(np.asarray(frames, dtype=np.float64).transpose(0, 2, 3, 1))
+
+
+class _Walker:
+    """Consumes the weight list in blob order (see jde_inputs.weights)."""
+
+    def __init__(self, layers, pre_hook):
+        self.layers = layers
+        self.i = 0
+        self.pre_hook = pre_hook
+
+    def conv(self, x, stride=1, act=True, res=None):
+        w, b = self.layers[self.i]
+        y = conv2d(x, w, b, stride)
+        if self.pre_hook is not None:
+            y = self.pre_hook(self.i, y)
+        self.i += 1
+        if act:
+            y = leaky(y)
+        if res is not None:
+            y = y + res
+        return y
+
+
+def forward(frames, layers, blocks, pre_hook=None):
+    """JDE forward (Sec. 3.1).
+
+    frames: [N, 3, H, W] (H, W divisible by 32).  layers: list of (w, b) in blob
+    order.  blocks: residual blocks per stage.  pre_hook(i, pre) may rewrite the
+    pre-activation of conv i (used by the batch-norm calibration).
+
+    Returns dict with 'det' = [d8, d16, d32] ([N, H/s, W/s, 6A]) and
+    'emb' = [e8, e16, e32] ([N, H/s, W/s, E]), all FP64, plus 'feat' = C3, C4, C5.
+    """
+    nb = _Walker(layers, pre_hook)
+    x = ingest(frames)
+    x = nb.conv(x)                                   # stem
+    feats = {}
+    for s, nblk in enumerate(blocks, 1):
+        x = nb.conv(x, stride=2)                     # downsample
+        for _ in range(nblk):
+            y = nb.conv(x)                           # 1x1 C -> C/2
+            x = nb.conv(y, res=x)                    # 3x3 C/2 -> C, + x after leaky
+        feats[s] = x
+    det, emb = {}, {}
+    lat = None
+    for lvl, stage in ((32, 5), (16, 4), (8, 3)):
+        x = feats[stage] if lat is None else concat(upsample2x(lat), feats[stage])
+        for _ in range(5):
+            x = nb.conv(x)                           # 1x1, 3x3, 1x1, 3x3, 1x1
+        d = nb.conv(x)                               # det 3x3
+        det[lvl] = nb.conv(d, act=False)             # det 1x1 (linear)
+        emb[lvl] = nb.conv(x, act=False)             # emb 3x3 (linear)
+        if lvl != 8:
+            lat = nb.conv(x)                         # lateral 1x1
+    assert nb.i == len(layers), (nb.i, len(layers))
+    return {"det": [det[8], det[16], det[32]], "emb": [emb[8], emb[16], emb[32]],
+            "feat": [feats[3], feats[4], feats[5]]}
+
+
+def calibrate_bn(frames, raw_layers, blocks, kinds):
+    """Batch-norm statistics of the synthetic network (stand-in for training).
+
+    Runs the forward with the raw weights (zero bias).  For every conv whose kind
+    is 'bn', in forward order, the per-channel mean and (population) variance of
+    its pre-activation over (n, y, x) are recorded, and the pre-activation is
+    replaced by (pre - mean) / sqrt(var + eps) before the activation, which is
+    exactly the folded conv w / sqrt(var + eps), bias -mean / sqrt(var + eps).
+    Returns (mu, var) dicts keyed by conv index.
+    """
+    mu, var = {}, {}
+
+    def hook(i, pre):
+        if kinds[i] != "bn":
+            return pre
+        m = pre.mean(axis=(0, 1, 2))
+        v = ((pre - m) ** 2).mean(axis=(0, 1, 2))
+        mu[i], var[i] = m, v
+        return (pre - m) / np.sqrt(v + BN_EPS)
+
+    layers = [(w, np.zeros(w.shape[0])) for w in raw_layers]
+    forward(frames, layers, blocks, pre_hook=hook)
+    return mu, var

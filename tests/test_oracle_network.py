@@ -1,0 +1,192 @@
+"""Pins of the oracle's forward pass (CPU only).
+
+Brute force on tiny tensors, closed-form special cases and structural
+invariants; none of them re-types the oracle's own formula.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+from jde_inputs import TINY, weight_specs, model_weights, tiny_frame, raw_weights, load_calib
+from oracle import network as net
+
+
+def brute_conv(x, w, b, stride):
+    """Pure-Python loops over every output and every tap (zero padding k//2)."""
+    n, h, wd, cin = x.shape
+    cout, k, _, _ = w.shape
+    p = k // 2
+    ho = (h + 2 * p - k) // stride + 1
+    wo = (wd + 2 * p - k) // stride + 1
+    out = np.zeros((n, ho, wo, cout))
+    for ni, y, xx, co in itertools.product(range(n), range(ho), range(wo), range(cout)):
+        acc = float(b[co])
+        for r, s, ci in itertools.product(range(k), range(k), range(cin)):
+            iy, ix = y * stride + r - p, xx * stride + s - p
+            if 0 <= iy < h and 0 <= ix < wd:
+                acc += x[ni, iy, ix, ci] * w[co, r, s, ci]
+        out[ni, y, xx, co] = acc
+    return out
+
+
+def im2col_conv(x, w, b, stride):
+    """Independent formulation: gather patches into columns, one einsum."""
+    n, h, wd, cin = x.shape
+    cout, k, _, _ = w.shape
+    p = k // 2
+    xp = np.pad(x, ((0, 0), (p, p), (p, p), (0, 0)))
+    ho = (h + 2 * p - k) // stride + 1
+    wo = (wd + 2 * p - k) // stride + 1
+    cols = np.empty((n, ho, wo, k, k, cin))
+    for y in range(ho):
+        for xx in range(wo):
+            cols[:, y, xx] = xp[:, y * stride:y * stride + k, xx * stride:xx * stride + k, :]
+    return np.einsum("nyxrsc,orsc->nyxo", cols, w) + b
+
+
+@pytest.mark.parametrize("k,stride,h,w,cin,cout", [
+    (3, 1, 5, 7, 3, 4), (3, 2, 6, 8, 2, 3), (1, 1, 4, 5, 6, 2), (3, 2, 4, 4, 5, 5), (3, 1, 1, 1, 2, 3)])
+def test_conv_matches_brute_force(rng, k, stride, h, w, cin, cout):
+    x = rng.standard_normal((2, h, w, cin))
+    wt = rng.standard_normal((cout, k, k, cin))
+    b = rng.standard_normal(cout)
+    ref = brute_conv(x, wt, b, stride)
+    got = net.conv2d(x, wt, b, stride)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(im2col_conv(x, wt, b, stride), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_conv_1x1_is_matmul(rng):
+    x = rng.standard_normal((2, 3, 4, 5))
+    wt = rng.standard_normal((7, 1, 1, 5))
+    got = net.conv2d(x, wt, None, 1)
+    ref = np.einsum("nyxc,oc->nyxo", x, wt[:, 0, 0, :])
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_conv_delta_kernel_is_shift(rng):
+    x = rng.standard_normal((1, 6, 7, 2))
+    wt = np.zeros((2, 3, 3, 2))
+    wt[0, 0, 2, 0] = 1.0     # out[y, x] = in[y - 1, x + 1]
+    wt[1, 1, 1, 1] = 1.0     # identity on channel 1
+    got = net.conv2d(x, wt, None, 1)
+    shifted = np.zeros((6, 7))
+    shifted[1:, :-1] = x[0, :-1, 1:, 0]
+    np.testing.assert_array_equal(got[0, :, :, 0], shifted)
+    np.testing.assert_array_equal(got[0, :, :, 1], x[0, :, :, 1])
+
+
+def test_conv_stride2_is_subsampled_stride1(rng):
+    x = rng.standard_normal((2, 8, 10, 3))
+    wt = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    s1 = net.conv2d(x, wt, b, 1)
+    s2 = net.conv2d(x, wt, b, 2)
+    np.testing.assert_allclose(s2, s1[:, ::2, ::2, :], rtol=1e-12, atol=1e-12)
+
+
+def test_elementwise_closed_forms():
+    x = np.array([-2.0, -0.0, 0.0, 3.5])
+    np.testing.assert_array_equal(net.leaky(x), [-0.2, 0.0, 0.0, 3.5])
+    a = np.arange(2 * 2 * 3 * 1, dtype=float).reshape(2, 2, 3, 1)
+    up = net.upsample2x(a)
+    assert up.shape == (2, 4, 6, 1)
+    for y in range(4):
+        for xx in range(6):
+            assert up[1, y, xx, 0] == a[1, y // 2, xx // 2, 0]
+    c = net.concat(np.zeros((1, 1, 1, 2)), np.ones((1, 1, 1, 3)))
+    np.testing.assert_array_equal(c[0, 0, 0], [0, 0, 1, 1, 1])
+
+
+def _tiny_layers():
+    return model_weights(TINY, 50)
+
+
+def test_forward_layer_sequence_and_shapes():
+    """Every conv runs once, in blob order, at the stride the topology gives it."""
+    specs = weight_specs(TINY)
+    seen = []
+    frame = tiny_frame(TINY.seed, 0)[None]
+    net.forward(frame, _tiny_layers(), TINY.blocks, pre_hook=lambda i, y: (seen.append((i, y.shape)), y)[1])
+    assert [i for i, _ in seen] == list(range(len(specs)))
+    stride = 1
+    for (i, shape), (name, cout, k, cin, kind) in zip(seen, specs):
+        if name.endswith(".down"):
+            stride *= 2
+        if name.startswith("p"):
+            stride = int(name[1:name.index(".")])
+        if name.startswith("lat"):
+            stride = int(name[3:])
+        assert shape == (1, 192 // stride, 320 // stride, cout), (name, shape)
+
+
+def test_forward_concat_order_is_upsampled_then_skip():
+    """Zero the skip-channel weights of p16.set0: its pre-activation must then be
+    constant on 2x2 blocks (it sees only the upsampled lateral)."""
+    specs = weight_specs(TINY)
+    layers = [(w.copy(), b.copy()) for w, b in _tiny_layers()]
+    i16 = [i for i, s in enumerate(specs) if s[0] == "p16.set0"][0]
+    lat_c = specs[[i for i, s in enumerate(specs) if s[0] == "lat32"][0]][1]
+    layers[i16][0][:, :, :, lat_c:] = 0.0
+    got = {}
+    net.forward(tiny_frame(TINY.seed, 0)[None], layers, TINY.blocks,
+                pre_hook=lambda i, y: (got.__setitem__(i, y), y)[1])
+    y = got[i16][0]
+    assert np.abs(y).max() > 0.1
+    np.testing.assert_array_equal(y[0::2, 0::2], y[1::2, 1::2])
+    np.testing.assert_array_equal(y[0::2, 0::2], y[0::2, 1::2])
+
+
+def test_forward_residual_after_activation_and_linear_outputs():
+    """A block whose 3x3 conv outputs the constant -1 adds leaky(-1) = -0.1 to the
+    stream; output convs with bias -1 and zero weights give exactly -1."""
+    specs = weight_specs(TINY)
+    layers = [(w.copy(), b.copy()) for w, b in _tiny_layers()]
+    ic2 = [i for i, s in enumerate(specs) if s[0] == "s5.b0.c2"][0]
+    layers[ic2][0][:] = 0.0
+    layers[ic2][1][:] = -1.0
+    for i, s in enumerate(specs):
+        if s[4] in ("det", "emb"):
+            layers[i][0][:] = 0.0
+            layers[i][1][:] = -1.0
+    got = {}
+    out = net.forward(tiny_frame(TINY.seed, 0)[None], layers, TINY.blocks,
+                      pre_hook=lambda i, y: (got.__setitem__(i, y), y)[1])
+    down5 = got[[i for i, s in enumerate(specs) if s[0] == "s5.down"][0]]
+    np.testing.assert_allclose(out["feat"][2], net.leaky(down5) - 0.1, rtol=0, atol=1e-15)
+    for d in out["det"] + out["emb"]:
+        assert np.all(d == -1.0)
+
+
+def test_bn_fold_invariant():
+    """On the calibration frame the folded conv's pre-activation has per-channel
+    mean 0 and variance var / (var + eps)."""
+    calib = load_calib(TINY)
+    layers = model_weights(TINY, None, calib)
+    kinds = [s[4] for s in weight_specs(TINY)]
+    checked = []
+
+    def hook(i, y):
+        if kinds[i] == "bn":
+            m = y.mean(axis=(0, 1, 2))
+            v = y.var(axis=(0, 1, 2))
+            ev = calib["var"][i] / (calib["var"][i] + 1e-5)
+            assert np.abs(m).max() < 1e-4, (i, np.abs(m).max())
+            np.testing.assert_allclose(v, ev, rtol=1e-4)
+            checked.append(i)
+        return y
+
+    net.forward(tiny_frame(TINY.seed, 0)[None], layers, TINY.blocks, pre_hook=hook)
+    assert len(checked) == kinds.count("bn")
+
+
+def test_calibration_reproduces_stored_statistics():
+    """The stored statistics are what calibrate_bn computes now (FP64, same seeds)."""
+    calib = load_calib(TINY)
+    kinds = [s[4] for s in weight_specs(TINY)]
+    mu, var = net.calibrate_bn(tiny_frame(TINY.seed, 0)[None], raw_weights(TINY), TINY.blocks, kinds)
+    for i in mu:
+        np.testing.assert_allclose(mu[i], calib["mu"][i], rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(var[i], calib["var"][i], rtol=1e-9)
