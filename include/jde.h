@@ -1,0 +1,208 @@
+/*
+ * jde.h -- C ABI of the MI355X (gfx950) JDE hot-path library (libjde.so).
+ *
+ * The library runs the joint detection-and-embedding (JDE) tracker's hot path
+ * on one GPU: the model forward over a batch of frames (Sec. 3.1 and the
+ * batch-wise inference of Sec. 4.2), then the post-processing of Appendix A up
+ * to the cost matrix: confidence threshold (item 2), sort and IoU non-max
+ * suppression (item 3), embedding normalisation, and the tracks x detections
+ * cosine cost with Kalman-gated infinite entries (items 5-6).  The Kalman
+ * filter (item 4, 7) and the Hungarian assignment (item 7) run on the host in
+ * FP64 through the jde_kf_* and jde_assign calls.
+ *
+ * Conventions (every call):
+ *  - Device memory is owned by the caller.  The library never allocates device
+ *    memory: the caller allocates the weight buffer (jde_weights_bytes), the
+ *    workspace (jde_workspace_bytes) and all inputs/outputs, and passes raw
+ *    device pointers.  Host pointers are marked "host".
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Device calls only enqueue work on it; nothing synchronises implicitly.
+ *    Device-side results (counts, overflow flags) are valid after the caller
+ *    synchronises the stream.
+ *  - Errors are returned as jde_status; jde_last_error() gives a thread-local
+ *    message.  No exception crosses the ABI.  Argument checks happen before
+ *    any work is enqueued, so a failing call enqueues nothing.
+ *  - A context is used by one host thread at a time; contexts share nothing.
+ *  - Layouts: activations NHWC; frames NCHW FP32; frames of one batch are
+ *    packed back to back in submission order, each with its own size
+ *    (jde_frame_desc), which may differ within a batch.
+ */
+#ifndef JDE_H
+#define JDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jde_ctx jde_ctx;
+
+typedef enum {
+    JDE_OK = 0,
+    JDE_EINVAL = -1,        /* bad argument (shape, pointer, size, alignment)        */
+    JDE_ENOMEM = -2,        /* caller buffer smaller than the size query returned    */
+    JDE_EDEVICE = -3,       /* a HIP call failed                                     */
+    JDE_ECAPACITY = -4,     /* batch exceeds the capacity given at jde_create        */
+    JDE_EUNSUPPORTED = -5,  /* configuration the library does not implement          */
+    JDE_ESTATE = -6         /* call out of order (e.g. forward before load_weights)  */
+} jde_status;
+
+/* Arithmetic of the convolutions (Sec. 4.1 runs the model in mixed precision).
+ * Accumulation is FP32 in every mode; head outputs, decode and normalisation
+ * stay FP32.  JDE_FP8 runs the backbone convolutions in OCP FP8 e4m3 with
+ * per-output-channel weight scales and per-tensor activation scales, and the
+ * neck/heads in BF16. */
+typedef enum { JDE_FP32 = 0, JDE_BF16 = 1, JDE_FP16 = 2, JDE_FP8 = 3 } jde_precision;
+
+typedef struct {
+    int base_ch;             /* stem width c0 (32 for Darknet-53)                       */
+    int blocks[5];           /* residual blocks per stage (1,2,8,8,4 for Darknet-53)    */
+    int emb_dim;             /* embedding length E (512 in Appendix A item 1); mult. of 64 */
+    int num_anchors;         /* anchors per cell per scale, A (4)                       */
+    float anchors[3][4][2];  /* (w, h) in pixels for strides 8, 16, 32                  */
+    int precision;           /* jde_precision                                            */
+    int max_frames;          /* largest batch (frames) any call will pass               */
+    int max_h, max_w;        /* largest frame; every frame's h, w divisible by 32       */
+    int max_candidates;      /* per-frame cap on candidates entering NMS (<= 8192)      */
+} jde_config;
+
+typedef struct { int h, w; } jde_frame_desc;
+
+/* Model outputs (device, FP32, NHWC, frames packed back to back per scale).
+ * Scale index 0, 1, 2 = stride 8, 16, 32.  det[s]: [sum_f H_f/st * W_f/st, 6A],
+ * channel 6a + (dx, dy, dw, dh, c_bg, c_fg).  emb[s]: [sum_f ..., E]. */
+typedef struct { float* det[3]; float* emb[3]; } jde_head_out;
+
+/* Detections after threshold + NMS (device).  Frame f owns rows
+ * [f*cap, f*cap + count[f]) of every array, in keep order (score descending,
+ * canonical anchor index ascending on ties).  The canonical anchor index is
+ * base_s + A*(i*W_s + j) + a with scales ordered 8, 16, 32. */
+typedef struct {
+    float* boxes;      /* [n*cap, 4] x1, y1, x2, y2 (pixels of the frame)        */
+    float* scores;     /* [n*cap] foreground softmax score                      */
+    float* margins;    /* [n*cap] c_fg - c_bg (the sort key)                    */
+    float* emb;        /* [n*cap, E] L2-normalised embeddings                   */
+    int* anchor_idx;   /* [n*cap] canonical anchor index                        */
+    int* count;        /* [n] detections kept                                   */
+    int* n_cand;       /* [n] candidates over the threshold before the cap      */
+    int* overflow;     /* [n] 1 if n_cand > cap (the top-cap by key were kept)  */
+    int cap;           /* rows per frame; must equal the context's max_candidates */
+} jde_dets;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Validates cfg and builds the layer plan (Darknet-53 backbone, FPN, three
+ * heads; Sec. 3.1) and the workspace plan.  Host-only.  *out receives a
+ * context to free with jde_destroy.  JDE_EINVAL on bad sizes, JDE_EUNSUPPORTED
+ * on an unknown precision or num_anchors != 4. */
+jde_status jde_create(const jde_config* cfg, jde_ctx** out);
+void jde_destroy(jde_ctx* ctx);
+const char* jde_status_str(int status);
+const char* jde_last_error(void);
+
+/* Number of convolutions and their shapes, in weight-blob order:
+ * stem; per stage: down, then (c1, c2) per block; per head at strides 32, 16,
+ * 8: set0..set4, det3, det1, emb, and lat (strides 32, 16 only). */
+int jde_num_layers(const jde_ctx* ctx);
+jde_status jde_layer_info(const jde_ctx* ctx, int i, int* cout, int* k, int* cin, int* stride);
+
+/* ---- weights ------------------------------------------------------------ */
+
+/* Length in floats of the host FP32 weight blob: per layer in blob order,
+ * w[Cout][k][k][Cin] then b[Cout] (batch norm already folded into w, b). */
+size_t jde_blob_floats(const jde_ctx* ctx);
+/* Bytes of the device weight buffer in the context's precision. */
+size_t jde_weights_bytes(const jde_ctx* ctx);
+/* Converts the host blob (host, FP32, jde_blob_floats floats) to the device
+ * format of the context's precision and copies it into d_weights (device,
+ * >= jde_weights_bytes, 256-byte aligned).  Blocks until the copy is done.
+ * The context keeps d_weights; the caller keeps it alive until jde_destroy. */
+jde_status jde_load_weights(jde_ctx* ctx, const float* host_blob, size_t n_floats,
+                            void* d_weights, size_t weights_bytes, void* stream);
+
+/* ---- workspace ---------------------------------------------------------- */
+
+/* Bytes of device workspace that jde_forward, jde_decode and jde_nms need for
+ * any batch within the context's capacity (total pixels of a batch <=
+ * max_frames * max_h * max_w, frames <= max_frames). */
+size_t jde_workspace_bytes(const jde_ctx* ctx);
+/* Float counts of each head output for a batch: det[s] and emb[s] lengths. */
+jde_status jde_head_sizes(const jde_ctx* ctx, const jde_frame_desc* descs, int n,
+                          size_t det_floats[3], size_t emb_floats[3]);
+
+/* ---- hot path ------------------------------------------------------------ */
+
+/* Model forward over a batch (Sec. 3.1, Sec. 4.2).  d_frames: device FP32
+ * NCHW pixels, frames packed back to back (frame f: 3*h_f*w_f floats).  descs:
+ * host, n entries.  d_ws: device workspace (>= jde_workspace_bytes).  out:
+ * host struct of device pointers sized by jde_head_sizes.  The frames and
+ * workspace must stay valid until the stream reaches the end of the call. */
+jde_status jde_forward(jde_ctx* ctx, const float* d_frames, const jde_frame_desc* descs, int n,
+                       void* d_ws, size_t ws_bytes, const jde_head_out* out, void* stream);
+
+/* Post-processing of Appendix A items 1-3 plus embedding normalisation, for
+ * every frame of the batch: anchor decode, keep iff score >= conf_thr
+ * (evaluated as c_fg - c_bg >= ln(conf_thr / (1 - conf_thr)) in FP32), sort
+ * by (margin desc, index asc), keep the top cap, greedy NMS (suppress iff IoU
+ * with an earlier kept box > nms_iou, FP32 predicate inter > thr * union), and
+ * gather + L2-normalise the embedding at each kept anchor's cell.  heads as
+ * written by jde_forward; out: host struct of device pointers. */
+jde_status jde_decode(jde_ctx* ctx, const jde_head_out* heads, const jde_frame_desc* descs, int n,
+                      float conf_thr, float nms_iou, void* d_ws, size_t ws_bytes,
+                      const jde_dets* out, void* stream);
+
+/* Greedy NMS alone (Appendix A item 3) on one list of K <= max_candidates
+ * candidates (device): boxes [K,4], margins [K], idx [K] (distinct).  Writes
+ * the positions (into the inputs) of the kept boxes, in keep order, to d_keep
+ * [K] and their number to d_nkeep [1]. */
+jde_status jde_nms(jde_ctx* ctx, const float* d_boxes, const float* d_margins, const int* d_idx,
+                   int K, float nms_iou, void* d_ws, size_t ws_bytes, int* d_keep, int* d_nkeep,
+                   void* stream);
+
+/* Tracks x detections cost (Appendix A items 5-6).  All pointers device.
+ * track_emb [T,E] FP32, mean [T,8] FP64 (cx, cy, a, h, vcx, vcy, va, vh),
+ * cov [T,8,8] FP64 (predicted state), det_boxes [D,4] FP32 (x1, y1, x2, y2),
+ * det_emb [D,E] FP32.  cost [T,D] FP32 row-major:
+ *   cost = +inf if d2 > gate_chi2, else clamp(1 - <f_t, e_d>, 0, 2),
+ * d2 = (z - Hx)^T S^-1 (z - Hx), S = H P H^T + R(h), z = (cx, cy, w/h, h),
+ * R = diag((h/20)^2, (h/20)^2, 0.1^2, (h/20)^2) with h the track's height,
+ * solved in FP64 by Cholesky.  T, D >= 0; E multiple of 4. */
+jde_status jde_cost_matrix(const float* d_track_emb, const double* d_mean, const double* d_cov, int T,
+                           const float* d_det_boxes, const float* d_det_emb, int D, int E,
+                           double gate_chi2, float* d_cost, void* stream);
+
+/* Track embedding smoothing for matched pairs: f_t <- normalise(m f_t + (1-m) e_d)
+ * (the track's appearance state follows its matched detections).  d_pairs
+ * [P,2] int (t, d) device, each t at most once; pairs with t outside [0, T) or
+ * d outside [0, D) are skipped.  d_det_emb [D,E], d_track_emb [T,E] FP32. */
+jde_status jde_track_emb_update(const int* d_pairs, int P, const float* d_det_emb, int D,
+                                float* d_track_emb, int T, int E, float momentum, void* stream);
+
+/* ---- host FP64 association (Appendix A items 4, 7-9) --------------------- */
+
+/* Kalman filter on the state (cx, cy, a, h, vcx, vcy, va, vh) with constant
+ * velocity, stds scaled by the height h (process: h/20 position, h/160
+ * velocity, 1e-2 / 1e-5 for a / va; measurement: h/20, and 0.1 for a).
+ * All arrays host, row-major. */
+void jde_kf_initiate(const double z[4], double mean[8], double cov[64]);
+/* Predicts T states in place (mean [T,8], cov [T,8,8]). */
+void jde_kf_predict(int T, double* mean, double* cov);
+/* Update with measurement z; Joseph-form covariance, symmetrised.
+ * JDE_EINVAL if S is not positive definite. */
+jde_status jde_kf_update(double mean[8], double cov[64], const double z[4]);
+
+/* Min-cost assignment (Hungarian) on cost [T,D] (host, FP32, row-major):
+ * entries > max_cost (and +inf) are forbidden; among complete matchings the
+ * one with the most allowed pairs, then the least total cost, is chosen, and
+ * forbidden pairs are dropped.  det_of_track [T] / track_of_det [D] (host)
+ * receive the partner index or -1; *total (host, may be NULL) the kept cost.
+ * Returns the number of kept pairs, or a negative jde_status. */
+int jde_assign(const float* cost, int T, int D, float max_cost, int* det_of_track,
+               int* track_of_det, double* total);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JDE_H */

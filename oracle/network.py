@@ -71,13 +71,28 @@ def ingest(frames):
     return np.ascontiguousarray(np.asarray(frames, dtype=np.float64).transpose(0, 2, 3, 1))
 
 
+def round_bf16(x):
+    """Round to the nearest bfloat16 (ties to even), returned as FP64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isfinite(f), out, f.astype(np.float64))
+
+
+def round_fp16(x):
+    """Round to the nearest IEEE half (ties to even), returned as FP64."""
+    return np.asarray(x, dtype=np.float32).astype(np.float16).astype(np.float64)
+
+
 class _Walker:
     """Consumes the weight list in blob order (see jde_inputs.weights)."""
 
-    def __init__(self, layers, pre_hook):
+    def __init__(self, layers, pre_hook, store):
         self.layers = layers
         self.i = 0
         self.pre_hook = pre_hook
+        self.store = store
 
     def conv(self, x, stride=1, act=True, res=None):
         w, b = self.layers[self.i]
@@ -89,20 +104,25 @@ class _Walker:
             y = leaky(y)
         if res is not None:
             y = y + res
+        if act and self.store is not None:
+            y = self.store(y)
         return y
 
 
-def forward(frames, layers, blocks, pre_hook=None):
+def forward(frames, layers, blocks, pre_hook=None, store=None):
     """JDE forward (Sec. 3.1).
 
     frames: [N, 3, H, W] (H, W divisible by 32).  layers: list of (w, b) in blob
     order.  blocks: residual blocks per stage.  pre_hook(i, pre) may rewrite the
-    pre-activation of conv i (used by the batch-norm calibration).
+    pre-activation of conv i (used by the batch-norm calibration).  store(y), if
+    given, is applied to every activation a non-output conv stores (after its
+    activation and residual add): round_bf16 / round_fp16 model a network whose
+    activations are kept in that format (the exact arithmetic stays FP64).
 
     Returns dict with 'det' = [d8, d16, d32] ([N, H/s, W/s, 6A]) and
     'emb' = [e8, e16, e32] ([N, H/s, W/s, E]), all FP64, plus 'feat' = C3, C4, C5.
     """
-    nb = _Walker(layers, pre_hook)
+    nb = _Walker(layers, pre_hook, store)
     x = ingest(frames)
     x = nb.conv(x)                                   # stem
     feats = {}

@@ -1,0 +1,670 @@
+// C ABI of libjde: context, layer plan, workspace planner, weight packing, and
+// the orchestration of the forward, decode, NMS and cost launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "jde_internal.h"
+
+using namespace jde;
+
+namespace {
+
+thread_local std::string g_err;
+
+jde_status fail(jde_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+jde_status fail(jde_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return fail(JDE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// One convolution of the weight blob.
+struct Layer {
+    int cout, k, cin, stride;
+    size_t blob_w, blob_b;   // float offsets in the host blob
+};
+
+enum OpKind { OP_STEM = 0, OP_CONV = 1 };
+enum { HEAD_NONE = -1 };
+
+// One launch of the forward.
+struct Op {
+    int kind;
+    int layer, layer2;       // weights (layer2: fused second GEMM sharing the input, or -1)
+    int in_t, in2_t, res_t, out_t;
+    int det_out;             // scale index if out0 is the det head output (FP32), else -1
+    int emb_out;             // scale index if out1 is the emb head output (FP32), else -1
+    int lvl_in, lvl_out, cin, cout, ksz, stride, cin1, n_split, act;
+    size_t dev_w, dev_b;     // byte offsets in the device weight buffer
+    int tile;                // tile configuration (-1: default)
+};
+
+struct Tensor {
+    int lvl, ch;
+    int first, last;         // op indices of definition and last use
+    size_t off, bytes;
+};
+
+}  // namespace
+
+struct jde_ctx {
+    jde_config cfg;
+    int et;                          // element type of activations / conv operands
+    std::vector<Layer> layers;
+    std::vector<Op> ops;
+    std::vector<Tensor> tens;
+    size_t blob_floats = 0;
+    size_t weights_bytes = 0;
+    size_t arena_bytes = 0;
+    // decode scratch layout (byte offsets in the workspace)
+    size_t ws_geom = 0, ws_counts = 0, ws_keys = 0, ws_vals = 0, ws_sboxes = 0, ws_kcount = 0, ws_mask = 0,
+           ws_keep = 0, ws_nkeep = 0, ws_total = 0;
+    int keycap = 0, cap = 0, max_anchors = 0;
+    char* d_weights = nullptr;
+    bool loaded = false;
+};
+
+namespace {
+
+int ilog2(int x) {
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+// Builds the layer list (blob order) and the op list (launch order).
+void build_plan(jde_ctx* c) {
+    const jde_config& g = c->cfg;
+    auto add_layer = [&](int cout, int k, int cin, int stride) {
+        Layer L{cout, k, cin, stride, 0, 0};
+        L.blob_w = c->blob_floats;
+        c->blob_floats += (size_t)cout * k * k * cin;
+        L.blob_b = c->blob_floats;
+        c->blob_floats += cout;
+        c->layers.push_back(L);
+        return (int)c->layers.size() - 1;
+    };
+    auto add_tensor = [&](int lvl, int ch) {
+        c->tens.push_back(Tensor{lvl, ch, -1, -1, 0, 0});
+        return (int)c->tens.size() - 1;
+    };
+    auto add_op = [&](int kind, int layer, int in_t, int out_t, int lvl_in, int lvl_out) {
+        Op o{};
+        o.kind = kind;
+        o.layer = layer;
+        o.layer2 = -1;
+        o.in_t = in_t;
+        o.in2_t = -1;
+        o.res_t = -1;
+        o.out_t = out_t;
+        o.det_out = HEAD_NONE;
+        o.emb_out = HEAD_NONE;
+        o.lvl_in = lvl_in;
+        o.lvl_out = lvl_out;
+        const Layer& L = c->layers[layer];
+        o.cin = L.cin;
+        o.cout = L.cout;
+        o.ksz = L.k;
+        o.stride = L.stride;
+        o.cin1 = 0;
+        o.n_split = L.cout;
+        o.act = 1;
+        o.tile = -1;
+        c->ops.push_back(o);
+        return (int)c->ops.size() - 1;
+    };
+
+    int ch = g.base_ch;
+    const int stem = add_layer(ch, 3, 3, 1);
+    int x = add_tensor(0, ch);
+    add_op(OP_STEM, stem, -1, x, 0, 0);
+    int feat[6] = {-1, -1, -1, -1, -1, -1};
+    for (int s = 1; s <= 5; ++s) {
+        const int down = add_layer(2 * ch, 3, ch, 2);
+        ch *= 2;
+        const int t = add_tensor(s, ch);
+        add_op(OP_CONV, down, x, t, s - 1, s);
+        x = t;
+        for (int b = 0; b < g.blocks[s - 1]; ++b) {
+            const int c1 = add_layer(ch / 2, 1, ch, 1);
+            const int c2 = add_layer(ch, 3, ch / 2, 1);
+            const int mid = add_tensor(s, ch / 2);
+            add_op(OP_CONV, c1, x, mid, s, s);
+            const int o = add_op(OP_CONV, c2, mid, x, s, s);
+            c->ops[o].res_t = x;   // in place: out = leaky(conv) + x
+        }
+        feat[s] = x;
+    }
+    const int nout = 6 * g.num_anchors;
+    int lat = -1, lat_c = 0;
+    const int lv[3] = {5, 4, 3};
+    for (int h = 0; h < 3; ++h) {
+        const int L = lv[h];
+        const int cl = c->tens[feat[L]].ch;
+        const int F = cl / 2;
+        const int cin0 = cl + lat_c;
+        const int set0 = add_layer(F, 1, cin0, 1);
+        const int set1 = add_layer(2 * F, 3, F, 1);
+        const int set2 = add_layer(F, 1, 2 * F, 1);
+        const int set3 = add_layer(2 * F, 3, F, 1);
+        const int set4 = add_layer(F, 1, 2 * F, 1);
+        const int det3 = add_layer(2 * F, 3, F, 1);
+        const int det1 = add_layer(nout, 1, 2 * F, 1);
+        const int emb = add_layer(g.emb_dim, 3, F, 1);
+        int lat_layer = -1;
+        if (L != 3) lat_layer = add_layer(F / 2, 1, F, 1);
+
+        int t0 = add_tensor(L, F);
+        int o = add_op(OP_CONV, set0, lat < 0 ? feat[L] : lat, t0, lat < 0 ? L : L + 1, L);
+        if (lat >= 0) {
+            c->ops[o].in2_t = feat[L];
+            c->ops[o].cin1 = lat_c;
+        }
+        int t1 = add_tensor(L, 2 * F);
+        add_op(OP_CONV, set1, t0, t1, L, L);
+        int t2 = add_tensor(L, F);
+        add_op(OP_CONV, set2, t1, t2, L, L);
+        int t3 = add_tensor(L, 2 * F);
+        add_op(OP_CONV, set3, t2, t3, L, L);
+        int t4 = add_tensor(L, F);
+        add_op(OP_CONV, set4, t3, t4, L, L);
+        // det 3x3 (leaky, to a tensor) and emb 3x3 (linear, FP32 head output) as one GEMM
+        int td = add_tensor(L, 2 * F);
+        o = add_op(OP_CONV, det3, t4, td, L, L);
+        c->ops[o].layer2 = emb;
+        c->ops[o].cout = 2 * F + g.emb_dim;
+        c->ops[o].n_split = 2 * F;
+        c->ops[o].emb_out = L - 3;
+        o = add_op(OP_CONV, det1, td, -1, L, L);
+        c->ops[o].det_out = L - 3;
+        c->ops[o].act = 0;
+        if (lat_layer >= 0) {
+            lat = add_tensor(L, F / 2);
+            lat_c = F / 2;
+            add_op(OP_CONV, lat_layer, t4, lat, L, L);
+        }
+    }
+}
+
+// Liveness-based first-fit arena over the op sequence, sized for the capacity.
+void plan_arena(jde_ctx* c) {
+    const size_t pix0 = (size_t)c->cfg.max_frames * c->cfg.max_h * c->cfg.max_w;
+    const size_t eb = elem_bytes(c->et);
+    for (auto& t : c->tens) {
+        t.first = -1;
+        t.last = -1;
+        t.bytes = align256((pix0 >> (2 * t.lvl)) * t.ch * eb);
+    }
+    for (int i = 0; i < (int)c->ops.size(); ++i) {
+        const Op& o = c->ops[i];
+        const int reads[3] = {o.in_t, o.in2_t, o.res_t};
+        for (int r : reads)
+            if (r >= 0) c->tens[r].last = std::max(c->tens[r].last, i);
+        if (o.out_t >= 0) {
+            Tensor& t = c->tens[o.out_t];
+            if (t.first < 0) t.first = i;
+            t.last = std::max(t.last, i);
+        }
+    }
+    struct Block { size_t off, bytes; int tensor; };
+    std::vector<Block> live;
+    size_t top = 0;
+    for (int i = 0; i < (int)c->ops.size(); ++i) {
+        live.erase(std::remove_if(live.begin(), live.end(),
+                                  [&](const Block& b) { return c->tens[b.tensor].last < i; }),
+                   live.end());
+        const int ot = c->ops[i].out_t;
+        if (ot < 0 || c->tens[ot].first != i) continue;
+        Tensor& t = c->tens[ot];
+        std::sort(live.begin(), live.end(), [](const Block& a, const Block& b) { return a.off < b.off; });
+        size_t cur = 0;
+        for (const Block& b : live) {
+            if (b.off >= cur + t.bytes) break;
+            cur = std::max(cur, b.off + b.bytes);
+        }
+        t.off = cur;
+        live.push_back(Block{cur, t.bytes, ot});
+        top = std::max(top, cur + t.bytes);
+    }
+    c->arena_bytes = align256(top);
+}
+
+void plan_weights(jde_ctx* c) {
+    size_t off = 0;
+    const size_t eb = elem_bytes(c->et);
+    for (auto& o : c->ops) {
+        const int K = o.ksz * o.ksz * o.cin;
+        const size_t wb = (o.kind == OP_STEM) ? (size_t)o.cout * K * 4 : (size_t)o.cout * K * eb;
+        o.dev_w = off;
+        off = align256(off + wb);
+        o.dev_b = off;
+        off = align256(off + (size_t)o.cout * 4);
+    }
+    c->weights_bytes = off;
+}
+
+void plan_decode_scratch(jde_ctx* c) {
+    const jde_config& g = c->cfg;
+    const int H = g.max_h, W = g.max_w, A = g.num_anchors;
+    c->max_anchors = ((H >> 3) * (W >> 3) + (H >> 4) * (W >> 4) + (H >> 5) * (W >> 5)) * A;
+    int kc = 1;
+    while (kc < c->max_anchors) kc <<= 1;
+    int kcap = 1;
+    while (kcap < g.max_candidates) kcap <<= 1;
+    c->keycap = std::max(kc, kcap);
+    c->cap = g.max_candidates;
+    const size_t n = g.max_frames;
+    size_t off = c->arena_bytes;
+    c->ws_geom = off;   off = align256(off + n * kGeomInts * 4);
+    c->ws_counts = off; off = align256(off + n * 4);
+    c->ws_kcount = off; off = align256(off + n * 4);
+    c->ws_nkeep = off;  off = align256(off + n * 4);
+    c->ws_keys = off;   off = align256(off + n * c->keycap * 8);
+    c->ws_vals = off;   off = align256(off + n * c->keycap * 4);
+    c->ws_sboxes = off; off = align256(off + n * c->cap * 16);
+    c->ws_mask = off;   off = align256(off + n * (size_t)c->cap * (c->cap / 64) * 8);
+    c->ws_keep = off;   off = align256(off + n * c->cap * 4);
+    c->ws_total = off;
+}
+
+jde_status batch_ok(const jde_ctx* c, const jde_frame_desc* d, int n, bool* uniform) {
+    if (!d || n <= 0) return fail(JDE_EINVAL, "empty batch");
+    if (n > c->cfg.max_frames || n > kMaxFrames)
+        return fail(JDE_ECAPACITY, "batch of %d frames exceeds capacity %d", n, c->cfg.max_frames);
+    size_t pix = 0;
+    *uniform = true;
+    for (int i = 0; i < n; ++i) {
+        if (d[i].h <= 0 || d[i].w <= 0 || d[i].h % 32 || d[i].w % 32)
+            return fail(JDE_EINVAL, "frame %d: %dx%d not a positive multiple of 32", i, d[i].h, d[i].w);
+        if (d[i].h > c->cfg.max_h || d[i].w > c->cfg.max_w)
+            return fail(JDE_ECAPACITY, "frame %d: %dx%d exceeds max %dx%d", i, d[i].h, d[i].w, c->cfg.max_h,
+                        c->cfg.max_w);
+        pix += (size_t)d[i].h * d[i].w;
+        if (d[i].h != d[0].h || d[i].w != d[0].w) *uniform = false;
+    }
+    if (pix > (size_t)c->cfg.max_frames * c->cfg.max_h * c->cfg.max_w)
+        return fail(JDE_ECAPACITY, "batch pixels exceed capacity");
+    return JDE_OK;
+}
+
+size_t level_pixels(const jde_frame_desc* d, int n, int lvl) {
+    size_t p = 0;
+    for (int i = 0; i < n; ++i) p += (size_t)(d[i].h >> lvl) * (d[i].w >> lvl);
+    return p;
+}
+
+GeomParams geom_params(const jde_frame_desc* d, int n) {
+    GeomParams p{};
+    p.n = n;
+    for (int i = 0; i < n; ++i) {
+        p.hw[i][0] = d[i].h;
+        p.hw[i][1] = d[i].w;
+    }
+    return p;
+}
+
+}  // namespace
+
+// ---- setup kernel: geometry table + counter reset ---------------------------
+namespace jde {
+__global__ void setup_kernel(GeomParams p, int* geom, int* counters, int ncount) {
+    const int t = threadIdx.x;
+    if (t < p.n) {
+        int pre[kLevels], nxt[kLevels];
+        for (int l = 0; l < kLevels; ++l) pre[l] = 0;
+        for (int i = 0; i < t; ++i)
+            for (int l = 0; l < kLevels; ++l) pre[l] += (p.hw[i][0] >> l) * (p.hw[i][1] >> l);
+        for (int l = 0; l < kLevels; ++l) nxt[l] = pre[l] + (p.hw[t][0] >> l) * (p.hw[t][1] >> l);
+        int* g = geom + t * kGeomInts;
+        g[0] = p.hw[t][0];
+        g[1] = p.hw[t][1];
+        for (int l = 0; l < kLevels; ++l) {
+            g[2 + l] = pre[l];
+            g[8 + l] = nxt[l];
+        }
+    }
+    for (int i = t; i < ncount; i += blockDim.x) counters[i] = 0;
+}
+hipError_t launch_setup(const GeomParams& p, int* geom, int* counters, int ncount, hipStream_t s) {
+    setup_kernel<<<1, 256, 0, s>>>(p, geom, counters, ncount);
+    return hipGetLastError();
+}
+
+uint16_t f32_to_bf16_rne(float x) {
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+uint16_t f32_to_f16_rne(float x) {
+    _Float16 h = (_Float16)x;   // host conversion is IEEE round-to-nearest-even
+    uint16_t r;
+    memcpy(&r, &h, 2);
+    return r;
+}
+}  // namespace jde
+
+// ---- C ABI -----------------------------------------------------------------
+extern "C" {
+
+const char* jde_status_str(int s) {
+    switch (s) {
+        case JDE_OK: return "ok";
+        case JDE_EINVAL: return "invalid argument";
+        case JDE_ENOMEM: return "buffer too small";
+        case JDE_EDEVICE: return "device error";
+        case JDE_ECAPACITY: return "capacity exceeded";
+        case JDE_EUNSUPPORTED: return "unsupported";
+        case JDE_ESTATE: return "bad call order";
+    }
+    return "unknown status";
+}
+
+const char* jde_last_error(void) { return g_err.c_str(); }
+
+jde_status jde_create(const jde_config* cfg, jde_ctx** out) {
+    if (!cfg || !out) return fail(JDE_EINVAL, "null argument");
+    *out = nullptr;
+    const jde_config& g = *cfg;
+    if (g.base_ch != 16 && g.base_ch != 32) return fail(JDE_EUNSUPPORTED, "base_ch must be 16 or 32");
+    for (int i = 0; i < 5; ++i)
+        if (g.blocks[i] < 0 || g.blocks[i] > 64) return fail(JDE_EINVAL, "blocks[%d] out of range", i);
+    if (g.num_anchors != 4) return fail(JDE_EUNSUPPORTED, "num_anchors must be 4");
+    if (g.emb_dim <= 0 || g.emb_dim % 64) return fail(JDE_EINVAL, "emb_dim must be a positive multiple of 64");
+    if (g.precision != JDE_FP32 && g.precision != JDE_BF16 && g.precision != JDE_FP16)
+        return fail(JDE_EUNSUPPORTED, "precision %d not implemented", g.precision);
+    if (g.max_frames <= 0 || g.max_frames > kMaxFrames) return fail(JDE_EINVAL, "max_frames must be 1..%d", kMaxFrames);
+    if (g.max_h <= 0 || g.max_w <= 0 || g.max_h % 32 || g.max_w % 32)
+        return fail(JDE_EINVAL, "max_h, max_w must be positive multiples of 32");
+    if ((size_t)g.max_frames * g.max_h * g.max_w > ((size_t)1 << 31) / 4)
+        return fail(JDE_EINVAL, "capacity too large for 32-bit pixel indexing");
+    if (g.max_candidates < 64 || g.max_candidates > kMaxCap || g.max_candidates % 64)
+        return fail(JDE_EINVAL, "max_candidates must be a multiple of 64 in [64, %d]", kMaxCap);
+    jde_ctx* c = new jde_ctx();
+    c->cfg = g;
+    c->et = g.precision == JDE_FP32 ? kF32 : (g.precision == JDE_FP16 ? kF16 : kBF16);
+    build_plan(c);
+    plan_arena(c);
+    plan_weights(c);
+    plan_decode_scratch(c);
+    *out = c;
+    return JDE_OK;
+}
+
+void jde_destroy(jde_ctx* c) { delete c; }
+
+int jde_num_layers(const jde_ctx* c) { return c ? (int)c->layers.size() : 0; }
+
+jde_status jde_layer_info(const jde_ctx* c, int i, int* cout, int* k, int* cin, int* stride) {
+    if (!c || i < 0 || i >= (int)c->layers.size()) return fail(JDE_EINVAL, "layer index out of range");
+    const Layer& L = c->layers[i];
+    if (cout) *cout = L.cout;
+    if (k) *k = L.k;
+    if (cin) *cin = L.cin;
+    if (stride) *stride = L.stride;
+    return JDE_OK;
+}
+
+size_t jde_blob_floats(const jde_ctx* c) { return c ? c->blob_floats : 0; }
+size_t jde_weights_bytes(const jde_ctx* c) { return c ? c->weights_bytes : 0; }
+size_t jde_workspace_bytes(const jde_ctx* c) { return c ? c->ws_total : 0; }
+
+jde_status jde_head_sizes(const jde_ctx* c, const jde_frame_desc* d, int n, size_t det[3], size_t emb[3]) {
+    if (!c || !det || !emb) return fail(JDE_EINVAL, "null argument");
+    bool uni;
+    if (jde_status st = batch_ok(c, d, n, &uni)) return st;
+    for (int s = 0; s < 3; ++s) {
+        const size_t p = level_pixels(d, n, 3 + s);
+        det[s] = p * 6 * c->cfg.num_anchors;
+        emb[s] = p * c->cfg.emb_dim;
+    }
+    return JDE_OK;
+}
+
+jde_status jde_load_weights(jde_ctx* c, const float* blob, size_t nf, void* d_weights, size_t wbytes, void* stream) {
+    if (!c || !blob || !d_weights) return fail(JDE_EINVAL, "null argument");
+    if (nf != c->blob_floats) return fail(JDE_EINVAL, "blob has %zu floats, expected %zu", nf, c->blob_floats);
+    if (wbytes < c->weights_bytes) return fail(JDE_ENOMEM, "weight buffer %zu < %zu bytes", wbytes, c->weights_bytes);
+    if ((uintptr_t)d_weights % 256) return fail(JDE_EINVAL, "weight buffer not 256-byte aligned");
+    std::vector<unsigned char> host(c->weights_bytes, 0);
+    const size_t eb = elem_bytes(c->et);
+    for (const Op& o : c->ops) {
+        const int K = o.ksz * o.ksz * o.cin;
+        const int nl = o.layer2 >= 0 ? 2 : 1;
+        size_t row = 0;
+        for (int q = 0; q < nl; ++q) {
+            const Layer& L = c->layers[q == 0 ? o.layer : o.layer2];
+            const float* w = blob + L.blob_w;
+            const float* b = blob + L.blob_b;
+            for (int co = 0; co < L.cout; ++co, ++row) {
+                for (int k = 0; k < K; ++k) {
+                    const float v = w[(size_t)co * K + k];
+                    unsigned char* dst = host.data() + o.dev_w;
+                    if (o.kind == OP_STEM || c->et == kF32) {
+                        memcpy(dst + (row * K + k) * 4, &v, 4);
+                    } else {
+                        const uint16_t h = c->et == kBF16 ? f32_to_bf16_rne(v) : f32_to_f16_rne(v);
+                        memcpy(dst + (row * K + k) * eb, &h, 2);
+                    }
+                }
+                memcpy(host.data() + o.dev_b + row * 4, &b[co], 4);
+            }
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(d_weights, host.data(), c->weights_bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    c->d_weights = (char*)d_weights;
+    c->loaded = true;
+    return JDE_OK;
+}
+
+jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws, size_t wsb,
+                       const jde_head_out* out, void* stream) {
+    if (!c || !frames || !ws || !out) return fail(JDE_EINVAL, "null argument");
+    if (!c->loaded) return fail(JDE_ESTATE, "weights not loaded");
+    if (wsb < c->ws_total) return fail(JDE_ENOMEM, "workspace %zu < %zu bytes", wsb, c->ws_total);
+    for (int s = 0; s < 3; ++s)
+        if (!out->det[s] || !out->emb[s]) return fail(JDE_EINVAL, "null head output %d", s);
+    bool uniform;
+    if (jde_status st = batch_ok(c, d, n, &uniform)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    char* W = (char*)ws;
+    int* geom = (int*)(W + c->ws_geom);
+    HIP_TRY(launch_setup(geom_params(d, n), geom, nullptr, 0, s));
+    auto tptr = [&](int t) -> void* { return t < 0 ? nullptr : (void*)(W + c->tens[t].off); };
+    for (const Op& o : c->ops) {
+        const char* wb = c->d_weights;
+        if (o.kind == OP_STEM) {
+            const int M = (int)level_pixels(d, n, 0);
+            HIP_TRY(launch_stem(frames, geom, n, uniform, d[0].h, d[0].w, M, (const float*)(wb + o.dev_w),
+                                (const float*)(wb + o.dev_b), o.cout, tptr(o.out_t), c->et, s));
+            continue;
+        }
+        ConvArgs a{};
+        a.in = tptr(o.in_t);
+        a.in2 = tptr(o.in2_t);
+        a.w = wb + o.dev_w;
+        a.bias = (const float*)(wb + o.dev_b);
+        a.wscale = nullptr;
+        a.res = tptr(o.res_t);
+        a.geom = geom;
+        a.nframes = n;
+        a.uniform = uniform;
+        a.lvl_in = o.lvl_in;
+        a.lvl_out = o.lvl_out;
+        a.cin = o.cin;
+        a.cout = o.cout;
+        a.ksz = o.ksz;
+        a.stride = o.stride;
+        a.pad = o.ksz / 2;
+        a.cin1 = o.cin1;
+        a.K = o.ksz * o.ksz * o.cin;
+        a.M = (int)level_pixels(d, n, o.lvl_out);
+        a.n_split = o.n_split;
+        a.act = o.act;
+        a.in_scale = 1.f;
+        if (o.det_out >= 0) {
+            a.out0 = out->det[o.det_out];
+            a.ld0 = o.cout;
+            a.out0_f32 = 1;
+        } else {
+            a.out0 = tptr(o.out_t);
+            a.ld0 = o.n_split;
+            a.out0_f32 = 0;
+        }
+        if (o.emb_out >= 0) {
+            a.out1 = out->emb[o.emb_out];
+            a.ld1 = o.cout - o.n_split;
+        }
+        const int tile = (o.tile >= 0 && conv_tile_ok(o.tile, c->et, a)) ? o.tile : conv_default_tile(c->et, a);
+        HIP_TRY(launch_conv(a, c->et, tile, s));
+    }
+    return JDE_OK;
+}
+
+jde_status jde_decode(jde_ctx* c, const jde_head_out* heads, const jde_frame_desc* d, int n, float conf_thr,
+                      float nms_iou, void* ws, size_t wsb, const jde_dets* out, void* stream) {
+    if (!c || !heads || !ws || !out) return fail(JDE_EINVAL, "null argument");
+    if (wsb < c->ws_total) return fail(JDE_ENOMEM, "workspace %zu < %zu bytes", wsb, c->ws_total);
+    if (out->cap != c->cap) return fail(JDE_EINVAL, "dets.cap %d != max_candidates %d", out->cap, c->cap);
+    if (!out->boxes || !out->scores || !out->margins || !out->emb || !out->anchor_idx || !out->count ||
+        !out->n_cand || !out->overflow)
+        return fail(JDE_EINVAL, "null detection output");
+    if (!(conf_thr >= 0.f && conf_thr <= 1.f)) return fail(JDE_EINVAL, "conf_thr outside [0, 1]");
+    if (!(nms_iou >= 0.f)) return fail(JDE_EINVAL, "nms_iou must be >= 0");
+    bool uniform;
+    if (jde_status st = batch_ok(c, d, n, &uniform)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    char* W = (char*)ws;
+    int* geom = (int*)(W + c->ws_geom);
+    int* counts = (int*)(W + c->ws_counts);
+    HIP_TRY(launch_setup(geom_params(d, n), geom, counts, n, s));
+    float lthr;
+    if (conf_thr <= 0.f) lthr = -INFINITY;
+    else if (conf_thr >= 1.f) lthr = INFINITY;
+    else lthr = (float)log((double)conf_thr / (1.0 - (double)conf_thr));
+    int max_anchors = 0;
+    for (int i = 0; i < n; ++i) {
+        const int h = d[i].h, w = d[i].w;
+        max_anchors = std::max(max_anchors, ((h >> 3) * (w >> 3) + (h >> 4) * (w >> 4) + (h >> 5) * (w >> 5)) * 4);
+    }
+    DecodeArgs da{};
+    GatherArgs ga{};
+    EmitArgs ea{};
+    for (int q = 0; q < 3; ++q) {
+        da.det[q] = heads->det[q];
+        ga.det[q] = heads->det[q];
+        ea.emb[q] = heads->emb[q];
+    }
+    memcpy(da.anchors, c->cfg.anchors, sizeof da.anchors);
+    memcpy(ga.anchors, c->cfg.anchors, sizeof ga.anchors);
+    unsigned long long* keys = (unsigned long long*)(W + c->ws_keys);
+    da.geom = geom;
+    da.nframes = n;
+    da.A = c->cfg.num_anchors;
+    da.lthr = lthr;
+    da.keycap = c->keycap;
+    da.keys = keys;
+    da.vals = nullptr;
+    da.cand_count = counts;
+    HIP_TRY(launch_decode(da, max_anchors, s));
+    HIP_TRY(launch_sort(keys, nullptr, counts, c->keycap, n, s));
+    float* sboxes = (float*)(W + c->ws_sboxes);
+    int* kcount = (int*)(W + c->ws_kcount);
+    ga.geom = geom;
+    ga.A = c->cfg.num_anchors;
+    ga.keys = keys;
+    ga.cand_count = counts;
+    ga.keycap = c->keycap;
+    ga.cap = c->cap;
+    ga.sboxes = sboxes;
+    ga.kcount = kcount;
+    HIP_TRY(launch_gather_boxes(ga, n, s));
+    int* keep = (int*)(W + c->ws_keep);
+    int* nkeep = (int*)(W + c->ws_nkeep);
+    HIP_TRY(launch_nms(sboxes, kcount, c->cap, nms_iou, (unsigned long long*)(W + c->ws_mask), keep, nkeep, n, s));
+    ea.geom = geom;
+    ea.A = c->cfg.num_anchors;
+    ea.E = c->cfg.emb_dim;
+    ea.keys = keys;
+    ea.keycap = c->keycap;
+    ea.cap = c->cap;
+    ea.sboxes = sboxes;
+    ea.keep = keep;
+    ea.nkeep = nkeep;
+    ea.cand_count = counts;
+    ea.boxes = out->boxes;
+    ea.scores = out->scores;
+    ea.margins = out->margins;
+    ea.emb_out = out->emb;
+    ea.anchor_idx = out->anchor_idx;
+    ea.count = out->count;
+    ea.n_cand = out->n_cand;
+    ea.overflow = out->overflow;
+    HIP_TRY(launch_emit(ea, n, s));
+    return JDE_OK;
+}
+
+jde_status jde_nms(jde_ctx* c, const float* boxes, const float* margins, const int* idx, int K, float iou, void* ws,
+                   size_t wsb, int* keep_out, int* nkeep_out, void* stream) {
+    if (!c || !ws || !keep_out || !nkeep_out) return fail(JDE_EINVAL, "null argument");
+    if (K < 0 || K > c->cap) return fail(JDE_ECAPACITY, "K=%d outside [0, %d]", K, c->cap);
+    if (K > 0 && (!boxes || !margins || !idx)) return fail(JDE_EINVAL, "null candidate arrays");
+    if (wsb < c->ws_total) return fail(JDE_ENOMEM, "workspace %zu < %zu bytes", wsb, c->ws_total);
+    if (!(iou >= 0.f)) return fail(JDE_EINVAL, "nms_iou must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    char* W = (char*)ws;
+    unsigned long long* keys = (unsigned long long*)(W + c->ws_keys);
+    int* vals = (int*)(W + c->ws_vals);
+    int* counts = (int*)(W + c->ws_counts);
+    float* sboxes = (float*)(W + c->ws_sboxes);
+    int* kcount = (int*)(W + c->ws_kcount);
+    int* keep = (int*)(W + c->ws_keep);
+    int* nkeep = (int*)(W + c->ws_nkeep);
+    HIP_TRY(launch_nms_prepare(boxes, margins, idx, K, keys, vals, counts, s));
+    HIP_TRY(launch_sort(keys, vals, counts, c->keycap, 1, s));
+    HIP_TRY(launch_nms_gather(boxes, keys, vals, K, sboxes, kcount, s));
+    HIP_TRY(launch_nms(sboxes, kcount, c->cap, iou, (unsigned long long*)(W + c->ws_mask), keep, nkeep, 1, s));
+    HIP_TRY(launch_nms_finish(keep, nkeep, vals, keep_out, nkeep_out, K, s));
+    return JDE_OK;
+}
+
+jde_status jde_cost_matrix(const float* fe, const double* mean, const double* cov, int T, const float* boxes,
+                           const float* de, int D, int E, double gate, float* cost, void* stream) {
+    if (T < 0 || D < 0 || E <= 0 || E % 4) return fail(JDE_EINVAL, "bad sizes T=%d D=%d E=%d", T, D, E);
+    if (T > 0 && D > 0 && (!fe || !mean || !cov || !boxes || !de || !cost)) return fail(JDE_EINVAL, "null argument");
+    if (!(gate >= 0.0)) return fail(JDE_EINVAL, "gate must be >= 0");
+    HIP_TRY(launch_cost(fe, mean, cov, T, boxes, de, D, E, gate, cost, (hipStream_t)stream));
+    return JDE_OK;
+}
+
+jde_status jde_track_emb_update(const int* pairs, int P, const float* de, int D, float* fe, int T, int E, float mom,
+                                void* stream) {
+    if (P < 0 || E <= 0 || T < 0 || D < 0) return fail(JDE_EINVAL, "bad sizes P=%d T=%d D=%d E=%d", P, T, D, E);
+    if (P > 0 && (!pairs || !de || !fe)) return fail(JDE_EINVAL, "null argument");
+    HIP_TRY(launch_emb_update(pairs, P, de, D, fe, T, E, mom, (hipStream_t)stream));
+    return JDE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,475 @@
+// Convolutions of the JDE forward (Darknet-53 backbone, FPN, heads; Sec. 3.1)
+// for gfx950.
+//
+// * stem: frame ingest (NCHW FP32 pixels) fused with the 3x3 3->c0 conv, folded
+//   BN bias and leaky ReLU.  K = 27 is too shallow for MFMA; it is HBM-bound and
+//   runs on the vector ALUs, one output pixel per thread.
+// * conv_igemm: every other conv as an implicit GEMM on MFMA.  Rows of the MFMA
+//   A operand are output channels (weights [Cout][k][k][Cin] are K-contiguous),
+//   rows of the B operand are output pixels gathered from NHWC activations
+//   (im2col on the fly with zero halo).  Both tiles are staged through LDS,
+//   double-buffered, one barrier per K chunk.  The epilogue is fused: folded-BN
+//   bias, leaky ReLU 0.1, residual add (after the activation), cast, and an
+//   optional split of the output columns into a second, linear FP32 output (the
+//   det 3x3 and emb 3x3 of a head share their input and run as one GEMM).
+//   The FPN's nearest x2 upsample + concat is fused into the B-tile loader: the
+//   first conv of the stride-16 and stride-8 heads reads channels [0, cin1)
+//   from the half-resolution lateral map at (y/2, x/2) and the rest from the
+//   skip map at (y, x), so the concatenated tensor is never materialised.
+#include "jde_internal.h"
+
+namespace jde {
+
+__device__ __forceinline__ float leaky01(float x) { return x > 0.f ? x : 0.1f * x; }
+
+template <typename T> struct V16;
+template <> struct V16<float> { typedef f32x4 type; };
+template <> struct V16<bf16> { typedef bf16x8 type; };
+template <> struct V16<f16> { typedef f16x8 type; };
+
+template <typename T> __device__ __forceinline__ T cvt_out(float x) { return (T)x; }
+
+// Row m of a level-`lvl` packed tensor -> (frame, y, x).
+__device__ __forceinline__ void map_pixel(const int* __restrict__ geom, int nframes, int uniform, int lvl,
+                                          int m, int& f, int& y, int& x) {
+    if (uniform) {
+        const int h = geom[0] >> lvl, w = geom[1] >> lvl;
+        const int hw = h * w;
+        f = m / hw;
+        const int p = m - f * hw;
+        y = p / w;
+        x = p - y * w;
+    } else {
+        f = 0;
+        while (f + 1 < nframes && m >= geom[(f + 1) * kGeomInts + 2 + lvl]) ++f;
+        const int p = m - geom[f * kGeomInts + 2 + lvl];
+        const int w = geom[f * kGeomInts + 1] >> lvl;
+        y = p / w;
+        x = p - y * w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stem: out[m][co] = leaky(b[co] + sum_{r,s,c} frame[c][y+r-1][x+s-1] w[co][r][s][c]).
+// ---------------------------------------------------------------------------
+template <typename TO, int COUT>
+__global__ __launch_bounds__(256) void stem_kernel(const float* __restrict__ frames,
+                                                   const int* __restrict__ geom, int nframes,
+                                                   int uniform, int M,
+                                                   const float* __restrict__ w,
+                                                   const float* __restrict__ bias,
+                                                   TO* __restrict__ out) {
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= M) return;
+    int f, y, x;
+    map_pixel(geom, nframes, uniform, 0, m, f, y, x);
+    const int h = geom[f * kGeomInts + 0], wd = geom[f * kGeomInts + 1];
+    const float* fr = frames + (size_t)geom[f * kGeomInts + 2] * 3;
+    float in[27];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int iy = y + r - 1, ix = x + s - 1;
+            const bool ok = (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)wd;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                in[(r * 3 + s) * 3 + c] = ok ? fr[((size_t)c * h + iy) * wd + ix] : 0.f;
+        }
+    TO* o = out + (size_t)m * COUT;
+#pragma unroll
+    for (int c0 = 0; c0 < COUT; c0 += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float* wc = w + (c0 + j) * 27;
+            float acc = bias[c0 + j];
+#pragma unroll
+            for (int t = 0; t < 27; ++t) acc = __builtin_fmaf(in[t], wc[t], acc);
+            v[j] = leaky01(acc);
+        }
+        if constexpr (sizeof(TO) == 4) {
+            *(f32x4*)(o + c0) = f32x4{v[0], v[1], v[2], v[3]};
+            *(f32x4*)(o + c0 + 4) = f32x4{v[4], v[5], v[6], v[7]};
+        } else {
+            typedef TO T8 __attribute__((ext_vector_type(8)));
+            T8 pk;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) pk[j] = (TO)v[j];
+            *(T8*)(o + c0) = pk;
+        }
+    }
+}
+
+hipError_t launch_stem(const float* frames, const int* geom, int nframes, int uniform, int h0, int w0,
+                       int M, const float* w, const float* bias, int cout, void* out, int out_type,
+                       hipStream_t s) {
+    (void)h0;
+    (void)w0;
+    dim3 grid((M + 255) / 256), block(256);
+    if (cout == 32) {
+        if (out_type == kF32)
+            stem_kernel<float, 32><<<grid, block, 0, s>>>(frames, geom, nframes, uniform, M, w, bias, (float*)out);
+        else if (out_type == kF16)
+            stem_kernel<f16, 32><<<grid, block, 0, s>>>(frames, geom, nframes, uniform, M, w, bias, (f16*)out);
+        else
+            stem_kernel<bf16, 32><<<grid, block, 0, s>>>(frames, geom, nframes, uniform, M, w, bias, (bf16*)out);
+    } else if (cout == 16) {
+        if (out_type == kF32)
+            stem_kernel<float, 16><<<grid, block, 0, s>>>(frames, geom, nframes, uniform, M, w, bias, (float*)out);
+        else if (out_type == kF16)
+            stem_kernel<f16, 16><<<grid, block, 0, s>>>(frames, geom, nframes, uniform, M, w, bias, (f16*)out);
+        else
+            stem_kernel<bf16, 16><<<grid, block, 0, s>>>(frames, geom, nframes, uniform, M, w, bias, (bf16*)out);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// MFMA implicit GEMM.
+//   BM pixels x BN channels per workgroup of 4 waves (WGM x WGN), BK = 32.
+//   Each wave owns a (BM/WGM) x (BN/WGN) tile of 16x16 MFMA blocks.
+//   bf16/f16: v_mfma_f32_16x16x32 -- each lane feeds 8 consecutive k of one
+//   row of A (a channel) and of B (a pixel), one 16-byte LDS read each.
+//   fp32: v_mfma_f32_16x16x4 -- each lane reads 4 consecutive k (16 bytes)
+//   and issues 4 MFMAs; lane group g = lane/16 covers k = 4g + t at step t,
+//   the same assignment on both operands, so the contraction is unchanged.
+//   Output: lane l holds channels 4(l/16) .. +3 of pixel l%16 of each block.
+// ---------------------------------------------------------------------------
+template <typename T, int BM, int BN, int WGM, int WGN, bool ALIGNED>
+__global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
+    constexpr int BK = 32;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int VR = BK / VEC;
+    constexpr int LDR = BK + VEC;  // padded LDS row, in elements
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int TM = WTM / 16, TN = WTN / 16;
+    constexpr int BVEC = BM * VR, AVEC = BN * VR;
+    constexpr int BPT = (BVEC + 255) / 256, APT = (AVEC + 255) / 256;
+    static_assert(WGM * WGN == 4, "4 waves");
+    static_assert(TM >= 1 && TN >= 1, "wave tile");
+    typedef typename V16<T>::type V;
+
+    __shared__ __attribute__((aligned(16))) T sA[2][BN * LDR];
+    __shared__ __attribute__((aligned(16))) T sB[2][BM * LDR];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const T* __restrict__ in = (const T*)a.in;
+    const T* __restrict__ in2 = (const T*)a.in2;
+    const T* __restrict__ wt = (const T*)a.w;
+    const bool concat = a.cin1 > 0;
+
+    // ---- pixel-side rows owned by this thread (fixed over the K loop) ----
+    long b_base[BPT], b_base2[BPT];
+    int b_iy0[BPT], b_ix0[BPT], b_h[BPT], b_w[BPT], b_lds[BPT];
+    bool b_ok[BPT];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int v = tid + i * 256;
+        const int row = v / VR, kv = v % VR;
+        b_lds[i] = row * LDR + kv * VEC;
+        const int m = m0 + row;
+        b_ok[i] = (v < BVEC) && (m < a.M);
+        b_base[i] = 0;
+        b_base2[i] = 0;
+        b_iy0[i] = -0x40000000;
+        b_ix0[i] = -0x40000000;
+        b_h[i] = 0;
+        b_w[i] = 0;
+        if (b_ok[i]) {
+            int f, y, x;
+            map_pixel(a.geom, a.nframes, a.uniform, a.lvl_out, m, f, y, x);
+            const int* g = a.geom + f * kGeomInts;
+            if (concat) {
+                const int l1 = a.lvl_out + 1;
+                b_base[i] = ((long)g[2 + l1] + (long)(y >> 1) * (g[1] >> l1) + (x >> 1)) * a.cin1 + kv * VEC;
+                b_base2[i] = ((long)g[2 + a.lvl_out] + (long)y * (g[1] >> a.lvl_out) + x) * (a.cin - a.cin1) +
+                             kv * VEC;
+            } else {
+                b_base[i] = (long)g[2 + a.lvl_in] * a.cin;
+                b_iy0[i] = y * a.stride - a.pad;
+                b_ix0[i] = x * a.stride - a.pad;
+                b_h[i] = g[0] >> a.lvl_in;
+                b_w[i] = g[1] >> a.lvl_in;
+            }
+        }
+    }
+    int a_lds[APT];
+    long a_off[APT];
+    bool a_ok[APT];
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+        const int v = tid + i * 256;
+        const int row = v / VR, kv = v % VR;
+        a_lds[i] = row * LDR + kv * VEC;
+        a_ok[i] = (v < AVEC) && (n0 + row < a.cout);
+        a_off[i] = (long)(n0 + row) * a.K + kv * VEC;
+    }
+
+    // incremental (tap, ci) position of the chunk being loaded (ALIGNED: cin % BK == 0)
+    int ld_ci = 0, ld_r = 0, ld_s = 0;
+    V ra[APT], rb[BPT];
+
+    auto load_chunk = [&](int kc) {
+        const int k0 = kc * BK;
+#pragma unroll
+        for (int i = 0; i < APT; ++i) {
+            V z = {};
+            ra[i] = (a_ok[i] && k0 + (int)((a_lds[i] % LDR)) < a.K) ? *(const V*)(wt + a_off[i] + k0) : z;
+        }
+        if constexpr (ALIGNED) {
+#pragma unroll
+            for (int i = 0; i < BPT; ++i) {
+                V z = {};
+                rb[i] = z;
+                if (!b_ok[i]) continue;
+                if (concat) {
+                    rb[i] = (k0 < a.cin1) ? *(const V*)(in + b_base[i] + k0)
+                                          : *(const V*)(in2 + b_base2[i] + (k0 - a.cin1));
+                } else {
+                    const int iy = b_iy0[i] + ld_r, ix = b_ix0[i] + ld_s;
+                    if ((unsigned)iy < (unsigned)b_h[i] && (unsigned)ix < (unsigned)b_w[i])
+                        rb[i] = *(const V*)(in + b_base[i] + ((long)iy * b_w[i] + ix) * a.cin + ld_ci +
+                                            (b_lds[i] % LDR));
+                }
+            }
+            ld_ci += BK;
+            if (ld_ci >= a.cin) {
+                ld_ci = 0;
+                if (++ld_s == a.ksz) {
+                    ld_s = 0;
+                    ++ld_r;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < BPT; ++i) {
+                V z = {};
+                rb[i] = z;
+                const int k = k0 + (b_lds[i] % LDR);
+                if (!b_ok[i] || k >= a.K) continue;
+                const int tap = k / a.cin, ci = k - tap * a.cin;
+                const int r = tap / a.ksz, s = tap - r * a.ksz;
+                const int iy = b_iy0[i] + r, ix = b_ix0[i] + s;
+                if ((unsigned)iy < (unsigned)b_h[i] && (unsigned)ix < (unsigned)b_w[i])
+                    rb[i] = *(const V*)(in + b_base[i] + ((long)iy * b_w[i] + ix) * a.cin + ci);
+            }
+        }
+    };
+    auto store_chunk = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < APT; ++i)
+            if (tid + i * 256 < AVEC) *(V*)(&sA[buf][a_lds[i]]) = ra[i];
+#pragma unroll
+        for (int i = 0; i < BPT; ++i)
+            if (tid + i * 256 < BVEC) *(V*)(&sB[buf][b_lds[i]]) = rb[i];
+    };
+
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int arow = wn * WTN + (lane & 15), brow = wm * WTM + (lane & 15);
+    const int kofs = (lane >> 4) * VEC;
+    auto compute = [&](int buf) {
+        const T* A = sA[buf];
+        const T* B = sB[buf];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4 * VEC) {
+            V af[TN], bfr[TM];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) af[j] = *(const V*)(A + (arow + j * 16) * LDR + kk + kofs);
+#pragma unroll
+            for (int i = 0; i < TM; ++i) bfr[i] = *(const V*)(B + (brow + i * 16) * LDR + kk + kofs);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[j][t], bfr[i][t], acc[i][j], 0, 0, 0);
+                    } else if constexpr (__is_same(T, bf16)) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfr[i], acc[i][j], 0, 0, 0);
+                    } else {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[j], bfr[i], acc[i][j], 0, 0, 0);
+                    }
+                }
+        }
+    };
+
+    const int nk = (a.K + BK - 1) / BK;
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+        const int cur = kc & 1;
+        if (kc + 1 < nk) load_chunk(kc + 1);
+        compute(cur);
+        if (kc + 1 < nk) store_chunk(cur ^ 1);
+        __syncthreads();
+    }
+
+    // ---- fused epilogue ----
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int m = m0 + wm * WTM + i * 16 + (lane & 15);
+        if (m >= a.M) continue;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int cb = n0 + wn * WTN + j * 16 + (lane >> 4) * 4;
+            if (cb >= a.cout) continue;
+            float v[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v[t] = acc[i][j][t] + ((cb + t < a.cout) ? a.bias[cb + t] : 0.f);
+            if (cb + 4 <= a.n_split) {
+                if (a.act) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) v[t] = leaky01(v[t]);
+                }
+                const size_t o = (size_t)m * a.ld0 + cb;
+                if (a.out0_f32) {
+                    float* op = (float*)a.out0 + o;
+                    if (a.res) {
+                        const f32x4 r = *(const f32x4*)((const float*)a.res + o);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) v[t] += r[t];
+                    }
+                    *(f32x4*)op = f32x4{v[0], v[1], v[2], v[3]};
+                } else {
+                    T* op = (T*)a.out0 + o;
+                    typedef T T4 __attribute__((ext_vector_type(4)));
+                    if (a.res) {
+                        const T4 r = *(const T4*)((const T*)a.res + o);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) v[t] += (float)r[t];
+                    }
+                    T4 pk;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) pk[t] = cvt_out<T>(v[t]);
+                    *(T4*)op = pk;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int co = cb + t;
+                    if (co >= a.cout) break;
+                    if (co < a.n_split) {
+                        float x = a.act ? leaky01(v[t]) : v[t];
+                        const size_t o = (size_t)m * a.ld0 + co;
+                        if (a.out0_f32) {
+                            if (a.res) x += ((const float*)a.res)[o];
+                            ((float*)a.out0)[o] = x;
+                        } else {
+                            if (a.res) x += (float)((const T*)a.res)[o];
+                            ((T*)a.out0)[o] = cvt_out<T>(x);
+                        }
+                    } else {
+                        a.out1[(size_t)m * a.ld1 + (co - a.n_split)] = v[t];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile configurations and dispatch.
+// ---------------------------------------------------------------------------
+struct TileCfg { int bm, bn, wgm, wgn; };
+static constexpr TileCfg kTiles[] = {
+    {128, 128, 2, 2},  // 0: 64x64 per wave
+    {256, 64, 4, 1},   // 1: 64x64 per wave (Cout 64)
+    {128, 64, 2, 2},   // 2: 64x32 per wave
+    {64, 128, 2, 2},   // 3: 32x64 per wave
+    {256, 32, 4, 1},   // 4: 64x32 per wave (Cout <= 32)
+    {64, 64, 2, 2},    // 5: 32x32 per wave (also the unaligned-Cin path)
+    {128, 32, 4, 1},   // 6: 32x32 per wave
+    {32, 128, 2, 2},   // 7: 16x64 per wave
+};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+int conv_num_tile_cfgs() { return kNumTiles; }
+void conv_tile_shape(int c, int* bm, int* bn) {
+    *bm = kTiles[c].bm;
+    *bn = kTiles[c].bn;
+}
+
+static bool aligned_cin(const ConvArgs& a) {
+    if (a.cin % 32) return false;
+    if (a.cin1 > 0 && (a.cin1 % 32 || a.ksz != 1 || a.stride != 1)) return false;
+    return true;
+}
+
+bool conv_tile_ok(int c, int et, const ConvArgs& a) {
+    if (c < 0 || c >= kNumTiles) return false;
+    if (et != kF32 && et != kBF16 && et != kF16) return false;
+    if (!aligned_cin(a)) return c == 5 && a.cin1 == 0 && a.cin % (et == kF32 ? 4 : 8) == 0;
+    return true;
+}
+
+int conv_default_tile(int et, const ConvArgs& a) {
+    (void)et;
+    if (!aligned_cin(a)) return 5;
+    // Prefer the largest tile that still gives at least ~2 workgroups per CU.
+    static const int pref_wide[] = {0, 2, 3, 5, 7};
+    static const int pref_64[] = {1, 2, 5};
+    static const int pref_32[] = {4, 6};
+    const int* pref;
+    int np;
+    if (a.cout <= 32) { pref = pref_32; np = 2; }
+    else if (a.cout <= 64) { pref = pref_64; np = 3; }
+    else { pref = pref_wide; np = 5; }
+    int best = pref[np - 1];
+    for (int i = 0; i < np; ++i) {
+        const TileCfg& t = kTiles[pref[i]];
+        const long wgs = (long)((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn);
+        if (wgs >= 512) { best = pref[i]; break; }
+    }
+    return best;
+}
+
+template <typename T, int C>
+static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
+    constexpr TileCfg t = kTiles[C];
+    dim3 grid((a.M + t.bm - 1) / t.bm, (a.cout + t.bn - 1) / t.bn), block(256);
+    if (aligned)
+        conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, true><<<grid, block, 0, s>>>(a);
+    else if constexpr (C == 5)
+        conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, false><<<grid, block, 0, s>>>(a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_type(const ConvArgs& a, int c, bool aligned, hipStream_t s) {
+    switch (c) {
+        case 0: return launch_t<T, 0>(a, aligned, s);
+        case 1: return launch_t<T, 1>(a, aligned, s);
+        case 2: return launch_t<T, 2>(a, aligned, s);
+        case 3: return launch_t<T, 3>(a, aligned, s);
+        case 4: return launch_t<T, 4>(a, aligned, s);
+        case 5: return launch_t<T, 5>(a, aligned, s);
+        case 6: return launch_t<T, 6>(a, aligned, s);
+        case 7: return launch_t<T, 7>(a, aligned, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_conv(const ConvArgs& a, int et, int c, hipStream_t s) {
+    if (!conv_tile_ok(c, et, a)) return hipErrorInvalidValue;
+    const bool aligned = aligned_cin(a);
+    if (et == kF32) return launch_type<float>(a, c, aligned, s);
+    if (et == kBF16) return launch_type<bf16>(a, c, aligned, s);
+    return launch_type<f16>(a, c, aligned, s);
+}
+
+}  // namespace jde

@@ -1,0 +1,135 @@
+// Internal declarations of libjde (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "jde.h"
+
+namespace jde {
+
+typedef __bf16 bf16;
+typedef _Float16 f16;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMaxFrames = 64;     // frames per batch
+constexpr int kLevels = 6;         // strides 1, 2, 4, 8, 16, 32
+constexpr int kMaxCap = 8192;      // per-frame candidate cap entering NMS
+constexpr int kSortLds = 8192;     // keys sorted in LDS; larger lists sort in global memory
+
+// Per-frame geometry of a batch, stored in device memory (int32 each):
+//   [0] h, [1] w of the frame (pixels),
+//   [2 + l] first packed pixel of the frame at level l (stride 2^l), l = 0..5,
+//   [8 + l] = [2 + l] of the next frame (so a frame's range is [2+l], [8+l]).
+constexpr int kGeomInts = 14;
+
+enum ElemType { kF32 = 0, kBF16 = 1, kF16 = 2, kFP8 = 3 };
+
+inline size_t elem_bytes(int t) { return t == kF32 ? 4 : (t == kFP8 ? 1 : 2); }
+
+// Arguments of one convolution launch (implicit GEMM: M = output pixels of the
+// batch, N = output channels, K = k*k*Cin).
+struct ConvArgs {
+    const void* in;        // NHWC input, level lvl_in (for concat: the half-res source)
+    const void* in2;       // concat: the skip source (same level as the output), else null
+    const void* w;         // [Cout][k][k][Cin]
+    const float* bias;     // [Cout]
+    const float* wscale;   // FP8: per-output-channel dequantisation scale, else null
+    const void* res;       // residual [M][Cout] (same type as out0), or null
+    void* out0;            // [M][ld0], columns [0, n_split)
+    float* out1;           // [M][ld1] FP32, columns [n_split, Cout) (linear), or null
+    const int* geom;       // [nframes][kGeomInts]
+    int nframes;
+    int uniform;           // all frames the same size (row -> frame by division)
+    int lvl_in, lvl_out;
+    int cin, cout, ksz, stride, pad;
+    int cin1;              // concat: channels taken from `in` (upsampled x2); 0 = no concat
+    int K;                 // ksz*ksz*cin
+    int M;                 // output pixels of the batch
+    int n_split;           // columns < n_split go to out0
+    int ld0, ld1;
+    int act;               // leaky ReLU 0.1 on out0 columns
+    int out0_f32;          // out0 holds FP32 (head outputs) instead of the activation type
+    float in_scale;        // FP8: activation quantisation scale of the input (x / in_scale)
+};
+
+// Launchers (conv.hip).
+hipError_t launch_stem(const float* frames, const int* geom, int nframes, int uniform, int h0, int w0,
+                       int M, const float* w, const float* bias, int cout, void* out, int out_type,
+                       hipStream_t s);
+hipError_t launch_conv(const ConvArgs& a, int elem_type, int tile_cfg, hipStream_t s);
+int conv_num_tile_cfgs();
+bool conv_tile_ok(int tile_cfg, int elem_type, const ConvArgs& a);
+int conv_default_tile(int elem_type, const ConvArgs& a);
+void conv_tile_shape(int tile_cfg, int* bm, int* bn);
+
+// Post-processing launchers (post.hip).
+struct DecodeArgs {
+    const float* det[3];
+    const int* geom;
+    int nframes;
+    int A;
+    float anchors[3][4][2];
+    float lthr;              // ln(thr / (1 - thr)) in FP32
+    int keycap;              // key slots per frame
+    unsigned long long* keys;  // [n][keycap]
+    int* vals;               // [n][keycap]
+    int* cand_count;         // [n]
+};
+hipError_t launch_decode(const DecodeArgs& a, int max_anchors, hipStream_t s);
+// Writes the batch geometry table and zeroes `ncount` ints (graph-safe: a kernel, no memset).
+struct GeomParams { int n; int hw[kMaxFrames][2]; };
+hipError_t launch_setup(const GeomParams& p, int* geom, int* counters, int ncount, hipStream_t s);
+hipError_t launch_sort(unsigned long long* keys, int* vals, const int* counts, int keycap, int n,
+                       hipStream_t s);
+struct GatherArgs {
+    const float* det[3];
+    const int* geom;
+    int A;
+    float anchors[3][4][2];
+    const unsigned long long* keys;
+    const int* cand_count;
+    int keycap;
+    int cap;
+    float* sboxes;           // [n][cap][4]
+    int* kcount;             // [n] min(count, cap)
+};
+hipError_t launch_gather_boxes(const GatherArgs& a, int n, hipStream_t s);
+hipError_t launch_nms(const float* sboxes, const int* kcount, int cap, float thr,
+                      unsigned long long* mask, int* keep, int* nkeep, int n, hipStream_t s);
+struct EmitArgs {
+    const float* emb[3];
+    const int* geom;
+    int A, E;
+    const unsigned long long* keys;  // sorted
+    int keycap, cap;
+    const float* sboxes;
+    const int* keep;                 // [n][cap] positions in sorted order
+    const int* nkeep;                // [n]
+    const int* cand_count;           // [n]
+    float* boxes; float* scores; float* margins; float* emb_out;
+    int* anchor_idx; int* count; int* n_cand; int* overflow;
+};
+hipError_t launch_emit(const EmitArgs& a, int n, hipStream_t s);
+hipError_t launch_nms_prepare(const float* boxes, const float* margins, const int* idx, int K,
+                              unsigned long long* keys, int* vals, int* count, hipStream_t s);
+hipError_t launch_nms_gather(const float* boxes, const unsigned long long* keys, const int* vals,
+                             int K, float* sboxes, int* kcount, hipStream_t s);
+hipError_t launch_nms_finish(const int* keep, const int* nkeep, const int* vals, int* out_keep,
+                             int* out_nkeep, int K, hipStream_t s);
+hipError_t launch_cost(const float* trk_emb, const double* mean, const double* cov, int T,
+                       const float* det_boxes, const float* det_emb, int D, int E, double gate,
+                       float* cost, hipStream_t s);
+hipError_t launch_emb_update(const int* pairs, int P, const float* det_emb, int D, float* trk_emb, int T,
+                             int E, float momentum, hipStream_t s);
+
+// Host-side weight conversion helpers (api.cpp).
+uint16_t f32_to_bf16_rne(float x);
+uint16_t f32_to_f16_rne(float x);
+
+}  // namespace jde

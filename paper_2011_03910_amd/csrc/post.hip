@@ -1,0 +1,533 @@
+// Post-processing of the JDE detections (Appendix A items 1-3, 5-6) for gfx950:
+// decode + confidence threshold, sort, greedy IoU NMS, embedding gather and L2
+// normalisation, the tracks x detections cost with Mahalanobis gating, and the
+// track embedding update.  All per-frame work of a batch runs in one launch
+// per step, with the frame on the grid's y axis.
+#include "jde_internal.h"
+
+namespace jde {
+
+typedef unsigned long long u64;
+
+// Order-preserving map of FP32 bits to uint32 (larger float -> larger uint).
+__device__ __forceinline__ unsigned ord_f32(float x) {
+    unsigned u = __float_as_uint(x);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unord_f32(unsigned o) {
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+// Ascending order of the key = margin descending, then index ascending.
+__device__ __forceinline__ u64 make_key(float margin, unsigned idx) {
+    return ((u64)(~ord_f32(margin)) << 32) | idx;
+}
+__device__ __forceinline__ float key_margin(u64 k) { return unord_f32(~(unsigned)(k >> 32)); }
+
+__device__ __forceinline__ u64 shfl64(u64 v, int src) {
+    const unsigned lo = __shfl((int)(unsigned)v, src), hi = __shfl((int)(unsigned)(v >> 32), src);
+    return ((u64)hi << 32) | lo;
+}
+
+// Anchor decode of candidate `idx` (canonical order: scales 8, 16, 32; cell; anchor).
+struct AnchorLoc { int s, cell, an; };
+__device__ __forceinline__ AnchorLoc locate(unsigned idx, const int* g, int A) {
+    const int h = g[0], w = g[1];
+    const unsigned n8 = (unsigned)((h >> 3) * (w >> 3)) * A, n16 = (unsigned)((h >> 4) * (w >> 4)) * A;
+    AnchorLoc L;
+    unsigned t = idx;
+    if (t < n8) L.s = 0;
+    else if (t < n8 + n16) { L.s = 1; t -= n8; }
+    else { L.s = 2; t -= n8 + n16; }
+    L.cell = t / A;
+    L.an = t - L.cell * A;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// Decode + threshold: one thread per anchor; kept anchors are appended to the
+// frame's key list by a wave ballot and one atomic per wave.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void decode_kernel(DecodeArgs a) {
+    const int f = blockIdx.y;
+    const int* g = a.geom + f * kGeomInts;
+    const int h = g[0], w = g[1];
+    const int A = a.A;
+    const int total = ((h >> 3) * (w >> 3) + (h >> 4) * (w >> 4) + (h >> 5) * (w >> 5)) * A;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    bool keep = false;
+    u64 key = 0;
+    if (t < total) {
+        const AnchorLoc L = locate((unsigned)t, g, A);
+        const float* d = a.det[L.s] + ((size_t)g[2 + 3 + L.s] + L.cell) * (6 * A) + 6 * L.an;
+        const float margin = (d[5] - d[4]) + 0.0f;   // +0.0 folds -0 into +0
+        keep = margin >= a.lthr;
+        key = make_key(margin, (unsigned)t);
+    }
+    const u64 bal = __ballot(keep);
+    if (bal == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)bal) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(a.cand_count + f, __popcll(bal));
+    base = __shfl(base, leader);
+    if (keep) {
+        const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+        if (pos < a.keycap) {
+            a.keys[(size_t)f * a.keycap + pos] = key;
+            if (a.vals) a.vals[(size_t)f * a.keycap + pos] = t;
+        }
+    }
+}
+
+hipError_t launch_decode(const DecodeArgs& a, int max_anchors, hipStream_t s) {
+    dim3 grid((max_anchors + 255) / 256, a.nframes), block(256);
+    decode_kernel<<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sort each frame's keys ascending (bitonic); values follow when given.
+// Lists up to kSortLds sort in LDS; longer ones sort in place in global memory
+// (the key buffer has a power-of-two capacity per frame).
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 1024;
+constexpr int kSortLdsKV = 4096;
+
+__global__ __launch_bounds__(kSortThreads) void sort_kernel(u64* keys, int* vals, const int* counts, int keycap) {
+    __shared__ u64 sk[kSortLdsKV];
+    __shared__ int sv[kSortLdsKV];
+    const int f = blockIdx.x;
+    const int tid = threadIdx.x;
+    int n = counts[f];
+    if (n > keycap) n = keycap;
+    if (n <= 1) return;
+    int n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    u64* K = keys + (size_t)f * keycap;
+    int* Vv = vals ? vals + (size_t)f * keycap : nullptr;
+    if (n2 <= kSortLdsKV) {
+        for (int i = tid; i < n2; i += kSortThreads) {
+            sk[i] = i < n ? K[i] : ~0ull;
+            if (Vv) sv[i] = i < n ? Vv[i] : 0;
+        }
+        __syncthreads();
+        for (int k = 2; k <= n2; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = tid; i < n2; i += kSortThreads) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const bool up = (i & k) == 0;
+                        const u64 x = sk[i], y = sk[ixj];
+                        if ((x > y) == up) {
+                            sk[i] = y;
+                            sk[ixj] = x;
+                            if (Vv) {
+                                const int t = sv[i];
+                                sv[i] = sv[ixj];
+                                sv[ixj] = t;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int i = tid; i < n; i += kSortThreads) {
+            K[i] = sk[i];
+            if (Vv) Vv[i] = sv[i];
+        }
+    } else {
+        for (int i = n + tid; i < n2; i += kSortThreads) {
+            K[i] = ~0ull;
+            if (Vv) Vv[i] = 0;
+        }
+        __syncthreads();
+        for (int k = 2; k <= n2; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = tid; i < n2; i += kSortThreads) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const bool up = (i & k) == 0;
+                        const u64 x = K[i], y = K[ixj];
+                        if ((x > y) == up) {
+                            K[i] = y;
+                            K[ixj] = x;
+                            if (Vv) {
+                                const int t = Vv[i];
+                                Vv[i] = Vv[ixj];
+                                Vv[ixj] = t;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+    }
+}
+
+hipError_t launch_sort(u64* keys, int* vals, const int* counts, int keycap, int n, hipStream_t s) {
+    sort_kernel<<<n, kSortThreads, 0, s>>>(keys, vals, counts, keycap);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Boxes of the top-cap sorted candidates, decoded from the head outputs.
+// ---------------------------------------------------------------------------
+__constant__ float kClipLog64 = 4.15888308335967186f;  // ln 64
+
+__global__ __launch_bounds__(256) void gather_boxes_kernel(GatherArgs a) {
+    const int f = blockIdx.y;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    int n = a.cand_count[f];
+    if (n > a.cap) n = a.cap;
+    if (p == 0) a.kcount[f] = n;
+    if (p >= n) return;
+    const int* g = a.geom + f * kGeomInts;
+    const u64 key = a.keys[(size_t)f * a.keycap + p];
+    const unsigned idx = (unsigned)key;
+    const AnchorLoc L = locate(idx, g, a.A);
+    const int ws = g[1] >> (3 + L.s);
+    const int i = L.cell / ws, j = L.cell - (L.cell / ws) * ws;
+    const float st = (float)(8 << L.s);
+    const float* d = a.det[L.s] + ((size_t)g[2 + 3 + L.s] + L.cell) * (6 * a.A) + 6 * L.an;
+    const float aw = a.anchors[L.s][L.an][0], ah = a.anchors[L.s][L.an][1];
+    const float cx = ((float)j + 0.5f) * st + d[0] * aw;
+    const float cy = ((float)i + 0.5f) * st + d[1] * ah;
+    const float bw = aw * __expf(fminf(d[2], kClipLog64));
+    const float bh = ah * __expf(fminf(d[3], kClipLog64));
+    *(float4*)(a.sboxes + ((size_t)f * a.cap + p) * 4) =
+        make_float4(cx - 0.5f * bw, cy - 0.5f * bh, cx + 0.5f * bw, cy + 0.5f * bh);
+}
+
+hipError_t launch_gather_boxes(const GatherArgs& a, int n, hipStream_t s) {
+    dim3 grid((a.cap + 255) / 256, n), block(256);
+    gather_boxes_kernel<<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Greedy NMS in two kernels.
+//   mask: bit c of mask[row][cb] is set iff column cb*64+c comes after `row`
+//         in sorted order and IoU(row, col) > thr (FP32, no contraction).
+//   scan: one wave walks the sorted rows 64 at a time; the diagonal word of a
+//         block is resolved lane-serially in registers, the kept rows' mask
+//         words are OR-ed into the removed set of the later blocks.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool iou_exceeds(float4 a, float4 b, float thr) {
+#pragma clang fp contract(off)
+    const float iw = fmaxf(0.f, fminf(a.z, b.z) - fmaxf(a.x, b.x));
+    const float ih = fmaxf(0.f, fminf(a.w, b.w) - fmaxf(a.y, b.y));
+    const float inter = iw * ih;
+    const float area_a = (a.z - a.x) * (a.w - a.y);
+    const float area_b = (b.z - b.x) * (b.w - b.y);
+    const float uni = (area_a + area_b) - inter;
+    return inter > thr * uni;
+}
+
+__global__ __launch_bounds__(256) void nms_mask_kernel(const float* sboxes, const int* kcount, int cap, float thr,
+                                                       u64* mask) {
+    __shared__ float4 scol[4][64];
+    const int f = blockIdx.y;
+    const int K = kcount[f];
+    const int nb = (K + 63) / 64;
+    const int words = cap / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float4* B = (const float4*)(sboxes + (size_t)f * cap * 4);
+    for (int rb = blockIdx.x; rb < nb; rb += gridDim.x) {
+        const int row = rb * 64 + lane;
+        const float4 rbox = row < K ? B[row] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int cb = rb + wave; cb < nb; cb += 4) {
+            const int col0 = cb * 64;
+            scol[wave][lane] = (col0 + lane < K) ? B[col0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+            __builtin_amdgcn_wave_barrier();
+            u64 bits = 0;
+            if (row < K) {
+                const int cmax = min(64, K - col0);
+                for (int c = 0; c < cmax; ++c) {
+                    const int col = col0 + c;
+                    if (col > row && iou_exceeds(rbox, scol[wave][c], thr)) bits |= 1ull << c;
+                }
+                mask[((size_t)f * cap + row) * words + cb] = bits;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void nms_scan_kernel(const u64* mask, const int* kcount, int cap, int* keep,
+                                                      int* nkeep) {
+    const int f = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int K = kcount[f];
+    const int nb = (K + 63) / 64;
+    const int words = cap / 64;
+    const u64* Mf = mask + (size_t)f * cap * words;
+    u64 rem0 = 0, rem1 = 0;  // removed bits of word `lane` and `lane + 64`
+    int nk = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int row = b * 64 + lane;
+        const u64 diag = row < K ? Mf[(size_t)row * words + b] : 0ull;
+        u64 remb = shfl64(b < 64 ? rem0 : rem1, b & 63);
+        u64 kept = 0;
+        const int lim = min(64, K - b * 64);
+        for (int i = 0; i < lim; ++i) {
+            const u64 di = shfl64(diag, i);
+            if (!((remb >> i) & 1ull)) {
+                kept |= 1ull << i;
+                remb |= di;
+            }
+        }
+        if ((kept >> lane) & 1ull) keep[(size_t)f * cap + nk + __popcll(kept & ((1ull << lane) - 1ull))] = row;
+        nk += __popcll(kept);
+        u64 k2 = kept;
+        while (k2) {
+            const int i = __ffsll((long long)k2) - 1;
+            k2 &= k2 - 1;
+            const u64* mr = Mf + (size_t)(b * 64 + i) * words;
+            if (lane > b && lane < nb) rem0 |= mr[lane];
+            if (lane + 64 > b && lane + 64 < nb) rem1 |= mr[lane + 64];
+        }
+    }
+    if (lane == 0) nkeep[f] = nk;
+}
+
+hipError_t launch_nms(const float* sboxes, const int* kcount, int cap, float thr, u64* mask, int* keep, int* nkeep,
+                      int n, hipStream_t s) {
+    const int gx = (cap + 63) / 64 < 32 ? (cap + 63) / 64 : 32;
+    nms_mask_kernel<<<dim3(gx, n), 256, 0, s>>>(sboxes, kcount, cap, thr, mask);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    nms_scan_kernel<<<n, 64, 0, s>>>(mask, kcount, cap, keep, nkeep);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Emit the kept detections: box, margin, score, index, and the L2-normalised
+// embedding at the anchor's cell (one wave per detection).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void emit_kernel(EmitArgs a) {
+    const int f = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int nk = a.nkeep[f];
+    const int* g = a.geom + f * kGeomInts;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.count[f] = nk;
+        a.n_cand[f] = a.cand_count[f];
+        a.overflow[f] = a.cand_count[f] > a.cap ? 1 : 0;
+    }
+    for (int k = blockIdx.x * 4 + (threadIdx.x >> 6); k < nk; k += gridDim.x * 4) {
+        const int p = a.keep[(size_t)f * a.cap + k];
+        const u64 key = a.keys[(size_t)f * a.keycap + p];
+        const unsigned idx = (unsigned)key;
+        const size_t r = (size_t)f * a.cap + k;
+        const AnchorLoc L = locate(idx, g, a.A);
+        const float* e = a.emb[L.s] + ((size_t)g[2 + 3 + L.s] + L.cell) * a.E;
+        float ss = 0.f;
+        for (int c = lane; c < a.E; c += 64) {
+            const float v = e[c];
+            ss = __builtin_fmaf(v, v, ss);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+        const float inv = 1.0f / fmaxf(sqrtf(ss), 1e-12f);
+        float* eo = a.emb_out + r * a.E;
+        for (int c = lane; c < a.E; c += 64) eo[c] = e[c] * inv;
+        if (lane == 0) {
+            const float m = key_margin(key);
+            *(float4*)(a.boxes + r * 4) = *(const float4*)(a.sboxes + ((size_t)f * a.cap + p) * 4);
+            a.margins[r] = m;
+            a.scores[r] = 1.0f / (1.0f + __expf(-m));
+            a.anchor_idx[r] = (int)idx;
+        }
+    }
+}
+
+hipError_t launch_emit(const EmitArgs& a, int n, hipStream_t s) {
+    const int gx = (a.cap + 3) / 4 < 64 ? (a.cap + 3) / 4 : 64;
+    emit_kernel<<<dim3(gx, n), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Standalone NMS (one list): keys/values from the inputs, gather, unmap.
+// ---------------------------------------------------------------------------
+__global__ void nms_prepare_kernel(const float* margins, const int* idx, int K, u64* keys, int* vals, int* count) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) *count = K;
+    if (p < K) {
+        keys[p] = make_key(margins[p] + 0.0f, (unsigned)idx[p]);
+        vals[p] = p;
+    }
+}
+hipError_t launch_nms_prepare(const float* boxes, const float* margins, const int* idx, int K, u64* keys, int* vals,
+                              int* count, hipStream_t s) {
+    (void)boxes;
+    nms_prepare_kernel<<<(K + 255) / 256 + (K == 0), 256, 0, s>>>(margins, idx, K, keys, vals, count);
+    return hipGetLastError();
+}
+
+__global__ void nms_gather_kernel(const float* boxes, const int* vals, int K, float* sboxes, int* kcount) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) *kcount = K;
+    if (q < K) *(float4*)(sboxes + (size_t)q * 4) = *(const float4*)(boxes + (size_t)vals[q] * 4);
+}
+hipError_t launch_nms_gather(const float* boxes, const u64* keys, const int* vals, int K, float* sboxes, int* kcount,
+                             hipStream_t s) {
+    (void)keys;
+    nms_gather_kernel<<<(K + 255) / 256 + (K == 0), 256, 0, s>>>(boxes, vals, K, sboxes, kcount);
+    return hipGetLastError();
+}
+
+__global__ void nms_finish_kernel(const int* keep, const int* nkeep, const int* vals, int* out_keep, int* out_nkeep) {
+    const int n = *nkeep;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) out_keep[k] = vals[keep[k]];
+    if (threadIdx.x == 0) *out_nkeep = n;
+}
+hipError_t launch_nms_finish(const int* keep, const int* nkeep, const int* vals, int* out_keep, int* out_nkeep, int K,
+                             hipStream_t s) {
+    (void)K;
+    nms_finish_kernel<<<1, 256, 0, s>>>(keep, nkeep, vals, out_keep, out_nkeep);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cost matrix: 32 tracks x 32 detections per workgroup.  The FP32 dot products
+// of the embeddings are staged through LDS in 64-wide chunks; each track's
+// innovation covariance S = P[0:4,0:4] + R(h) is factored once per workgroup
+// in FP64 (Cholesky), each pair's gate distance is an FP64 forward solve.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void cost_kernel(const float* __restrict__ fe, const double* __restrict__ mean,
+                                                   const double* __restrict__ cov, int T,
+                                                   const float* __restrict__ boxes, const float* __restrict__ de,
+                                                   int D, int E, double gate, float* __restrict__ cost) {
+    __shared__ float sf[32][65], se[32][65];
+    __shared__ double sL[32][10], sHx[32][4], sZ[32][4];
+    __shared__ int sPD[32];
+    const int tid = threadIdx.x;
+    const int t0 = blockIdx.y * 32, d0 = blockIdx.x * 32;
+    if (tid < 32) {
+        const int t = t0 + tid;
+        if (t < T) {
+            const double* m = mean + (size_t)t * 8;
+            const double* P = cov + (size_t)t * 64;
+            const double h = m[3];
+            const double sp = h / 20.0;
+            const double r[4] = {sp * sp, sp * sp, 0.1 * 0.1, sp * sp};
+            double S[4][4];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) S[i][j] = P[i * 8 + j] + (i == j ? r[i] : 0.0);
+            // Cholesky S = L L^T (lower), packed row-wise: L00, L10, L11, L20, L21, L22, L30..L33.
+            double L[4][4] = {};
+            int pd = 1;
+            for (int i = 0; i < 4; ++i) {
+                for (int j = 0; j <= i; ++j) {
+                    double acc = S[i][j];
+                    for (int k = 0; k < j; ++k) acc -= L[i][k] * L[j][k];
+                    if (i == j) {
+                        if (!(acc > 0.0)) pd = 0;
+                        L[i][i] = sqrt(acc > 0.0 ? acc : 1.0);
+                    } else {
+                        L[i][j] = acc / L[j][j];
+                    }
+                }
+            }
+            int q = 0;
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j <= i; ++j) sL[tid][q++] = L[i][j];
+            for (int i = 0; i < 4; ++i) sHx[tid][i] = m[i];
+            sPD[tid] = pd;
+        }
+    } else if (tid < 64) {
+        const int d = d0 + tid - 32;
+        if (d < D) {
+            const float* b = boxes + (size_t)d * 4;
+            const double x1 = b[0], y1 = b[1], x2 = b[2], y2 = b[3];
+            const double w = x2 - x1, h = y2 - y1;
+            sZ[tid - 32][0] = (x1 + x2) / 2.0;
+            sZ[tid - 32][1] = (y1 + y2) / 2.0;
+            sZ[tid - 32][2] = w / h;
+            sZ[tid - 32][3] = h;
+        }
+    }
+    const int ty = tid >> 4, tx = tid & 15;  // rows ty*2 + {0,1}, cols tx*2 + {0,1}
+    float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+    for (int e0 = 0; e0 < E; e0 += 64) {
+        __syncthreads();
+        for (int v = tid; v < 32 * 64; v += 256) {
+            const int r = v >> 6, c = v & 63;
+            const int t = t0 + r, d = d0 + r, e = e0 + c;
+            sf[r][c] = (t < T && e < E) ? fe[(size_t)t * E + e] : 0.f;
+            se[r][c] = (d < D && e < E) ? de[(size_t)d * E + e] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int c = 0; c < 64; ++c) {
+            const float f0 = sf[ty * 2][c], f1 = sf[ty * 2 + 1][c];
+            const float g0 = se[tx * 2][c], g1 = se[tx * 2 + 1][c];
+            acc[0][0] = __builtin_fmaf(f0, g0, acc[0][0]);
+            acc[0][1] = __builtin_fmaf(f0, g1, acc[0][1]);
+            acc[1][0] = __builtin_fmaf(f1, g0, acc[1][0]);
+            acc[1][1] = __builtin_fmaf(f1, g1, acc[1][1]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int tl = ty * 2 + i, dl = tx * 2 + j;
+            const int t = t0 + tl, d = d0 + dl;
+            if (t >= T || d >= D) continue;
+            const double* L = sL[tl];
+            const double y0 = sZ[dl][0] - sHx[tl][0], y1 = sZ[dl][1] - sHx[tl][1];
+            const double y2 = sZ[dl][2] - sHx[tl][2], y3 = sZ[dl][3] - sHx[tl][3];
+            const double u0 = y0 / L[0];
+            const double u1 = (y1 - L[1] * u0) / L[2];
+            const double u2 = (y2 - L[3] * u0 - L[4] * u1) / L[5];
+            const double u3 = (y3 - L[6] * u0 - L[7] * u1 - L[8] * u2) / L[9];
+            const double d2 = u0 * u0 + u1 * u1 + u2 * u2 + u3 * u3;
+            float c = fminf(fmaxf(1.0f - acc[i][j], 0.f), 2.f);
+            if (!sPD[tl] || !(d2 <= gate)) c = __builtin_inff();
+            cost[(size_t)t * D + d] = c;
+        }
+}
+
+hipError_t launch_cost(const float* trk_emb, const double* mean, const double* cov, int T, const float* det_boxes,
+                         const float* det_emb, int D, int E, double gate, float* cost, hipStream_t s) {
+    if (T == 0 || D == 0) return hipSuccess;
+    dim3 grid((D + 31) / 32, (T + 31) / 32);
+    cost_kernel<<<grid, 256, 0, s>>>(trk_emb, mean, cov, T, det_boxes, det_emb, D, E, gate, cost);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Track embedding smoothing f_t <- normalise(m f_t + (1 - m) e_d), one wave per pair.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void emb_update_kernel(const int* pairs, int P, const float* de, int D, float* fe,
+                                                         int T, int E, float mom) {
+    const int lane = threadIdx.x & 63;
+    for (int p = blockIdx.x * 4 + (threadIdx.x >> 6); p < P; p += gridDim.x * 4) {
+        const int t = pairs[2 * p], d = pairs[2 * p + 1];
+        if (t < 0 || t >= T || d < 0 || d >= D) continue;
+        float* f = fe + (size_t)t * E;
+        const float* e = de + (size_t)d * E;
+        float ss = 0.f;
+        for (int c = lane; c < E; c += 64) {
+            const float v = mom * f[c] + (1.0f - mom) * e[c];
+            ss = __builtin_fmaf(v, v, ss);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+        const float inv = 1.0f / fmaxf(sqrtf(ss), 1e-12f);
+        for (int c = lane; c < E; c += 64) f[c] = (mom * f[c] + (1.0f - mom) * e[c]) * inv;
+    }
+}
+
+hipError_t launch_emb_update(const int* pairs, int P, const float* det_emb, int D, float* trk_emb, int T, int E,
+                             float momentum, hipStream_t s) {
+    if (P == 0) return hipSuccess;
+    const int gx = (P + 3) / 4 < 256 ? (P + 3) / 4 : 256;
+    emb_update_kernel<<<gx, 256, 0, s>>>(pairs, P, det_emb, D, trk_emb, T, E, momentum);
+    return hipGetLastError();
+}
+
+}  // namespace jde

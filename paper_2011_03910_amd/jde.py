@@ -1,0 +1,233 @@
+"""Python binding of libjde (argument marshalling only).
+
+Every step of the hot path runs in the library's HIP kernels; torch tensors are
+used only as device memory and the current HIP stream as the launch stream.
+Function names follow the C ABI (include/jde.h).
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (JdeConfig, JdeFrameDesc, JdeHeadOut, JdeDets, check, load,  # noqa: F401
+                   JDE_FP32, JDE_BF16, JDE_FP16, JDE_FP8)
+
+PRECISIONS = {"fp32": JDE_FP32, "bf16": JDE_BF16, "fp16": JDE_FP16, "fp8": JDE_FP8}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _descs(descs):
+    arr = (JdeFrameDesc * len(descs))()
+    for i, (h, w) in enumerate(descs):
+        arr[i].h, arr[i].w = int(h), int(w)
+    return arr
+
+
+def jde_create(c0, blocks, emb_dim, anchors, precision="fp32", max_frames=1, max_h=608, max_w=1088,
+               max_candidates=1024):
+    """Create a context (host plan); returns an opaque handle (ctypes.c_void_p)."""
+    lib = load()
+    cfg = JdeConfig()
+    cfg.base_ch = c0
+    for i, b in enumerate(blocks):
+        cfg.blocks[i] = b
+    cfg.emb_dim = emb_dim
+    cfg.num_anchors = 4
+    an = np.asarray(anchors, dtype=np.float32).reshape(3, 4, 2)
+    for s in range(3):
+        for a in range(4):
+            cfg.anchors[s][a][0] = float(an[s, a, 0])
+            cfg.anchors[s][a][1] = float(an[s, a, 1])
+    cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    cfg.max_frames = max_frames
+    cfg.max_h = max_h
+    cfg.max_w = max_w
+    cfg.max_candidates = max_candidates
+    h = ctypes.c_void_p()
+    check(lib.jde_create(ctypes.byref(cfg), ctypes.byref(h)), "jde_create")
+    return h
+
+
+def jde_destroy(ctx):
+    load().jde_destroy(ctx)
+
+
+def jde_layer_info(ctx, i):
+    co, k, ci, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(load().jde_layer_info(ctx, i, ctypes.byref(co), ctypes.byref(k), ctypes.byref(ci), ctypes.byref(st)),
+          "jde_layer_info")
+    return co.value, k.value, ci.value, st.value
+
+
+def jde_cost_matrix(trk_emb, mean, cov, det_boxes, det_emb, gate=9.4877, cost=None, stream=None):
+    """Device tensors in, [T, D] FP32 device cost out."""
+    torch = _torch()
+    T, E = trk_emb.shape
+    D = det_boxes.shape[0]
+    if cost is None:
+        cost = torch.empty((T, D), dtype=torch.float32, device=trk_emb.device)
+    check(load().jde_cost_matrix(_ptr(trk_emb), _ptr(mean), _ptr(cov), T, _ptr(det_boxes), _ptr(det_emb), D, E,
+                                 float(gate), _ptr(cost), _stream(stream)), "jde_cost_matrix")
+    return cost
+
+
+def jde_track_emb_update(pairs, det_emb, trk_emb, momentum=0.9, stream=None):
+    P = pairs.shape[0]
+    check(load().jde_track_emb_update(_ptr(pairs), P, _ptr(det_emb), det_emb.shape[0], _ptr(trk_emb),
+                                      trk_emb.shape[0], trk_emb.shape[1], float(momentum), _stream(stream)),
+          "jde_track_emb_update")
+    return trk_emb
+
+
+def jde_kf_initiate(z):
+    mean = np.zeros(8)
+    cov = np.zeros(64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    load().jde_kf_initiate(z.ctypes.data_as(_lib.c_double_p), mean.ctypes.data_as(_lib.c_double_p),
+                           cov.ctypes.data_as(_lib.c_double_p))
+    return mean, cov.reshape(8, 8)
+
+
+def jde_kf_predict(mean, cov):
+    """In place on contiguous FP64 arrays [T, 8], [T, 8, 8]."""
+    assert mean.dtype == np.float64 and cov.dtype == np.float64 and mean.flags.c_contiguous and cov.flags.c_contiguous
+    load().jde_kf_predict(mean.shape[0], mean.ctypes.data_as(_lib.c_double_p), cov.ctypes.data_as(_lib.c_double_p))
+    return mean, cov
+
+
+def jde_kf_update(mean, cov, z):
+    mean = np.ascontiguousarray(mean, dtype=np.float64).copy()
+    cov = np.ascontiguousarray(cov, dtype=np.float64).copy()
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    check(load().jde_kf_update(mean.ctypes.data_as(_lib.c_double_p), cov.ctypes.data_as(_lib.c_double_p),
+                               z.ctypes.data_as(_lib.c_double_p)), "jde_kf_update")
+    return mean, cov
+
+
+def jde_assign(cost, max_cost):
+    """Host cost [T, D] -> (pairs [P, 2] (t, d) sorted by t, total)."""
+    c = np.ascontiguousarray(cost, dtype=np.float32)
+    T, D = c.shape
+    dot = np.full(max(T, 1), -1, dtype=np.int32)
+    tod = np.full(max(D, 1), -1, dtype=np.int32)
+    tot = ctypes.c_double()
+    k = load().jde_assign(c.ctypes.data_as(_lib.c_float_p), T, D, float(max_cost),
+                          dot.ctypes.data_as(_lib.c_int_p), tod.ctypes.data_as(_lib.c_int_p), ctypes.byref(tot))
+    if k < 0:
+        check(k, "jde_assign")
+    pairs = np.array([(t, dot[t]) for t in range(T) if dot[t] >= 0], dtype=np.int64).reshape(-1, 2)
+    return pairs, tot.value
+
+
+class JDE:
+    """A context plus the device buffers it needs (weights, workspace).
+
+    `layers` for load_weights is the blob-order list of (w [Cout,k,k,Cin], b [Cout]) FP32 arrays.
+    """
+
+    def __init__(self, c0, blocks, emb_dim, anchors, precision="fp32", max_frames=1, max_h=608, max_w=1088,
+                 max_candidates=1024, device="cuda"):
+        torch = _torch()
+        self.lib = load()
+        self.ctx = jde_create(c0, blocks, emb_dim, anchors, precision, max_frames, max_h, max_w, max_candidates)
+        self.E = emb_dim
+        self.cap = max_candidates
+        self.device = torch.device(device)
+        self.weights = torch.empty(self.lib.jde_weights_bytes(self.ctx), dtype=torch.uint8, device=self.device)
+        self.ws = torch.empty(self.lib.jde_workspace_bytes(self.ctx), dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None) is not None:
+                self.lib.jde_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    def num_layers(self):
+        return self.lib.jde_num_layers(self.ctx)
+
+    def layer_shapes(self):
+        return [jde_layer_info(self.ctx, i) for i in range(self.num_layers())]
+
+    def load_weights(self, layers, stream=None):
+        blob = np.concatenate([np.concatenate([np.asarray(w, np.float32).ravel(), np.asarray(b, np.float32).ravel()])
+                               for w, b in layers])
+        blob = np.ascontiguousarray(blob, dtype=np.float32)
+        check(self.lib.jde_load_weights(self.ctx, blob.ctypes.data_as(_lib.c_float_p), blob.size,
+                                        _ptr(self.weights), self.weights.numel(), _stream(stream)),
+              "jde_load_weights")
+
+    def head_buffers(self, descs):
+        torch = _torch()
+        d = _descs(descs)
+        det = (ctypes.c_size_t * 3)()
+        emb = (ctypes.c_size_t * 3)()
+        check(self.lib.jde_head_sizes(self.ctx, d, len(descs), det, emb), "jde_head_sizes")
+        return {"det": [torch.empty(det[s], dtype=torch.float32, device=self.device) for s in range(3)],
+                "emb": [torch.empty(emb[s], dtype=torch.float32, device=self.device) for s in range(3)]}
+
+    def _head_struct(self, heads):
+        h = JdeHeadOut()
+        for s in range(3):
+            h.det[s] = heads["det"][s].data_ptr()
+            h.emb[s] = heads["emb"][s].data_ptr()
+        return h
+
+    def forward(self, frames, descs=None, heads=None, stream=None):
+        """frames: contiguous FP32 device tensor, [n, 3, H, W] or packed 1-D with `descs`."""
+        if descs is None:
+            n, _, H, W = frames.shape
+            descs = [(H, W)] * n
+        if heads is None:
+            heads = self.head_buffers(descs)
+        hs = self._head_struct(heads)
+        check(self.lib.jde_forward(self.ctx, _ptr(frames), _descs(descs), len(descs), _ptr(self.ws),
+                                   self.ws.numel(), ctypes.byref(hs), _stream(stream)), "jde_forward")
+        return heads
+
+    def dets_buffers(self, n):
+        torch = _torch()
+        f32 = dict(dtype=torch.float32, device=self.device)
+        i32 = dict(dtype=torch.int32, device=self.device)
+        return {"boxes": torch.empty((n * self.cap, 4), **f32), "scores": torch.empty(n * self.cap, **f32),
+                "margins": torch.empty(n * self.cap, **f32), "emb": torch.empty((n * self.cap, self.E), **f32),
+                "anchor_idx": torch.empty(n * self.cap, **i32), "count": torch.empty(n, **i32),
+                "n_cand": torch.empty(n, **i32), "overflow": torch.empty(n, **i32)}
+
+    def decode(self, heads, descs, conf_thr=0.5, nms_iou=0.4, dets=None, stream=None):
+        if dets is None:
+            dets = self.dets_buffers(len(descs))
+        ds = JdeDets()
+        for k in ("boxes", "scores", "margins", "emb", "anchor_idx", "count", "n_cand", "overflow"):
+            setattr(ds, k, dets[k].data_ptr())
+        ds.cap = self.cap
+        hs = self._head_struct(heads)
+        check(self.lib.jde_decode(self.ctx, ctypes.byref(hs), _descs(descs), len(descs), float(conf_thr),
+                                  float(nms_iou), _ptr(self.ws), self.ws.numel(), ctypes.byref(ds),
+                                  _stream(stream)), "jde_decode")
+        return dets
+
+    def nms(self, boxes, margins, idx, nms_iou=0.4, stream=None):
+        torch = _torch()
+        K = int(boxes.shape[0])
+        keep = torch.empty(max(K, 1), dtype=torch.int32, device=self.device)
+        nkeep = torch.empty(1, dtype=torch.int32, device=self.device)
+        check(self.lib.jde_nms(self.ctx, _ptr(boxes), _ptr(margins), _ptr(idx), K, float(nms_iou), _ptr(self.ws),
+                               self.ws.numel(), _ptr(keep), _ptr(nkeep), _stream(stream)), "jde_nms")
+        return keep, nkeep

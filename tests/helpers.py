@@ -1,0 +1,108 @@
+"""Shared helpers of the tests (inputs, oracle runs, comparisons)."""
+
+import functools
+
+import numpy as np
+
+from jde_inputs import TINY, FULL, model_weights, tiny_frame, scene_batch, anchors_px
+
+
+def rel_err(got, ref):
+    """Normwise max relative error max|g - r| / max|r| (per output tensor)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30))
+
+
+@functools.lru_cache(maxsize=None)
+def weights(cfg_name, k):
+    cfg = TINY if cfg_name == "tiny" else FULL
+    return model_weights(cfg, k)
+
+
+@functools.lru_cache(maxsize=None)
+def frames(cfg_name, n, t0=0, h=None, w=None):
+    cfg = TINY if cfg_name == "tiny" else FULL
+    h = h or cfg.height
+    w = w or cfg.width
+    if cfg_name == "tiny":
+        return np.stack([tiny_frame(cfg.seed, t0 + i, h, w) for i in range(n)])
+    return scene_batch(cfg.seed, n, h, w, t0=t0)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_forward(cfg_name, k, n, t0=0, h=None, w=None):
+    from oracle.network import forward
+    cfg = TINY if cfg_name == "tiny" else FULL
+    return forward(frames(cfg_name, n, t0, h, w), weights(cfg_name, k), cfg.blocks)
+
+
+def head_views(heads, descs):
+    """Per-frame [Hs, Ws, C] numpy views of packed GPU head outputs."""
+    out = {"det": [], "emb": []}
+    for key in ("det", "emb"):
+        for s in range(3):
+            flat = heads[key][s].cpu().numpy()
+            st = 8 << s
+            pix = [(h // st) * (w // st) for h, w in descs]
+            c = flat.size // sum(pix)
+            off = 0
+            per = []
+            for (h, w), p in zip(descs, pix):
+                per.append(flat[off * c:(off + p) * c].reshape(h // st, w // st, c))
+                off += p
+            out[key].append(per)
+    return out
+
+
+def gpu_dets(d, f, cap):
+    cnt = int(d["count"][f])
+    sl = slice(f * cap, f * cap + cnt)
+    return {k: d[k][sl].cpu().numpy() for k in ("boxes", "scores", "margins", "emb", "anchor_idx")} | {
+        "n_cand": int(d["n_cand"][f]), "overflow": int(d["overflow"][f])}
+
+
+def iou_matrix(a, b):
+    a = np.asarray(a, np.float64)[:, None, :]
+    b = np.asarray(b, np.float64)[None, :, :]
+    iw = np.clip(np.minimum(a[..., 2], b[..., 2]) - np.maximum(a[..., 0], b[..., 0]), 0, None)
+    ih = np.clip(np.minimum(a[..., 3], b[..., 3]) - np.maximum(a[..., 1], b[..., 1]), 0, None)
+    inter = iw * ih
+    ua = (a[..., 2] - a[..., 0]) * (a[..., 3] - a[..., 1]) + (b[..., 2] - b[..., 0]) * (b[..., 3] - b[..., 1]) - inter
+    return inter / np.maximum(ua, 1e-30)
+
+
+def match_fraction(gpu_boxes, ref_boxes, ref_order_scores, iou_min=0.9):
+    """One-to-one greedy matching in reference-score order; fraction of reference
+    detections matched by a GPU detection at IoU >= iou_min."""
+    if len(ref_boxes) == 0:
+        return 1.0, []
+    if len(gpu_boxes) == 0:
+        return 0.0, []
+    m = iou_matrix(ref_boxes, gpu_boxes)
+    used = set()
+    pairs = []
+    for r in np.argsort(-np.asarray(ref_order_scores), kind="stable"):
+        cand = [(m[r, g], g) for g in range(m.shape[1]) if g not in used and m[r, g] >= iou_min]
+        if cand:
+            best = max(cand)[1]
+            used.add(best)
+            pairs.append((r, best))
+    return len(pairs) / len(ref_boxes), pairs
+
+
+def anchors(cfg_name):
+    return anchors_px(TINY if cfg_name == "tiny" else FULL)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_forward_rounded(cfg_name, k, n, fmt):
+    """Oracle forward of the network as stored in `fmt` ('bf16' or 'fp16'): conv
+    weights rounded to the format (the stem stays FP32) and every stored
+    activation rounded; arithmetic FP64."""
+    from oracle.network import forward, round_bf16, round_fp16
+    cfg = TINY if cfg_name == "tiny" else FULL
+    rnd = round_bf16 if fmt == "bf16" else round_fp16
+    layers = weights(cfg_name, k)
+    layers = [layers[0]] + [(rnd(w), b) for w, b in layers[1:]]
+    return forward(frames(cfg_name, n), layers, cfg.blocks, store=rnd)

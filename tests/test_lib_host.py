@@ -1,0 +1,165 @@
+"""CPU tests of libjde: exported symbols, layer plan, argument checks, and the
+host FP64 association code (Kalman filter, assignment) against the oracle.
+
+No device work is enqueued here: every call either is host code or fails its
+argument checks before touching the GPU.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from jde_inputs import TINY, FULL, weight_specs, anchors_px
+from oracle import track as otrack
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2011_03910_amd import _lib
+    return _lib.load()
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "jde.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(jde_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2011_03910_amd import _lib
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, n
+    nm = os.popen(f"nm -D --defined-only {_lib.LIB_PATH}").read()
+    for n in names:
+        assert re.search(rf"\bT {n}\b", nm), n
+
+
+@pytest.mark.parametrize("cfg", [TINY, FULL])
+def test_layer_plan_matches_weight_blob_order(cfg):
+    import paper_2011_03910_amd as P
+    ctx = P.jde_create(cfg.c0, cfg.blocks, cfg.emb_dim, anchors_px(cfg), "bf16", 2, cfg.height, cfg.width, 512)
+    try:
+        from paper_2011_03910_amd import _lib
+        L = _lib.load()
+        shapes = [P.jde_layer_info(ctx, i) for i in range(L.jde_num_layers(ctx))]
+        specs = weight_specs(cfg)
+        assert [(s[1], s[2], s[3]) for s in specs] == [(a, b, c) for a, b, c, _ in shapes]
+        assert L.jde_blob_floats(ctx) == sum(co * k * k * ci + co for _, co, k, ci, _ in specs)
+        strides = [st for *_, st in shapes]
+        assert strides.count(2) == 5
+    finally:
+        P.jde_destroy(ctx)
+
+
+def _cfg(**kw):
+    from paper_2011_03910_amd import _lib
+    c = _lib.JdeConfig()
+    c.base_ch, c.emb_dim, c.num_anchors, c.precision = 16, 64, 4, 0
+    for i, b in enumerate(TINY.blocks):
+        c.blocks[i] = b
+    c.max_frames, c.max_h, c.max_w, c.max_candidates = 2, 192, 320, 256
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(num_anchors=3), -5), (dict(precision=7), -5), (dict(max_h=100), -1), (dict(max_frames=0), -1),
+    (dict(max_frames=65), -1), (dict(max_candidates=100), -1), (dict(max_candidates=16384), -1),
+    (dict(emb_dim=60), -1), (dict(base_ch=24), -5)])
+def test_create_rejects_bad_configs(lib, kw, status):
+    h = ctypes.c_void_p()
+    assert lib.jde_create(ctypes.byref(_cfg(**kw)), ctypes.byref(h)) == status
+    assert lib.jde_last_error()
+
+
+def test_calls_fail_before_device_work(lib):
+    from paper_2011_03910_amd import _lib
+    h = ctypes.c_void_p()
+    assert lib.jde_create(ctypes.byref(_cfg()), ctypes.byref(h)) == 0
+    try:
+        d = (_lib.JdeFrameDesc * 3)()
+        for i in range(3):
+            d[i].h, d[i].w = 192, 320
+        heads = _lib.JdeHeadOut()
+        ws = lib.jde_workspace_bytes(h)
+        fake = ctypes.c_void_p(0x1000)
+        # forward before weights are loaded
+        assert lib.jde_forward(h, fake, d, 1, fake, ws, ctypes.byref(heads), None) == _lib.JDE_ESTATE
+        # wrong blob size
+        assert lib.jde_load_weights(h, None, 5, fake, 10, None) == _lib.JDE_EINVAL
+        blob = np.zeros(lib.jde_blob_floats(h), dtype=np.float32)
+        assert lib.jde_load_weights(h, blob.ctypes.data_as(_lib.c_float_p), blob.size, fake, 10,
+                                    None) == _lib.JDE_ENOMEM
+        # too many frames / bad frame size / small workspace / cap mismatch
+        dets = _lib.JdeDets()
+        assert lib.jde_decode(h, ctypes.byref(heads), d, 3, 0.5, 0.4, fake, ws, ctypes.byref(dets),
+                              None) == _lib.JDE_EINVAL
+        dets.cap = 256
+        for k in ("boxes", "scores", "margins", "emb", "anchor_idx", "count", "n_cand", "overflow"):
+            setattr(dets, k, 0x1000)
+        assert lib.jde_decode(h, ctypes.byref(heads), d, 3, 0.5, 0.4, fake, ws, ctypes.byref(dets),
+                              None) == _lib.JDE_ECAPACITY
+        d[0].h = 100
+        assert lib.jde_decode(h, ctypes.byref(heads), d, 1, 0.5, 0.4, fake, ws, ctypes.byref(dets),
+                              None) == _lib.JDE_EINVAL
+        d[0].h = 192
+        assert lib.jde_decode(h, ctypes.byref(heads), d, 1, 0.5, 0.4, fake, ws - 1, ctypes.byref(dets),
+                              None) == _lib.JDE_ENOMEM
+        assert lib.jde_decode(h, ctypes.byref(heads), d, 1, 1.5, 0.4, fake, ws, ctypes.byref(dets),
+                              None) == _lib.JDE_EINVAL
+        assert lib.jde_nms(h, fake, fake, fake, 257, 0.4, fake, ws, fake, fake, None) == _lib.JDE_ECAPACITY
+        assert lib.jde_cost_matrix(None, None, None, 3, None, None, 4, 64, 9.4877, None, None) == _lib.JDE_EINVAL
+        assert lib.jde_cost_matrix(None, None, None, 3, None, None, 4, 62, 9.4877, None, None) == _lib.JDE_EINVAL
+        sizes = (ctypes.c_size_t * 3)(), (ctypes.c_size_t * 3)()
+        assert lib.jde_head_sizes(h, d, 2, *sizes) == 0
+        assert sizes[0][0] == 2 * 24 * 40 * 24 and sizes[1][2] == 2 * 6 * 10 * 64
+    finally:
+        lib.jde_destroy(h)
+
+
+def test_kalman_matches_oracle(rng):
+    import paper_2011_03910_amd as P
+    z = np.array([300.0, 200.0, 0.45, 120.0])
+    m, c = P.jde_kf_initiate(z)
+    mo, co = otrack.kf_initiate(z)
+    np.testing.assert_array_equal(m, mo)
+    np.testing.assert_array_equal(c, co)
+    for step in range(50):
+        mm = m[None].copy()
+        cc = c[None].copy()
+        P.jde_kf_predict(mm, cc)
+        mo, co = otrack.kf_predict(mo, co)
+        np.testing.assert_allclose(mm[0], mo, rtol=1e-14, atol=1e-12)
+        np.testing.assert_allclose(cc[0], co, rtol=1e-12, atol=1e-12)
+        zz = mo[:4] + rng.normal(0, 1, 4) * [3, 3, 0.01, 2]
+        m, c = P.jde_kf_update(mm[0], cc[0], zz)
+        mo, co = otrack.kf_update(mo, co, zz)
+        np.testing.assert_allclose(m, mo, rtol=1e-10, atol=1e-9)
+        np.testing.assert_allclose(c, co, rtol=1e-8, atol=1e-9)
+        assert np.array_equal(c, c.T)
+        m, c = mo.copy(), co.copy()
+
+
+@pytest.mark.parametrize("t_n,d_n", [(5, 5), (8, 13), (13, 8), (1, 1), (0, 4), (60, 45), (200, 200)])
+def test_assign_matches_oracle(rng, t_n, d_n):
+    import paper_2011_03910_amd as P
+    for _ in range(3):
+        c = rng.uniform(0, 1.3, (t_n, d_n)).astype(np.float32)
+        if c.size:
+            c[rng.random(c.shape) < 0.4] = np.inf
+        pairs, total = P.jde_assign(c, 0.7)
+        rp, rt = otrack.assign(c.astype(np.float64), 0.7)
+        assert len(pairs) == len(rp)
+        assert total == pytest.approx(rt, abs=1e-9)
+        if len(pairs):
+            assert np.all(c[pairs[:, 0], pairs[:, 1]] <= 0.7)
+            assert len(set(pairs[:, 1])) == len(pairs)

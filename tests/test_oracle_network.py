@@ -190,3 +190,16 @@ def test_calibration_reproduces_stored_statistics():
     for i in mu:
         np.testing.assert_allclose(mu[i], calib["mu"][i], rtol=1e-9, atol=1e-12)
         np.testing.assert_allclose(var[i], calib["var"][i], rtol=1e-9)
+
+
+def test_rounding_models_match_library_casts_and_ties(rng):
+    import torch
+    x = (rng.standard_normal(20000) * 10.0 ** rng.uniform(-6, 6, 20000)).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+    np.testing.assert_array_equal(net.round_bf16(x), ref)
+    # ties go to even: 1 + 2^-8 is halfway between 1 and 1 + 2^-7
+    assert net.round_bf16(np.float32(1 + 2 ** -8)) == 1.0
+    assert net.round_bf16(np.float32(1 + 3 * 2 ** -8)) == 1 + 2 ** -6
+    assert net.round_fp16(np.float32(1 + 2 ** -11)) == 1.0
+    assert net.round_fp16(np.float32(1 + 3 * 2 ** -11)) == 1 + 2 ** -9
+    assert np.isinf(net.round_bf16(np.float32(np.inf)))
