@@ -1,0 +1,224 @@
+"""Benchmark of the JDE hot path on one MI355X.
+
+One step = one pass of the whole hot path over one batch of synthetic
+3x608x1088 frames already resident in HBM: the JDE forward (Darknet-53, FPN,
+three heads), decode + confidence threshold, sort, NMS, embedding
+L2-normalisation, and the tracks x detections cost matrix (cosine distance with
+Mahalanobis gating) of every frame against 40 synthetic tracks.
+
+Prints ONE JSON line on stdout; a per-launch breakdown goes to stderr.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--precision bf16]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "frames/s at 1088x608 (BF16 batched vs FP32 batch-1) + p99 frame latency"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3, "fp8": 5000.0}
+N_TRACKS = 40
+K_CAND = 40
+CONF, NMS_IOU = 0.5, 0.4
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(batch, torch):
+    """Frames [B, 3, 608, 1088] and, per frame, its own set of N_TRACKS tracks."""
+    import numpy as np
+    from jde_inputs import FULL, scene_batch, synthetic_dets_tracks
+    fr = scene_batch(FULL.seed, batch, FULL.height, FULL.width)
+    trk = [synthetic_dets_tracks(FULL.seed + f, N_TRACKS, N_TRACKS, FULL.emb_dim) for f in range(batch)]
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    cat = lambda k: cu(np.concatenate([t[k] for t in trk]))
+    return cu(fr), cat("trk_emb"), cat("mean"), cat("cov")
+
+
+class Pipeline:
+    """Preallocated buffers and one step of the hot path for a fixed batch."""
+
+    def __init__(self, precision, batch, layers, torch, tune_frames=None, tiles=None):
+        from jde_inputs import FULL, anchors_px
+        from paper_2011_03910_amd import JDE
+        self.torch = torch
+        self.batch = batch
+        self.descs = [(FULL.height, FULL.width)] * batch
+        self.m = JDE(FULL.c0, FULL.blocks, FULL.emb_dim, anchors_px(FULL), precision, batch, FULL.height,
+                     FULL.width, 512)
+        self.m.load_weights(layers)
+        self.heads = self.m.head_buffers(self.descs)
+        self.dets = self.m.dets_buffers(batch)
+        self.track_begin = [N_TRACKS * f for f in range(batch + 1)]
+        self.cost = torch.empty((batch * N_TRACKS, self.m.cap), dtype=torch.float32, device="cuda")
+        self.tiles = None
+        if tiles is not None:
+            self.m.set_tiles(tiles)
+            self.tiles = self.m.tiles()
+        elif tune_frames is not None:
+            t0 = time.perf_counter()
+            self.tiles = self.m.autotune(tune_frames, self.descs, heads=self.heads, reps=3)
+            log(f"autotuned {precision} b{batch} tiles in {time.perf_counter() - t0:.1f} s: {self.tiles.tolist()}")
+
+    def step(self, frames, trk_emb, mean, cov):
+        self.m.forward(frames, self.descs, heads=self.heads)
+        self.m.decode(self.heads, self.descs, CONF, NMS_IOU, dets=self.dets)
+        self.m.cost_batch(trk_emb, mean, cov, self.track_begin, self.dets, cost=self.cost)
+
+
+def run(pipe, inputs, steps, warmup, torch, profile=False):
+    for _ in range(warmup):
+        pipe.step(*inputs)
+    torch.cuda.synchronize()
+    if profile:
+        pipe.m.profile_begin(True)
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(stream)
+        pipe.step(*inputs)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = sorted(a.elapsed_time(b) for a, b in evs)
+    prof = pipe.m.profile_collect() if profile else None
+    if profile:
+        pipe.m.profile_begin(False)
+    return wall, step_ms, prof
+
+
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def cpu_baseline(layers):
+    """The FP64 oracle on a bounded sample: one full-resolution frame through
+    forward, decode, NMS, normalisation and the cost against 40 tracks."""
+    import numpy as np
+    from jde_inputs import FULL, scene_batch, synthetic_dets_tracks, anchors_px
+    from oracle.network import forward
+    from oracle.post import detections
+    from oracle.track import cost_matrix
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    fr = scene_batch(FULL.seed, 1, FULL.height, FULL.width)
+    trk = synthetic_dets_tracks(FULL.seed, N_TRACKS, N_TRACKS, FULL.emb_dim)
+    t0 = time.perf_counter()
+    out = forward(fr, layers, FULL.blocks)
+    d = detections(out, anchors_px(FULL), CONF, NMS_IOU)
+    cost_matrix(trk["trk_emb"], trk["mean"], trk["cov"], d["boxes"], d["emb"])
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "frames/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"1 frame 3x608x1088, FP64 numpy: forward + decode + NMS + normalise + "
+                      f"{N_TRACKS}-track cost ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--fp32-steps", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 batch-1 plain form")
+    ap.add_argument("--no-tune", action="store_true", help="built-in tile choice instead of the autotuner")
+    ap.add_argument("--save-tiles", help="write the tile choices to this JSON file")
+    ap.add_argument("--load-tiles", help="use tile choices from this JSON file instead of tuning")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (frames are independent, "
+              "so more GPUs would each run this same single-GPU path on their own streams)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from jde_inputs import FULL, model_weights
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"device: {torch.cuda.get_device_name(0)}")
+    layers = model_weights(FULL, K_CAND)
+    inputs_b = make_inputs(args.batch, torch)
+
+    saved = json.load(open(args.load_tiles)) if args.load_tiles else {}
+    key = f"{args.precision}_b{args.batch}"
+    pipe = Pipeline(args.precision, args.batch, layers, torch, None if args.no_tune else inputs_b[0],
+                    saved.get(key))
+    tiles_out = {key: None if pipe.tiles is None else pipe.tiles.tolist()}
+    wall, step_ms, prof = run(pipe, inputs_b, args.steps, args.warmup, torch, profile=True)
+    fps = args.batch * args.steps / wall
+    counts = pipe.dets["count"].cpu().numpy()
+    ncand = pipe.dets["n_cand"].cpu().numpy()
+    log(f"{args.precision} b{args.batch}: {fps:.1f} frames/s, step p50 {pct(step_ms, 50):.2f} ms "
+        f"p99 {pct(step_ms, 99):.2f} ms; candidates/frame {ncand.mean():.1f}, kept {counts.mean():.1f}")
+
+    ms, fl, kind, nfwd = prof
+    conv = kind == 1
+    conv_ms = ms[conv].sum() / nfwd
+    conv_flop = fl[conv].sum()
+    n_launch = int(conv.sum())
+    achieved = conv_flop / (conv_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    fwd_ms = ms.sum() / nfwd
+    log(f"forward launches: {len(ms)}; conv {n_launch} launches {conv_ms:.3f} ms/step "
+        f"({conv_flop / 1e9:.1f} GFLOP) -> {achieved:.1f} TFLOP/s; all forward launches {fwd_ms:.3f} ms")
+    for i in range(len(ms)):
+        t = ms[i] / nfwd
+        log(f"  op {i:2d} kind {kind[i]} {t * 1e3:9.1f} us  {fl[i] / 1e9:8.2f} GFLOP  "
+            f"{(fl[i] / (t * 1e-3) / 1e12 if t > 0 else 0):7.1f} TFLOP/s")
+    del pipe
+    torch.cuda.empty_cache()
+
+    fp32 = None
+    if not args.no_fp32:
+        in1 = (inputs_b[0][:1].contiguous(), inputs_b[1][:N_TRACKS], inputs_b[2][:N_TRACKS], inputs_b[3][:N_TRACKS])
+        p32 = Pipeline("fp32", 1, layers, torch, None if args.no_tune else in1[0], saved.get("fp32_b1"))
+        tiles_out["fp32_b1"] = None if p32.tiles is None else p32.tiles.tolist()
+        w32, s32, _ = run(p32, in1, args.fp32_steps, 3, torch)
+        fp32 = {"fps": 1 * args.fp32_steps / w32, "p50_ms": pct(s32, 50), "p99_ms": pct(s32, 99)}
+        log(f"fp32 b1: {fp32['fps']:.1f} frames/s, p50 {fp32['p50_ms']:.2f} ms")
+        del p32
+        torch.cuda.empty_cache()
+
+    if args.save_tiles:
+        json.dump(tiles_out, open(args.save_tiles, "w"))
+    cpu = None if args.no_cpu else cpu_baseline(layers)
+    if cpu:
+        log(f"cpu oracle: {cpu['value']:.4f} frames/s on {cpu['cores']} threads")
+
+    rec = {
+        "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"JDE Darknet-53+FPN+3 heads (E=512), 3x608x1088 synthetic scene frames, "
+                               f"{args.precision.upper()} batch {args.batch}, ~{K_CAND} candidates/frame; "
+                               f"forward + decode + NMS + L2-normalise + {N_TRACKS}-track gated cost",
+                   "global_batch": args.batch, "seq_len": None, "parallelism": "none (1 GPU)",
+                   "resolution": "608x1088"},
+        "p50_frame_latency_ms": round(pct(step_ms, 50), 3), "p99_frame_latency_ms": round(pct(step_ms, 99), 3),
+        "fp32_b1": None if fp32 is None else {k: round(v, 3) for k, v in fp32.items()},
+        "speedup_vs_fp32_b1": None if fp32 is None else round(fps / fp32["fps"], 2),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": f"conv_igemm ({n_launch} launches/step, {conv_flop / 1e9:.1f} GFLOP/step, "
+                               f"mean {conv_ms / n_launch * 1e3:.1f} us/launch)"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

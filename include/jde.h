@@ -142,6 +142,20 @@ jde_status jde_head_sizes(const jde_ctx* ctx, const jde_frame_desc* descs, int n
 jde_status jde_forward(jde_ctx* ctx, const float* d_frames, const jde_frame_desc* descs, int n,
                        void* d_ws, size_t ws_bytes, const jde_head_out* out, void* stream);
 
+/* Tile autotuner of the convolutions (batch-wise inference, Sec. 4.2, is only
+ * as fast as its kernels on the batch shape used).  Runs one forward, then
+ * times every tile configuration that fits each convolution (reps launches
+ * each, on the stream; blocks until done) and keeps the fastest per launch for
+ * later forwards of any batch.  Arguments as for jde_forward; the buffers hold
+ * meaningless values afterwards. */
+jde_status jde_autotune(jde_ctx* ctx, const float* d_frames, const jde_frame_desc* descs, int n,
+                        void* d_ws, size_t ws_bytes, const jde_head_out* out, int reps, void* stream);
+/* Reads (set = 0) or writes (set = 1) the tile choice of every forward launch:
+ * tiles[n_ops] host, n_ops = number of forward launches (jde_profile_collect's
+ * *n_ops); -1 = the built-in default.  Entries of non-MFMA launches are ignored
+ * on write. */
+jde_status jde_tiles(jde_ctx* ctx, int* tiles, int n_ops, int set);
+
 /* Post-processing of Appendix A items 1-3 plus embedding normalisation, for
  * every frame of the batch: anchor decode, keep iff score >= conf_thr
  * (evaluated as c_fg - c_bg >= ln(conf_thr / (1 - conf_thr)) in FP32), sort
@@ -173,12 +187,44 @@ jde_status jde_cost_matrix(const float* d_track_emb, const double* d_mean, const
                            const float* d_det_boxes, const float* d_det_emb, int D, int E,
                            double gate_chi2, float* d_cost, void* stream);
 
+/* The same cost against one frame of a jde_decode result, with D read from
+ * dets->count[frame] on the device (no host round trip).  d_cost [T, cap]
+ * (row stride cap = dets->cap); columns >= count[frame] are left untouched. */
+jde_status jde_cost_matrix_dets(const float* d_track_emb, const double* d_mean, const double* d_cov,
+                                int T, const jde_dets* dets, int frame, int E, double gate_chi2,
+                                float* d_cost, void* stream);
+
+/* The cost for every frame of a jde_decode result in one launch.  Frame f
+ * (0 <= f < n) is scored against tracks [track_begin[f], track_begin[f+1]) of
+ * the track arrays (e.g. the tracks of the video stream the frame belongs to)
+ * and its rows start at row track_begin[f] of d_cost [track_begin[n], cap]
+ * (row stride cap).  track_begin: host, n+1 non-decreasing ints, n <= 64.
+ * D of each frame is read from dets->count[f] on the device. */
+jde_status jde_cost_matrix_batch(const float* d_track_emb, const double* d_mean, const double* d_cov,
+                                 const int* track_begin, const jde_dets* dets, int n, int E,
+                                 double gate_chi2, float* d_cost, void* stream);
+
 /* Track embedding smoothing for matched pairs: f_t <- normalise(m f_t + (1-m) e_d)
  * (the track's appearance state follows its matched detections).  d_pairs
  * [P,2] int (t, d) device, each t at most once; pairs with t outside [0, T) or
  * d outside [0, D) are skipped.  d_det_emb [D,E], d_track_emb [T,E] FP32. */
 jde_status jde_track_emb_update(const int* d_pairs, int P, const float* d_det_emb, int D,
                                 float* d_track_emb, int T, int E, float momentum, void* stream);
+
+/* ---- per-launch timing of the forward (Sec. 5.1 profiles where time goes) -- */
+
+/* on = 1: every later jde_forward records a HIP event pair around each of its
+ * launches, on the launch stream, into a ring of 8 forwards (a 9th forward
+ * first waits for the oldest ring entry).  Resets the accumulators.  on = 0
+ * stops recording.  Not for use inside graph capture. */
+jde_status jde_profile_begin(jde_ctx* ctx, int on);
+/* Waits for the recorded events and returns, per forward launch i < *n_ops
+ * (launch order; at most max_ops entries written): summed duration in ms over
+ * the profiled forwards (op_ms), FLOPs of one launch for the last batch
+ * (op_flop: 2*M*N*K), kind (op_kind: 0 = stem, 1 = MFMA conv).  *n_fwd gets
+ * the number of forwards summed.  All arrays host. */
+jde_status jde_profile_collect(jde_ctx* ctx, int max_ops, double* op_ms, double* op_flop, int* op_kind,
+                               int* n_ops, int* n_fwd);
 
 /* ---- host FP64 association (Appendix A items 4, 7-9) --------------------- */
 

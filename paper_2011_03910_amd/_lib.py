@@ -64,6 +64,19 @@ SIGNATURES = {
     "jde_cost_matrix": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "jde_cost_matrix_dets": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.POINTER(JdeDets), ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "jde_cost_matrix_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, c_int_p,
+                                             ctypes.POINTER(JdeDets), ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "jde_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(JdeFrameDesc), ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(JdeHeadOut), ctypes.c_int,
+                                    ctypes.c_void_p]),
+    "jde_tiles": (ctypes.c_int, [ctypes.c_void_p, c_int_p, ctypes.c_int, ctypes.c_int]),
+    "jde_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "jde_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p, c_int_p, c_int_p,
+                                           c_int_p]),
     "jde_track_emb_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                             ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_float,
                                             ctypes.c_void_p]),

@@ -80,6 +80,17 @@ struct jde_ctx {
     int keycap = 0, cap = 0, max_anchors = 0;
     char* d_weights = nullptr;
     bool loaded = false;
+    // Per-launch timing: a ring of event pairs, one entry per profiled forward.
+    static constexpr int kRing = 8;
+    bool prof = false;
+    std::vector<hipEvent_t> ev;          // [kRing][ops][2]
+    bool pending[kRing] = {};
+    int ring_pos = 0;
+    std::vector<double> op_ms, op_flop;
+    int n_fwd = 0;
+    ~jde_ctx() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -321,6 +332,50 @@ GeomParams geom_params(const jde_frame_desc* d, int n) {
     return p;
 }
 
+// Arguments of conv op `o` for a batch (d, n) with workspace W and head outputs `out`.
+ConvArgs conv_args(const jde_ctx* c, const Op& o, const jde_frame_desc* d, int n, bool uniform, char* W,
+                   const int* geom, const jde_head_out* out) {
+    auto tptr = [&](int t) -> void* { return t < 0 ? nullptr : (void*)(W + c->tens[t].off); };
+    const char* wb = c->d_weights;
+    ConvArgs a{};
+    a.in = tptr(o.in_t);
+    a.in2 = tptr(o.in2_t);
+    a.w = wb + o.dev_w;
+    a.bias = (const float*)(wb + o.dev_b);
+    a.wscale = nullptr;
+    a.res = tptr(o.res_t);
+    a.geom = geom;
+    a.nframes = n;
+    a.uniform = uniform;
+    a.lvl_in = o.lvl_in;
+    a.lvl_out = o.lvl_out;
+    a.cin = o.cin;
+    a.cout = o.cout;
+    a.ksz = o.ksz;
+    a.stride = o.stride;
+    a.pad = o.ksz / 2;
+    a.cin1 = o.cin1;
+    a.K = o.ksz * o.ksz * o.cin;
+    a.M = (int)level_pixels(d, n, o.lvl_out);
+    a.n_split = o.n_split;
+    a.act = o.act;
+    a.in_scale = 1.f;
+    if (o.det_out >= 0) {
+        a.out0 = out->det[o.det_out];
+        a.ld0 = o.cout;
+        a.out0_f32 = 1;
+    } else {
+        a.out0 = tptr(o.out_t);
+        a.ld0 = o.n_split;
+        a.out0_f32 = 0;
+    }
+    if (o.emb_out >= 0) {
+        a.out1 = out->emb[o.emb_out];
+        a.ld1 = o.cout - o.n_split;
+    }
+    return a;
+}
+
 }  // namespace
 
 // ---- setup kernel: geometry table + counter reset ---------------------------
@@ -413,6 +468,53 @@ jde_status jde_create(const jde_config* cfg, jde_ctx** out) {
 
 void jde_destroy(jde_ctx* c) { delete c; }
 
+static jde_status prof_harvest(jde_ctx* c, int slot) {
+    if (!c->pending[slot]) return JDE_OK;
+    const size_t nops = c->ops.size();
+    hipEvent_t* e = c->ev.data() + (size_t)slot * nops * 2;
+    HIP_TRY(hipEventSynchronize(e[nops * 2 - 1]));
+    for (size_t i = 0; i < nops; ++i) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e[2 * i], e[2 * i + 1]));
+        c->op_ms[i] += ms;
+    }
+    c->pending[slot] = false;
+    c->n_fwd += 1;
+    return JDE_OK;
+}
+
+jde_status jde_profile_begin(jde_ctx* c, int on) {
+    if (!c) return fail(JDE_EINVAL, "null context");
+    for (int k = 0; k < jde_ctx::kRing; ++k) c->pending[k] = false;
+    c->ring_pos = 0;
+    c->n_fwd = 0;
+    c->op_ms.assign(c->ops.size(), 0.0);
+    c->op_flop.assign(c->ops.size(), 0.0);
+    if (on && c->ev.empty()) {
+        c->ev.resize((size_t)jde_ctx::kRing * c->ops.size() * 2);
+        for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    c->prof = on != 0;
+    return JDE_OK;
+}
+
+jde_status jde_profile_collect(jde_ctx* c, int max_ops, double* op_ms, double* op_flop, int* op_kind, int* n_ops,
+                               int* n_fwd) {
+    if (!c) return fail(JDE_EINVAL, "null context");
+    if (c->prof)
+        for (int k = 0; k < jde_ctx::kRing; ++k)
+            if (jde_status st = prof_harvest(c, k)) return st;
+    const int n = (int)c->ops.size();
+    for (int i = 0; i < n && i < max_ops; ++i) {
+        if (op_ms) op_ms[i] = i < (int)c->op_ms.size() ? c->op_ms[i] : 0.0;
+        if (op_flop) op_flop[i] = i < (int)c->op_flop.size() ? c->op_flop[i] : 0.0;
+        if (op_kind) op_kind[i] = c->ops[i].kind;
+    }
+    if (n_ops) *n_ops = n;
+    if (n_fwd) *n_fwd = c->n_fwd;
+    return JDE_OK;
+}
+
 int jde_num_layers(const jde_ctx* c) { return c ? (int)c->layers.size() : 0; }
 
 jde_status jde_layer_info(const jde_ctx* c, int i, int* cout, int* k, int* cin, int* stride) {
@@ -493,52 +595,96 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
     int* geom = (int*)(W + c->ws_geom);
     HIP_TRY(launch_setup(geom_params(d, n), geom, nullptr, 0, s));
     auto tptr = [&](int t) -> void* { return t < 0 ? nullptr : (void*)(W + c->tens[t].off); };
-    for (const Op& o : c->ops) {
+    hipEvent_t* pev = nullptr;
+    if (c->prof) {
+        const int slot = c->ring_pos;
+        if (jde_status st = prof_harvest(c, slot)) return st;
+        pev = c->ev.data() + (size_t)slot * c->ops.size() * 2;
+        c->pending[slot] = true;
+        c->ring_pos = (slot + 1) % jde_ctx::kRing;
+    }
+    for (size_t oi = 0; oi < c->ops.size(); ++oi) {
+        const Op& o = c->ops[oi];
         const char* wb = c->d_weights;
+        if (pev) HIP_TRY(hipEventRecord(pev[2 * oi], s));
         if (o.kind == OP_STEM) {
             const int M = (int)level_pixels(d, n, 0);
             HIP_TRY(launch_stem(frames, geom, n, uniform, d[0].h, d[0].w, M, (const float*)(wb + o.dev_w),
                                 (const float*)(wb + o.dev_b), o.cout, tptr(o.out_t), c->et, s));
+            if (pev) {
+                HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));
+                c->op_flop[oi] = 2.0 * M * o.cout * 27;
+            }
             continue;
         }
-        ConvArgs a{};
-        a.in = tptr(o.in_t);
-        a.in2 = tptr(o.in2_t);
-        a.w = wb + o.dev_w;
-        a.bias = (const float*)(wb + o.dev_b);
-        a.wscale = nullptr;
-        a.res = tptr(o.res_t);
-        a.geom = geom;
-        a.nframes = n;
-        a.uniform = uniform;
-        a.lvl_in = o.lvl_in;
-        a.lvl_out = o.lvl_out;
-        a.cin = o.cin;
-        a.cout = o.cout;
-        a.ksz = o.ksz;
-        a.stride = o.stride;
-        a.pad = o.ksz / 2;
-        a.cin1 = o.cin1;
-        a.K = o.ksz * o.ksz * o.cin;
-        a.M = (int)level_pixels(d, n, o.lvl_out);
-        a.n_split = o.n_split;
-        a.act = o.act;
-        a.in_scale = 1.f;
-        if (o.det_out >= 0) {
-            a.out0 = out->det[o.det_out];
-            a.ld0 = o.cout;
-            a.out0_f32 = 1;
-        } else {
-            a.out0 = tptr(o.out_t);
-            a.ld0 = o.n_split;
-            a.out0_f32 = 0;
-        }
-        if (o.emb_out >= 0) {
-            a.out1 = out->emb[o.emb_out];
-            a.ld1 = o.cout - o.n_split;
-        }
+        const ConvArgs a = conv_args(c, o, d, n, uniform, W, geom, out);
         const int tile = (o.tile >= 0 && conv_tile_ok(o.tile, c->et, a)) ? o.tile : conv_default_tile(c->et, a);
         HIP_TRY(launch_conv(a, c->et, tile, s));
+        if (pev) {
+            HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));
+            c->op_flop[oi] = 2.0 * a.M * (double)a.cout * a.K;
+        }
+    }
+    return JDE_OK;
+}
+
+jde_status jde_autotune(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws, size_t wsb,
+                        const jde_head_out* out, int reps, void* stream) {
+    if (reps <= 0) return fail(JDE_EINVAL, "reps must be positive");
+    if (c && c->prof) return fail(JDE_ESTATE, "autotune while profiling");
+    // A plain forward validates the arguments and fills every buffer.
+    if (jde_status st = jde_forward(c, frames, d, n, ws, wsb, out, stream)) return st;
+    bool uniform;
+    (void)batch_ok(c, d, n, &uniform);
+    hipStream_t s = (hipStream_t)stream;
+    char* W = (char*)ws;
+    const int* geom = (const int*)(W + c->ws_geom);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    jde_status st = JDE_OK;
+    for (Op& o : c->ops) {
+        if (o.kind != OP_CONV) continue;
+        const ConvArgs a = conv_args(c, o, d, n, uniform, W, geom, out);
+        float best = 1e30f;
+        int best_t = -1;
+        for (int t = 0; t < conv_num_tile_cfgs() && st == JDE_OK; ++t) {
+            if (!conv_tile_ok(t, c->et, a)) continue;
+            hipError_t e = launch_conv(a, c->et, t, s);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_conv(a, c->et, t, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = fail(JDE_EDEVICE, "autotune launch: %s", hipGetErrorString(e));
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                best_t = t;
+            }
+        }
+        if (st != JDE_OK) break;
+        o.tile = best_t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+jde_status jde_tiles(jde_ctx* c, int* tiles, int n_ops, int set) {
+    if (!c || !tiles) return fail(JDE_EINVAL, "null argument");
+    if (n_ops != (int)c->ops.size()) return fail(JDE_EINVAL, "expected %zu entries", c->ops.size());
+    for (int i = 0; i < n_ops; ++i) {
+        if (set) {
+            if (tiles[i] < -1 || tiles[i] >= conv_num_tile_cfgs())
+                return fail(JDE_EINVAL, "tile %d out of range", tiles[i]);
+            c->ops[i].tile = c->ops[i].kind == OP_CONV ? tiles[i] : -1;
+        } else {
+            tiles[i] = c->ops[i].tile;
+        }
     }
     return JDE_OK;
 }
@@ -655,7 +801,40 @@ jde_status jde_cost_matrix(const float* fe, const double* mean, const double* co
     if (T < 0 || D < 0 || E <= 0 || E % 4) return fail(JDE_EINVAL, "bad sizes T=%d D=%d E=%d", T, D, E);
     if (T > 0 && D > 0 && (!fe || !mean || !cov || !boxes || !de || !cost)) return fail(JDE_EINVAL, "null argument");
     if (!(gate >= 0.0)) return fail(JDE_EINVAL, "gate must be >= 0");
-    HIP_TRY(launch_cost(fe, mean, cov, T, boxes, de, D, E, gate, cost, (hipStream_t)stream));
+    HIP_TRY(launch_cost(fe, mean, cov, T, boxes, de, D, nullptr, D, E, gate, cost, (hipStream_t)stream));
+    return JDE_OK;
+}
+
+jde_status jde_cost_matrix_batch(const float* fe, const double* mean, const double* cov, const int* tb,
+                                 const jde_dets* dets, int n, int E, double gate, float* cost, void* stream) {
+    if (!dets || !tb || n < 0 || n > kMaxFrames || E <= 0 || E % 4 || dets->cap <= 0)
+        return fail(JDE_EINVAL, "bad arguments n=%d E=%d", n, E);
+    CostBatch b{};
+    b.n = n;
+    int max_t = 0;
+    for (int f = 0; f <= n; ++f) {
+        if (tb[f] < 0 || (f > 0 && tb[f] < tb[f - 1])) return fail(JDE_EINVAL, "track_begin must be non-decreasing");
+        b.begin[f] = tb[f];
+        if (f > 0) max_t = std::max(max_t, tb[f] - tb[f - 1]);
+    }
+    if (max_t > 0 && (!fe || !mean || !cov || !cost || !dets->boxes || !dets->emb || !dets->count))
+        return fail(JDE_EINVAL, "null argument");
+    if (!(gate >= 0.0)) return fail(JDE_EINVAL, "gate must be >= 0");
+    HIP_TRY(launch_cost_batch(fe, mean, cov, b, max_t, dets->boxes, dets->emb, dets->count, dets->cap, E, gate, cost,
+                              (hipStream_t)stream));
+    return JDE_OK;
+}
+
+jde_status jde_cost_matrix_dets(const float* fe, const double* mean, const double* cov, int T, const jde_dets* dets,
+                                int frame, int E, double gate, float* cost, void* stream) {
+    if (!dets || T < 0 || frame < 0 || E <= 0 || E % 4 || dets->cap <= 0)
+        return fail(JDE_EINVAL, "bad arguments T=%d frame=%d E=%d", T, frame, E);
+    if (T > 0 && (!fe || !mean || !cov || !cost || !dets->boxes || !dets->emb || !dets->count))
+        return fail(JDE_EINVAL, "null argument");
+    if (!(gate >= 0.0)) return fail(JDE_EINVAL, "gate must be >= 0");
+    const size_t row = (size_t)frame * dets->cap;
+    HIP_TRY(launch_cost(fe, mean, cov, T, dets->boxes + row * 4, dets->emb + row * E, dets->cap,
+                        dets->count + frame, dets->cap, E, gate, cost, (hipStream_t)stream));
     return JDE_OK;
 }
 

@@ -129,7 +129,7 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
 
 // ---------------------------------------------------------------------------
 // MFMA implicit GEMM.
-//   BM pixels x BN channels per workgroup of 4 waves (WGM x WGN), BK = 32.
+//   BM pixels x BN channels per workgroup of 4 waves (WGM x WGN), K chunks of BK.
 //   Each wave owns a (BM/WGM) x (BN/WGN) tile of 16x16 MFMA blocks.
 //   bf16/f16: v_mfma_f32_16x16x32 -- each lane feeds 8 consecutive k of one
 //   row of A (a channel) and of B (a pixel), one 16-byte LDS read each.
@@ -138,9 +138,8 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
 //   the same assignment on both operands, so the contraction is unchanged.
 //   Output: lane l holds channels 4(l/16) .. +3 of pixel l%16 of each block.
 // ---------------------------------------------------------------------------
-template <typename T, int BM, int BN, int WGM, int WGN, bool ALIGNED>
+template <typename T, int BM, int BN, int WGM, int WGN, int BK, bool ALIGNED>
 __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
-    constexpr int BK = 32;
     constexpr int VEC = 16 / sizeof(T);
     constexpr int VR = BK / VEC;
     constexpr int LDR = BK + VEC;  // padded LDS row, in elements
@@ -383,18 +382,35 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
 // ---------------------------------------------------------------------------
 // Tile configurations and dispatch.
 // ---------------------------------------------------------------------------
-struct TileCfg { int bm, bn, wgm, wgn; };
+struct TileCfg { int bm, bn, wgm, wgn, bk; };
 static constexpr TileCfg kTiles[] = {
-    {128, 128, 2, 2},  // 0: 64x64 per wave
-    {256, 64, 4, 1},   // 1: 64x64 per wave (Cout 64)
-    {128, 64, 2, 2},   // 2: 64x32 per wave
-    {64, 128, 2, 2},   // 3: 32x64 per wave
-    {256, 32, 4, 1},   // 4: 64x32 per wave (Cout <= 32)
-    {64, 64, 2, 2},    // 5: 32x32 per wave (also the unaligned-Cin path)
-    {128, 32, 4, 1},   // 6: 32x32 per wave
-    {32, 128, 2, 2},   // 7: 16x64 per wave
+    {128, 128, 2, 2, 32},  // 0: 64x64 per wave
+    {256, 64, 4, 1, 32},   // 1: 64x64 per wave (Cout 64)
+    {128, 64, 2, 2, 32},   // 2: 64x32 per wave
+    {64, 128, 2, 2, 32},   // 3: 32x64 per wave
+    {256, 32, 4, 1, 32},   // 4: 64x32 per wave (Cout <= 32)
+    {64, 64, 2, 2, 32},    // 5: 32x32 per wave (also the unaligned-Cin path)
+    {128, 32, 4, 1, 32},   // 6: 32x32 per wave
+    {32, 128, 2, 2, 32},   // 7: 16x64 per wave
+    {128, 128, 2, 2, 64},  // 8: as 0, K chunks of 64 (16-bit types)
+    {256, 64, 4, 1, 64},   // 9: as 1, K chunks of 64
+    {128, 64, 2, 2, 64},   // 10: as 2, K chunks of 64
+    {64, 128, 2, 2, 64},   // 11: as 3, K chunks of 64
+    {256, 128, 2, 2, 32},  // 12: 128x64 per wave
+    {128, 256, 2, 2, 32},  // 13: 64x128 per wave
+    {256, 128, 2, 2, 64},  // 14: 128x64 per wave, K chunks of 64
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+template <typename T>
+constexpr int lds_bytes(const TileCfg& t) {
+    return 2 * (t.bm + t.bn) * (t.bk + 16 / (int)sizeof(T)) * (int)sizeof(T);
+}
+// 16-bit types may use every tile; FP32 only the K-32 tiles whose LDS fits.
+template <typename T>
+constexpr bool tile_built(int c) {
+    return (sizeof(T) == 2 || kTiles[c].bk == 32) && lds_bytes<T>(kTiles[c]) <= 96 * 1024;
+}
 
 int conv_num_tile_cfgs() { return kNumTiles; }
 void conv_tile_shape(int c, int* bm, int* bn) {
@@ -402,22 +418,28 @@ void conv_tile_shape(int c, int* bm, int* bn) {
     *bn = kTiles[c].bn;
 }
 
-static bool aligned_cin(const ConvArgs& a) {
-    if (a.cin % 32) return false;
-    if (a.cin1 > 0 && (a.cin1 % 32 || a.ksz != 1 || a.stride != 1)) return false;
+static bool aligned_cin(const ConvArgs& a, int bk) {
+    if (a.cin % bk) return false;
+    if (a.cin1 > 0 && (a.cin1 % bk || a.ksz != 1 || a.stride != 1)) return false;
     return true;
+}
+
+static bool built(int c, int et) {
+    if (et == kF32) return tile_built<float>(c);
+    return tile_built<bf16>(c);
 }
 
 bool conv_tile_ok(int c, int et, const ConvArgs& a) {
     if (c < 0 || c >= kNumTiles) return false;
     if (et != kF32 && et != kBF16 && et != kF16) return false;
-    if (!aligned_cin(a)) return c == 5 && a.cin1 == 0 && a.cin % (et == kF32 ? 4 : 8) == 0;
+    if (!built(c, et)) return false;
+    if (!aligned_cin(a, kTiles[c].bk)) return c == 5 && a.cin1 == 0 && a.cin % (et == kF32 ? 4 : 8) == 0;
     return true;
 }
 
 int conv_default_tile(int et, const ConvArgs& a) {
     (void)et;
-    if (!aligned_cin(a)) return 5;
+    if (!aligned_cin(a, 32)) return 5;
     // Prefer the largest tile that still gives at least ~2 workgroups per CU.
     static const int pref_wide[] = {0, 2, 3, 5, 7};
     static const int pref_64[] = {1, 2, 5};
@@ -438,15 +460,19 @@ int conv_default_tile(int et, const ConvArgs& a) {
 
 template <typename T, int C>
 static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
-    constexpr TileCfg t = kTiles[C];
-    dim3 grid((a.M + t.bm - 1) / t.bm, (a.cout + t.bn - 1) / t.bn), block(256);
-    if (aligned)
-        conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, true><<<grid, block, 0, s>>>(a);
-    else if constexpr (C == 5)
-        conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, false><<<grid, block, 0, s>>>(a);
-    else
+    if constexpr (!tile_built<T>(C)) {
         return hipErrorInvalidValue;
-    return hipGetLastError();
+    } else {
+        constexpr TileCfg t = kTiles[C];
+        dim3 grid((a.M + t.bm - 1) / t.bm, (a.cout + t.bn - 1) / t.bn), block(256);
+        if (aligned)
+            conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, true><<<grid, block, 0, s>>>(a);
+        else if constexpr (C == 5)
+            conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, false><<<grid, block, 0, s>>>(a);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
 }
 
 template <typename T>
@@ -460,13 +486,20 @@ static hipError_t launch_type(const ConvArgs& a, int c, bool aligned, hipStream_
         case 5: return launch_t<T, 5>(a, aligned, s);
         case 6: return launch_t<T, 6>(a, aligned, s);
         case 7: return launch_t<T, 7>(a, aligned, s);
+        case 8: return launch_t<T, 8>(a, aligned, s);
+        case 9: return launch_t<T, 9>(a, aligned, s);
+        case 10: return launch_t<T, 10>(a, aligned, s);
+        case 11: return launch_t<T, 11>(a, aligned, s);
+        case 12: return launch_t<T, 12>(a, aligned, s);
+        case 13: return launch_t<T, 13>(a, aligned, s);
+        case 14: return launch_t<T, 14>(a, aligned, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_conv(const ConvArgs& a, int et, int c, hipStream_t s) {
     if (!conv_tile_ok(c, et, a)) return hipErrorInvalidValue;
-    const bool aligned = aligned_cin(a);
+    const bool aligned = aligned_cin(a, kTiles[c].bk);
     if (et == kF32) return launch_type<float>(a, c, aligned, s);
     if (et == kBF16) return launch_type<bf16>(a, c, aligned, s);
     return launch_type<f16>(a, c, aligned, s);

@@ -123,8 +123,12 @@ hipError_t launch_nms_gather(const float* boxes, const unsigned long long* keys,
 hipError_t launch_nms_finish(const int* keep, const int* nkeep, const int* vals, int* out_keep,
                              int* out_nkeep, int K, hipStream_t s);
 hipError_t launch_cost(const float* trk_emb, const double* mean, const double* cov, int T,
-                       const float* det_boxes, const float* det_emb, int D, int E, double gate,
-                       float* cost, hipStream_t s);
+                       const float* det_boxes, const float* det_emb, int D, const int* dcount, int ldc,
+                       int E, double gate, float* cost, hipStream_t s);
+struct CostBatch { int n; int begin[kMaxFrames + 1]; };
+hipError_t launch_cost_batch(const float* trk_emb, const double* mean, const double* cov, const CostBatch& b,
+                             int max_t, const float* det_boxes, const float* det_emb, const int* dcount, int cap,
+                             int E, double gate, float* cost, hipStream_t s);
 hipError_t launch_emb_update(const int* pairs, int P, const float* det_emb, int D, float* trk_emb, int T,
                              int E, float momentum, hipStream_t s);
 

@@ -398,12 +398,33 @@ hipError_t launch_nms_finish(const int* keep, const int* nkeep, const int* vals,
 __global__ __launch_bounds__(256) void cost_kernel(const float* __restrict__ fe, const double* __restrict__ mean,
                                                    const double* __restrict__ cov, int T,
                                                    const float* __restrict__ boxes, const float* __restrict__ de,
-                                                   int D, int E, double gate, float* __restrict__ cost) {
+                                                   int D, const int* __restrict__ dcount, int ldc, int E,
+                                                   double gate, float* __restrict__ cost,
+                                                   CostBatch batch) {
     __shared__ float sf[32][65], se[32][65];
     __shared__ double sL[32][10], sHx[32][4], sZ[32][4];
     __shared__ int sPD[32];
     const int tid = threadIdx.x;
     const int t0 = blockIdx.y * 32, d0 = blockIdx.x * 32;
+    if (batch.n) {
+        // frame blockIdx.z: tracks [tb[z], tb[z+1]), detections at rows z*ldc of the dets, cost rows from tb[z]
+        const int z = blockIdx.z;
+        const int tb = batch.begin[z];
+        T = batch.begin[z + 1] - tb;
+        fe += (size_t)tb * E;
+        mean += (size_t)tb * 8;
+        cov += (size_t)tb * 64;
+        cost += (size_t)tb * ldc;
+        boxes += (size_t)z * ldc * 4;
+        de += (size_t)z * ldc * E;
+        dcount += z;
+        if (t0 >= T) return;
+    }
+    if (dcount) {
+        const int dn = *dcount;
+        D = dn < D ? dn : D;
+    }
+    if (d0 >= D) return;
     if (tid < 32) {
         const int t = t0 + tid;
         if (t < T) {
@@ -487,15 +508,26 @@ __global__ __launch_bounds__(256) void cost_kernel(const float* __restrict__ fe,
             const double d2 = u0 * u0 + u1 * u1 + u2 * u2 + u3 * u3;
             float c = fminf(fmaxf(1.0f - acc[i][j], 0.f), 2.f);
             if (!sPD[tl] || !(d2 <= gate)) c = __builtin_inff();
-            cost[(size_t)t * D + d] = c;
+            cost[(size_t)t * ldc + d] = c;
         }
 }
 
 hipError_t launch_cost(const float* trk_emb, const double* mean, const double* cov, int T, const float* det_boxes,
-                         const float* det_emb, int D, int E, double gate, float* cost, hipStream_t s) {
+                       const float* det_emb, int D, const int* dcount, int ldc, int E, double gate, float* cost,
+                       hipStream_t s) {
     if (T == 0 || D == 0) return hipSuccess;
     dim3 grid((D + 31) / 32, (T + 31) / 32);
-    cost_kernel<<<grid, 256, 0, s>>>(trk_emb, mean, cov, T, det_boxes, det_emb, D, E, gate, cost);
+    CostBatch none{};
+    cost_kernel<<<grid, 256, 0, s>>>(trk_emb, mean, cov, T, det_boxes, det_emb, D, dcount, ldc, E, gate, cost, none);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_batch(const float* trk_emb, const double* mean, const double* cov, const CostBatch& b,
+                             int max_t, const float* det_boxes, const float* det_emb, const int* dcount, int cap,
+                             int E, double gate, float* cost, hipStream_t s) {
+    if (b.n == 0 || max_t == 0) return hipSuccess;
+    dim3 grid((cap + 31) / 32, (max_t + 31) / 32, b.n);
+    cost_kernel<<<grid, 256, 0, s>>>(trk_emb, mean, cov, 0, det_boxes, det_emb, cap, dcount, cap, E, gate, cost, b);
     return hipGetLastError();
 }
 

@@ -210,13 +210,17 @@ class JDE:
                 "anchor_idx": torch.empty(n * self.cap, **i32), "count": torch.empty(n, **i32),
                 "n_cand": torch.empty(n, **i32), "overflow": torch.empty(n, **i32)}
 
-    def decode(self, heads, descs, conf_thr=0.5, nms_iou=0.4, dets=None, stream=None):
-        if dets is None:
-            dets = self.dets_buffers(len(descs))
+    def _dets_struct(self, dets):
         ds = JdeDets()
         for k in ("boxes", "scores", "margins", "emb", "anchor_idx", "count", "n_cand", "overflow"):
             setattr(ds, k, dets[k].data_ptr())
         ds.cap = self.cap
+        return ds
+
+    def decode(self, heads, descs, conf_thr=0.5, nms_iou=0.4, dets=None, stream=None):
+        if dets is None:
+            dets = self.dets_buffers(len(descs))
+        ds = self._dets_struct(dets)
         hs = self._head_struct(heads)
         check(self.lib.jde_decode(self.ctx, ctypes.byref(hs), _descs(descs), len(descs), float(conf_thr),
                                   float(nms_iou), _ptr(self.ws), self.ws.numel(), ctypes.byref(ds),
@@ -231,3 +235,74 @@ class JDE:
         check(self.lib.jde_nms(self.ctx, _ptr(boxes), _ptr(margins), _ptr(idx), K, float(nms_iou), _ptr(self.ws),
                                self.ws.numel(), _ptr(keep), _ptr(nkeep), _stream(stream)), "jde_nms")
         return keep, nkeep
+
+    def cost_dets(self, trk_emb, mean, cov, dets, frame, gate=9.4877, cost=None, stream=None):
+        """Cost of tracks against frame `frame` of a decode result; [T, cap] FP32 (columns
+        >= count[frame] untouched)."""
+        torch = _torch()
+        T = int(trk_emb.shape[0])
+        if cost is None:
+            cost = torch.empty((T, self.cap), dtype=torch.float32, device=self.device)
+        ds = self._dets_struct(dets)
+        check(self.lib.jde_cost_matrix_dets(_ptr(trk_emb), _ptr(mean), _ptr(cov), T, ctypes.byref(ds), int(frame),
+                                            self.E, float(gate), _ptr(cost), _stream(stream)),
+              "jde_cost_matrix_dets")
+        return cost
+
+    def cost_batch(self, trk_emb, mean, cov, track_begin, dets, gate=9.4877, cost=None, stream=None):
+        """Cost of every frame of a decode result against its own track range
+        [track_begin[f], track_begin[f+1]); [track_begin[-1], cap] FP32."""
+        torch = _torch()
+        tb = np.ascontiguousarray(track_begin, dtype=np.int32)
+        n = tb.size - 1
+        if cost is None:
+            cost = torch.empty((int(tb[-1]), self.cap), dtype=torch.float32, device=self.device)
+        ds = self._dets_struct(dets)
+        check(self.lib.jde_cost_matrix_batch(_ptr(trk_emb), _ptr(mean), _ptr(cov), tb.ctypes.data_as(_lib.c_int_p),
+                                             ctypes.byref(ds), n, self.E, float(gate), _ptr(cost), _stream(stream)),
+              "jde_cost_matrix_batch")
+        return cost
+
+    def autotune(self, frames, descs=None, heads=None, reps=3, stream=None):
+        """Pick each convolution's tile by timing on this batch; returns the choices."""
+        if descs is None:
+            n, _, H, W = frames.shape
+            descs = [(H, W)] * n
+        if heads is None:
+            heads = self.head_buffers(descs)
+        hs = self._head_struct(heads)
+        check(self.lib.jde_autotune(self.ctx, _ptr(frames), _descs(descs), len(descs), _ptr(self.ws),
+                                    self.ws.numel(), ctypes.byref(hs), int(reps), _stream(stream)), "jde_autotune")
+        return self.tiles()
+
+    def _n_ops(self):
+        n = ctypes.c_int()
+        check(self.lib.jde_profile_collect(self.ctx, 0, None, None, None, ctypes.byref(n), None),
+              "jde_profile_collect")
+        return n.value
+
+    def tiles(self):
+        t = np.zeros(self._n_ops(), dtype=np.int32)
+        check(self.lib.jde_tiles(self.ctx, t.ctypes.data_as(_lib.c_int_p), t.size, 0), "jde_tiles")
+        return t
+
+    def set_tiles(self, tiles):
+        t = np.ascontiguousarray(tiles, dtype=np.int32)
+        check(self.lib.jde_tiles(self.ctx, t.ctypes.data_as(_lib.c_int_p), t.size, 1), "jde_tiles")
+
+    def profile_begin(self, on=True):
+        check(self.lib.jde_profile_begin(self.ctx, 1 if on else 0), "jde_profile_begin")
+
+    def profile_collect(self):
+        """(op_ms summed over profiled forwards, op_flop per launch, op_kind, n_forwards)."""
+        n = self.num_layers() + 8
+        ms = np.zeros(n)
+        fl = np.zeros(n)
+        kind = np.zeros(n, dtype=np.int32)
+        nops = ctypes.c_int()
+        nfwd = ctypes.c_int()
+        check(self.lib.jde_profile_collect(self.ctx, n, ms.ctypes.data_as(_lib.c_double_p),
+                                           fl.ctypes.data_as(_lib.c_double_p), kind.ctypes.data_as(_lib.c_int_p),
+                                           ctypes.byref(nops), ctypes.byref(nfwd)), "jde_profile_collect")
+        k = nops.value
+        return ms[:k], fl[:k], kind[:k], nfwd.value

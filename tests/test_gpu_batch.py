@@ -1,0 +1,125 @@
+"""GPU tests of batching, tile selection and the batched cost (through the C ABI)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from jde_inputs import TINY, FULL, synthetic_dets_tracks
+from oracle import track as otrack
+from tests.helpers import rel_err, weights, frames, oracle_forward, head_views, gpu_dets, anchors
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a visible MI355X"
+    return t
+
+
+def _model(cfg, precision, max_frames, cap=512, max_h=None, max_w=None):
+    from paper_2011_03910_amd import JDE
+    return JDE(cfg.c0, cfg.blocks, cfg.emb_dim, anchors(cfg.name), precision, max_frames,
+               max_h or cfg.height, max_w or cfg.width, cap)
+
+
+def test_tiny_batch_matches_single_frames_and_oracle(torch):
+    """Four different frames in one batch: each frame's outputs equal the oracle
+    (FP32, 1e-4) and the frame run alone."""
+    _say("case: tiny fp32 batch 4 vs single")
+    n = 4
+    m = _model(TINY, "fp32", n)
+    m.load_weights(weights("tiny", 50))
+    fr = frames("tiny", n)
+    x = torch.from_numpy(fr).cuda()
+    heads = m.forward(x)
+    torch.cuda.synchronize()
+    v = head_views(heads, [(192, 320)] * n)
+    ref = oracle_forward("tiny", 50, n)
+    for f in range(n):
+        for key in ("det", "emb"):
+            for s in range(3):
+                e = rel_err(v[key][s][f], ref[key][s][f])
+                assert e <= 1e-4, (f, key, s, e)
+    single = head_views(m.forward(x[2:3].contiguous()), [(192, 320)])
+    torch.cuda.synchronize()
+    for key in ("det", "emb"):
+        for s in range(3):
+            assert rel_err(single[key][s][0], v[key][s][2]) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_autotuned_tiles_match_default_tiles(torch, precision):
+    _say(f"case: tiny {precision} autotune vs default")
+    m = _model(TINY, precision, 2)
+    m.load_weights(weights("tiny", 50))
+    x = torch.from_numpy(frames("tiny", 2)).cuda()
+    ref = head_views(m.forward(x), [(192, 320)] * 2)
+    tiles = m.autotune(x, reps=1)
+    _say(f"  tiles {tiles.tolist()}")
+    got = head_views(m.forward(x), [(192, 320)] * 2)
+    torch.cuda.synchronize()
+    tol = 1e-5 if precision == "fp32" else 3e-2
+    for key in ("det", "emb"):
+        for s in range(3):
+            for f in range(2):
+                assert rel_err(got[key][s][f], ref[key][s][f]) <= tol
+    # every legal tile of one launch gives the same result
+    n_ops = len(tiles)
+    for t in range(15):
+        forced = np.full(n_ops, -1, dtype=np.int32)
+        forced[:] = t
+        try:
+            m.set_tiles(forced)
+        except Exception:
+            continue
+        out = head_views(m.forward(x), [(192, 320)] * 2)
+        torch.cuda.synchronize()
+        e = max(rel_err(out[k][s][f], ref[k][s][f]) for k in ("det", "emb") for s in range(3) for f in range(2))
+        _say(f"  forced tile {t}: rel err vs default {e:.2e}")
+        assert e <= tol, (t, e)
+
+
+def test_cost_batch_and_dets_vs_oracle(torch):
+    """Batched and device-count cost on real decode output equal the oracle's
+    cost of the same detections."""
+    _say("case: cost batch on tiny decode")
+    n = 3
+    m = _model(TINY, "fp32", n, cap=512)
+    m.load_weights(weights("tiny", 50))
+    x = torch.from_numpy(frames("tiny", n)).cuda()
+    descs = [(192, 320)] * n
+    dets = m.decode(m.forward(x), descs)
+    T = [5, 0, 37]
+    tb = np.concatenate([[0], np.cumsum(T)]).astype(np.int32)
+    trk = [synthetic_dets_tracks(11 + f, max(T[f], 1), 8, TINY.emb_dim, 192, 320) for f in range(n)]
+    cat = lambda k: np.concatenate([t[k][:T[f]] for f, t in enumerate(trk)])
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    fe, mean, cov = cu(cat("trk_emb")), cu(cat("mean")), cu(cat("cov"))
+    cost = torch.full((int(tb[-1]), m.cap), -7.0, device="cuda")
+    m.cost_batch(fe, mean, cov, tb, dets, cost=cost)
+    torch.cuda.synchronize()
+    cost = cost.cpu().numpy()
+    for f in range(n):
+        d = gpu_dets(dets, f, m.cap)
+        D = len(d["boxes"])
+        assert D > 0
+        ref = otrack.cost_matrix(cat("trk_emb")[tb[f]:tb[f + 1]], cat("mean")[tb[f]:tb[f + 1]],
+                                 cat("cov")[tb[f]:tb[f + 1]], d["boxes"], d["emb"])
+        got = cost[tb[f]:tb[f + 1], :D]
+        np.testing.assert_array_equal(np.isinf(got), np.isinf(ref))
+        fin = np.isfinite(ref)
+        assert np.abs(got[fin] - ref[fin]).max(initial=0) <= 2e-6
+        assert np.all(cost[tb[f]:tb[f + 1], D:] == -7.0)
+        if T[f]:
+            one = m.cost_dets(cu(trk[f]["trk_emb"][:T[f]]), cu(trk[f]["mean"][:T[f]]), cu(trk[f]["cov"][:T[f]]),
+                              dets, f)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(one.cpu().numpy()[:, :D], got)
