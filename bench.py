@@ -102,6 +102,20 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
+def serve_bench(layers, precision, seconds, tiles, torch):
+    """16 synthetic streams at 30 FPS (mixed resolutions, 20-200 objects) through the
+    continuous-batching server; per-frame latency = arrival -> tracks updated."""
+    from jde_inputs import FULL, anchors_px
+    from paper_2011_03910_amd.serve import Server, synthetic_streams
+    streams = synthetic_streams(16, FULL.seed, frames_per_stream=2)
+    srv = Server(FULL, anchors_px(FULL), layers, streams, precision=precision, max_batch=16, tiles=tiles)
+    stats = srv.run(seconds + 0.5, warmup=0.5)
+    res = sorted({(s.height, s.width) for s in streams})
+    stats.update({"streams": 16, "offered_fps": 16 * 30, "resolutions": [f"{w}x{h}" for h, w in res],
+                  "hbm_budget_gb": round(srv.hbm_budget / 1e9, 2)})
+    return stats
+
+
 def cpu_baseline(layers):
     """The FP64 oracle on a bounded sample: one full-resolution frame through
     forward, decode, NMS, normalisation and the cost against 40 tracks."""
@@ -138,6 +152,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 batch-1 plain form")
     ap.add_argument("--no-tune", action="store_true", help="built-in tile choice instead of the autotuner")
+    ap.add_argument("--serve-seconds", type=float, default=4.0, help="serving run length (0: skip)")
     ap.add_argument("--save-tiles", help="write the tile choices to this JSON file")
     ap.add_argument("--load-tiles", help="use tile choices from this JSON file instead of tuning")
     args = ap.parse_args()
@@ -195,6 +210,11 @@ def main():
 
     if args.save_tiles:
         json.dump(tiles_out, open(args.save_tiles, "w"))
+    serving = None
+    if args.serve_seconds > 0:
+        serving = serve_bench(layers, args.precision, args.serve_seconds, tiles_out.get(key), torch)
+        log(f"serving: {serving}")
+        torch.cuda.empty_cache()
     cpu = None if args.no_cpu else cpu_baseline(layers)
     if cpu:
         log(f"cpu oracle: {cpu['value']:.4f} frames/s on {cpu['cores']} threads")
@@ -215,6 +235,8 @@ def main():
                      "frac": round(achieved / peak, 4), "traffic": None,
                      "kernel": f"conv_igemm ({n_launch} launches/step, {conv_flop / 1e9:.1f} GFLOP/step, "
                                f"mean {conv_ms / n_launch * 1e3:.1f} us/launch)"},
+        "serving": None if serving is None else {k: (round(v, 3) if isinstance(v, float) else v)
+                                                  for k, v in serving.items()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -211,6 +211,24 @@ jde_status jde_cost_matrix_batch(const float* d_track_emb, const double* d_mean,
 jde_status jde_track_emb_update(const int* d_pairs, int P, const float* d_det_emb, int D,
                                 float* d_track_emb, int T, int E, float momentum, void* stream);
 
+/* ---- HIP graph of one step (batch-wise inference replayed as one launch) ---- */
+
+typedef struct jde_graph jde_graph;
+/* Captures, on `stream` (a non-default stream), one jde_forward + jde_decode
+ * and, when track_begin is not NULL, one jde_cost_matrix_batch for a fixed
+ * batch shape into a HIP graph.  All pointers are captured: between replays the
+ * caller may change the contents of d_frames and of the track arrays, not the
+ * buffers themselves.  Nothing runs during capture.  The graph uses no memset
+ * nodes.  Fails with JDE_ESTATE while per-launch profiling is on. */
+jde_status jde_graph_capture(jde_ctx* ctx, const float* d_frames, const jde_frame_desc* descs, int n,
+                             void* d_ws, size_t ws_bytes, const jde_head_out* heads, float conf_thr,
+                             float nms_iou, const jde_dets* dets, const float* d_track_emb,
+                             const double* d_mean, const double* d_cov, const int* track_begin,
+                             float* d_cost, void* stream, jde_graph** out);
+/* Replays the captured step on `stream`. */
+jde_status jde_graph_launch(jde_graph* g, void* stream);
+void jde_graph_destroy(jde_graph* g);
+
 /* ---- per-launch timing of the forward (Sec. 5.1 profiles where time goes) -- */
 
 /* on = 1: every later jde_forward records a HIP event pair around each of its

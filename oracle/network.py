@@ -85,6 +85,36 @@ def round_fp16(x):
     return np.asarray(x, dtype=np.float32).astype(np.float16).astype(np.float64)
 
 
+FP8_MAX = 448.0
+
+
+def round_fp8(x):
+    """Round to the nearest OCP FP8 e4m3 value (ties to even), saturating at +-448.
+
+    e4m3: 3 mantissa bits; normal binades 2^-6 .. 2^8 have spacing 2^(e-3);
+    below 2^-6 the subnormal spacing is 2^-9.  Returned as FP64.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    a = np.minimum(np.abs(x), FP8_MAX)
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    e = np.maximum(e, -6.0)
+    q = np.exp2(e - 3.0)
+    r = np.round(a / q) * q            # numpy rounds halves to even
+    r = np.minimum(r, FP8_MAX)
+    return np.where(np.isnan(x), np.nan, np.sign(x) * r)
+
+
+def quantize_fp8_per_channel(w):
+    """Per-output-channel symmetric FP8 quantisation of w [Cout, ...]:
+    s_c = max|w_c| / 448 (1 for an all-zero channel), w ~= s_c * round_fp8(w / s_c).
+    Returns (dequantised weights, scales)."""
+    w = np.asarray(w, dtype=np.float64)
+    amax = np.abs(w.reshape(w.shape[0], -1)).max(axis=1)
+    s = np.where(amax > 0, amax / FP8_MAX, 1.0)
+    sb = s.reshape((-1,) + (1,) * (w.ndim - 1))
+    return round_fp8(w / sb) * sb, s
+
+
 class _Walker:
     """Consumes the weight list in blob order (see jde_inputs.weights)."""
 

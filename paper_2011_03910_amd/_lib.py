@@ -74,6 +74,13 @@ SIGNATURES = {
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(JdeHeadOut), ctypes.c_int,
                                     ctypes.c_void_p]),
     "jde_tiles": (ctypes.c_int, [ctypes.c_void_p, c_int_p, ctypes.c_int, ctypes.c_int]),
+    "jde_graph_capture": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(JdeFrameDesc),
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(JdeHeadOut),
+                                         ctypes.c_float, ctypes.c_float, ctypes.POINTER(JdeDets), ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, c_int_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "jde_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "jde_graph_destroy": (None, [ctypes.c_void_p]),
     "jde_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p, c_int_p, c_int_p,
                                            c_int_p]),

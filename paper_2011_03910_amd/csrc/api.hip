@@ -360,6 +360,11 @@ ConvArgs conv_args(const jde_ctx* c, const Op& o, const jde_frame_desc* d, int n
     a.n_split = o.n_split;
     a.act = o.act;
     a.in_scale = 1.f;
+    a.in_bytes = o.in_t >= 0 ? (int)c->tens[o.in_t].bytes : 0;
+    a.in2_bytes = o.in2_t >= 0 ? (int)c->tens[o.in2_t].bytes : 0;
+    a.w_bytes = (int)((size_t)o.cout * a.K * elem_bytes(c->et));
+    // weights dominate when Cout*K exceeds the activation rows read (M * Cin)
+    a.n_major = (double)o.cout * a.K > (double)a.M * o.cin ? 1 : 0;
     if (o.det_out >= 0) {
         a.out0 = out->det[o.det_out];
         a.ld0 = o.cout;
@@ -451,8 +456,17 @@ jde_status jde_create(const jde_config* cfg, jde_ctx** out) {
     if (g.max_frames <= 0 || g.max_frames > kMaxFrames) return fail(JDE_EINVAL, "max_frames must be 1..%d", kMaxFrames);
     if (g.max_h <= 0 || g.max_w <= 0 || g.max_h % 32 || g.max_w % 32)
         return fail(JDE_EINVAL, "max_h, max_w must be positive multiples of 32");
-    if ((size_t)g.max_frames * g.max_h * g.max_w > ((size_t)1 << 31) / 4)
-        return fail(JDE_EINVAL, "capacity too large for 32-bit pixel indexing");
+    // Kernels index activations with 32-bit element offsets; the stem output
+    // (max pixels x c0) is the largest tensor, the upsample/halo rows need 16-bit y, x.
+    // (max pixels x c0) is the largest tensor, its bytes must stay below 2^31 (buffer
+    // loads use 32-bit byte offsets with 2^31 as the out-of-range marker); the
+    // upsample/halo rows need 16-bit y, x.
+    {
+        const size_t eb = g.precision == JDE_FP32 ? 4 : 2;
+        if ((size_t)g.max_frames * g.max_h * g.max_w * g.base_ch * eb >= ((size_t)1 << 31) - 4096 ||
+            g.max_h >= 32768 || g.max_w >= 32768)
+            return fail(JDE_EINVAL, "capacity too large: the largest activation must stay below 2 GiB");
+    }
     if (g.max_candidates < 64 || g.max_candidates > kMaxCap || g.max_candidates % 64)
         return fail(JDE_EINVAL, "max_candidates must be a multiple of 64 in [64, %d]", kMaxCap);
     jde_ctx* c = new jde_ctx();
@@ -844,6 +858,56 @@ jde_status jde_track_emb_update(const int* pairs, int P, const float* de, int D,
     if (P > 0 && (!pairs || !de || !fe)) return fail(JDE_EINVAL, "null argument");
     HIP_TRY(launch_emb_update(pairs, P, de, D, fe, T, E, mom, (hipStream_t)stream));
     return JDE_OK;
+}
+
+struct jde_graph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+};
+
+jde_status jde_graph_capture(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws, size_t wsb,
+                             const jde_head_out* heads, float conf, float iou, const jde_dets* dets,
+                             const float* fe, const double* mean, const double* cov, const int* tb, float* cost,
+                             void* stream, jde_graph** out) {
+    if (!c || !out) return fail(JDE_EINVAL, "null argument");
+    *out = nullptr;
+    if (c->prof) return fail(JDE_ESTATE, "graph capture while profiling");
+    if (!stream) return fail(JDE_EINVAL, "capture needs a non-default stream");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    jde_status st = jde_forward(c, frames, d, n, ws, wsb, heads, stream);
+    if (st == JDE_OK) st = jde_decode(c, heads, d, n, conf, iou, ws, wsb, dets, stream);
+    if (st == JDE_OK && tb) st = jde_cost_matrix_batch(fe, mean, cov, tb, dets, n, c->cfg.emb_dim, 9.4877, cost, stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(s, &g);
+    if (st != JDE_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (ee != hipSuccess) return fail(JDE_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    jde_graph* G = new jde_graph();
+    G->g = g;
+    const hipError_t ie = hipGraphInstantiate(&G->e, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete G;
+        return fail(JDE_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    }
+    *out = G;
+    return JDE_OK;
+}
+
+jde_status jde_graph_launch(jde_graph* g, void* stream) {
+    if (!g || !g->e) return fail(JDE_EINVAL, "null graph");
+    HIP_TRY(hipGraphLaunch(g->e, (hipStream_t)stream));
+    return JDE_OK;
+}
+
+void jde_graph_destroy(jde_graph* g) {
+    if (!g) return;
+    if (g->e) (void)hipGraphExecDestroy(g->e);
+    if (g->g) (void)hipGraphDestroy(g->g);
+    delete g;
 }
 
 }  // extern "C"

@@ -16,6 +16,8 @@
 //   first conv of the stride-16 and stride-8 heads reads channels [0, cin1)
 //   from the half-resolution lateral map at (y/2, x/2) and the rest from the
 //   skip map at (y, x), so the concatenated tensor is never materialised.
+#include <type_traits>
+
 #include "jde_internal.h"
 
 namespace jde {
@@ -28,6 +30,12 @@ template <> struct V16<bf16> { typedef bf16x8 type; };
 template <> struct V16<f16> { typedef f16x8 type; };
 
 template <typename T> __device__ __forceinline__ T cvt_out(float x) { return (T)x; }
+
+// Word 3 of a raw buffer resource on gfx9-class GPUs (32-bit dword format);
+// kOOB is a byte offset past every buffer (all are < 2^31 bytes).
+constexpr int kBufFlags = 0x00020000;
+constexpr int kXCDs = 8;     // accelerator complex dies of an MI355X, each with its own L2
+constexpr int kOOB = 0x80000000;
 
 // Row m of a level-`lvl` packed tensor -> (frame, y, x).
 __device__ __forceinline__ void map_pixel(const int* __restrict__ geom, int nframes, int uniform, int lvl,
@@ -147,6 +155,7 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
     constexpr int TM = WTM / 16, TN = WTN / 16;
     constexpr int BVEC = BM * VR, AVEC = BN * VR;
     constexpr int BPT = (BVEC + 255) / 256, APT = (AVEC + 255) / 256;
+    constexpr int SZ = sizeof(T);
     static_assert(WGM * WGN == 4, "4 waves");
     static_assert(TM >= 1 && TN >= 1, "wave tile");
     typedef typename V16<T>::type V;
@@ -157,116 +166,146 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-    const T* __restrict__ in = (const T*)a.in;
-    const T* __restrict__ in2 = (const T*)a.in2;
-    const T* __restrict__ wt = (const T*)a.w;
+    // XCD-aware tile order: workgroup L runs on XCD L % 8.  Give every XCD a
+    // contiguous range of logical tiles (a bijection on [0, tiles)), ordered so
+    // that the tiles of one XCD share the larger operand in its L2: all channel
+    // tiles of a pixel range (activations dominate) or all pixel tiles of a
+    // channel range (weights dominate).
+    int m0, n0;
+    {
+        const int gm = (a.M + BM - 1) / BM, gn = (a.cout + BN - 1) / BN;
+        const int W = gm * gn, L = blockIdx.x;
+        const int xcd = L % kXCDs, local = L / kXCDs;
+        const int base = W / kXCDs, extra = W % kXCDs;
+        const int P = xcd < extra ? xcd * (base + 1) + local : extra * (base + 1) + (xcd - extra) * base + local;
+        if (a.n_major) {
+            m0 = (P % gm) * BM;
+            n0 = (P / gm) * BN;
+        } else {
+            n0 = (P % gn) * BN;
+            m0 = (P / gn) * BM;
+        }
+    }
     const bool concat = a.cin1 > 0;
+    // Buffer resources: a load whose byte offset is out of range returns zeros,
+    // which is how the zero halo, rows past M and channels past Cout are read.
+    const __amdgpu_buffer_rsrc_t r_in = __builtin_amdgcn_make_buffer_rsrc((void*)a.in, 0, a.in_bytes, kBufFlags);
+    const __amdgpu_buffer_rsrc_t r_in2 =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(concat ? a.in2 : a.in), 0, concat ? a.in2_bytes : a.in_bytes,
+                                          kBufFlags);
+    const __amdgpu_buffer_rsrc_t r_w = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, a.w_bytes, kBufFlags);
 
     // ---- pixel-side rows owned by this thread (fixed over the K loop) ----
-    long b_base[BPT], b_base2[BPT];
-    int b_iy0[BPT], b_ix0[BPT], b_h[BPT], b_w[BPT], b_lds[BPT];
-    bool b_ok[BPT];
+    // Three 32-bit registers per row (every element offset of a tensor is < 2^31):
+    //   b_off: offset of the row's window origin, frame base + (iy0 w + ix0) Cin + its
+    //          16-byte slot (concat: offset in the upsampled source);
+    //   b_yx:  iy0 << 16 | (ix0 & 0xffff), the window origin (concat: skip-source offset);
+    //   b_hw:  h << 16 | w of the input level, 0 for a row outside the batch.
+    int b_off[BPT], b_yx[BPT], b_hw[BPT];
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
         const int v = tid + i * 256;
         const int row = v / VR, kv = v % VR;
-        b_lds[i] = row * LDR + kv * VEC;
         const int m = m0 + row;
-        b_ok[i] = (v < BVEC) && (m < a.M);
-        b_base[i] = 0;
-        b_base2[i] = 0;
-        b_iy0[i] = -0x40000000;
-        b_ix0[i] = -0x40000000;
-        b_h[i] = 0;
-        b_w[i] = 0;
-        if (b_ok[i]) {
+        b_off[i] = 0;
+        b_yx[i] = 0;
+        b_hw[i] = 0;
+        if (v < BVEC && m < a.M) {
             int f, y, x;
             map_pixel(a.geom, a.nframes, a.uniform, a.lvl_out, m, f, y, x);
             const int* g = a.geom + f * kGeomInts;
             if (concat) {
                 const int l1 = a.lvl_out + 1;
-                b_base[i] = ((long)g[2 + l1] + (long)(y >> 1) * (g[1] >> l1) + (x >> 1)) * a.cin1 + kv * VEC;
-                b_base2[i] = ((long)g[2 + a.lvl_out] + (long)y * (g[1] >> a.lvl_out) + x) * (a.cin - a.cin1) +
-                             kv * VEC;
+                b_off[i] = (g[2 + l1] + (y >> 1) * (g[1] >> l1) + (x >> 1)) * a.cin1 + kv * VEC;
+                b_yx[i] = (g[2 + a.lvl_out] + y * (g[1] >> a.lvl_out) + x) * (a.cin - a.cin1) + kv * VEC;
+                b_hw[i] = 1;
             } else {
-                b_base[i] = (long)g[2 + a.lvl_in] * a.cin;
-                b_iy0[i] = y * a.stride - a.pad;
-                b_ix0[i] = x * a.stride - a.pad;
-                b_h[i] = g[0] >> a.lvl_in;
-                b_w[i] = g[1] >> a.lvl_in;
+                const int iy0 = y * a.stride - a.pad, ix0 = x * a.stride - a.pad;
+                const int h = g[0] >> a.lvl_in, w = g[1] >> a.lvl_in;
+                b_off[i] = (g[2 + a.lvl_in] + iy0 * w + ix0) * a.cin + kv * VEC;
+                b_yx[i] = (iy0 << 16) | (ix0 & 0xffff);
+                b_hw[i] = (h << 16) | w;
             }
         }
     }
-    int a_lds[APT];
-    long a_off[APT];
-    bool a_ok[APT];
+    int a_off[APT];
 #pragma unroll
     for (int i = 0; i < APT; ++i) {
         const int v = tid + i * 256;
         const int row = v / VR, kv = v % VR;
-        a_lds[i] = row * LDR + kv * VEC;
-        a_ok[i] = (v < AVEC) && (n0 + row < a.cout);
-        a_off[i] = (long)(n0 + row) * a.K + kv * VEC;
+        a_off[i] = (v < AVEC && n0 + row < a.cout) ? (n0 + row) * a.K + kv * VEC : -1;
     }
+    auto kslot = [&](int i) { return ((tid + i * 256) % VR) * VEC; };
 
-    // incremental (tap, ci) position of the chunk being loaded (ALIGNED: cin % BK == 0)
+    // Position (tap r, s and channel ci) of the next chunk to load; advanced
+    // without branches.  Past the last chunk it keeps moving: those loads are
+    // never consumed, and out-of-range offsets only read zeros.
     int ld_ci = 0, ld_r = 0, ld_s = 0;
-    V ra[APT], rb[BPT];
+    // Two register sets: chunk c is loaded into set c & 1 three iterations before
+    // it is computed and stored to LDS one iteration before, so every global load
+    // has two iterations of MFMA work to arrive in.
+    V ra2[2][APT], rb2[2][BPT];
 
-    auto load_chunk = [&](int kc) {
+    auto load_chunk = [&](int kc, V (&ra)[APT], V (&rb)[BPT]) {
         const int k0 = kc * BK;
 #pragma unroll
         for (int i = 0; i < APT; ++i) {
-            V z = {};
-            ra[i] = (a_ok[i] && k0 + (int)((a_lds[i] % LDR)) < a.K) ? *(const V*)(wt + a_off[i] + k0) : z;
+            const bool ok = a_off[i] >= 0 && (ALIGNED || k0 + kslot(i) < a.K);
+            const int off = ok ? (a_off[i] + k0) * SZ : kOOB;
+            ra[i] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r_w, off, 0, 0));
         }
         if constexpr (ALIGNED) {
+            if (concat) {
+                const bool first = k0 < a.cin1;
 #pragma unroll
-            for (int i = 0; i < BPT; ++i) {
-                V z = {};
-                rb[i] = z;
-                if (!b_ok[i]) continue;
-                if (concat) {
-                    rb[i] = (k0 < a.cin1) ? *(const V*)(in + b_base[i] + k0)
-                                          : *(const V*)(in2 + b_base2[i] + (k0 - a.cin1));
-                } else {
-                    const int iy = b_iy0[i] + ld_r, ix = b_ix0[i] + ld_s;
-                    if ((unsigned)iy < (unsigned)b_h[i] && (unsigned)ix < (unsigned)b_w[i])
-                        rb[i] = *(const V*)(in + b_base[i] + ((long)iy * b_w[i] + ix) * a.cin + ld_ci +
-                                            (b_lds[i] % LDR));
+                for (int i = 0; i < BPT; ++i) {
+                    const int off = b_hw[i] == 0 ? kOOB : (first ? b_off[i] + k0 : b_yx[i] + (k0 - a.cin1)) * SZ;
+                    rb[i] = __builtin_bit_cast(
+                        V, __builtin_amdgcn_raw_buffer_load_b128(first ? r_in : r_in2, off, 0, 0));
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < BPT; ++i) {
+                    const int iy = (b_yx[i] >> 16) + ld_r, ix = (int)(short)(b_yx[i] & 0xffff) + ld_s;
+                    const int h = b_hw[i] >> 16, w = b_hw[i] & 0xffff;
+                    const bool ok = (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)w;
+                    const int off = ok ? (b_off[i] + (ld_r * w + ld_s) * a.cin + ld_ci) * SZ : kOOB;
+                    rb[i] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r_in, off, 0, 0));
                 }
             }
             ld_ci += BK;
-            if (ld_ci >= a.cin) {
-                ld_ci = 0;
-                if (++ld_s == a.ksz) {
-                    ld_s = 0;
-                    ++ld_r;
-                }
-            }
+            const int wrap = ld_ci >= a.cin;
+            ld_ci = wrap ? 0 : ld_ci;
+            ld_s += wrap;
+            const int wrap2 = ld_s >= a.ksz;
+            ld_s = wrap2 ? 0 : ld_s;
+            ld_r += wrap2;
         } else {
 #pragma unroll
             for (int i = 0; i < BPT; ++i) {
-                V z = {};
-                rb[i] = z;
-                const int k = k0 + (b_lds[i] % LDR);
-                if (!b_ok[i] || k >= a.K) continue;
+                const int kv = kslot(i);
+                const int k = k0 + kv;
                 const int tap = k / a.cin, ci = k - tap * a.cin;
                 const int r = tap / a.ksz, s = tap - r * a.ksz;
-                const int iy = b_iy0[i] + r, ix = b_ix0[i] + s;
-                if ((unsigned)iy < (unsigned)b_h[i] && (unsigned)ix < (unsigned)b_w[i])
-                    rb[i] = *(const V*)(in + b_base[i] + ((long)iy * b_w[i] + ix) * a.cin + ci);
+                const int iy = (b_yx[i] >> 16) + r, ix = (int)(short)(b_yx[i] & 0xffff) + s;
+                const int h = b_hw[i] >> 16, w = b_hw[i] & 0xffff;
+                const bool ok = k < a.K && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)w;
+                const int off = ok ? (b_off[i] - kv + (r * w + s) * a.cin + ci) * SZ : kOOB;
+                rb[i] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r_in, off, 0, 0));
             }
         }
     };
-    auto store_chunk = [&](int buf) {
+    auto lds_slot = [&](int i) {
+        const int v = tid + i * 256;
+        return (v / VR) * LDR + (v % VR) * VEC;
+    };
+    auto store_chunk = [&](int buf, const V (&ra)[APT], const V (&rb)[BPT]) {
 #pragma unroll
         for (int i = 0; i < APT; ++i)
-            if (tid + i * 256 < AVEC) *(V*)(&sA[buf][a_lds[i]]) = ra[i];
+            if (AVEC % 256 == 0 || tid + i * 256 < AVEC) *(V*)(&sA[buf][lds_slot(i)]) = ra[i];
 #pragma unroll
         for (int i = 0; i < BPT; ++i)
-            if (tid + i * 256 < BVEC) *(V*)(&sB[buf][b_lds[i]]) = rb[i];
+            if (BVEC % 256 == 0 || tid + i * 256 < BVEC) *(V*)(&sB[buf][lds_slot(i)]) = rb[i];
     };
 
     f32x4 acc[TM][TN];
@@ -305,18 +344,29 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
     };
 
     const int nk = (a.K + BK - 1) / BK;
-    load_chunk(0);
-    store_chunk(0);
+    load_chunk(0, ra2[0], rb2[0]);
+    load_chunk(1, ra2[1], rb2[1]);
+    store_chunk(0, ra2[0], rb2[0]);
+    load_chunk(2, ra2[0], rb2[0]);
     __syncthreads();
-    for (int kc = 0; kc < nk; ++kc) {
-        const int cur = kc & 1;
-        if (kc + 1 < nk) load_chunk(kc + 1);
+    // Iteration kc: store chunk kc+1 (set (kc+1)&1) to LDS buffer (kc+1)&1, load
+    // chunk kc+3 into the same set, compute chunk kc from LDS buffer kc&1.
+    auto iter = [&](int kc, auto cur_c) {
+        constexpr int cur = decltype(cur_c)::value;
+        store_chunk(cur ^ 1, ra2[cur ^ 1], rb2[cur ^ 1]);
+        load_chunk(kc + 3, ra2[cur ^ 1], rb2[cur ^ 1]);
         compute(cur);
-        if (kc + 1 < nk) store_chunk(cur ^ 1);
         __syncthreads();
+    };
+    int kc = 0;
+    for (; kc + 1 < nk; kc += 2) {
+        iter(kc, std::integral_constant<int, 0>{});
+        iter(kc + 1, std::integral_constant<int, 1>{});
     }
+    if (kc < nk) iter(kc, std::integral_constant<int, 0>{});
 
-    // ---- fused epilogue ----
+    // ---- fused epilogue: every group of 4 channels lies entirely below or at/above
+    // n_split and below Cout (n_split and Cout are multiples of 4) ----
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         const int m = m0 + wm * WTM + i * 16 + (lane & 15);
@@ -325,10 +375,11 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
         for (int j = 0; j < TN; ++j) {
             const int cb = n0 + wn * WTN + j * 16 + (lane >> 4) * 4;
             if (cb >= a.cout) continue;
+            const f32x4 bv = *(const f32x4*)(a.bias + cb);
             float v[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) v[t] = acc[i][j][t] + ((cb + t < a.cout) ? a.bias[cb + t] : 0.f);
-            if (cb + 4 <= a.n_split) {
+            for (int t = 0; t < 4; ++t) v[t] = acc[i][j][t] + bv[t];
+            if (cb < a.n_split) {
                 if (a.act) {
 #pragma unroll
                     for (int t = 0; t < 4; ++t) v[t] = leaky01(v[t]);
@@ -356,24 +407,7 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
                     *(T4*)op = pk;
                 }
             } else {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int co = cb + t;
-                    if (co >= a.cout) break;
-                    if (co < a.n_split) {
-                        float x = a.act ? leaky01(v[t]) : v[t];
-                        const size_t o = (size_t)m * a.ld0 + co;
-                        if (a.out0_f32) {
-                            if (a.res) x += ((const float*)a.res)[o];
-                            ((float*)a.out0)[o] = x;
-                        } else {
-                            if (a.res) x += (float)((const T*)a.res)[o];
-                            ((T*)a.out0)[o] = cvt_out<T>(x);
-                        }
-                    } else {
-                        a.out1[(size_t)m * a.ld1 + (co - a.n_split)] = v[t];
-                    }
-                }
+                *(f32x4*)(a.out1 + (size_t)m * a.ld1 + (cb - a.n_split)) = f32x4{v[0], v[1], v[2], v[3]};
             }
         }
     }
@@ -464,7 +498,7 @@ static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
         return hipErrorInvalidValue;
     } else {
         constexpr TileCfg t = kTiles[C];
-        dim3 grid((a.M + t.bm - 1) / t.bm, (a.cout + t.bn - 1) / t.bn), block(256);
+        dim3 grid(((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn)), block(256);
         if (aligned)
             conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, true><<<grid, block, 0, s>>>(a);
         else if constexpr (C == 5)

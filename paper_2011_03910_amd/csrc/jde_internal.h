@@ -56,6 +56,8 @@ struct ConvArgs {
     int act;               // leaky ReLU 0.1 on out0 columns
     int out0_f32;          // out0 holds FP32 (head outputs) instead of the activation type
     float in_scale;        // FP8: activation quantisation scale of the input (x / in_scale)
+    int in_bytes, in2_bytes, w_bytes;  // sizes of the in / in2 / w buffers (< 2^31): loads past them read 0
+    int n_major;           // tile order per XCD: 1 = pixel tiles of a channel range (weights dominate)
 };
 
 // Launchers (conv.hip).

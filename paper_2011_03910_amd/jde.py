@@ -290,6 +290,25 @@ class JDE:
         t = np.ascontiguousarray(tiles, dtype=np.int32)
         check(self.lib.jde_tiles(self.ctx, t.ctypes.data_as(_lib.c_int_p), t.size, 1), "jde_tiles")
 
+    def graph_capture(self, frames, descs, heads, dets, conf_thr=0.5, nms_iou=0.4, tracks=None, cost=None,
+                      stream=None):
+        """Capture forward + decode (+ batched cost when tracks = (trk_emb, mean, cov, track_begin))
+        on `stream` (a torch.cuda.Stream, not the default stream); returns a Graph."""
+        hs = self._head_struct(heads)
+        ds = self._dets_struct(dets)
+        tb = None
+        fe = mean = cov = None
+        if tracks is not None:
+            fe, mean, cov, track_begin = tracks
+            tb = np.ascontiguousarray(track_begin, dtype=np.int32)
+        g = ctypes.c_void_p()
+        check(self.lib.jde_graph_capture(self.ctx, _ptr(frames), _descs(descs), len(descs), _ptr(self.ws),
+                                         self.ws.numel(), ctypes.byref(hs), float(conf_thr), float(nms_iou),
+                                         ctypes.byref(ds), _ptr(fe), _ptr(mean), _ptr(cov),
+                                         None if tb is None else tb.ctypes.data_as(_lib.c_int_p), _ptr(cost),
+                                         _stream(stream), ctypes.byref(g)), "jde_graph_capture")
+        return Graph(self.lib, g, (frames, heads, dets, tracks, cost, tb))
+
     def profile_begin(self, on=True):
         check(self.lib.jde_profile_begin(self.ctx, 1 if on else 0), "jde_profile_begin")
 
@@ -306,3 +325,23 @@ class JDE:
                                            ctypes.byref(nops), ctypes.byref(nfwd)), "jde_profile_collect")
         k = nops.value
         return ms[:k], fl[:k], kind[:k], nfwd.value
+
+
+class Graph:
+    """A captured step; keeps the captured buffers alive."""
+
+    def __init__(self, lib, handle, keep):
+        self.lib = lib
+        self.h = handle
+        self._keep = keep
+
+    def launch(self, stream=None):
+        check(self.lib.jde_graph_launch(self.h, _stream(stream)), "jde_graph_launch")
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.lib.jde_graph_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass

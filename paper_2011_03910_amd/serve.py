@@ -1,0 +1,351 @@
+"""Serving loop: concurrent video streams through the JDE hot path.
+
+The paper's updated pipeline (Sec. 4.4) runs model prediction on batches of
+frames while a separate post-processing worker consumes the model's outputs
+and does the association (Appendix A items 4-9), so the forward never waits for
+post-processing (Sec. 4.3).  This module is that pipeline for one GPU:
+
+* frames of several streams arrive in real time (each stream at its own frame
+  rate and resolution); they wait in arrival order;
+* continuous batching: whenever a batch slot is free, every waiting frame that
+  fits is admitted -- at most `max_batch` frames, and only while the frames in
+  flight stay within the HBM budget (per-frame activation footprint x frames);
+  frames of different resolutions share one ragged batch;
+* each slot owns a library context (workspace, head and detection buffers) and
+  a HIP stream; its forward + decode overlap the other slot's work;
+* a post-processing thread takes finished batches in order and, per frame in
+  stream order, runs the association: Kalman predict on the host (FP64), the
+  gated cost matrix on the GPU against the stream's device-resident track
+  embeddings, Hungarian assignment on the host, Kalman update, track embedding
+  smoothing on the GPU, and the track lifecycle;
+* latency of a frame = its arrival time -> its tracks updated.
+
+Everything on the device runs in the library's kernels; this module only
+schedules and marshals.
+"""
+
+import queue
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .jde import JDE, jde_kf_initiate, jde_kf_predict, jde_kf_update, jde_assign, jde_track_emb_update
+
+CHI2_GATE = 9.4877
+
+
+@dataclass
+class StreamSpec:
+    sid: int
+    height: int
+    width: int
+    fps: float
+    phase: float                 # seconds after start of frame 0
+    frames: np.ndarray           # [F, 3, H, W] FP32 host frames cycled through
+
+
+@dataclass
+class Track:
+    tid: int
+    mean: np.ndarray
+    cov: np.ndarray
+    slot: int                    # row of the stream's device embedding table
+    lost: int = 0
+
+
+@dataclass
+class StreamState:
+    spec: StreamSpec
+    tracks: list = field(default_factory=list)
+    free_rows: list = field(default_factory=list)   # free rows of this stream's range of the pool
+    next_id: int = 1
+
+
+@dataclass
+class FrameJob:
+    sid: int
+    t: int                       # frame index within its stream
+    arrival: float
+    admitted: float = 0.0
+
+
+class Server:
+    def __init__(self, cfg, anchors, layers, streams, precision="bf16", max_batch=16, hbm_budget=None,
+                 max_tracks=512, max_cost=0.7, max_lost=30, conf_thr=0.5, nms_iou=0.4, cap=512, tiles=None,
+                 device="cuda"):
+        import torch
+        self.torch = torch
+        self.streams = {s.sid: StreamState(s) for s in streams}
+        self.max_batch = max_batch
+        self.max_cost, self.max_lost = max_cost, max_lost
+        self.conf_thr, self.nms_iou = conf_thr, nms_iou
+        self.E = cfg.emb_dim
+        max_h = max(s.height for s in streams)
+        max_w = max(s.width for s in streams)
+        self.slots = []
+        for _ in range(2):
+            m = JDE(cfg.c0, cfg.blocks, cfg.emb_dim, anchors, precision, max_batch, max_h, max_w, cap, device)
+            m.load_weights(layers)
+            if tiles is not None:
+                m.set_tiles(tiles)
+            self.slots.append({"m": m, "stream": torch.cuda.Stream(), "busy": False})
+        # per-frame activation footprint: a slot's workspace covers max_batch frames of the largest size
+        self.frame_bytes = self.slots[0]["m"].ws.numel() / max_batch
+        self.hbm_budget = hbm_budget if hbm_budget is not None else 2 * self.slots[0]["m"].ws.numel()
+        self.in_flight_bytes = 0.0
+        self.post_stream = torch.cuda.Stream()
+        # Device-resident track embeddings of every stream in one pool: stream k owns
+        # rows [k * max_tracks, (k + 1) * max_tracks).
+        self.pool = torch.zeros((len(self.streams) * max_tracks, self.E), dtype=torch.float32, device=device)
+        for k, st in enumerate(self.streams.values()):
+            st.free_rows = list(range(k * max_tracks, (k + 1) * max_tracks))[::-1]
+        # pinned staging for frame uploads, one per slot
+        self.max_pix = max_batch * max_h * max_w * 3
+        for sl in self.slots:
+            sl["host"] = torch.empty(self.max_pix, dtype=torch.float32).pin_memory()
+            sl["dev"] = torch.empty(self.max_pix, dtype=torch.float32, device=device)
+            # outputs sized for a full batch of the largest frames; smaller batches use a prefix
+            sl["heads"] = sl["m"].head_buffers([(max_h, max_w)] * max_batch)
+            sl["dets"] = sl["m"].dets_buffers(max_batch)
+        self.lock = threading.Lock()
+        self.results = []            # per frame: dict(sid, t, boxes, ids, latency)
+
+    # ---- producer side -------------------------------------------------------
+    def _free_slot(self):
+        for i, sl in enumerate(self.slots):
+            if not sl["busy"]:
+                return i
+        return None
+
+    def _launch(self, slot_i, jobs):
+        torch = self.torch
+        sl = self.slots[slot_i]
+        m = sl["m"]
+        descs, off = [], 0
+        for j in jobs:
+            sp = self.streams[j.sid].spec
+            fr = sp.frames[j.t % len(sp.frames)]
+            n = fr.size
+            sl["host"][off:off + n].copy_(torch.from_numpy(fr.ravel()))
+            off += n
+            descs.append((sp.height, sp.width))
+        s = sl["stream"]
+        heads, dets = sl["heads"], sl["dets"]
+        with torch.cuda.stream(s):
+            sl["dev"][:off].copy_(sl["host"][:off], non_blocking=True)
+            m.forward(sl["dev"][:off], descs, heads=heads, stream=s)
+            m.decode(heads, descs, self.conf_thr, self.nms_iou, dets=dets, stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        sl["busy"] = True
+        return {"slot": slot_i, "jobs": jobs, "descs": descs, "dets": dets, "heads": heads, "event": ev}
+
+    def run(self, duration, post_queue_depth=4, warmup=0.0):
+        """Serve for `duration` seconds of arrivals; returns the statistics dict
+        (frames arriving in the first `warmup` seconds are served but not counted)."""
+        torch = self.torch
+        q = queue.Queue(maxsize=post_queue_depth)
+        post = threading.Thread(target=self._post_worker, args=(q,), daemon=True)
+        post.start()
+        pending = []
+        next_t = {sid: 0 for sid in self.streams}
+        t_start = time.perf_counter()
+        n_batches = 0
+        while True:
+            now = time.perf_counter() - t_start
+            for sid, st in self.streams.items():
+                sp = st.spec
+                while True:
+                    arr = sp.phase + next_t[sid] / sp.fps
+                    if arr > now or arr >= duration:
+                        break
+                    pending.append(FrameJob(sid, next_t[sid], t_start + arr))
+                    next_t[sid] += 1
+            done_arrivals = all(st.spec.phase + next_t[sid] / st.spec.fps >= duration
+                                for sid, st in self.streams.items())
+            slot = self._free_slot()
+            if pending and slot is not None:
+                pending.sort(key=lambda j: j.arrival)
+                batch = []
+                with self.lock:
+                    for j in pending:
+                        if len(batch) >= self.max_batch:
+                            break
+                        if self.in_flight_bytes + (len(batch) + 1) * self.frame_bytes > self.hbm_budget:
+                            break
+                        batch.append(j)
+                    self.in_flight_bytes += len(batch) * self.frame_bytes
+                if batch:
+                    for j in batch:
+                        j.admitted = time.perf_counter()
+                    pending = pending[len(batch):]
+                    q.put(self._launch(slot, batch))
+                    n_batches += 1
+                    continue
+            if done_arrivals and not pending:
+                break
+            time.sleep(0.0002)
+        q.put(None)
+        post.join()
+        wall = time.perf_counter() - t_start
+        counted = [r for r in self.results if r["arrival"] >= t_start + warmup]
+        lat = np.array([r["latency"] for r in counted]) * 1e3
+        span = wall - warmup
+        stats = {"frames": len(counted), "batches": n_batches, "wall_s": wall,
+                 "fps": len(counted) / span if span > 0 else 0.0,
+                 "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+                 "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+                 "mean_batch": len(self.results) / max(n_batches, 1)}
+        return stats
+
+    # ---- post-processing side (the paper's separate post-processing worker) --------
+    def _post_worker(self, q):
+        torch = self.torch
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            with torch.cuda.stream(self.post_stream):
+                self.post_stream.wait_event(item["event"])
+                jobs = sorted(enumerate(item["jobs"]), key=lambda x: (x[1].sid, x[1].t))
+                # frames of a stream must be associated in order: the first frame of
+                # every stream goes in one batched round, later ones in further rounds
+                rounds, seen = [], {}
+                for f, j in jobs:
+                    r = seen.get(j.sid, 0)
+                    seen[j.sid] = r + 1
+                    while len(rounds) <= r:
+                        rounds.append([])
+                    rounds[r].append((f, j))
+                m = self.slots[item["slot"]]["m"]
+                dets = item["dets"]
+                n = len(jobs)
+                counts = dets["count"][:n].cpu().numpy()
+                boxes_all = dets["boxes"].view(-1, m.cap, 4)[:n].cpu().numpy()
+                i0 = len(self.results)
+                for rnd in rounds:
+                    self._associate_round(sorted(rnd, key=lambda x: x[0]), m, dets, counts, boxes_all)
+                done = time.perf_counter()
+                for r in self.results[i0:]:
+                    r["latency"] = done - r["arrival"]
+            with self.lock:
+                self.in_flight_bytes -= len(item["jobs"]) * self.frame_bytes
+                self.slots[item["slot"]]["busy"] = False
+
+    def _associate_round(self, rnd, m, dets, counts, boxes_all):
+        """Appendix A items 4-9 for a set of frames of distinct streams, batched on the device."""
+        torch = self.torch
+        s = self.post_stream
+        cap = m.cap
+        dev = self.pool.device
+        # host: predict every track of the involved streams (one call)
+        sts = [self.streams[j.sid] for _, j in rnd]
+        counts_t = [len(st.tracks) for st in sts]
+        tb = np.concatenate([[0], np.cumsum(counts_t)]).astype(np.int32)
+        T = int(tb[-1])
+        maxd = int(max((counts[f] for f, _ in rnd), default=0))
+        if T:
+            mean = np.ascontiguousarray(np.stack([tr.mean for st in sts for tr in st.tracks]))
+            cov = np.ascontiguousarray(np.stack([tr.cov for st in sts for tr in st.tracks]))
+            jde_kf_predict(mean, cov)
+            k = 0
+            for st in sts:
+                for tr in st.tracks:
+                    tr.mean, tr.cov = mean[k].copy(), cov[k].copy()
+                    k += 1
+        cost_h = None
+        if T and maxd:
+            rows = torch.tensor([tr.slot for st in sts for tr in st.tracks], dtype=torch.int64).to(dev, non_blocking=True)
+            fe = self.pool.index_select(0, rows)
+            dmean = torch.from_numpy(mean).to(dev, non_blocking=True)
+            dcov = torch.from_numpy(cov).to(dev, non_blocking=True)
+            # the batched cost scores frame f of the slot's dets against its stream's tracks;
+            # frames of this round are a subset of the batch, so score each against its own range
+            sub = self._sub_dets(dets, [f for f, _ in rnd], cap)
+            cost = m.cost_batch(fe, dmean, dcov, tb, sub, CHI2_GATE, stream=s)
+            cost_h = cost[:, :maxd].cpu().numpy()
+        boxes_h = [boxes_all[f, :counts[f]] for f, _ in rnd]
+        upd_t, upd_d, new_rows, new_src = [], [], [], []
+        for i, (f, j) in enumerate(rnd):
+            st = sts[i]
+            boxes = boxes_h[i]
+            D = len(boxes)
+            ids = np.zeros(D, dtype=np.int64)
+            zs = np.stack([(boxes[:, 0] + boxes[:, 2]) / 2, (boxes[:, 1] + boxes[:, 3]) / 2,
+                           (boxes[:, 2] - boxes[:, 0]) / (boxes[:, 3] - boxes[:, 1]), boxes[:, 3] - boxes[:, 1]],
+                          axis=1).astype(np.float64) if D else np.zeros((0, 4))
+            matched_t, matched_d = set(), set()
+            if counts_t[i] and D:
+                c = cost_h[tb[i]:tb[i + 1], :D]
+                pairs, _ = jde_assign(c, self.max_cost)
+                for t, d in pairs:
+                    tr = st.tracks[t]
+                    tr.mean, tr.cov = jde_kf_update(tr.mean, tr.cov, zs[d])
+                    tr.lost = 0
+                    ids[d] = tr.tid
+                    matched_t.add(int(t))
+                    matched_d.add(int(d))
+                    upd_t.append(tr.slot)
+                    upd_d.append(f * cap + int(d))
+            survivors = []
+            for ti, tr in enumerate(st.tracks):
+                if ti not in matched_t:
+                    tr.lost += 1
+                    if tr.lost > self.max_lost:
+                        st.free_rows.append(tr.slot)
+                        continue
+                survivors.append(tr)
+            st.tracks = survivors
+            for d in range(D):
+                if d in matched_d or not st.free_rows:
+                    continue
+                mean0, cov0 = jde_kf_initiate(zs[d])
+                row = st.free_rows.pop()
+                new_rows.append(row)
+                new_src.append(f * cap + d)
+                st.tracks.append(Track(st.next_id, mean0, cov0, row))
+                ids[d] = st.next_id
+                st.next_id += 1
+            self.results.append({"sid": j.sid, "t": j.t, "boxes": boxes.copy(), "ids": ids,
+                                 "arrival": j.arrival, "latency": 0.0})
+        emb = dets["emb"]
+        if upd_t:
+            pr = torch.from_numpy(np.stack([upd_t, upd_d], axis=1).astype(np.int32)).to(dev, non_blocking=True)
+            jde_track_emb_update(pr, emb, self.pool, 0.9, stream=s)
+        if new_rows:
+            dst = torch.tensor(new_rows, dtype=torch.int64).to(dev, non_blocking=True)
+            src = torch.tensor(new_src, dtype=torch.int64).to(dev, non_blocking=True)
+            self.pool.index_copy_(0, dst, emb.index_select(0, src))
+        s.synchronize()
+
+    @staticmethod
+    def _sub_dets(dets, frames, cap):
+        """Views of the detection buffers restricted to the given frames, in order
+        (a contiguous selection when the frames are consecutive, else a gather)."""
+        idx = np.asarray(frames)
+        if np.all(np.diff(idx) == 1):
+            lo, hi = int(idx[0]), int(idx[-1]) + 1
+            return {k: (v[lo:hi] if k in ("count", "n_cand", "overflow") else
+                        v.view(-1, cap, *v.shape[1:])[lo:hi].reshape(-1, *v.shape[1:]))
+                    for k, v in dets.items()}
+        import torch
+        ti = torch.from_numpy(idx).to(dets["count"].device)
+        return {k: (v.index_select(0, ti) if k in ("count", "n_cand", "overflow") else
+                    v.view(-1, cap, *v.shape[1:]).index_select(0, ti).reshape(-1, *v.shape[1:]).contiguous())
+                for k, v in dets.items()}
+
+
+def synthetic_streams(n_streams, seed, frames_per_stream=4, fps=30.0, resolutions=((608, 1088), (480, 864),
+                      (320, 576)), objects=(20, 200)):
+    """Seeded stream specs: resolution uniform over `resolutions`, 20-200 objects, random phase."""
+    from jde_inputs import scene_batch
+    rng = np.random.Generator(np.random.PCG64([seed, 23]))
+    out = []
+    for s in range(n_streams):
+        h, w = resolutions[int(rng.integers(len(resolutions)))]
+        n_obj = int(rng.integers(objects[0], objects[1] + 1))
+        fr = scene_batch(seed, frames_per_stream, h, w, n_obj=n_obj, stream=s)
+        out.append(StreamSpec(s, h, w, fps, float(rng.uniform(0, 1.0 / fps)), fr))
+    return out

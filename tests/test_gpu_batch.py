@@ -123,3 +123,82 @@ def test_cost_batch_and_dets_vs_oracle(torch):
                               dets, f)
             torch.cuda.synchronize()
             np.testing.assert_array_equal(one.cpu().numpy()[:, :D], got)
+
+
+def test_ragged_batch_matches_oracle_per_frame(torch):
+    """Frames of three sizes in one batch (one launch per layer): each frame's
+    outputs equal the oracle of that frame alone (FP32, 1e-4)."""
+    _say("case: tiny fp32 ragged batch")
+    from jde_inputs import tiny_frame
+    from oracle.network import forward
+    sizes = [(192, 320), (128, 224), (96, 160), (192, 320), (64, 96)]
+    m = _model(TINY, "fp32", 5, cap=512)
+    m.load_weights(weights("tiny", 50))
+    frs = [tiny_frame(TINY.seed, 10 + i, h, w) for i, (h, w) in enumerate(sizes)]
+    packed = torch.from_numpy(np.concatenate([f.ravel() for f in frs])).cuda()
+    heads = m.forward(packed, sizes)
+    dets = m.decode(heads, sizes)
+    torch.cuda.synchronize()
+    v = head_views(heads, sizes)
+    for i, fr in enumerate(frs):
+        ref = forward(fr[None], weights("tiny", 50), TINY.blocks)
+        for key in ("det", "emb"):
+            for s in range(3):
+                e = rel_err(v[key][s][i], ref[key][s][0])
+                assert e <= 1e-4, (i, sizes[i], key, s, e)
+        # decode of frame i inside the batch equals decode of frame i alone
+        alone = m.decode(m.forward(torch.from_numpy(fr[None]).cuda()), [sizes[i]])
+        torch.cuda.synchronize()
+        a, b = gpu_dets(dets, i, m.cap), gpu_dets(alone, 0, m.cap)
+        np.testing.assert_array_equal(a["anchor_idx"], b["anchor_idx"])
+        np.testing.assert_allclose(a["boxes"], b["boxes"], rtol=1e-5, atol=1e-3)
+
+
+def test_graph_replays_equal_eager(torch):
+    """A captured forward+decode+cost step, replayed several times with eager
+    work between replays and with new frame contents, equals the eager step."""
+    _say("case: graph replay")
+    n = 2
+    m = _model(TINY, "bf16", n, cap=512)
+    m.load_weights(weights("tiny", 50))
+    descs = [(192, 320)] * n
+    frames_buf = torch.from_numpy(frames("tiny", n)).cuda()
+    heads = m.head_buffers(descs)
+    dets = m.dets_buffers(n)
+    trk = [synthetic_dets_tracks(21 + f, 6, 6, TINY.emb_dim, 192, 320) for f in range(n)]
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    fe = cu(np.concatenate([t["trk_emb"] for t in trk]))
+    mean = cu(np.concatenate([t["mean"] for t in trk]))
+    cov = cu(np.concatenate([t["cov"] for t in trk]))
+    tb = [0, 6, 12]
+    cost = torch.zeros((12, m.cap), device="cuda")
+
+    def eager():
+        h = m.forward(frames_buf, descs)
+        d = m.decode(h, descs)
+        c = torch.zeros((12, m.cap), device="cuda")
+        m.cost_batch(fe, mean, cov, tb, d, cost=c)
+        torch.cuda.synchronize()
+        return h, d, c
+
+    s = torch.cuda.Stream()
+    g = m.graph_capture(frames_buf, descs, heads, dets, tracks=(fe, mean, cov, tb), cost=cost, stream=s)
+    for rep in range(4):
+        if rep == 2:
+            frames_buf.copy_(torch.from_numpy(frames("tiny", n, t0=5)).cuda())
+        eh, ed, ec = eager()
+        with torch.cuda.stream(s):
+            g.launch(s)
+        s.synchronize()
+        for key in ("det", "emb"):
+            for q in range(3):
+                assert torch.equal(heads[key][q], eh[key][q]), (rep, key, q)
+        for k in ("count", "n_cand", "anchor_idx", "boxes", "emb"):
+            assert torch.equal(dets[k], ed[k]) or k in ("anchor_idx", "boxes", "emb"), (rep, k)
+        for f in range(n):
+            a, b = gpu_dets(dets, f, m.cap), gpu_dets(ed, f, m.cap)
+            np.testing.assert_array_equal(a["anchor_idx"], b["anchor_idx"])
+            np.testing.assert_array_equal(a["emb"], b["emb"])
+            D = len(a["anchor_idx"])
+            np.testing.assert_array_equal(cost[6 * f:6 * f + 6, :D].cpu().numpy(), ec[6 * f:6 * f + 6, :D].cpu().numpy())
+        _say(f"  replay {rep} ok: {[int(x) for x in dets['count'].cpu()]} detections")

@@ -203,3 +203,27 @@ def test_rounding_models_match_library_casts_and_ties(rng):
     assert net.round_fp16(np.float32(1 + 2 ** -11)) == 1.0
     assert net.round_fp16(np.float32(1 + 3 * 2 ** -11)) == 1 + 2 ** -9
     assert np.isinf(net.round_bf16(np.float32(np.inf)))
+
+
+def test_fp8_rounding_model_matches_library_cast_and_format(rng):
+    """round_fp8 equals torch's float8_e4m3fn cast on every in-range value, and
+    saturates at 448 where torch gives NaN; every e4m3 code point is a fixed point."""
+    import torch
+    x = (rng.standard_normal(50000) * 10.0 ** rng.uniform(-4, 2.6, 50000)).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).to(torch.float32).numpy().astype(np.float64)
+    got = net.round_fp8(x)
+    inr = np.abs(x) <= 448.0
+    np.testing.assert_array_equal(got[inr], ref[inr])
+    assert np.all(np.abs(got[~inr]) == 448.0)
+    codes = torch.arange(0, 256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float32).numpy()
+    codes = codes[np.isfinite(codes)].astype(np.float64)
+    np.testing.assert_array_equal(net.round_fp8(codes), codes)
+    assert len(np.unique(codes)) == 253          # 254 finite codes, +0 and -0 equal
+    assert net.round_fp8(1.0625) == 1.0 and net.round_fp8(1.1875) == 1.25   # ties to even
+    w = rng.standard_normal((5, 3, 3, 7))
+    w[2] = 0.0
+    wq, s = net.quantize_fp8_per_channel(w)
+    assert s[2] == 1.0 and np.all(wq[2] == 0)
+    np.testing.assert_allclose(np.abs(wq).reshape(5, -1).max(1)[[0, 1, 3, 4]],
+                               np.abs(w).reshape(5, -1).max(1)[[0, 1, 3, 4]], rtol=1e-12)
+    assert np.abs(wq - w).max() <= np.abs(w).max() / 16
