@@ -46,7 +46,7 @@ def make_inputs(batch, torch):
 class Pipeline:
     """Preallocated buffers and one step of the hot path for a fixed batch."""
 
-    def __init__(self, precision, batch, layers, torch, tune_frames=None, tiles=None):
+    def __init__(self, precision, batch, layers, torch, tune_frames=None, tiles=None, calib_frames=None):
         from jde_inputs import FULL, anchors_px
         from paper_2011_03910_amd import JDE
         self.torch = torch
@@ -60,6 +60,9 @@ class Pipeline:
         self.track_begin = [N_TRACKS * f for f in range(batch + 1)]
         self.cost = torch.empty((batch * N_TRACKS, self.m.cap), dtype=torch.float32, device="cuda")
         self.tiles = None
+        if precision == "fp8":
+            # static activation scales from one BF16 pass over this batch
+            self.m.calibrate(tune_frames if tune_frames is not None else calib_frames, self.descs, heads=self.heads)
         if tiles is not None:
             self.m.set_tiles(tiles)
             self.tiles = self.m.tiles()
@@ -147,7 +150,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32", "fp8"])
     ap.add_argument("--fp32-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 batch-1 plain form")
@@ -155,6 +158,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="serving run length (0: skip)")
     ap.add_argument("--save-tiles", help="write the tile choices to this JSON file")
     ap.add_argument("--load-tiles", help="use tile choices from this JSON file instead of tuning")
+    ap.add_argument("--retune", action="store_true", help="run the autotuner instead of the stored tile choices")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (frames are independent, "
@@ -168,10 +172,16 @@ def main():
     layers = model_weights(FULL, K_CAND)
     inputs_b = make_inputs(args.batch, torch)
 
-    saved = json.load(open(args.load_tiles)) if args.load_tiles else {}
+    cache = os.path.join(ROOT, "paper_2011_03910_amd", "tiles_mi355x.json")
+    if args.load_tiles:
+        saved = json.load(open(args.load_tiles))
+    elif not args.retune and not args.no_tune and os.path.exists(cache):
+        saved = json.load(open(cache))          # autotuner results for this workload
+    else:
+        saved = {}
     key = f"{args.precision}_b{args.batch}"
     pipe = Pipeline(args.precision, args.batch, layers, torch, None if args.no_tune else inputs_b[0],
-                    saved.get(key))
+                    saved.get(key), calib_frames=inputs_b[0])
     tiles_out = {key: None if pipe.tiles is None else pipe.tiles.tolist()}
     wall, step_ms, prof = run(pipe, inputs_b, args.steps, args.warmup, torch, profile=True)
     fps = args.batch * args.steps / wall

@@ -156,6 +156,24 @@ jde_status jde_autotune(jde_ctx* ctx, const float* d_frames, const jde_frame_des
  * on write. */
 jde_status jde_tiles(jde_ctx* ctx, int* tiles, int n_ops, int set);
 
+/* FP8 calibration (mixed precision, Sec. 4.1, taken to the e4m3 format of
+ * gfx950).  In a JDE_FP8 context the backbone convolutions whose Cin is a
+ * multiple of 128 run on e4m3 operands: weights with a per-output-channel
+ * scale max|w_c| / 448, input activations (stored BF16) with a static
+ * per-tensor scale.  This call runs one BF16 forward of the given batch,
+ * records the largest |value| each convolution writes, and sets every FP8
+ * launch's input scale to that of its producer / 448.  Arguments as for
+ * jde_forward; blocks until done.  Until it has run, jde_forward of a JDE_FP8
+ * context returns JDE_ESTATE; jde_load_weights resets it. */
+jde_status jde_calibrate(jde_ctx* ctx, const float* d_frames, const jde_frame_desc* descs, int n,
+                         void* d_ws, size_t ws_bytes, const jde_head_out* out, void* stream);
+/* Input scale of every forward launch (0 for launches that do not run in FP8);
+ * in_scales: host, n_ops = number of forward launches. */
+jde_status jde_fp8_scales(const jde_ctx* ctx, float* in_scales, int n_ops);
+/* Host helper: x (host, n floats) -> OCP e4m3 codes (host, n bytes), round to
+ * nearest even, saturating at +-448, NaN -> 0x7f; the encoding of the weights. */
+void jde_fp8_encode(const float* x, uint8_t* out, size_t n);
+
 /* Post-processing of Appendix A items 1-3 plus embedding normalisation, for
  * every frame of the batch: anchor decode, keep iff score >= conf_thr
  * (evaluated as c_fg - c_bg >= ln(conf_thr / (1 - conf_thr)) in FP32), sort
@@ -251,6 +269,8 @@ jde_status jde_profile_collect(jde_ctx* ctx, int max_ops, double* op_ms, double*
  * velocity, 1e-2 / 1e-5 for a / va; measurement: h/20, and 0.1 for a).
  * All arrays host, row-major. */
 void jde_kf_initiate(const double z[4], double mean[8], double cov[64]);
+/* jde_kf_initiate for n measurements z [n,4] -> mean [n,8], cov [n,8,8]. */
+void jde_kf_initiate_n(int n, const double* z, double* mean, double* cov);
 /* Predicts T states in place (mean [T,8], cov [T,8,8]). */
 void jde_kf_predict(int T, double* mean, double* cov);
 /* Update with measurement z; Joseph-form covariance, symmetrised.

@@ -118,15 +118,17 @@ def quantize_fp8_per_channel(w):
 class _Walker:
     """Consumes the weight list in blob order (see jde_inputs.weights)."""
 
-    def __init__(self, layers, pre_hook, store):
+    def __init__(self, layers, pre_hook, store, in_hook):
         self.layers = layers
         self.i = 0
         self.pre_hook = pre_hook
         self.store = store
+        self.in_hook = in_hook
 
     def conv(self, x, stride=1, act=True, res=None):
         w, b = self.layers[self.i]
-        y = conv2d(x, w, b, stride)
+        xin = x if self.in_hook is None else self.in_hook(self.i, x)
+        y = conv2d(xin, w, b, stride)
         if self.pre_hook is not None:
             y = self.pre_hook(self.i, y)
         self.i += 1
@@ -139,7 +141,7 @@ class _Walker:
         return y
 
 
-def forward(frames, layers, blocks, pre_hook=None, store=None):
+def forward(frames, layers, blocks, pre_hook=None, store=None, in_hook=None):
     """JDE forward (Sec. 3.1).
 
     frames: [N, 3, H, W] (H, W divisible by 32).  layers: list of (w, b) in blob
@@ -148,11 +150,13 @@ def forward(frames, layers, blocks, pre_hook=None, store=None):
     given, is applied to every activation a non-output conv stores (after its
     activation and residual add): round_bf16 / round_fp16 model a network whose
     activations are kept in that format (the exact arithmetic stays FP64).
+    in_hook(i, x), if given, replaces the input conv i reads (the residual and
+    the stored tensor are unchanged): it models an input quantised for conv i.
 
     Returns dict with 'det' = [d8, d16, d32] ([N, H/s, W/s, 6A]) and
     'emb' = [e8, e16, e32] ([N, H/s, W/s, E]), all FP64, plus 'feat' = C3, C4, C5.
     """
-    nb = _Walker(layers, pre_hook, store)
+    nb = _Walker(layers, pre_hook, store, in_hook)
     x = ingest(frames)
     x = nb.conv(x)                                   # stem
     feats = {}

@@ -81,6 +81,10 @@ SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "jde_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "jde_graph_destroy": (None, [ctypes.c_void_p]),
+    "jde_calibrate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(JdeFrameDesc), ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(JdeHeadOut), ctypes.c_void_p]),
+    "jde_fp8_scales": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int]),
+    "jde_fp8_encode": (None, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t]),
     "jde_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p, c_int_p, c_int_p,
                                            c_int_p]),
@@ -89,6 +93,7 @@ SIGNATURES = {
                                             ctypes.c_void_p]),
     "jde_kf_initiate": (None, [c_double_p, c_double_p, c_double_p]),
     "jde_kf_predict": (None, [ctypes.c_int, c_double_p, c_double_p]),
+    "jde_kf_initiate_n": (None, [ctypes.c_int, c_double_p, c_double_p, c_double_p]),
     "jde_kf_update": (ctypes.c_int, [c_double_p, c_double_p, c_double_p]),
     "jde_assign": (ctypes.c_int, [c_float_p, ctypes.c_int, ctypes.c_int, ctypes.c_float, c_int_p, c_int_p,
                                   c_double_p]),

@@ -1,6 +1,8 @@
 // C ABI of libjde: context, layer plan, workspace planner, weight packing, and
 // the orchestration of the forward, decode, NMS and cost launches.
 #include <math.h>
+
+#include <cmath>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -55,6 +57,11 @@ struct Op {
     int lvl_in, lvl_out, cin, cout, ksz, stride, cin1, n_split, act;
     size_t dev_w, dev_b;     // byte offsets in the device weight buffer
     int tile;                // tile configuration (-1: default)
+    int fp8;                 // runs as an FP8 e4m3 convolution once calibrated
+    size_t dev_w8, dev_ws;   // FP8 weights [Cout][K] and their per-channel scales
+    float in_scale;          // per-tensor scale of the input activations (calibrated)
+    int producer;            // op whose output this op reads (-1: the stem or none)
+    int tile8;               // FP8 tile configuration
 };
 
 struct Tensor {
@@ -80,6 +87,9 @@ struct jde_ctx {
     int keycap = 0, cap = 0, max_anchors = 0;
     char* d_weights = nullptr;
     bool loaded = false;
+    int n_backbone_ops = 0;
+    bool fp8 = false, fp8_ready = false, calibrating = false;
+    size_t ws_amax = 0;
     // Per-launch timing: a ring of event pairs, one entry per profiled forward.
     static constexpr int kRing = 8;
     bool prof = false;
@@ -139,6 +149,10 @@ void build_plan(jde_ctx* c) {
         o.n_split = L.cout;
         o.act = 1;
         o.tile = -1;
+        o.fp8 = 0;
+        o.in_scale = 1.f;
+        o.producer = -1;
+        o.tile8 = 0;
         c->ops.push_back(o);
         return (int)c->ops.size() - 1;
     };
@@ -164,6 +178,7 @@ void build_plan(jde_ctx* c) {
         }
         feat[s] = x;
     }
+    c->n_backbone_ops = (int)c->ops.size();
     const int nout = 6 * g.num_anchors;
     int lat = -1, lat_c = 0;
     const int lv[3] = {5, 4, 3};
@@ -258,6 +273,21 @@ void plan_arena(jde_ctx* c) {
     c->arena_bytes = align256(top);
 }
 
+// FP8 launches: backbone convolutions whose Cin is a multiple of 128 (every
+// 128-wide K chunk then lies in one tap).  Each op also learns its producer.
+void plan_fp8(jde_ctx* c) {
+    for (int i = 0; i < (int)c->ops.size(); ++i) {
+        Op& o = c->ops[i];
+        for (int j = i - 1; j >= 0; --j)
+            if (c->ops[j].out_t >= 0 && c->ops[j].out_t == o.in_t) {
+                o.producer = j;
+                break;
+            }
+        o.fp8 = c->fp8 && o.kind == OP_CONV && i < c->n_backbone_ops && o.cin % 128 == 0 && o.cin1 == 0 &&
+                o.producer >= 0;
+    }
+}
+
 void plan_weights(jde_ctx* c) {
     size_t off = 0;
     const size_t eb = elem_bytes(c->et);
@@ -268,6 +298,12 @@ void plan_weights(jde_ctx* c) {
         off = align256(off + wb);
         o.dev_b = off;
         off = align256(off + (size_t)o.cout * 4);
+        if (o.fp8) {
+            o.dev_w8 = off;
+            off = align256(off + (size_t)o.cout * K);
+            o.dev_ws = off;
+            off = align256(off + (size_t)o.cout * 4);
+        }
     }
     c->weights_bytes = off;
 }
@@ -293,6 +329,7 @@ void plan_decode_scratch(jde_ctx* c) {
     c->ws_sboxes = off; off = align256(off + n * c->cap * 16);
     c->ws_mask = off;   off = align256(off + n * (size_t)c->cap * (c->cap / 64) * 8);
     c->ws_keep = off;   off = align256(off + n * c->cap * 4);
+    c->ws_amax = off;   off = align256(off + c->ops.size() * 4);
     c->ws_total = off;
 }
 
@@ -334,7 +371,7 @@ GeomParams geom_params(const jde_frame_desc* d, int n) {
 
 // Arguments of conv op `o` for a batch (d, n) with workspace W and head outputs `out`.
 ConvArgs conv_args(const jde_ctx* c, const Op& o, const jde_frame_desc* d, int n, bool uniform, char* W,
-                   const int* geom, const jde_head_out* out) {
+                   const int* geom, const jde_head_out* out, int op_index = -1) {
     auto tptr = [&](int t) -> void* { return t < 0 ? nullptr : (void*)(W + c->tens[t].off); };
     const char* wb = c->d_weights;
     ConvArgs a{};
@@ -378,8 +415,17 @@ ConvArgs conv_args(const jde_ctx* c, const Op& o, const jde_frame_desc* d, int n
         a.out1 = out->emb[o.emb_out];
         a.ld1 = o.cout - o.n_split;
     }
+    if (o.fp8 && c->fp8_ready && !c->calibrating) {
+        a.w = wb + o.dev_w8;
+        a.wscale = (const float*)(wb + o.dev_ws);
+        a.in_scale = o.in_scale;
+        a.w_bytes = o.cout * a.K;
+    }
+    if (c->calibrating && op_index >= 0) a.amax = (unsigned*)(W + c->ws_amax) + op_index;
     return a;
 }
+
+bool runs_fp8(const jde_ctx* c, const Op& o) { return o.fp8 && c->fp8_ready && !c->calibrating; }
 
 }  // namespace
 
@@ -416,6 +462,28 @@ uint16_t f32_to_bf16_rne(float x) {
     u += 0x7fffu + lsb;
     return (uint16_t)(u >> 16);
 }
+// OCP FP8 e4m3 (bias 7, 3 mantissa bits, no infinities, max 448), round to
+// nearest even, saturating at +-448; NaN -> 0x7f.
+uint8_t f32_to_e4m3(float x) {
+    if (x != x) return 0x7f;
+    const uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
+    float a = fabsf(x);
+    if (a >= 448.f) return sign | 0x7e;
+    if (a == 0.f) return sign;
+    int e;
+    frexpf(a, &e);
+    int E = e - 1 < -6 ? -6 : e - 1;          // binade; below 2^-6 the spacing stays 2^-9
+    const float q = ldexpf(1.f, E - 3);
+    const float v = nearbyintf(a / q) * q;     // the default rounding mode is to nearest even
+    if (v >= 448.f) return sign | 0x7e;
+    if (v == 0.f) return sign;
+    frexpf(v, &e);
+    E = e - 1;
+    if (E < -6) return sign | (uint8_t)(v / ldexpf(1.f, -9));
+    const int m = (int)((v / ldexpf(1.f, E) - 1.f) * 8.f);
+    return sign | (uint8_t)(((E + 7) << 3) | m);
+}
+
 uint16_t f32_to_f16_rne(float x) {
     _Float16 h = (_Float16)x;   // host conversion is IEEE round-to-nearest-even
     uint16_t r;
@@ -451,7 +519,7 @@ jde_status jde_create(const jde_config* cfg, jde_ctx** out) {
         if (g.blocks[i] < 0 || g.blocks[i] > 64) return fail(JDE_EINVAL, "blocks[%d] out of range", i);
     if (g.num_anchors != 4) return fail(JDE_EUNSUPPORTED, "num_anchors must be 4");
     if (g.emb_dim <= 0 || g.emb_dim % 64) return fail(JDE_EINVAL, "emb_dim must be a positive multiple of 64");
-    if (g.precision != JDE_FP32 && g.precision != JDE_BF16 && g.precision != JDE_FP16)
+    if (g.precision != JDE_FP32 && g.precision != JDE_BF16 && g.precision != JDE_FP16 && g.precision != JDE_FP8)
         return fail(JDE_EUNSUPPORTED, "precision %d not implemented", g.precision);
     if (g.max_frames <= 0 || g.max_frames > kMaxFrames) return fail(JDE_EINVAL, "max_frames must be 1..%d", kMaxFrames);
     if (g.max_h <= 0 || g.max_w <= 0 || g.max_h % 32 || g.max_w % 32)
@@ -472,7 +540,9 @@ jde_status jde_create(const jde_config* cfg, jde_ctx** out) {
     jde_ctx* c = new jde_ctx();
     c->cfg = g;
     c->et = g.precision == JDE_FP32 ? kF32 : (g.precision == JDE_FP16 ? kF16 : kBF16);
+    c->fp8 = g.precision == JDE_FP8;
     build_plan(c);
+    plan_fp8(c);
     plan_arena(c);
     plan_weights(c);
     plan_decode_scratch(c);
@@ -584,6 +654,14 @@ jde_status jde_load_weights(jde_ctx* c, const float* blob, size_t nf, void* d_we
                     }
                 }
                 memcpy(host.data() + o.dev_b + row * 4, &b[co], 4);
+                if (o.fp8) {
+                    float amax = 0.f;
+                    for (int k = 0; k < K; ++k) amax = std::max(amax, fabsf(w[(size_t)co * K + k]));
+                    const float sc = amax > 0.f ? amax / 448.f : 1.f;
+                    memcpy(host.data() + o.dev_ws + row * 4, &sc, 4);
+                    for (int k = 0; k < K; ++k)
+                        host[o.dev_w8 + row * K + k] = f32_to_e4m3(w[(size_t)co * K + k] / sc);
+                }
             }
         }
     }
@@ -592,6 +670,7 @@ jde_status jde_load_weights(jde_ctx* c, const float* blob, size_t nf, void* d_we
     HIP_TRY(hipStreamSynchronize(s));
     c->d_weights = (char*)d_weights;
     c->loaded = true;
+    c->fp8_ready = false;
     return JDE_OK;
 }
 
@@ -599,6 +678,7 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
                        const jde_head_out* out, void* stream) {
     if (!c || !frames || !ws || !out) return fail(JDE_EINVAL, "null argument");
     if (!c->loaded) return fail(JDE_ESTATE, "weights not loaded");
+    if (c->fp8 && !c->fp8_ready && !c->calibrating) return fail(JDE_ESTATE, "FP8 context not calibrated");
     if (wsb < c->ws_total) return fail(JDE_ENOMEM, "workspace %zu < %zu bytes", wsb, c->ws_total);
     for (int s = 0; s < 3; ++s)
         if (!out->det[s] || !out->emb[s]) return fail(JDE_EINVAL, "null head output %d", s);
@@ -631,9 +711,13 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
             }
             continue;
         }
-        const ConvArgs a = conv_args(c, o, d, n, uniform, W, geom, out);
-        const int tile = (o.tile >= 0 && conv_tile_ok(o.tile, c->et, a)) ? o.tile : conv_default_tile(c->et, a);
-        HIP_TRY(launch_conv(a, c->et, tile, s));
+        const ConvArgs a = conv_args(c, o, d, n, uniform, W, geom, out, (int)oi);
+        if (runs_fp8(c, o)) {
+            HIP_TRY(launch_conv_fp8(a, o.tile8, s));
+        } else {
+            const int tile = (o.tile >= 0 && conv_tile_ok(o.tile, c->et, a)) ? o.tile : conv_default_tile(c->et, a);
+            HIP_TRY(launch_conv(a, c->et, tile, s));
+        }
         if (pev) {
             HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));
             c->op_flop[oi] = 2.0 * a.M * (double)a.cout * a.K;
@@ -660,13 +744,16 @@ jde_status jde_autotune(jde_ctx* c, const float* frames, const jde_frame_desc* d
     for (Op& o : c->ops) {
         if (o.kind != OP_CONV) continue;
         const ConvArgs a = conv_args(c, o, d, n, uniform, W, geom, out);
+        const bool f8 = runs_fp8(c, o);
         float best = 1e30f;
         int best_t = -1;
-        for (int t = 0; t < conv_num_tile_cfgs() && st == JDE_OK; ++t) {
-            if (!conv_tile_ok(t, c->et, a)) continue;
-            hipError_t e = launch_conv(a, c->et, t, s);
+        const int nt = f8 ? conv_fp8_num_tiles() : conv_num_tile_cfgs();
+        auto go = [&](int t) { return f8 ? launch_conv_fp8(a, t, s) : launch_conv(a, c->et, t, s); };
+        for (int t = 0; t < nt && st == JDE_OK; ++t) {
+            if (!f8 && !conv_tile_ok(t, c->et, a)) continue;
+            hipError_t e = go(t);
             if (e == hipSuccess) e = hipEventRecord(e0, s);
-            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_conv(a, c->et, t, s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = go(t);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -681,7 +768,10 @@ jde_status jde_autotune(jde_ctx* c, const float* frames, const jde_frame_desc* d
             }
         }
         if (st != JDE_OK) break;
-        o.tile = best_t;
+        if (f8)
+            o.tile8 = best_t;
+        else
+            o.tile = best_t;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -858,6 +948,47 @@ jde_status jde_track_emb_update(const int* pairs, int P, const float* de, int D,
     if (P > 0 && (!pairs || !de || !fe)) return fail(JDE_EINVAL, "null argument");
     HIP_TRY(launch_emb_update(pairs, P, de, D, fe, T, E, mom, (hipStream_t)stream));
     return JDE_OK;
+}
+
+jde_status jde_calibrate(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws, size_t wsb,
+                         const jde_head_out* out, void* stream) {
+    if (!c || !ws) return fail(JDE_EINVAL, "null argument");
+    if (!c->fp8) return fail(JDE_EUNSUPPORTED, "calibration applies to FP8 contexts");
+    if (!c->loaded) return fail(JDE_ESTATE, "weights not loaded");
+    if (c->prof) return fail(JDE_ESTATE, "calibration while profiling");
+    if (wsb < c->ws_total) return fail(JDE_ENOMEM, "workspace %zu < %zu bytes", wsb, c->ws_total);
+    bool uniform;
+    if (jde_status st = batch_ok(c, d, n, &uniform)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    char* W = (char*)ws;
+    unsigned* amax = (unsigned*)(W + c->ws_amax);
+    HIP_TRY(launch_setup(geom_params(d, n), (int*)(W + c->ws_geom), (int*)amax, (int)c->ops.size(), s));
+    c->calibrating = true;
+    const jde_status st = jde_forward(c, frames, d, n, ws, wsb, out, stream);
+    c->calibrating = false;
+    if (st != JDE_OK) return st;
+    std::vector<unsigned> h(c->ops.size());
+    HIP_TRY(hipMemcpyAsync(h.data(), amax, h.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (Op& o : c->ops) {
+        if (!o.fp8) continue;
+        float m;
+        memcpy(&m, &h[o.producer], 4);
+        o.in_scale = m > 0.f ? m / 448.f : 1.f;
+    }
+    c->fp8_ready = true;
+    return JDE_OK;
+}
+
+jde_status jde_fp8_scales(const jde_ctx* c, float* in_scales, int n_ops) {
+    if (!c || !in_scales) return fail(JDE_EINVAL, "null argument");
+    if (n_ops != (int)c->ops.size()) return fail(JDE_EINVAL, "expected %zu entries", c->ops.size());
+    for (int i = 0; i < n_ops; ++i) in_scales[i] = c->ops[i].fp8 ? c->ops[i].in_scale : 0.f;
+    return JDE_OK;
+}
+
+void jde_fp8_encode(const float* x, uint8_t* out, size_t n) {
+    for (size_t i = 0; i < n; ++i) out[i] = f32_to_e4m3(x[i]);
 }
 
 struct jde_graph {

@@ -136,6 +136,77 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
 }
 
 // ---------------------------------------------------------------------------
+// Fused epilogue of one wave's tile (rows m_base.., channels n_base..): + bias
+// (after an optional per-channel dequantisation scale), leaky ReLU 0.1, residual
+// add, cast and store; columns >= n_split go linear to the FP32 output out1.
+// Every group of 4 channels lies entirely below or at/above n_split and below
+// Cout (both are multiples of 4).  With a.amax set, the largest |value| stored
+// to out0 is folded into *a.amax (float bits as unsigned, non-negative).
+// ---------------------------------------------------------------------------
+template <typename T, int TM, int TN, int WTM, int WTN>
+__device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)[TM][TN], int m_base, int n_base,
+                                           int lane, const float* __restrict__ dq) {
+    float amax = 0.f;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int m = m_base + i * 16 + (lane & 15);
+        if (m >= a.M) continue;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int cb = n_base + j * 16 + (lane >> 4) * 4;
+            if (cb >= a.cout) continue;
+            const f32x4 bv = *(const f32x4*)(a.bias + cb);
+            float v[4];
+            if (dq) {
+                const f32x4 sv = *(const f32x4*)(dq + cb);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) v[t] = acc[i][j][t] * (sv[t] * a.in_scale) + bv[t];
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) v[t] = acc[i][j][t] + bv[t];
+            }
+            if (cb < a.n_split) {
+                if (a.act) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) v[t] = leaky01(v[t]);
+                }
+                const size_t o = (size_t)m * a.ld0 + cb;
+                if (a.out0_f32) {
+                    float* op = (float*)a.out0 + o;
+                    if (a.res) {
+                        const f32x4 r = *(const f32x4*)((const float*)a.res + o);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) v[t] += r[t];
+                    }
+                    *(f32x4*)op = f32x4{v[0], v[1], v[2], v[3]};
+                } else {
+                    T* op = (T*)a.out0 + o;
+                    typedef T T4 __attribute__((ext_vector_type(4)));
+                    if (a.res) {
+                        const T4 r = *(const T4*)((const T*)a.res + o);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) v[t] += (float)r[t];
+                    }
+                    T4 pk;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) pk[t] = cvt_out<T>(v[t]);
+                    *(T4*)op = pk;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) amax = fmaxf(amax, fabsf(v[t]));
+            } else {
+                *(f32x4*)(a.out1 + (size_t)m * a.ld1 + (cb - a.n_split)) = f32x4{v[0], v[1], v[2], v[3]};
+            }
+        }
+    }
+    if (a.amax) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
+        if (lane == 0) atomicMax(a.amax, __float_as_uint(amax));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // MFMA implicit GEMM.
 //   BM pixels x BN channels per workgroup of 4 waves (WGM x WGN), K chunks of BK.
 //   Each wave owns a (BM/WGM) x (BN/WGN) tile of 16x16 MFMA blocks.
@@ -365,52 +436,220 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
     }
     if (kc < nk) iter(kc, std::integral_constant<int, 0>{});
 
-    // ---- fused epilogue: every group of 4 channels lies entirely below or at/above
-    // n_split and below Cout (n_split and Cout are multiples of 4) ----
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        const int m = m0 + wm * WTM + i * 16 + (lane & 15);
-        if (m >= a.M) continue;
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int cb = n0 + wn * WTN + j * 16 + (lane >> 4) * 4;
-            if (cb >= a.cout) continue;
-            const f32x4 bv = *(const f32x4*)(a.bias + cb);
-            float v[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) v[t] = acc[i][j][t] + bv[t];
-            if (cb < a.n_split) {
-                if (a.act) {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) v[t] = leaky01(v[t]);
-                }
-                const size_t o = (size_t)m * a.ld0 + cb;
-                if (a.out0_f32) {
-                    float* op = (float*)a.out0 + o;
-                    if (a.res) {
-                        const f32x4 r = *(const f32x4*)((const float*)a.res + o);
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) v[t] += r[t];
-                    }
-                    *(f32x4*)op = f32x4{v[0], v[1], v[2], v[3]};
-                } else {
-                    T* op = (T*)a.out0 + o;
-                    typedef T T4 __attribute__((ext_vector_type(4)));
-                    if (a.res) {
-                        const T4 r = *(const T4*)((const T*)a.res + o);
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) v[t] += (float)r[t];
-                    }
-                    T4 pk;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) pk[t] = cvt_out<T>(v[t]);
-                    *(T4*)op = pk;
-                }
-            } else {
-                *(f32x4*)(a.out1 + (size_t)m * a.ld1 + (cb - a.n_split)) = f32x4{v[0], v[1], v[2], v[3]};
-            }
+    store_tile<T, TM, TN, WTM, WTN>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// FP8 (OCP e4m3) implicit GEMM for the deep backbone convolutions.
+//   K chunks of 128 = one v_mfma_scale_f32_16x16x128_f8f6f4 (unit block scales)
+//   per 16x16 output block; each lane feeds 32 consecutive k of its row (two
+//   16-byte LDS reads per operand).  Activations stay BF16 in HBM: the B loader
+//   fetches 8 channels (16 bytes) per buffer load and, when staging to LDS,
+//   converts them to e4m3 as round(clamp(x / in_scale, +-448)).  Weights are
+//   e4m3 in HBM with a per-output-channel scale; the epilogue multiplies the
+//   FP32 accumulator by wscale[co] * in_scale.  Requires Cin % 128 == 0 (every
+//   chunk lies within one tap) and no concat input.
+// ---------------------------------------------------------------------------
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
+    constexpr int BK = 128;                  // fp8 elements (bytes) per chunk
+    constexpr int LDR = BK + 16;             // padded LDS row, bytes
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int TM = WTM / 16, TN = WTN / 16;
+    constexpr int VRB = BK / 8;              // 16-byte BF16 loads per pixel row and chunk
+    constexpr int VRA = BK / 16;             // 16-byte FP8 loads per weight row and chunk
+    constexpr int BVEC = BM * VRB, AVEC = BN * VRA;
+    constexpr int BPT = (BVEC + 255) / 256, APT = (AVEC + 255) / 256;
+    static_assert(WGM * WGN == 4 && TM >= 1 && TN >= 1, "tile");
+    typedef int i32x4 __attribute__((ext_vector_type(4)));
+    typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+    __shared__ __attribute__((aligned(16))) unsigned char sA[2][BN * LDR];
+    __shared__ __attribute__((aligned(16))) unsigned char sB[2][BM * LDR];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+    int m0, n0;
+    {
+        const int gm = (a.M + BM - 1) / BM, gn = (a.cout + BN - 1) / BN;
+        const int W = gm * gn, L = blockIdx.x;
+        const int xcd = L % kXCDs, local = L / kXCDs;
+        const int base = W / kXCDs, extra = W % kXCDs;
+        const int P = xcd < extra ? xcd * (base + 1) + local : extra * (base + 1) + (xcd - extra) * base + local;
+        if (a.n_major) {
+            m0 = (P % gm) * BM;
+            n0 = (P / gm) * BN;
+        } else {
+            n0 = (P % gn) * BN;
+            m0 = (P / gn) * BM;
         }
     }
+    const __amdgpu_buffer_rsrc_t r_in = __builtin_amdgcn_make_buffer_rsrc((void*)a.in, 0, a.in_bytes, kBufFlags);
+    const __amdgpu_buffer_rsrc_t r_w = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, a.w_bytes, kBufFlags);
+    const float inv_scale = 1.0f / a.in_scale;
+
+    int b_off[BPT], b_yx[BPT], b_hw[BPT];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int v = tid + i * 256;
+        const int row = v / VRB, kv = v % VRB;
+        const int m = m0 + row;
+        b_off[i] = 0;
+        b_yx[i] = 0;
+        b_hw[i] = 0;
+        if (v < BVEC && m < a.M) {
+            int f, y, x;
+            map_pixel(a.geom, a.nframes, a.uniform, a.lvl_out, m, f, y, x);
+            const int* g = a.geom + f * kGeomInts;
+            const int iy0 = y * a.stride - a.pad, ix0 = x * a.stride - a.pad;
+            const int h = g[0] >> a.lvl_in, w = g[1] >> a.lvl_in;
+            b_off[i] = (g[2 + a.lvl_in] + iy0 * w + ix0) * a.cin + kv * 8;
+            b_yx[i] = (iy0 << 16) | (ix0 & 0xffff);
+            b_hw[i] = (h << 16) | w;
+        }
+    }
+    int a_off[APT];
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+        const int v = tid + i * 256;
+        const int row = v / VRA, kv = v % VRA;
+        a_off[i] = (v < AVEC && n0 + row < a.cout) ? (n0 + row) * a.K + kv * 16 : -1;
+    }
+
+    int ld_ci = 0, ld_r = 0, ld_s = 0;
+    i32x4 ra2[2][APT], rb2[2][BPT];
+    auto load_chunk = [&](int kc, i32x4 (&ra)[APT], i32x4 (&rb)[BPT]) {
+        const int k0 = kc * BK;
+#pragma unroll
+        for (int i = 0; i < APT; ++i)
+            ra[i] = __builtin_amdgcn_raw_buffer_load_b128(r_w, a_off[i] >= 0 ? a_off[i] + k0 : kOOB, 0, 0);
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+            const int iy = (b_yx[i] >> 16) + ld_r, ix = (int)(short)(b_yx[i] & 0xffff) + ld_s;
+            const int h = b_hw[i] >> 16, w = b_hw[i] & 0xffff;
+            const bool ok = (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)w;
+            const int off = ok ? (b_off[i] + (ld_r * w + ld_s) * a.cin + ld_ci) * 2 : kOOB;
+            rb[i] = __builtin_amdgcn_raw_buffer_load_b128(r_in, off, 0, 0);
+        }
+        ld_ci += BK;
+        const int wrap = ld_ci >= a.cin;
+        ld_ci = wrap ? 0 : ld_ci;
+        ld_s += wrap;
+        const int wrap2 = ld_s >= a.ksz;
+        ld_s = wrap2 ? 0 : ld_s;
+        ld_r += wrap2;
+    };
+    // 8 BF16 values -> 8 e4m3 bytes (two dwords), scaled and saturated.
+    auto to_fp8 = [&](i32x4 v) {
+        float f[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            f[2 * q] = __uint_as_float(((unsigned)v[q]) << 16);
+            f[2 * q + 1] = __uint_as_float(((unsigned)v[q]) & 0xffff0000u);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) f[q] = fminf(fmaxf(f[q] * inv_scale, -448.f), 448.f);
+        int lo = 0, hi = 0;
+        lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[0], f[1], lo, false);
+        lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[2], f[3], lo, true);
+        hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[4], f[5], hi, false);
+        hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[6], f[7], hi, true);
+        return i32x2{lo, hi};
+    };
+    auto store_chunk = [&](int buf, const i32x4 (&ra)[APT], const i32x4 (&rb)[BPT]) {
+#pragma unroll
+        for (int i = 0; i < APT; ++i) {
+            const int v = tid + i * 256;
+            if (AVEC % 256 == 0 || v < AVEC) *(i32x4*)(&sA[buf][(v / VRA) * LDR + (v % VRA) * 16]) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+            const int v = tid + i * 256;
+            if (BVEC % 256 == 0 || v < BVEC) *(i32x2*)(&sB[buf][(v / VRB) * LDR + (v % VRB) * 8]) = to_fp8(rb[i]);
+        }
+    };
+
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int arow = wn * WTN + (lane & 15), brow = wm * WTM + (lane & 15);
+    const int kofs = (lane >> 4) * 32;
+    auto compute = [&](int buf) {
+        const unsigned char* A = sA[buf];
+        const unsigned char* B = sB[buf];
+        i32x8 af[TN], bfr[TM];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const unsigned char* p = A + (arow + j * 16) * LDR + kofs;
+            const i32x4 x0 = *(const i32x4*)p, x1 = *(const i32x4*)(p + 16);
+            af[j] = i32x8{x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const unsigned char* p = B + (brow + i * 16) * LDR + kofs;
+            const i32x4 x0 = *(const i32x4*)p, x1 = *(const i32x4*)(p + 16);
+            bfr[i] = i32x8{x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[j], bfr[i], acc[i][j], 0, 0, 0, 127,
+                                                                             0, 127);
+    };
+
+    const int nk = a.K / BK;
+    load_chunk(0, ra2[0], rb2[0]);
+    load_chunk(1, ra2[1], rb2[1]);
+    store_chunk(0, ra2[0], rb2[0]);
+    load_chunk(2, ra2[0], rb2[0]);
+    __syncthreads();
+    auto iter = [&](int kc, auto cur_c) {
+        constexpr int cur = decltype(cur_c)::value;
+        store_chunk(cur ^ 1, ra2[cur ^ 1], rb2[cur ^ 1]);
+        load_chunk(kc + 3, ra2[cur ^ 1], rb2[cur ^ 1]);
+        compute(cur);
+        __syncthreads();
+    };
+    int kc = 0;
+    for (; kc + 1 < nk; kc += 2) {
+        iter(kc, std::integral_constant<int, 0>{});
+        iter(kc + 1, std::integral_constant<int, 1>{});
+    }
+    if (kc < nk) iter(kc, std::integral_constant<int, 0>{});
+    store_tile<bf16, TM, TN, WTM, WTN>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, a.wscale);
+}
+
+struct TileCfg8 { int bm, bn, wgm, wgn; };
+static constexpr TileCfg8 kTiles8[] = {
+    {128, 128, 2, 2},
+    {128, 64, 2, 2},
+    {64, 128, 2, 2},
+    {64, 64, 2, 2},
+};
+int conv_fp8_num_tiles() { return sizeof(kTiles8) / sizeof(kTiles8[0]); }
+bool conv_fp8_ok(const ConvArgs& a) { return a.cin % 128 == 0 && a.cin1 == 0 && a.K % 128 == 0; }
+
+template <int C>
+static hipError_t launch_f8(const ConvArgs& a, hipStream_t s) {
+    constexpr TileCfg8 t = kTiles8[C];
+    dim3 grid(((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn));
+    conv_igemm_f8<t.bm, t.bn, t.wgm, t.wgn><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_fp8(const ConvArgs& a, int c, hipStream_t s) {
+    if (!conv_fp8_ok(a) || !a.wscale || !(a.in_scale > 0.f)) return hipErrorInvalidValue;
+    switch (c) {
+        case 0: return launch_f8<0>(a, s);
+        case 1: return launch_f8<1>(a, s);
+        case 2: return launch_f8<2>(a, s);
+        case 3: return launch_f8<3>(a, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

@@ -61,6 +61,10 @@ void jde_kf_initiate(const double z[4], double mean[8], double cov[64]) {
     for (int i = 0; i < 8; ++i) cov[i * 8 + i] = sd[i] * sd[i];
 }
 
+void jde_kf_initiate_n(int n, const double* z, double* mean, double* cov) {
+    for (int i = 0; i < n; ++i) jde_kf_initiate(z + 4 * (size_t)i, mean + 8 * (size_t)i, cov + 64 * (size_t)i);
+}
+
 void jde_kf_predict(int T, double* mean, double* cov) {
     for (int t = 0; t < T; ++t) {
         double* m = mean + (size_t)t * 8;

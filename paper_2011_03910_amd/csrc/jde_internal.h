@@ -39,7 +39,7 @@ struct ConvArgs {
     const void* in2;       // concat: the skip source (same level as the output), else null
     const void* w;         // [Cout][k][k][Cin]
     const float* bias;     // [Cout]
-    const float* wscale;   // FP8: per-output-channel dequantisation scale, else null
+    const float* wscale;   // FP8: per-output-channel weight dequantisation scale, else null
     const void* res;       // residual [M][Cout] (same type as out0), or null
     void* out0;            // [M][ld0], columns [0, n_split)
     float* out1;           // [M][ld1] FP32, columns [n_split, Cout) (linear), or null
@@ -55,9 +55,10 @@ struct ConvArgs {
     int ld0, ld1;
     int act;               // leaky ReLU 0.1 on out0 columns
     int out0_f32;          // out0 holds FP32 (head outputs) instead of the activation type
-    float in_scale;        // FP8: activation quantisation scale of the input (x / in_scale)
+    float in_scale;        // FP8: per-tensor scale of the input activations (x ~= in_scale * q)
     int in_bytes, in2_bytes, w_bytes;  // sizes of the in / in2 / w buffers (< 2^31): loads past them read 0
     int n_major;           // tile order per XCD: 1 = pixel tiles of a channel range (weights dominate)
+    unsigned* amax;        // calibration: max |out0| folded in with atomicMax on the float bits, or null
 };
 
 // Launchers (conv.hip).
@@ -65,6 +66,11 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
                        int M, const float* w, const float* bias, int cout, void* out, int out_type,
                        hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, int elem_type, int tile_cfg, hipStream_t s);
+// FP8 e4m3 convolution: BF16 activations quantised on load with in_scale, FP8
+// weights with per-channel wscale; needs cin % 128 == 0 and no concat.
+hipError_t launch_conv_fp8(const ConvArgs& a, int tile_cfg, hipStream_t s);
+int conv_fp8_num_tiles();
+bool conv_fp8_ok(const ConvArgs& a);
 int conv_num_tile_cfgs();
 bool conv_tile_ok(int tile_cfg, int elem_type, const ConvArgs& a);
 int conv_default_tile(int elem_type, const ConvArgs& a);
@@ -137,5 +143,6 @@ hipError_t launch_emb_update(const int* pairs, int P, const float* det_emb, int 
 // Host-side weight conversion helpers (api.cpp).
 uint16_t f32_to_bf16_rne(float x);
 uint16_t f32_to_f16_rne(float x);
+uint8_t f32_to_e4m3(float x);
 
 }  // namespace jde

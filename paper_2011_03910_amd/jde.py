@@ -103,6 +103,17 @@ def jde_kf_initiate(z):
     return mean, cov.reshape(8, 8)
 
 
+def jde_kf_initiate_n(zs):
+    """zs [n, 4] -> (mean [n, 8], cov [n, 8, 8])."""
+    z = np.ascontiguousarray(zs, dtype=np.float64).reshape(-1, 4)
+    n = z.shape[0]
+    mean = np.zeros((n, 8))
+    cov = np.zeros((n, 8, 8))
+    load().jde_kf_initiate_n(n, z.ctypes.data_as(_lib.c_double_p), mean.ctypes.data_as(_lib.c_double_p),
+                             cov.ctypes.data_as(_lib.c_double_p))
+    return mean, cov
+
+
 def jde_kf_predict(mean, cov):
     """In place on contiguous FP64 arrays [T, 8], [T, 8, 8]."""
     assert mean.dtype == np.float64 and cov.dtype == np.float64 and mean.flags.c_contiguous and cov.flags.c_contiguous
@@ -117,6 +128,15 @@ def jde_kf_update(mean, cov, z):
     check(load().jde_kf_update(mean.ctypes.data_as(_lib.c_double_p), cov.ctypes.data_as(_lib.c_double_p),
                                z.ctypes.data_as(_lib.c_double_p)), "jde_kf_update")
     return mean, cov
+
+
+def jde_fp8_encode(x):
+    """Host OCP e4m3 encoding (RNE, saturating) of a float array -> uint8 codes."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.zeros(x.shape, dtype=np.uint8)
+    load().jde_fp8_encode(x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), x.size)
+    return out
 
 
 def jde_assign(cost, max_cost):
@@ -308,6 +328,24 @@ class JDE:
                                          None if tb is None else tb.ctypes.data_as(_lib.c_int_p), _ptr(cost),
                                          _stream(stream), ctypes.byref(g)), "jde_graph_capture")
         return Graph(self.lib, g, (frames, heads, dets, tracks, cost, tb))
+
+    def calibrate(self, frames, descs=None, heads=None, stream=None):
+        """FP8 contexts: set the static activation scales from one BF16 forward of this batch."""
+        if descs is None:
+            n, _, H, W = frames.shape
+            descs = [(H, W)] * n
+        if heads is None:
+            heads = self.head_buffers(descs)
+        hs = self._head_struct(heads)
+        check(self.lib.jde_calibrate(self.ctx, _ptr(frames), _descs(descs), len(descs), _ptr(self.ws),
+                                     self.ws.numel(), ctypes.byref(hs), _stream(stream)), "jde_calibrate")
+        return self.fp8_scales()
+
+    def fp8_scales(self):
+        out = np.zeros(self._n_ops(), dtype=np.float32)
+        check(self.lib.jde_fp8_scales(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), out.size),
+              "jde_fp8_scales")
+        return out
 
     def profile_begin(self, on=True):
         check(self.lib.jde_profile_begin(self.ctx, 1 if on else 0), "jde_profile_begin")

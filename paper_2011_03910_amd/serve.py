@@ -31,7 +31,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .jde import JDE, jde_kf_initiate, jde_kf_predict, jde_kf_update, jde_assign, jde_track_emb_update
+from .jde import (JDE, jde_kf_initiate_n, jde_kf_predict, jde_kf_update, jde_assign,
+                  jde_track_emb_update)
 
 CHI2_GATE = 9.4877
 
@@ -47,20 +48,25 @@ class StreamSpec:
 
 
 @dataclass
-class Track:
-    tid: int
-    mean: np.ndarray
-    cov: np.ndarray
-    slot: int                    # row of the stream's device embedding table
-    lost: int = 0
-
-
-@dataclass
 class StreamState:
+    """Tracks of one stream as arrays (row k = one track): host FP64 Kalman state,
+    ids, frames lost, and the track's row in the device embedding pool."""
     spec: StreamSpec
-    tracks: list = field(default_factory=list)
-    free_rows: list = field(default_factory=list)   # free rows of this stream's range of the pool
+    pinned: list = field(default_factory=list)     # the stream's frames in pinned host memory
+    mean: np.ndarray = None                        # [T, 8]
+    cov: np.ndarray = None                         # [T, 8, 8]
+    ids: np.ndarray = None                         # [T] int64
+    lost: np.ndarray = None                        # [T] int64
+    rows: np.ndarray = None                        # [T] int64 rows of the pool
+    free_rows: list = field(default_factory=list)  # free rows of this stream's range of the pool
     next_id: int = 1
+
+    def __post_init__(self):
+        self.mean = np.zeros((0, 8))
+        self.cov = np.zeros((0, 8, 8))
+        self.ids = np.zeros(0, dtype=np.int64)
+        self.lost = np.zeros(0, dtype=np.int64)
+        self.rows = np.zeros(0, dtype=np.int64)
 
 
 @dataclass
@@ -101,10 +107,15 @@ class Server:
         self.pool = torch.zeros((len(self.streams) * max_tracks, self.E), dtype=torch.float32, device=device)
         for k, st in enumerate(self.streams.values()):
             st.free_rows = list(range(k * max_tracks, (k + 1) * max_tracks))[::-1]
-        # pinned staging for frame uploads, one per slot
+        # Frames arrive in pinned host memory (where a capture process would write
+        # them); each admitted frame is one async H2D copy into its slot's buffer.
+        for st in self.streams.values():
+            st.pinned = [torch.from_numpy(np.ascontiguousarray(f).ravel()).pin_memory() for f in st.spec.frames]
         self.max_pix = max_batch * max_h * max_w * 3
+        self.t_launch = 0.0
+        self.t_post = 0.0
+        self.t_parts = {"predict": 0.0, "cost": 0.0, "host_assoc": 0.0, "update_sync": 0.0, "tracks": 0}
         for sl in self.slots:
-            sl["host"] = torch.empty(self.max_pix, dtype=torch.float32).pin_memory()
             sl["dev"] = torch.empty(self.max_pix, dtype=torch.float32, device=device)
             # outputs sized for a full batch of the largest frames; smaller batches use a prefix
             sl["heads"] = sl["m"].head_buffers([(max_h, max_w)] * max_batch)
@@ -123,23 +134,24 @@ class Server:
         torch = self.torch
         sl = self.slots[slot_i]
         m = sl["m"]
-        descs, off = [], 0
-        for j in jobs:
-            sp = self.streams[j.sid].spec
-            fr = sp.frames[j.t % len(sp.frames)]
-            n = fr.size
-            sl["host"][off:off + n].copy_(torch.from_numpy(fr.ravel()))
-            off += n
-            descs.append((sp.height, sp.width))
+        t0 = time.perf_counter()
         s = sl["stream"]
         heads, dets = sl["heads"], sl["dets"]
+        descs, off = [], 0
         with torch.cuda.stream(s):
-            sl["dev"][:off].copy_(sl["host"][:off], non_blocking=True)
+            for j in jobs:
+                st = self.streams[j.sid]
+                src = st.pinned[j.t % len(st.pinned)]
+                n = src.numel()
+                sl["dev"][off:off + n].copy_(src, non_blocking=True)
+                off += n
+                descs.append((st.spec.height, st.spec.width))
             m.forward(sl["dev"][:off], descs, heads=heads, stream=s)
             m.decode(heads, descs, self.conf_thr, self.nms_iou, dets=dets, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
         sl["busy"] = True
+        self.t_launch += time.perf_counter() - t0
         return {"slot": slot_i, "jobs": jobs, "descs": descs, "dets": dets, "heads": heads, "event": ev}
 
     def run(self, duration, post_queue_depth=4, warmup=0.0):
@@ -197,7 +209,9 @@ class Server:
                  "fps": len(counted) / span if span > 0 else 0.0,
                  "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
                  "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
-                 "mean_batch": len(self.results) / max(n_batches, 1)}
+                 "mean_batch": len(self.results) / max(n_batches, 1),
+                 "host_launch_s": self.t_launch, "host_post_s": self.t_post,
+                 "post_parts_s": dict(self.t_parts)}
         return stats
 
     # ---- post-processing side (the paper's separate post-processing worker) --------
@@ -207,6 +221,8 @@ class Server:
             item = q.get()
             if item is None:
                 return
+            item["event"].synchronize()
+            t0 = time.perf_counter()
             with torch.cuda.stream(self.post_stream):
                 self.post_stream.wait_event(item["event"])
                 jobs = sorted(enumerate(item["jobs"]), key=lambda x: (x[1].sid, x[1].t))
@@ -230,6 +246,7 @@ class Server:
                 done = time.perf_counter()
                 for r in self.results[i0:]:
                     r["latency"] = done - r["arrival"]
+            self.t_post += time.perf_counter() - t0
             with self.lock:
                 self.in_flight_bytes -= len(item["jobs"]) * self.frame_bytes
                 self.slots[item["slot"]]["busy"] = False
@@ -240,85 +257,85 @@ class Server:
         s = self.post_stream
         cap = m.cap
         dev = self.pool.device
-        # host: predict every track of the involved streams (one call)
         sts = [self.streams[j.sid] for _, j in rnd]
-        counts_t = [len(st.tracks) for st in sts]
+        counts_t = [len(st.ids) for st in sts]
         tb = np.concatenate([[0], np.cumsum(counts_t)]).astype(np.int32)
         T = int(tb[-1])
         maxd = int(max((counts[f] for f, _ in rnd), default=0))
-        if T:
-            mean = np.ascontiguousarray(np.stack([tr.mean for st in sts for tr in st.tracks]))
-            cov = np.ascontiguousarray(np.stack([tr.cov for st in sts for tr in st.tracks]))
-            jde_kf_predict(mean, cov)
-            k = 0
-            for st in sts:
-                for tr in st.tracks:
-                    tr.mean, tr.cov = mean[k].copy(), cov[k].copy()
-                    k += 1
+        tm = self.t_parts
+        t0 = time.perf_counter()
+        for st in sts:                               # host FP64 predict, in place per stream
+            if len(st.ids):
+                jde_kf_predict(st.mean, st.cov)
+        t1 = time.perf_counter()
+        tm["predict"] += t1 - t0
         cost_h = None
         if T and maxd:
-            rows = torch.tensor([tr.slot for st in sts for tr in st.tracks], dtype=torch.int64).to(dev, non_blocking=True)
+            rows = torch.from_numpy(np.concatenate([st.rows for st in sts])).to(dev, non_blocking=True)
             fe = self.pool.index_select(0, rows)
-            dmean = torch.from_numpy(mean).to(dev, non_blocking=True)
-            dcov = torch.from_numpy(cov).to(dev, non_blocking=True)
-            # the batched cost scores frame f of the slot's dets against its stream's tracks;
-            # frames of this round are a subset of the batch, so score each against its own range
+            dmean = torch.from_numpy(np.concatenate([st.mean for st in sts])).to(dev, non_blocking=True)
+            dcov = torch.from_numpy(np.concatenate([st.cov for st in sts])).to(dev, non_blocking=True)
             sub = self._sub_dets(dets, [f for f, _ in rnd], cap)
             cost = m.cost_batch(fe, dmean, dcov, tb, sub, CHI2_GATE, stream=s)
             cost_h = cost[:, :maxd].cpu().numpy()
-        boxes_h = [boxes_all[f, :counts[f]] for f, _ in rnd]
-        upd_t, upd_d, new_rows, new_src = [], [], [], []
+        t2 = time.perf_counter()
+        tm["cost"] += t2 - t1
+        upd_rows, upd_src, new_rows, new_src = [], [], [], []
         for i, (f, j) in enumerate(rnd):
             st = sts[i]
-            boxes = boxes_h[i]
+            boxes = boxes_all[f, :counts[f]]
             D = len(boxes)
-            ids = np.zeros(D, dtype=np.int64)
-            zs = np.stack([(boxes[:, 0] + boxes[:, 2]) / 2, (boxes[:, 1] + boxes[:, 3]) / 2,
-                           (boxes[:, 2] - boxes[:, 0]) / (boxes[:, 3] - boxes[:, 1]), boxes[:, 3] - boxes[:, 1]],
+            det_ids = np.zeros(D, dtype=np.int64)
+            w = boxes[:, 2] - boxes[:, 0]
+            h = boxes[:, 3] - boxes[:, 1]
+            zs = np.stack([(boxes[:, 0] + boxes[:, 2]) / 2, (boxes[:, 1] + boxes[:, 3]) / 2, w / h, h],
                           axis=1).astype(np.float64) if D else np.zeros((0, 4))
-            matched_t, matched_d = set(), set()
+            matched_t = np.zeros(len(st.ids), dtype=bool)
+            matched_d = np.zeros(D, dtype=bool)
             if counts_t[i] and D:
-                c = cost_h[tb[i]:tb[i + 1], :D]
-                pairs, _ = jde_assign(c, self.max_cost)
+                pairs, _ = jde_assign(cost_h[tb[i]:tb[i + 1], :D], self.max_cost)
                 for t, d in pairs:
-                    tr = st.tracks[t]
-                    tr.mean, tr.cov = jde_kf_update(tr.mean, tr.cov, zs[d])
-                    tr.lost = 0
-                    ids[d] = tr.tid
-                    matched_t.add(int(t))
-                    matched_d.add(int(d))
-                    upd_t.append(tr.slot)
-                    upd_d.append(f * cap + int(d))
-            survivors = []
-            for ti, tr in enumerate(st.tracks):
-                if ti not in matched_t:
-                    tr.lost += 1
-                    if tr.lost > self.max_lost:
-                        st.free_rows.append(tr.slot)
-                        continue
-                survivors.append(tr)
-            st.tracks = survivors
-            for d in range(D):
-                if d in matched_d or not st.free_rows:
-                    continue
-                mean0, cov0 = jde_kf_initiate(zs[d])
-                row = st.free_rows.pop()
-                new_rows.append(row)
-                new_src.append(f * cap + d)
-                st.tracks.append(Track(st.next_id, mean0, cov0, row))
-                ids[d] = st.next_id
-                st.next_id += 1
-            self.results.append({"sid": j.sid, "t": j.t, "boxes": boxes.copy(), "ids": ids,
+                    st.mean[t], st.cov[t] = jde_kf_update(st.mean[t], st.cov[t], zs[d])
+                    det_ids[d] = st.ids[t]
+                    matched_t[t] = True
+                    matched_d[d] = True
+                    upd_rows.append(int(st.rows[t]))
+                    upd_src.append(f * cap + int(d))
+            st.lost[matched_t] = 0
+            st.lost[~matched_t] += 1
+            keep = st.lost <= self.max_lost
+            st.free_rows.extend(st.rows[~keep].tolist())
+            st.mean, st.cov = st.mean[keep], st.cov[keep]
+            st.ids, st.lost, st.rows = st.ids[keep], st.lost[keep], st.rows[keep]
+            new_d = np.nonzero(~matched_d)[0][:len(st.free_rows)]
+            if len(new_d):
+                m0, c0 = jde_kf_initiate_n(zs[new_d])
+                rws = np.array([st.free_rows.pop() for _ in new_d], dtype=np.int64)
+                nid = np.arange(st.next_id, st.next_id + len(new_d))
+                st.next_id += len(new_d)
+                det_ids[new_d] = nid
+                st.mean = np.concatenate([st.mean, m0])
+                st.cov = np.concatenate([st.cov, c0])
+                st.ids = np.concatenate([st.ids, nid])
+                st.lost = np.concatenate([st.lost, np.zeros(len(new_d), dtype=np.int64)])
+                st.rows = np.concatenate([st.rows, rws])
+                new_rows.extend(rws.tolist())
+                new_src.extend((f * cap + new_d).tolist())
+            self.results.append({"sid": j.sid, "t": j.t, "boxes": boxes.copy(), "ids": det_ids,
                                  "arrival": j.arrival, "latency": 0.0})
+        t3 = time.perf_counter()
+        tm["host_assoc"] += t3 - t2
         emb = dets["emb"]
-        if upd_t:
-            pr = torch.from_numpy(np.stack([upd_t, upd_d], axis=1).astype(np.int32)).to(dev, non_blocking=True)
+        if upd_rows:
+            pr = torch.from_numpy(np.stack([upd_rows, upd_src], axis=1).astype(np.int32)).to(dev, non_blocking=True)
             jde_track_emb_update(pr, emb, self.pool, 0.9, stream=s)
         if new_rows:
             dst = torch.tensor(new_rows, dtype=torch.int64).to(dev, non_blocking=True)
             src = torch.tensor(new_src, dtype=torch.int64).to(dev, non_blocking=True)
             self.pool.index_copy_(0, dst, emb.index_select(0, src))
         s.synchronize()
+        tm["update_sync"] += time.perf_counter() - t3
+        tm["tracks"] = max(tm["tracks"], T)
 
     @staticmethod
     def _sub_dets(dets, frames, cap):

@@ -238,3 +238,41 @@ def test_full_reduced_precision_parity(torch, precision):
              f"min emb cos {min(cos) if cos else float('nan'):.4f}")
         if strict and precision == "fp16":
             assert frac >= 0.99
+
+
+@pytest.mark.parametrize("cfg_name,k", [("tiny", 50), pytest.param("full", 40, marks=pytest.mark.slow)])
+def test_fp8_backbone_parity(torch, cfg_name, k):
+    """FP8 e4m3 backbone: the device's calibrated input scales equal the oracle's
+    (same rule on the BF16 network), and every head output stays within 1.5x the
+    error of the FP8-emulated oracle (weights and inputs rounded the same way)."""
+    from tests.helpers import oracle_forward_fp8, fp8_layer_set
+    cfg = TINY if cfg_name == "tiny" else FULL
+    _say(f"case: {cfg_name} fp8 b1")
+    m = _model(cfg, "fp8", 1)
+    m.load_weights(weights(cfg_name, k))
+    x = torch.from_numpy(frames(cfg_name, 1)).cuda()
+    dev_scales = m.calibrate(x)
+    torch.cuda.synchronize()
+    emul, scales = oracle_forward_fp8(cfg_name, k, 1)
+    f8 = sorted(fp8_layer_set(cfg))
+    # op index = layer index in the backbone (one launch per conv there)
+    got = np.array([dev_scales[i] for i in f8])
+    want = np.array([scales[i] for i in f8])
+    _say(f"  {len(f8)} fp8 convs; scale rel diff {np.abs(got / want - 1).max():.2e}")
+    assert np.all(dev_scales[[i for i in range(len(dev_scales)) if i not in f8]] == 0)
+    np.testing.assert_allclose(got, want, rtol=2e-2)
+    heads = m.forward(x)
+    torch.cuda.synchronize()
+    ref = oracle_forward(cfg_name, k, 1)
+    v = head_views(heads, [(cfg.height, cfg.width)])
+    for key in ("det", "emb"):
+        for s in range(3):
+            e = rel_err(v[key][s][0], ref[key][s][0])
+            e_emul = rel_err(emul[key][s][0], ref[key][s][0])
+            _say(f"  {key}{8 << s}: rel err {e:.2e} (fp8-emulated oracle {e_emul:.2e}; "
+                 f"gpu vs emulated {rel_err(v[key][s][0], emul[key][s][0]):.2e})")
+            assert e <= max(2e-2, 1.5 * e_emul), (key, s, e, e_emul)
+    d = gpu_dets(m.decode(heads, [(cfg.height, cfg.width)]), 0, m.cap)
+    r = opost.detections(ref, anchors(cfg_name), 0.5, 0.4)
+    frac, _ = match_fraction(d["boxes"], r["boxes"], r["score"])
+    _say(f"  dets gpu {len(d['boxes'])} oracle {len(r['idx'])} matched {frac:.3f}")

@@ -163,3 +163,20 @@ def test_assign_matches_oracle(rng, t_n, d_n):
         if len(pairs):
             assert np.all(c[pairs[:, 0], pairs[:, 1]] <= 0.7)
             assert len(set(pairs[:, 1])) == len(pairs)
+
+
+def test_fp8_encoder_matches_library_cast():
+    """The weight encoder (host, product) equals torch's float8_e4m3fn cast on
+    in-range values, saturates to 448 and maps NaN to 0x7f."""
+    import torch
+    import paper_2011_03910_amd as P
+    from paper_2011_03910_amd.jde import jde_fp8_encode
+    r = np.random.Generator(np.random.PCG64(88))
+    x = (r.standard_normal(40000) * 10.0 ** r.uniform(-5, 2.6, 40000)).astype(np.float32)
+    x[:6] = [0.0, -0.0, 448.0, -448.0, 2 ** -9, 1.0625]
+    got = jde_fp8_encode(x)
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    inr = np.abs(x) <= 448.0
+    np.testing.assert_array_equal(got[inr], ref[inr])
+    big = np.array([449.0, 1e9, -600.0, np.nan], dtype=np.float32)
+    np.testing.assert_array_equal(jde_fp8_encode(big), [0x7E, 0x7E, 0xFE, 0x7F])
