@@ -22,8 +22,11 @@ ARCH = os.environ.get("JDE_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable", "-Wno-unused-lambda-capture"]
+# MFMA accumulators stay in ordinary VGPRs: left to its heuristics the compiler
+# splits them between VGPRs and AGPRs and copies them back and forth inside the
+# K loop (about four copies per MFMA in the implicit GEMM).
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-munsafe-fp-atomics"]
+             "-munsafe-fp-atomics", "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _hipcc():
