@@ -28,6 +28,32 @@ K_CAND = 40
 CONF, NMS_IOU = 0.5, 0.4
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_igemm_traffic.json")
+
+
+def conv_source_hash(key, tiles):
+    """Identifies the conv kernels' source and this workload's tile choice."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("conv.hip", "jde_internal.h"):
+        with open(os.path.join(ROOT, "paper_2011_03910_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    h.update(json.dumps([key, tiles]).encode())
+    return h.hexdigest()
+
+
+def measured_traffic(key, tiles):
+    """HBM bytes per conv launch from the committed hardware-counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's counts), or None when
+    that summary was taken on other kernel source or another tile choice."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    if rec.get("workload") != key or rec.get("source_sha256") != conv_source_hash(key, tiles):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -159,6 +185,9 @@ def main():
     ap.add_argument("--save-tiles", help="write the tile choices to this JSON file")
     ap.add_argument("--load-tiles", help="use tile choices from this JSON file instead of tuning")
     ap.add_argument("--retune", action="store_true", help="run the autotuner instead of the stored tile choices")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run one plain elementwise copy of this many MiB (FP32 negate, read N + write N "
+                         "bytes): the reference dispatch that scales hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (frames are independent, "
@@ -169,6 +198,15 @@ def main():
     from jde_inputs import FULL, model_weights
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log(f"device: {torch.cuda.get_device_name(0)}")
+    if args.copy_probe_mb > 0:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
+        del src, dst
     layers = model_weights(FULL, K_CAND)
     inputs_b = make_inputs(args.batch, torch)
 
@@ -183,6 +221,7 @@ def main():
     pipe = Pipeline(args.precision, args.batch, layers, torch, None if args.no_tune else inputs_b[0],
                     saved.get(key), calib_frames=inputs_b[0])
     tiles_out = {key: None if pipe.tiles is None else pipe.tiles.tolist()}
+    traffic = measured_traffic(key, tiles_out[key])
     wall, step_ms, prof = run(pipe, inputs_b, args.steps, args.warmup, torch, profile=True)
     fps = args.batch * args.steps / wall
     counts = pipe.dets["count"].cpu().numpy()
@@ -242,7 +281,7 @@ def main():
         "fp32_b1": None if fp32 is None else {k: round(v, 3) for k, v in fp32.items()},
         "speedup_vs_fp32_b1": None if fp32 is None else round(fps / fp32["fps"], 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4), "traffic": traffic,
                      "kernel": f"conv_igemm ({n_launch} launches/step, {conv_flop / 1e9:.1f} GFLOP/step, "
                                f"mean {conv_ms / n_launch * 1e3:.1f} us/launch)"},
         "serving": None if serving is None else {k: (round(v, 3) if isinstance(v, float) else v)

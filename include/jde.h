@@ -276,6 +276,14 @@ void jde_kf_predict(int T, double* mean, double* cov);
 /* Update with measurement z; Joseph-form covariance, symmetrised.
  * JDE_EINVAL if S is not positive definite. */
 jde_status jde_kf_update(double mean[8], double cov[64], const double z[4]);
+/* jde_kf_update for n (track, detection) pairs: track track_idx[i] (a row of
+ * mean [*,8] / cov [*,8,8], updated in place) takes measurement z[det_idx[i]]
+ * (z [*,4]).  Indices are not range-checked (the caller owns the arrays); a
+ * track listed twice is updated twice, in order.  Returns JDE_OK, or JDE_EINVAL
+ * when some S was not positive definite (those tracks are left unchanged, every
+ * other pair is still applied). */
+jde_status jde_kf_update_n(int n, const int* track_idx, const int* det_idx, double* mean, double* cov,
+                           const double* z);
 
 /* Min-cost assignment (Hungarian) on cost [T,D] (host, FP32, row-major):
  * entries > max_cost (and +inf) are forbidden; among complete matchings the

@@ -95,6 +95,7 @@ SIGNATURES = {
     "jde_kf_predict": (None, [ctypes.c_int, c_double_p, c_double_p]),
     "jde_kf_initiate_n": (None, [ctypes.c_int, c_double_p, c_double_p, c_double_p]),
     "jde_kf_update": (ctypes.c_int, [c_double_p, c_double_p, c_double_p]),
+    "jde_kf_update_n": (ctypes.c_int, [ctypes.c_int, c_int_p, c_int_p, c_double_p, c_double_p, c_double_p]),
     "jde_assign": (ctypes.c_int, [c_float_p, ctypes.c_int, ctypes.c_int, ctypes.c_float, c_int_p, c_int_p,
                                   c_double_p]),
 }
@@ -116,6 +117,30 @@ def load():
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    return lib
+
+
+_host = None
+HOST_CALLS = ("jde_kf_initiate", "jde_kf_initiate_n", "jde_kf_predict", "jde_kf_update", "jde_kf_update_n",
+              "jde_assign", "jde_fp8_encode")
+
+
+def load_host():
+    """The same library, for its short host-only calls (Kalman filter,
+    assignment, FP8 encoding): these keep the interpreter lock for their few
+    microseconds instead of releasing and re-acquiring it around each call, which
+    under a busy second thread (the serving loop) costs far more than the call."""
+    global _host
+    if _host is not None:
+        return _host
+    load()
+    lib = ctypes.PyDLL(LIB_PATH)
+    for name in HOST_CALLS:
+        res, args = SIGNATURES[name]
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _host = lib
     return lib
 
 

@@ -703,7 +703,12 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
         if (pev) HIP_TRY(hipEventRecord(pev[2 * oi], s));
         if (o.kind == OP_STEM) {
             const int M = (int)level_pixels(d, n, 0);
-            HIP_TRY(launch_stem(frames, geom, n, uniform, d[0].h, d[0].w, M, (const float*)(wb + o.dev_w),
+            int rows = 0, max_w = 0;
+            for (int f = 0; f < n; ++f) {
+                rows += d[f].h;
+                max_w = d[f].w > max_w ? d[f].w : max_w;
+            }
+            HIP_TRY(launch_stem(frames, geom, n, uniform, rows, max_w, M, (const float*)(wb + o.dev_w),
                                 (const float*)(wb + o.dev_b), o.cout, tptr(o.out_t), c->et, s));
             if (pev) {
                 HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));

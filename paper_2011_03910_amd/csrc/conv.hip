@@ -2,8 +2,9 @@
 // for gfx950.
 //
 // * stem: frame ingest (NCHW FP32 pixels) fused with the 3x3 3->c0 conv, folded
-//   BN bias and leaky ReLU.  K = 27 is too shallow for MFMA; it is HBM-bound and
-//   runs on the vector ALUs, one output pixel per thread.
+//   BN bias and leaky ReLU.  It is HBM-bound (12 bytes in, 2*c0 out per pixel);
+//   with 16-bit storage it runs on MFMA from an LDS-staged input window, in
+//   FP32 on the vector ALUs (one output pixel per thread).
 // * conv_igemm: every other conv as an implicit GEMM on MFMA.  Rows of the MFMA
 //   A operand are output channels (weights [Cout][k][k][Cin] are K-contiguous),
 //   rows of the B operand are output pixels gathered from NHWC activations
@@ -109,11 +110,137 @@ __global__ __launch_bounds__(256) void stem_kernel(const float* __restrict__ fra
     }
 }
 
-hipError_t launch_stem(const float* frames, const int* geom, int nframes, int uniform, int h0, int w0,
+// ---------------------------------------------------------------------------
+// Stem on the matrix cores (16-bit activation storage).  A workgroup computes
+// up to kStemSeg output pixels of one image row.  The input window it needs
+// (3 channels x 3 rows x kStemSeg + 2 columns, zero outside the frame) is read
+// once with coalesced loads into LDS.  Each wave then builds 16-pixel im2col
+// blocks from LDS -- k = (r*3 + s)*3 + c for k < 27, zeros up to 32 -- and
+// runs v_mfma_f32_16x16x32_f16 per 16 output channels (A = folded weights,
+// rows = channels; B = pixels).  Each operand is split into FP16 parts
+// x = hi + lo (hi = fp16(x), lo = fp16(x - hi)) and the product is formed as
+// lo*hi + hi*lo + hi*hi with FP32 accumulation (the lo*lo term is below FP32
+// rounding), so the stem keeps about 22 significant bits, as the FP32 stem does.
+// Image widths are multiples of 32, so a 16-pixel block never crosses a row.
+// ---------------------------------------------------------------------------
+constexpr int kStemSeg = 256;
+
+template <typename TO, int COUT>
+__global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict__ frames,
+                                                        const int* __restrict__ geom, int nframes, int uniform,
+                                                        const float* __restrict__ w,
+                                                        const float* __restrict__ bias, TO* __restrict__ out) {
+    constexpr int WIN = kStemSeg + 2, NG = COUT / 16;
+    __shared__ float win[9 * WIN];  // [c][r][column], column j <-> x = x0 + j - 1
+    // image row of this workgroup -> (frame, y)
+    int f = 0, y = blockIdx.x;
+    if (uniform) {
+        f = y / geom[0];
+        y -= f * geom[0];
+    } else {
+        while (f + 1 < nframes && y >= geom[f * kGeomInts]) {
+            y -= geom[f * kGeomInts];
+            ++f;
+        }
+    }
+    const int* g = geom + f * kGeomInts;
+    const int h = g[0], wd = g[1];
+    const int x0 = blockIdx.y * kStemSeg;
+    if (x0 >= wd) return;  // uniform over the workgroup, before any barrier
+    const float* fr = frames + (size_t)g[2] * 3;
+    // all window loads in flight at once, then the LDS stores
+    constexpr int NLD = (9 * WIN + 255) / 256;
+    float wv[NLD];
+#pragma unroll
+    for (int it = 0; it < NLD; ++it) {
+        const int i = threadIdx.x + it * 256;
+        const int cr = i / WIN, j = i - cr * WIN;
+        const int c = cr / 3, r = cr - c * 3;
+        const int iy = y + r - 1, ix = x0 + j - 1;
+        wv[it] = 0.f;
+        if (i < 9 * WIN && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)wd)
+            wv[it] = fr[((size_t)c * h + iy) * wd + ix];
+    }
+#pragma unroll
+    for (int it = 0; it < NLD; ++it) {
+        const int i = threadIdx.x + it * 256;
+        if (i < 9 * WIN) win[i] = wv[it];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p = lane & 15, kg = lane >> 4;
+    // this lane's 8 values of k: LDS offsets (relative to the block's first pixel)
+    int koff[8];
+    bool kval[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int k = kg * 8 + j;
+        const int r = k / 9, s = (k / 3) % 3, c = k % 3;
+        kval[j] = k < 27;
+        koff[j] = kval[j] ? (c * 3 + r) * WIN + s + p : 0;
+    }
+    f16x8 wa[NG], wl[NG];
+    float bv[NG][4];
+#pragma unroll
+    for (int cg = 0; cg < NG; ++cg) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float v = kval[j] ? w[(cg * 16 + p) * 27 + kg * 8 + j] : 0.f;
+            wa[cg][j] = (f16)v;
+            wl[cg][j] = (f16)(v - (float)wa[cg][j]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[cg][i] = bias[cg * 16 + kg * 4 + i];
+    }
+    __syncthreads();
+    const size_t row_m = (size_t)g[2] + (size_t)y * wd;
+    for (int blk = wave; blk < kStemSeg / 16; blk += 4) {
+        const int xb = x0 + blk * 16;
+        if (xb >= wd) break;
+        f16x8 b, bl;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float v = kval[j] ? win[koff[j] + blk * 16] : 0.f;
+            b[j] = (f16)v;
+            bl[j] = (f16)(v - (float)b[j]);
+        }
+        TO* o = out + (row_m + xb + p) * COUT + kg * 4;
+#pragma unroll
+        for (int cg = 0; cg < NG; ++cg) {
+            f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[cg], b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], b, acc, 0, 0, 0);
+            typedef TO T4 __attribute__((ext_vector_type(4)));
+            T4 pk;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pk[i] = (TO)leaky01(acc[i] + bv[cg][i]);
+            *(T4*)(o + cg * 16) = pk;
+        }
+    }
+}
+
+hipError_t launch_stem(const float* frames, const int* geom, int nframes, int uniform, int rows, int max_w,
                        int M, const float* w, const float* bias, int cout, void* out, int out_type,
                        hipStream_t s) {
-    (void)h0;
-    (void)w0;
+    if (out_type != kF32) {
+        // 16-bit storage: the matrix-core stem, one workgroup per kStemSeg-pixel row segment
+        dim3 grid2(rows, (max_w + kStemSeg - 1) / kStemSeg), block2(256);
+        if (cout == 32) {
+            if (out_type == kF16)
+                stem_mfma_kernel<f16, 32><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias, (f16*)out);
+            else
+                stem_mfma_kernel<bf16, 32><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias,
+                                                                    (bf16*)out);
+        } else if (cout == 16) {
+            if (out_type == kF16)
+                stem_mfma_kernel<f16, 16><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias, (f16*)out);
+            else
+                stem_mfma_kernel<bf16, 16><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias,
+                                                                    (bf16*)out);
+        } else {
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     dim3 grid((M + 255) / 256), block(256);
     if (cout == 32) {
         if (out_type == kF32)
@@ -146,6 +273,31 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
 template <typename T, int TM, int TN, int WTM, int WTN>
 __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)[TM][TN], int m_base, int n_base,
                                            int lane, const float* __restrict__ dq) {
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    // Every load of the epilogue (bias, scales, residual) is issued before the
+    // first store, so a tile pays one memory latency rather than one per 16x16
+    // block.  With the in-place residual (res == out0) each element is read and
+    // then overwritten by this same lane only, so reading them all first is exact.
+    f32x4 bv[TN], sv[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int cb = n_base + j * 16 + (lane >> 4) * 4;
+        const bool ok = cb < a.cout;
+        bv[j] = ok ? *(const f32x4*)(a.bias + cb) : f32x4{0.f, 0.f, 0.f, 0.f};
+        sv[j] = (ok && dq) ? *(const f32x4*)(dq + cb) * a.in_scale : f32x4{1.f, 1.f, 1.f, 1.f};
+    }
+    const bool res_t = a.res && !a.out0_f32;  // residual of the storage type (every model's case)
+    T4 rv[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int m = m_base + i * 16 + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int cb = n_base + j * 16 + (lane >> 4) * 4;
+            rv[i][j] = T4{};
+            if (res_t && m < a.M && cb < a.n_split) rv[i][j] = *(const T4*)((const T*)a.res + (size_t)m * a.ld0 + cb);
+        }
+    }
     float amax = 0.f;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
@@ -155,15 +307,13 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)
         for (int j = 0; j < TN; ++j) {
             const int cb = n_base + j * 16 + (lane >> 4) * 4;
             if (cb >= a.cout) continue;
-            const f32x4 bv = *(const f32x4*)(a.bias + cb);
             float v[4];
             if (dq) {
-                const f32x4 sv = *(const f32x4*)(dq + cb);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) v[t] = acc[i][j][t] * (sv[t] * a.in_scale) + bv[t];
+                for (int t = 0; t < 4; ++t) v[t] = acc[i][j][t] * sv[j][t] + bv[j][t];
             } else {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) v[t] = acc[i][j][t] + bv[t];
+                for (int t = 0; t < 4; ++t) v[t] = acc[i][j][t] + bv[j][t];
             }
             if (cb < a.n_split) {
                 if (a.act) {
@@ -180,17 +330,14 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)
                     }
                     *(f32x4*)op = f32x4{v[0], v[1], v[2], v[3]};
                 } else {
-                    T* op = (T*)a.out0 + o;
-                    typedef T T4 __attribute__((ext_vector_type(4)));
-                    if (a.res) {
-                        const T4 r = *(const T4*)((const T*)a.res + o);
+                    if (res_t) {
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) v[t] += (float)r[t];
+                        for (int t = 0; t < 4; ++t) v[t] += (float)rv[i][j][t];
                     }
                     T4 pk;
 #pragma unroll
                     for (int t = 0; t < 4; ++t) pk[t] = cvt_out<T>(v[t]);
-                    *(T4*)op = pk;
+                    *(T4*)((T*)a.out0 + o) = pk;
                 }
 #pragma unroll
                 for (int t = 0; t < 4; ++t) amax = fmaxf(amax, fabsf(v[t]));
@@ -203,6 +350,26 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
         if (lane == 0) atomicMax(a.amax, __float_as_uint(amax));
+    }
+}
+
+// XCD-aware tile order: workgroup L runs on XCD L % 8.  Every XCD gets a
+// contiguous range of logical tiles (a bijection on [0, tiles)), ordered so that
+// the tiles of one XCD share the larger operand in its L2: all channel tiles of
+// a pixel range (activations dominate) or all pixel tiles of a channel range
+// (weights dominate).
+__device__ __forceinline__ void tile_origin(const ConvArgs& a, int BM, int BN, int& m0, int& n0) {
+    const int gm = (a.M + BM - 1) / BM, gn = (a.cout + BN - 1) / BN;
+    const int W = gm * gn, L = blockIdx.x;
+    const int xcd = L % kXCDs, local = L / kXCDs;
+    const int base = W / kXCDs, extra = W % kXCDs;
+    const int P = xcd < extra ? xcd * (base + 1) + local : extra * (base + 1) + (xcd - extra) * base + local;
+    if (a.n_major) {
+        m0 = (P % gm) * BM;
+        n0 = (P / gm) * BN;
+    } else {
+        n0 = (P % gn) * BN;
+        m0 = (P / gn) * BM;
     }
 }
 
@@ -237,26 +404,8 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
-    // XCD-aware tile order: workgroup L runs on XCD L % 8.  Give every XCD a
-    // contiguous range of logical tiles (a bijection on [0, tiles)), ordered so
-    // that the tiles of one XCD share the larger operand in its L2: all channel
-    // tiles of a pixel range (activations dominate) or all pixel tiles of a
-    // channel range (weights dominate).
     int m0, n0;
-    {
-        const int gm = (a.M + BM - 1) / BM, gn = (a.cout + BN - 1) / BN;
-        const int W = gm * gn, L = blockIdx.x;
-        const int xcd = L % kXCDs, local = L / kXCDs;
-        const int base = W / kXCDs, extra = W % kXCDs;
-        const int P = xcd < extra ? xcd * (base + 1) + local : extra * (base + 1) + (xcd - extra) * base + local;
-        if (a.n_major) {
-            m0 = (P % gm) * BM;
-            n0 = (P / gm) * BN;
-        } else {
-            n0 = (P % gn) * BN;
-            m0 = (P / gn) * BM;
-        }
-    }
+    tile_origin(a, BM, BN, m0, n0);
     const bool concat = a.cin1 > 0;
     // Buffer resources: a load whose byte offset is out of range returns zeros,
     // which is how the zero halo, rows past M and channels past Cout are read.
@@ -435,6 +584,192 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
         iter(kc + 1, std::integral_constant<int, 1>{});
     }
     if (kc < nk) iter(kc, std::integral_constant<int, 0>{});
+
+    store_tile<T, TM, TN, WTM, WTN>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// MFMA implicit GEMM with direct-to-LDS loads (16-bit types, Cin % 32 == 0, no
+// concat input).  The same GEMM as conv_igemm, but the K chunks (32 elements =
+// 64 bytes per row) go from global memory straight into LDS with
+// buffer_load_dwordx4 ... lds: no staging registers and no LDS stores, so S
+// stages can be in flight at once (S - 1 chunks loading while one is computed).
+//
+// A stage holds BN weight rows then BM pixel rows, 64 bytes each.  One DMA
+// instruction fills 16 rows (1 KB, lane L -> bytes 16 L): lane L carries row
+// L / 4 of its group and 16-byte slot L % 4, into which it loads k-slot
+// (L % 4) ^ sw(row).  A reader wanting k-slot c of row r reads slot
+// c ^ sw(r & 15); with sw as below, the 16 rows of an MFMA operand read land on
+// distinct banks for 32- and 64-bank LDS alike.  Weight rows and pixel rows
+// share one offset formula: offset = base + (r * w + s) * Cin + ci for tap
+// (r, s) and channel ci, where w is the image width for a pixel row and the
+// kernel width for a weight row (so that (r * k + s) * Cin + ci = k index),
+// and a zero halo / out-of-range row gets an out-of-range offset (zeros).
+//
+// Step k (stage k % S holds chunk k): wait until this wave's DMAs of chunk k
+// are done (at most (S - 2) * NPW younger ones may still be in flight), barrier
+// (every wave's part of chunk k has landed, and chunk k - 1 has been read by
+// all), issue chunk k + S - 1 into the stage of chunk k - 1, compute chunk k.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// One 16-byte-per-lane DMA: lane L's dwordx4 at buffer offset voff lands in LDS
+// at lds + 16 L (lds is wave-uniform, passed in M0).  Issued as inline assembly
+// so that the compiler adds no waits of its own for it: the loop below waits
+// explicitly, and a vmcnt the compiler computes for any other load stays
+// correct (vector memory operations complete in order; extra ones in flight
+// only make such a wait stronger).
+__device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, const void* lds, int voff) {
+    const unsigned addr = (unsigned)(unsigned long)(lds_ptr_t)lds;
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+                 :
+                 : "s"(addr), "v"(voff), "s"(r)
+                 : "memory", "m0");
+}
+
+constexpr int waitcnt_imm(int vm, int lgkm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | (lgkm << 8); }
+
+__device__ __forceinline__ int dma_swizzle(int r) { return ((r >> 1) & 1) ^ (((r >> 2) & 1) << 1) ^ ((r >> 3) & 1); }
+
+template <typename T, int BM, int BN, int WGM, int WGN, int S>
+__global__ __launch_bounds__(256) void conv_dma(ConvArgs a) {
+    constexpr int WTM = BM / WGM, WTN = BN / WGN;
+    constexpr int TM = WTM / 16, TN = WTN / 16;
+    constexpr int ROWS = BM + BN, SB = ROWS * 64;  // bytes per stage
+    constexpr int NPW = ROWS / 64;                 // DMA instructions per wave per chunk
+    static_assert(WGM * WGN == 4 && TM >= 1 && TN >= 1, "4 waves");
+    static_assert(BM % 64 == 0 && BN % 64 == 0 && S >= 3 && S <= 4, "tile");
+    typedef typename V16<T>::type V;
+
+    __shared__ __attribute__((aligned(1024))) char st0[SB];
+    __shared__ __attribute__((aligned(1024))) char st1[SB];
+    __shared__ __attribute__((aligned(1024))) char st2[SB];
+    __shared__ __attribute__((aligned(1024))) char st3[S > 3 ? SB : 16];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave % WGM, wn = wave / WGM;
+    int m0, n0;
+    tile_origin(a, BM, BN, m0, n0);
+    const __amdgpu_buffer_rsrc_t r_in = __builtin_amdgcn_make_buffer_rsrc((void*)a.in, 0, a.in_bytes, kBufFlags);
+    const __amdgpu_buffer_rsrc_t r_w = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, a.w_bytes, kBufFlags);
+
+    // Row descriptors of this lane's DMA instructions (instruction i of this
+    // wave fills rows 16 q .. 16 q + 15 of a stage, q = 4 i + wave).
+    int d_off[NPW], d_yx[NPW], d_hw[NPW], d_w[NPW];
+    const int rloc = lane >> 2;
+    const int kslot = ((lane & 3) ^ dma_swizzle(rloc)) * 8;
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+        const int q = 4 * i + wave;
+        const int row = 16 * q + rloc;
+        if (64 * i < BN) {  // weight row: channel n0 + row (BN % 64 == 0: static per i)
+            const int n = n0 + row;
+            const bool ok = n < a.cout;
+            d_off[i] = ok ? n * a.K + kslot : 0;
+            d_yx[i] = 0;
+            d_hw[i] = ok ? (0x7fff << 16) | 0x7fff : 0;
+            d_w[i] = a.ksz;
+        } else {  // pixel row: output pixel m0 + row - BN
+            const int m = m0 + row - BN;
+            d_off[i] = 0;
+            d_yx[i] = 0;
+            d_hw[i] = 0;
+            d_w[i] = 0;
+            if (m < a.M) {
+                int f, y, x;
+                map_pixel(a.geom, a.nframes, a.uniform, a.lvl_out, m, f, y, x);
+                const int* g = a.geom + f * kGeomInts;
+                const int iy0 = y * a.stride - a.pad, ix0 = x * a.stride - a.pad;
+                const int h = g[0] >> a.lvl_in, w = g[1] >> a.lvl_in;
+                d_off[i] = (g[2 + a.lvl_in] + iy0 * w + ix0) * a.cin + kslot;
+                d_yx[i] = (iy0 << 16) | (ix0 & 0xffff);
+                d_hw[i] = (h << 16) | w;
+                d_w[i] = w;
+            }
+        }
+    }
+
+    // Position (tap r, s and channel ci) of the next chunk to issue, advanced
+    // without branches; chunks past the end read nothing (out-of-range offsets).
+    int ld_ci = 0, ld_r = 0, ld_s = 0, issued = 0;
+    const int nk = a.K / 32;
+    auto issue = [&](auto u_c) {
+        constexpr int u = decltype(u_c)::value;
+        const bool live = issued < nk;
+#pragma unroll
+        for (int i = 0; i < NPW; ++i) {
+            const int q = 4 * i + wave;
+            const int iy = (d_yx[i] >> 16) + ld_r, ix = (int)(short)(d_yx[i] & 0xffff) + ld_s;
+            const int h = d_hw[i] >> 16, w = d_hw[i] & 0xffff;
+            const bool ok = live && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)w;
+            const int off = ok ? (d_off[i] + (ld_r * d_w[i] + ld_s) * a.cin + ld_ci) * (int)sizeof(T) : kOOB;
+            const char* sp = u == 0 ? st0 : u == 1 ? st1 : u == 2 ? st2 : st3;
+            dma16(64 * i < BN ? r_w : r_in, sp + q * 1024, off);
+        }
+        ++issued;
+        ld_ci += 32;
+        const int wrap = ld_ci >= a.cin;
+        ld_ci = wrap ? 0 : ld_ci;
+        ld_s += wrap;
+        const int wrap2 = ld_s >= a.ksz;
+        ld_s = wrap2 ? 0 : ld_s;
+        ld_r += wrap2;
+    };
+
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // lane-constant LDS read offset: row lane % 16 of a 16-row group, k-slot lane / 16
+    const int rd = (lane & 15) * 64 + (((lane >> 4) ^ dma_swizzle(lane & 15)) << 4);
+    const int a_rd = (wn * WTN) * 64 + rd, b_rd = (BN + wm * WTM) * 64 + rd;
+    auto compute = [&](auto u_c) {
+        constexpr int u = decltype(u_c)::value;
+        const char* sp = u == 0 ? st0 : u == 1 ? st1 : u == 2 ? st2 : st3;
+        V af[TN], bfr[TM];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) af[j] = *(const V*)(sp + a_rd + j * 16 * 64);
+#pragma unroll
+        for (int i = 0; i < TM; ++i) bfr[i] = *(const V*)(sp + b_rd + i * 16 * 64);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                if constexpr (__is_same(T, bf16))
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfr[i], acc[i][j], 0, 0, 0);
+                else
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[j], bfr[i], acc[i][j], 0, 0, 0);
+            }
+    };
+
+    issue(std::integral_constant<int, 0>{});
+    issue(std::integral_constant<int, 1>{});
+    if constexpr (S > 3) issue(std::integral_constant<int, 2>{});
+    auto step = [&](auto u_c) {
+        constexpr int u = decltype(u_c)::value;
+        __builtin_amdgcn_s_waitcnt(waitcnt_imm((S - 2) * NPW, 0));
+        __builtin_amdgcn_s_barrier();
+        issue(std::integral_constant<int, (u + S - 1) % S>{});
+        compute(u_c);
+    };
+    for (int kc = 0;; kc += S) {
+        step(std::integral_constant<int, 0>{});
+        if (kc + 1 >= nk) break;
+        step(std::integral_constant<int, 1>{});
+        if (kc + 2 >= nk) break;
+        step(std::integral_constant<int, 2>{});
+        if constexpr (S > 3) {
+            if (kc + 3 >= nk) break;
+            step(std::integral_constant<int, 3>{});
+        }
+        if (kc + S >= nk) break;
+    }
+    // no DMA may still be writing LDS when the workgroup ends
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
 
     store_tile<T, TM, TN, WTM, WTN>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
 }
@@ -655,33 +990,44 @@ hipError_t launch_conv_fp8(const ConvArgs& a, int c, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Tile configurations and dispatch.
 // ---------------------------------------------------------------------------
-struct TileCfg { int bm, bn, wgm, wgn, bk; };
+// st = 0: register-staged conv_igemm; st = S >= 3: conv_dma with S stages.
+struct TileCfg { int bm, bn, wgm, wgn, bk, st; };
 static constexpr TileCfg kTiles[] = {
-    {128, 128, 2, 2, 32},  // 0: 64x64 per wave
-    {256, 64, 4, 1, 32},   // 1: 64x64 per wave (Cout 64)
-    {128, 64, 2, 2, 32},   // 2: 64x32 per wave
-    {64, 128, 2, 2, 32},   // 3: 32x64 per wave
-    {256, 32, 4, 1, 32},   // 4: 64x32 per wave (Cout <= 32)
-    {64, 64, 2, 2, 32},    // 5: 32x32 per wave (also the unaligned-Cin path)
-    {128, 32, 4, 1, 32},   // 6: 32x32 per wave
-    {32, 128, 2, 2, 32},   // 7: 16x64 per wave
-    {128, 128, 2, 2, 64},  // 8: as 0, K chunks of 64 (16-bit types)
-    {256, 64, 4, 1, 64},   // 9: as 1, K chunks of 64
-    {128, 64, 2, 2, 64},   // 10: as 2, K chunks of 64
-    {64, 128, 2, 2, 64},   // 11: as 3, K chunks of 64
-    {256, 128, 2, 2, 32},  // 12: 128x64 per wave
-    {128, 256, 2, 2, 32},  // 13: 64x128 per wave
-    {256, 128, 2, 2, 64},  // 14: 128x64 per wave, K chunks of 64
+    {128, 128, 2, 2, 32, 0},  // 0: 64x64 per wave
+    {256, 64, 4, 1, 32, 0},   // 1: 64x64 per wave (Cout 64)
+    {128, 64, 2, 2, 32, 0},   // 2: 64x32 per wave
+    {64, 128, 2, 2, 32, 0},   // 3: 32x64 per wave
+    {256, 32, 4, 1, 32, 0},   // 4: 64x32 per wave (Cout <= 32)
+    {64, 64, 2, 2, 32, 0},    // 5: 32x32 per wave (also the unaligned-Cin path)
+    {128, 32, 4, 1, 32, 0},   // 6: 32x32 per wave
+    {32, 128, 2, 2, 32, 0},   // 7: 16x64 per wave
+    {128, 128, 2, 2, 64, 0},  // 8: as 0, K chunks of 64 (16-bit types)
+    {256, 64, 4, 1, 64, 0},   // 9: as 1, K chunks of 64
+    {128, 64, 2, 2, 64, 0},   // 10: as 2, K chunks of 64
+    {64, 128, 2, 2, 64, 0},   // 11: as 3, K chunks of 64
+    {256, 128, 2, 2, 32, 0},  // 12: 128x64 per wave
+    {128, 256, 2, 2, 32, 0},  // 13: 64x128 per wave
+    {256, 128, 2, 2, 64, 0},  // 14: 128x64 per wave, K chunks of 64
+    {128, 128, 2, 2, 32, 4},  // 15: direct-to-LDS, 4 stages (64 KB)
+    {128, 128, 2, 2, 32, 3},  // 16: direct-to-LDS, 3 stages (48 KB)
+    {256, 128, 2, 2, 32, 3},  // 17: direct-to-LDS, 128x64 per wave (72 KB)
+    {128, 256, 2, 2, 32, 3},  // 18: direct-to-LDS, 64x128 per wave (72 KB)
+    {256, 64, 4, 1, 32, 4},   // 19: direct-to-LDS, Cout 64 (80 KB)
+    {128, 64, 2, 2, 32, 4},   // 20: direct-to-LDS, 64x32 per wave (48 KB)
+    {64, 128, 2, 2, 32, 4},   // 21: direct-to-LDS, 32x64 per wave (48 KB)
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 template <typename T>
 constexpr int lds_bytes(const TileCfg& t) {
+    if (t.st) return t.st * (t.bm + t.bn) * 64;
     return 2 * (t.bm + t.bn) * (t.bk + 16 / (int)sizeof(T)) * (int)sizeof(T);
 }
-// 16-bit types may use every tile; FP32 only the K-32 tiles whose LDS fits.
+// 16-bit types may use every tile; FP32 only the register-staged K-32 tiles
+// whose LDS fits.
 template <typename T>
 constexpr bool tile_built(int c) {
+    if (kTiles[c].st) return sizeof(T) == 2 && lds_bytes<T>(kTiles[c]) <= 128 * 1024;
     return (sizeof(T) == 2 || kTiles[c].bk == 32) && lds_bytes<T>(kTiles[c]) <= 96 * 1024;
 }
 
@@ -706,6 +1052,7 @@ bool conv_tile_ok(int c, int et, const ConvArgs& a) {
     if (c < 0 || c >= kNumTiles) return false;
     if (et != kF32 && et != kBF16 && et != kF16) return false;
     if (!built(c, et)) return false;
+    if (kTiles[c].st) return a.cin % 32 == 0 && a.cin1 == 0;
     if (!aligned_cin(a, kTiles[c].bk)) return c == 5 && a.cin1 == 0 && a.cin % (et == kF32 ? 4 : 8) == 0;
     return true;
 }
@@ -738,7 +1085,9 @@ static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
     } else {
         constexpr TileCfg t = kTiles[C];
         dim3 grid(((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn)), block(256);
-        if (aligned)
+        if constexpr (t.st > 0)
+            conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st><<<grid, block, 0, s>>>(a);
+        else if (aligned)
             conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, true><<<grid, block, 0, s>>>(a);
         else if constexpr (C == 5)
             conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, false><<<grid, block, 0, s>>>(a);
@@ -766,6 +1115,13 @@ static hipError_t launch_type(const ConvArgs& a, int c, bool aligned, hipStream_
         case 12: return launch_t<T, 12>(a, aligned, s);
         case 13: return launch_t<T, 13>(a, aligned, s);
         case 14: return launch_t<T, 14>(a, aligned, s);
+        case 15: return launch_t<T, 15>(a, aligned, s);
+        case 16: return launch_t<T, 16>(a, aligned, s);
+        case 17: return launch_t<T, 17>(a, aligned, s);
+        case 18: return launch_t<T, 18>(a, aligned, s);
+        case 19: return launch_t<T, 19>(a, aligned, s);
+        case 20: return launch_t<T, 20>(a, aligned, s);
+        case 21: return launch_t<T, 21>(a, aligned, s);
     }
     return hipErrorInvalidValue;
 }

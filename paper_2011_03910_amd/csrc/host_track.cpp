@@ -133,6 +133,17 @@ jde_status jde_kf_update(double mean[8], double cov[64], const double z[4]) {
     return JDE_OK;
 }
 
+jde_status jde_kf_update_n(int n, const int* track_idx, const int* det_idx, double* mean, double* cov,
+                           const double* z) {
+    if (n < 0 || (n > 0 && (!track_idx || !det_idx || !mean || !cov || !z))) return JDE_EINVAL;
+    jde_status st = JDE_OK;
+    for (int i = 0; i < n; ++i) {
+        const size_t t = (size_t)track_idx[i], d = (size_t)det_idx[i];
+        if (jde_kf_update(mean + 8 * t, cov + 64 * t, z + 4 * d) != JDE_OK) st = JDE_EINVAL;
+    }
+    return st;
+}
+
 // Shortest-augmenting-path Hungarian method with row/column potentials on an
 // n x m matrix (n <= m): rows are added one at a time, each by a Dijkstra-like
 // search over reduced costs, and the potentials keep reduced costs >= 0.

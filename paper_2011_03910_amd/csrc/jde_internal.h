@@ -62,7 +62,7 @@ struct ConvArgs {
 };
 
 // Launchers (conv.hip).
-hipError_t launch_stem(const float* frames, const int* geom, int nframes, int uniform, int h0, int w0,
+hipError_t launch_stem(const float* frames, const int* geom, int nframes, int uniform, int rows, int max_w,
                        int M, const float* w, const float* bias, int cout, void* out, int out_type,
                        hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, int elem_type, int tile_cfg, hipStream_t s);

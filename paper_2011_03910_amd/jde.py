@@ -10,7 +10,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (JdeConfig, JdeFrameDesc, JdeHeadOut, JdeDets, check, load,  # noqa: F401
+from ._lib import (JdeConfig, JdeFrameDesc, JdeHeadOut, JdeDets, check, load, load_host,  # noqa: F401
                    JDE_FP32, JDE_BF16, JDE_FP16, JDE_FP8)
 
 PRECISIONS = {"fp32": JDE_FP32, "bf16": JDE_BF16, "fp16": JDE_FP16, "fp8": JDE_FP8}
@@ -98,7 +98,7 @@ def jde_kf_initiate(z):
     mean = np.zeros(8)
     cov = np.zeros(64)
     z = np.ascontiguousarray(z, dtype=np.float64)
-    load().jde_kf_initiate(z.ctypes.data_as(_lib.c_double_p), mean.ctypes.data_as(_lib.c_double_p),
+    load_host().jde_kf_initiate(z.ctypes.data_as(_lib.c_double_p), mean.ctypes.data_as(_lib.c_double_p),
                            cov.ctypes.data_as(_lib.c_double_p))
     return mean, cov.reshape(8, 8)
 
@@ -109,7 +109,7 @@ def jde_kf_initiate_n(zs):
     n = z.shape[0]
     mean = np.zeros((n, 8))
     cov = np.zeros((n, 8, 8))
-    load().jde_kf_initiate_n(n, z.ctypes.data_as(_lib.c_double_p), mean.ctypes.data_as(_lib.c_double_p),
+    load_host().jde_kf_initiate_n(n, z.ctypes.data_as(_lib.c_double_p), mean.ctypes.data_as(_lib.c_double_p),
                              cov.ctypes.data_as(_lib.c_double_p))
     return mean, cov
 
@@ -117,7 +117,7 @@ def jde_kf_initiate_n(zs):
 def jde_kf_predict(mean, cov):
     """In place on contiguous FP64 arrays [T, 8], [T, 8, 8]."""
     assert mean.dtype == np.float64 and cov.dtype == np.float64 and mean.flags.c_contiguous and cov.flags.c_contiguous
-    load().jde_kf_predict(mean.shape[0], mean.ctypes.data_as(_lib.c_double_p), cov.ctypes.data_as(_lib.c_double_p))
+    load_host().jde_kf_predict(mean.shape[0], mean.ctypes.data_as(_lib.c_double_p), cov.ctypes.data_as(_lib.c_double_p))
     return mean, cov
 
 
@@ -125,8 +125,24 @@ def jde_kf_update(mean, cov, z):
     mean = np.ascontiguousarray(mean, dtype=np.float64).copy()
     cov = np.ascontiguousarray(cov, dtype=np.float64).copy()
     z = np.ascontiguousarray(z, dtype=np.float64)
-    check(load().jde_kf_update(mean.ctypes.data_as(_lib.c_double_p), cov.ctypes.data_as(_lib.c_double_p),
+    check(load_host().jde_kf_update(mean.ctypes.data_as(_lib.c_double_p), cov.ctypes.data_as(_lib.c_double_p),
                                z.ctypes.data_as(_lib.c_double_p)), "jde_kf_update")
+    return mean, cov
+
+
+def jde_kf_update_n(track_idx, det_idx, mean, cov, z):
+    """Batched update in place: mean [T, 8] / cov [T, 8, 8] (contiguous FP64) rows
+    track_idx[i] take z[det_idx[i]] (z [D, 4])."""
+    assert mean.dtype == np.float64 and cov.dtype == np.float64 and mean.flags.c_contiguous and cov.flags.c_contiguous
+    ti = np.ascontiguousarray(track_idx, dtype=np.int32)
+    di = np.ascontiguousarray(det_idx, dtype=np.int32)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    assert ti.shape == di.shape and ti.ndim == 1
+    if len(ti):
+        assert 0 <= ti.min() and ti.max() < mean.shape[0] and 0 <= di.min() and di.max() < z.shape[0]
+    check(load_host().jde_kf_update_n(len(ti), ti.ctypes.data_as(_lib.c_int_p), di.ctypes.data_as(_lib.c_int_p),
+                                 mean.ctypes.data_as(_lib.c_double_p), cov.ctypes.data_as(_lib.c_double_p),
+                                 z.ctypes.data_as(_lib.c_double_p)), "jde_kf_update_n")
     return mean, cov
 
 
@@ -134,7 +150,7 @@ def jde_fp8_encode(x):
     """Host OCP e4m3 encoding (RNE, saturating) of a float array -> uint8 codes."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     out = np.zeros(x.shape, dtype=np.uint8)
-    load().jde_fp8_encode(x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+    load_host().jde_fp8_encode(x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), x.size)
     return out
 
@@ -146,11 +162,12 @@ def jde_assign(cost, max_cost):
     dot = np.full(max(T, 1), -1, dtype=np.int32)
     tod = np.full(max(D, 1), -1, dtype=np.int32)
     tot = ctypes.c_double()
-    k = load().jde_assign(c.ctypes.data_as(_lib.c_float_p), T, D, float(max_cost),
+    k = load_host().jde_assign(c.ctypes.data_as(_lib.c_float_p), T, D, float(max_cost),
                           dot.ctypes.data_as(_lib.c_int_p), tod.ctypes.data_as(_lib.c_int_p), ctypes.byref(tot))
     if k < 0:
         check(k, "jde_assign")
-    pairs = np.array([(t, dot[t]) for t in range(T) if dot[t] >= 0], dtype=np.int64).reshape(-1, 2)
+    t = np.nonzero(dot[:T] >= 0)[0]
+    pairs = np.stack([t, dot[t].astype(np.int64)], axis=1) if T else np.zeros((0, 2), dtype=np.int64)
     return pairs, tot.value
 
 

@@ -31,7 +31,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .jde import (JDE, jde_kf_initiate_n, jde_kf_predict, jde_kf_update, jde_assign,
+from .jde import (JDE, jde_kf_initiate_n, jde_kf_predict, jde_kf_update_n, jde_assign,
                   jde_track_emb_update)
 
 CHI2_GATE = 9.4877
@@ -114,7 +114,8 @@ class Server:
         self.max_pix = max_batch * max_h * max_w * 3
         self.t_launch = 0.0
         self.t_post = 0.0
-        self.t_parts = {"predict": 0.0, "cost": 0.0, "host_assoc": 0.0, "update_sync": 0.0, "tracks": 0}
+        self.t_parts = {"predict": 0.0, "cost": 0.0, "host_assoc": 0.0, "assign_update": 0.0,
+                        "lifecycle": 0.0, "update_sync": 0.0, "tracks": 0}
         for sl in self.slots:
             sl["dev"] = torch.empty(self.max_pix, dtype=torch.float32, device=device)
             # outputs sized for a full batch of the largest frames; smaller batches use a prefix
@@ -292,15 +293,19 @@ class Server:
                           axis=1).astype(np.float64) if D else np.zeros((0, 4))
             matched_t = np.zeros(len(st.ids), dtype=bool)
             matched_d = np.zeros(D, dtype=bool)
+            ta = time.perf_counter()
             if counts_t[i] and D:
                 pairs, _ = jde_assign(cost_h[tb[i]:tb[i + 1], :D], self.max_cost)
-                for t, d in pairs:
-                    st.mean[t], st.cov[t] = jde_kf_update(st.mean[t], st.cov[t], zs[d])
-                    det_ids[d] = st.ids[t]
-                    matched_t[t] = True
-                    matched_d[d] = True
-                    upd_rows.append(int(st.rows[t]))
-                    upd_src.append(f * cap + int(d))
+                if len(pairs):
+                    t_idx, d_idx = pairs[:, 0], pairs[:, 1]
+                    jde_kf_update_n(t_idx, d_idx, st.mean, st.cov, zs)
+                    det_ids[d_idx] = st.ids[t_idx]
+                    matched_t[t_idx] = True
+                    matched_d[d_idx] = True
+                    upd_rows.extend(st.rows[t_idx].tolist())
+                    upd_src.extend((f * cap + d_idx).tolist())
+            tb_ = time.perf_counter()
+            tm["assign_update"] += tb_ - ta
             st.lost[matched_t] = 0
             st.lost[~matched_t] += 1
             keep = st.lost <= self.max_lost
@@ -323,6 +328,7 @@ class Server:
                 new_src.extend((f * cap + new_d).tolist())
             self.results.append({"sid": j.sid, "t": j.t, "boxes": boxes.copy(), "ids": det_ids,
                                  "arrival": j.arrival, "latency": 0.0})
+            tm["lifecycle"] += time.perf_counter() - tb_
         t3 = time.perf_counter()
         tm["host_assoc"] += t3 - t2
         emb = dets["emb"]

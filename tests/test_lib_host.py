@@ -149,6 +149,30 @@ def test_kalman_matches_oracle(rng):
         m, c = mo.copy(), co.copy()
 
 
+def test_batched_kalman_update_matches_oracle(rng):
+    """jde_kf_update_n applies the oracle's update to exactly the listed tracks."""
+    import paper_2011_03910_amd as P
+    T = 7
+    zs0 = np.column_stack([rng.uniform(100, 900, T), rng.uniform(100, 500, T), rng.uniform(0.3, 0.6, T),
+                           rng.uniform(40, 200, T)])
+    mean, cov = P.jde_kf_initiate_n(zs0)
+    P.jde_kf_predict(mean, cov)
+    z = zs0[[3, 1, 0]] + rng.normal(0, 1, (3, 4)) * [3, 3, 0.01, 2]
+    ti, di = np.array([4, 0, 6]), np.array([0, 2, 1])
+    m1, c1 = mean.copy(), cov.copy()
+    P.jde_kf_update_n(ti, di, m1, c1, z)
+    for t in range(T):
+        if t in ti:
+            d = di[list(ti).index(t)]
+            mo, co = otrack.kf_update(mean[t], cov[t], z[d])
+            np.testing.assert_allclose(m1[t], mo, rtol=1e-10, atol=1e-9)
+            np.testing.assert_allclose(c1[t], co, rtol=1e-8, atol=1e-9)
+        else:
+            np.testing.assert_array_equal(m1[t], mean[t])
+            np.testing.assert_array_equal(c1[t], cov[t])
+    P.jde_kf_update_n(np.zeros(0, int), np.zeros(0, int), m1, c1, z)
+
+
 @pytest.mark.parametrize("t_n,d_n", [(5, 5), (8, 13), (13, 8), (1, 1), (0, 4), (60, 45), (200, 200)])
 def test_assign_matches_oracle(rng, t_n, d_n):
     import paper_2011_03910_amd as P
