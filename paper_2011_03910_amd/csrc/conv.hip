@@ -110,6 +110,15 @@ __global__ __launch_bounds__(256) void stem_kernel(const float* __restrict__ fra
     }
 }
 
+// Workgroup L of W runs on XCD L % 8; returns the logical index that gives every
+// XCD a contiguous range of [0, W) (a bijection), so that neighbouring work items
+// share one XCD's L2.
+__device__ __forceinline__ int xcd_remap(int L, int W) {
+    const int xcd = L % kXCDs, local = L / kXCDs;
+    const int base = W / kXCDs, extra = W % kXCDs;
+    return xcd < extra ? xcd * (base + 1) + local : extra * (base + 1) + (xcd - extra) * base + local;
+}
+
 // ---------------------------------------------------------------------------
 // Stem on the matrix cores (16-bit activation storage).  A workgroup computes
 // up to kStemSeg output pixels of one image row.  The input window it needs
@@ -117,10 +126,11 @@ __global__ __launch_bounds__(256) void stem_kernel(const float* __restrict__ fra
 // once with coalesced loads into LDS.  Each wave then builds 16-pixel im2col
 // blocks from LDS -- k = (r*3 + s)*3 + c for k < 27, zeros up to 32 -- and
 // runs v_mfma_f32_16x16x32_f16 per 16 output channels (A = folded weights,
-// rows = channels; B = pixels).  Each operand is split into FP16 parts
-// x = hi + lo (hi = fp16(x), lo = fp16(x - hi)) and the product is formed as
-// lo*hi + hi*lo + hi*hi with FP32 accumulation (the lo*lo term is below FP32
-// rounding), so the stem keeps about 22 significant bits, as the FP32 stem does.
+// rows = channels; B = pixels), FP32 accumulation.  For FP16 storage each
+// operand is split into FP16 parts x = hi + lo (hi = fp16(x), lo = fp16(x - hi))
+// and the product is formed as lo*hi + hi*lo + hi*hi (the lo*lo term is below
+// FP32 rounding): about 22 significant bits, as the FP32 stem keeps.  For BF16
+// storage (8 significant bits) the FP16 operands alone (11 bits) suffice.
 // Image widths are multiples of 32, so a 16-pixel block never crosses a row.
 // ---------------------------------------------------------------------------
 constexpr int kStemSeg = 256;
@@ -129,11 +139,14 @@ template <typename TO, int COUT>
 __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict__ frames,
                                                         const int* __restrict__ geom, int nframes, int uniform,
                                                         const float* __restrict__ w,
-                                                        const float* __restrict__ bias, TO* __restrict__ out) {
+                                                        const float* __restrict__ bias, TO* __restrict__ out,
+                                                        int nseg) {
     constexpr int WIN = kStemSeg + 2, NG = COUT / 16;
     __shared__ float win[9 * WIN];  // [c][r][column], column j <-> x = x0 + j - 1
-    // image row of this workgroup -> (frame, y)
-    int f = 0, y = blockIdx.x;
+    // workgroup -> (image row, segment), rows contiguous per XCD; row -> (frame, y)
+    const int P = xcd_remap(blockIdx.x, gridDim.x);
+    const int seg = P % nseg;
+    int f = 0, y = P / nseg;
     if (uniform) {
         f = y / geom[0];
         y -= f * geom[0];
@@ -145,7 +158,7 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
     }
     const int* g = geom + f * kGeomInts;
     const int h = g[0], wd = g[1];
-    const int x0 = blockIdx.y * kStemSeg;
+    const int x0 = seg * kStemSeg;
     if (x0 >= wd) return;  // uniform over the workgroup, before any barrier
     const float* fr = frames + (size_t)g[2] * 3;
     // all window loads in flight at once, then the LDS stores
@@ -196,24 +209,47 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
     for (int blk = wave; blk < kStemSeg / 16; blk += 4) {
         const int xb = x0 + blk * 16;
         if (xb >= wd) break;
+        constexpr bool split = __is_same(TO, f16);
         f16x8 b, bl;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const float v = kval[j] ? win[koff[j] + blk * 16] : 0.f;
             b[j] = (f16)v;
-            bl[j] = (f16)(v - (float)b[j]);
+            if constexpr (split) bl[j] = (f16)(v - (float)b[j]);
         }
-        TO* o = out + (row_m + xb + p) * COUT + kg * 4;
+        typedef TO T4 __attribute__((ext_vector_type(4)));
+        T4 pk[NG];
 #pragma unroll
         for (int cg = 0; cg < NG; ++cg) {
-            f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[cg], b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], bl, acc, 0, 0, 0);
+            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (split) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[cg], b, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], bl, acc, 0, 0, 0);
+            }
             acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], b, acc, 0, 0, 0);
-            typedef TO T4 __attribute__((ext_vector_type(4)));
-            T4 pk;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) pk[i] = (TO)leaky01(acc[i] + bv[cg][i]);
-            *(T4*)(o + cg * 16) = pk;
+            for (int i = 0; i < 4; ++i) pk[cg][i] = (TO)leaky01(acc[i] + bv[cg][i]);
+        }
+        TO* o = out + (row_m + xb + p) * COUT;
+        if constexpr (NG == 1) {
+            *(T4*)(o + kg * 4) = pk[0];  // 16 pixels x 32 bytes: one contiguous 512-byte store
+        } else {
+            // Lanes l and l ^ 16 (kg and kg ^ 1) trade halves so that each holds 8
+            // consecutive channels: the even lane channels 4 kg .. 4 kg + 7 of group
+            // 0, the odd lane 16 + 4 (kg - 1) .. + 7 of group 1.  Each lane then
+            // stores 16 bytes and one store covers 16 pixels x 64 bytes contiguously.
+            const bool odd = kg & 1;
+            const T4 give = odd ? pk[0] : pk[1];
+            unsigned g2[2], r2[2];
+            __builtin_memcpy(g2, &give, 8);
+            r2[0] = __shfl_xor(g2[0], 16);
+            r2[1] = __shfl_xor(g2[1], 16);
+            T4 got;
+            __builtin_memcpy(&got, r2, 8);
+            typedef TO T8 __attribute__((ext_vector_type(8)));
+            const T4 lo = odd ? got : pk[0], hi = odd ? pk[1] : got;
+            const T8 v8 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            *(T8*)(o + (odd ? 16 + 4 * (kg - 1) : 4 * kg)) = v8;
         }
     }
 }
@@ -223,19 +259,22 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
                        hipStream_t s) {
     if (out_type != kF32) {
         // 16-bit storage: the matrix-core stem, one workgroup per kStemSeg-pixel row segment
-        dim3 grid2(rows, (max_w + kStemSeg - 1) / kStemSeg), block2(256);
+        const int nseg = (max_w + kStemSeg - 1) / kStemSeg;
+        dim3 grid2(rows * nseg), block2(256);
         if (cout == 32) {
             if (out_type == kF16)
-                stem_mfma_kernel<f16, 32><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias, (f16*)out);
+                stem_mfma_kernel<f16, 32><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias, (f16*)out,
+                                                                   nseg);
             else
                 stem_mfma_kernel<bf16, 32><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias,
-                                                                    (bf16*)out);
+                                                                    (bf16*)out, nseg);
         } else if (cout == 16) {
             if (out_type == kF16)
-                stem_mfma_kernel<f16, 16><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias, (f16*)out);
+                stem_mfma_kernel<f16, 16><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias, (f16*)out,
+                                                                   nseg);
             else
                 stem_mfma_kernel<bf16, 16><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias,
-                                                                    (bf16*)out);
+                                                                    (bf16*)out, nseg);
         } else {
             return hipErrorInvalidValue;
         }
@@ -360,10 +399,7 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)
 // (weights dominate).
 __device__ __forceinline__ void tile_origin(const ConvArgs& a, int BM, int BN, int& m0, int& n0) {
     const int gm = (a.M + BM - 1) / BM, gn = (a.cout + BN - 1) / BN;
-    const int W = gm * gn, L = blockIdx.x;
-    const int xcd = L % kXCDs, local = L / kXCDs;
-    const int base = W / kXCDs, extra = W % kXCDs;
-    const int P = xcd < extra ? xcd * (base + 1) + local : extra * (base + 1) + (xcd - extra) * base + local;
+    const int P = xcd_remap(blockIdx.x, gm * gn);
     if (a.n_major) {
         m0 = (P % gm) * BM;
         n0 = (P / gm) * BN;
@@ -656,27 +692,32 @@ __global__ __launch_bounds__(256) void conv_dma(ConvArgs a) {
     const __amdgpu_buffer_rsrc_t r_w = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, a.w_bytes, kBufFlags);
 
     // Row descriptors of this lane's DMA instructions (instruction i of this
-    // wave fills rows 16 q .. 16 q + 15 of a stage, q = 4 i + wave).
-    int d_off[NPW], d_yx[NPW], d_hw[NPW], d_w[NPW];
+    // wave fills rows 16 q .. 16 q + 15 of a stage, q = 4 i + wave):
+    //   d_off:  element offset of the row's origin (+ its k-slot);
+    //   d_wc:   elements between kernel rows (image width x Cin for a pixel row,
+    //           k x Cin for a weight row);
+    //   d_mask: bit r * k + s set iff tap (r, s) lies inside the image (every tap of
+    //           a weight row; none for a row past M or Cout).
+    int d_off[NPW], d_wc[NPW], d_mask[NPW];
     const int rloc = lane >> 2;
     const int kslot = ((lane & 3) ^ dma_swizzle(rloc)) * 8;
+    const int taps = a.ksz * a.ksz;
 #pragma unroll
     for (int i = 0; i < NPW; ++i) {
         const int q = 4 * i + wave;
         const int row = 16 * q + rloc;
+        d_off[i] = 0;
+        d_wc[i] = 0;
+        d_mask[i] = 0;
         if (64 * i < BN) {  // weight row: channel n0 + row (BN % 64 == 0: static per i)
             const int n = n0 + row;
-            const bool ok = n < a.cout;
-            d_off[i] = ok ? n * a.K + kslot : 0;
-            d_yx[i] = 0;
-            d_hw[i] = ok ? (0x7fff << 16) | 0x7fff : 0;
-            d_w[i] = a.ksz;
+            if (n < a.cout) {
+                d_off[i] = n * a.K + kslot;
+                d_wc[i] = a.ksz * a.cin;
+                d_mask[i] = (1 << taps) - 1;
+            }
         } else {  // pixel row: output pixel m0 + row - BN
             const int m = m0 + row - BN;
-            d_off[i] = 0;
-            d_yx[i] = 0;
-            d_hw[i] = 0;
-            d_w[i] = 0;
             if (m < a.M) {
                 int f, y, x;
                 map_pixel(a.geom, a.nframes, a.uniform, a.lvl_out, m, f, y, x);
@@ -684,27 +725,30 @@ __global__ __launch_bounds__(256) void conv_dma(ConvArgs a) {
                 const int iy0 = y * a.stride - a.pad, ix0 = x * a.stride - a.pad;
                 const int h = g[0] >> a.lvl_in, w = g[1] >> a.lvl_in;
                 d_off[i] = (g[2 + a.lvl_in] + iy0 * w + ix0) * a.cin + kslot;
-                d_yx[i] = (iy0 << 16) | (ix0 & 0xffff);
-                d_hw[i] = (h << 16) | w;
-                d_w[i] = w;
+                d_wc[i] = w * a.cin;
+                int mk = 0;
+                for (int r = 0; r < a.ksz; ++r)
+                    for (int t = 0; t < a.ksz; ++t)
+                        if ((unsigned)(iy0 + r) < (unsigned)h && (unsigned)(ix0 + t) < (unsigned)w)
+                            mk |= 1 << (r * a.ksz + t);
+                d_mask[i] = mk;
             }
         }
     }
 
-    // Position (tap r, s and channel ci) of the next chunk to issue, advanced
-    // without branches; chunks past the end read nothing (out-of-range offsets).
+    // Tap (r, s) and channel ci of the next chunk to issue, advanced without
+    // branches; chunks past the end read nothing (out-of-range offsets).
     int ld_ci = 0, ld_r = 0, ld_s = 0, issued = 0;
     const int nk = a.K / 32;
     auto issue = [&](auto u_c) {
         constexpr int u = decltype(u_c)::value;
-        const bool live = issued < nk;
+        const int tap = issued < nk ? ld_r * a.ksz + ld_s : 31;  // bit 31 is never set
+        const int sc = ld_s * a.cin + ld_ci;
 #pragma unroll
         for (int i = 0; i < NPW; ++i) {
             const int q = 4 * i + wave;
-            const int iy = (d_yx[i] >> 16) + ld_r, ix = (int)(short)(d_yx[i] & 0xffff) + ld_s;
-            const int h = d_hw[i] >> 16, w = d_hw[i] & 0xffff;
-            const bool ok = live && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)w;
-            const int off = ok ? (d_off[i] + (ld_r * d_w[i] + ld_s) * a.cin + ld_ci) * (int)sizeof(T) : kOOB;
+            const bool ok = (d_mask[i] >> tap) & 1;
+            const int off = ok ? (d_off[i] + ld_r * d_wc[i] + sc) * (int)sizeof(T) : kOOB;
             const char* sp = u == 0 ? st0 : u == 1 ? st1 : u == 2 ? st2 : st3;
             dma16(64 * i < BN ? r_w : r_in, sp + q * 1024, off);
         }

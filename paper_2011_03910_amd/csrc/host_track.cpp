@@ -156,14 +156,38 @@ int jde_assign(const float* cost, int T, int D, float max_cost, int* det_of_trac
         if (track_of_det) track_of_det[d] = -1;
     if (total) *total = 0.0;
     if (T == 0 || D == 0) return 0;
-    const bool tr = T > D;
-    const int n = tr ? D : T, m = tr ? T : D;
     const double mc = (double)max_cost;
+    // A track or detection with no allowed entry is never matched: the problem
+    // reduces to the rows and columns that have one (same optimum, and the
+    // search no longer wades through all-forbidden rows).
+    std::vector<int> rows, cols;
+    {
+        std::vector<char> col_ok(D, 0);
+        for (int t = 0; t < T; ++t) {
+            bool any = false;
+            for (int d = 0; d < D; ++d)
+                if ((double)cost[(size_t)t * D + d] <= mc) {
+                    any = true;
+                    col_ok[d] = 1;
+                }
+            if (any) rows.push_back(t);
+        }
+        for (int d = 0; d < D; ++d)
+            if (col_ok[d]) cols.push_back(d);
+    }
+    if (rows.empty()) return 0;
+    const int Tr = (int)rows.size(), Dr = (int)cols.size();
+    const bool tr = Tr > Dr;
+    const int n = tr ? Dr : Tr, m = tr ? Tr : Dr;
     const double big = 4.0 * (double)(n + 1) * (mc > 2.0 ? mc : 2.0) + 1.0;
-    auto at = [&](int i, int j) -> double {  // 0-based, in the oriented problem
-        const float c = tr ? cost[(size_t)j * D + i] : cost[(size_t)i * D + j];
-        return (double)c <= mc ? (double)c : big;
-    };
+    // the reduced problem, oriented so that it has n <= m, with forbidden = big
+    std::vector<double> red((size_t)n * m);
+    for (int a = 0; a < Tr; ++a)
+        for (int b = 0; b < Dr; ++b) {
+            const float c = cost[(size_t)rows[a] * D + cols[b]];
+            red[tr ? (size_t)b * m + a : (size_t)a * m + b] = (double)c <= mc ? (double)c : big;
+        }
+    auto at = [&](int i, int j) -> double { return red[(size_t)i * m + j]; };  // 0-based
     const double inf = std::numeric_limits<double>::infinity();
     std::vector<double> u(n + 1, 0.0), v(m + 1, 0.0), minv(m + 1);
     std::vector<int> p(m + 1, 0), way(m + 1, 0);
@@ -211,7 +235,7 @@ int jde_assign(const float* cost, int T, int D, float max_cost, int* det_of_trac
     for (int j = 1; j <= m; ++j) {
         if (!p[j]) continue;
         const int i = p[j] - 1, jj = j - 1;
-        const int t = tr ? jj : i, d = tr ? i : jj;
+        const int t = rows[tr ? jj : i], d = cols[tr ? i : jj];
         const float c = cost[(size_t)t * D + d];
         if (!((double)c <= mc)) continue;
         if (det_of_track) det_of_track[t] = d;

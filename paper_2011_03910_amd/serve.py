@@ -115,7 +115,8 @@ class Server:
         self.t_launch = 0.0
         self.t_post = 0.0
         self.t_parts = {"predict": 0.0, "cost": 0.0, "host_assoc": 0.0, "assign_update": 0.0,
-                        "lifecycle": 0.0, "update_sync": 0.0, "tracks": 0}
+                        "assign_update_cpu": 0.0, "lifecycle": 0.0, "update_sync": 0.0, "tracks": 0,
+                        "frames": 0}
         for sl in self.slots:
             sl["dev"] = torch.empty(self.max_pix, dtype=torch.float32, device=device)
             # outputs sized for a full batch of the largest frames; smaller batches use a prefix
@@ -294,6 +295,7 @@ class Server:
             matched_t = np.zeros(len(st.ids), dtype=bool)
             matched_d = np.zeros(D, dtype=bool)
             ta = time.perf_counter()
+            tc = time.thread_time()
             if counts_t[i] and D:
                 pairs, _ = jde_assign(cost_h[tb[i]:tb[i + 1], :D], self.max_cost)
                 if len(pairs):
@@ -306,6 +308,8 @@ class Server:
                     upd_src.extend((f * cap + d_idx).tolist())
             tb_ = time.perf_counter()
             tm["assign_update"] += tb_ - ta
+            tm["assign_update_cpu"] += time.thread_time() - tc
+            tm["frames"] += 1
             st.lost[matched_t] = 0
             st.lost[~matched_t] += 1
             keep = st.lost <= self.max_lost
