@@ -120,18 +120,25 @@ __device__ __forceinline__ int xcd_remap(int L, int W) {
 }
 
 // ---------------------------------------------------------------------------
-// Stem on the matrix cores (16-bit activation storage).  A workgroup computes
-// up to kStemSeg output pixels of one image row.  The input window it needs
-// (3 channels x 3 rows x kStemSeg + 2 columns, zero outside the frame) is read
-// once with coalesced loads into LDS.  Each wave then builds 16-pixel im2col
-// blocks from LDS -- k = (r*3 + s)*3 + c for k < 27, zeros up to 32 -- and
-// runs v_mfma_f32_16x16x32_f16 per 16 output channels (A = folded weights,
-// rows = channels; B = pixels), FP32 accumulation.  For FP16 storage each
-// operand is split into FP16 parts x = hi + lo (hi = fp16(x), lo = fp16(x - hi))
-// and the product is formed as lo*hi + hi*lo + hi*hi (the lo*lo term is below
-// FP32 rounding): about 22 significant bits, as the FP32 stem keeps.  For BF16
-// storage (8 significant bits) the FP16 operands alone (11 bits) suffice.
-// Image widths are multiples of 32, so a 16-pixel block never crosses a row.
+// Stem on the matrix cores (16-bit activation storage).  Work items are
+// segments of up to kStemSeg output pixels of one image row; a persistent
+// workgroup walks items P = blockIdx.x + t * gridDim.x (neighbouring workgroups
+// write neighbouring memory at any moment).  For each item the input window it
+// needs (3 channels x 3 rows x kStemSeg + 2 columns, zero outside the frame) is
+// read with coalesced loads -- the next item's window is loaded into registers
+// while the current one is computed -- and parked in LDS (double-buffered).
+// Each wave then builds 16-pixel im2col blocks from LDS -- k = (r*3 + s)*3 + c
+// for k < 27, zeros up to 32 -- and runs v_mfma_f32_16x16x32_f16 per 16 output
+// channels (A = folded weights, rows = channels; B = pixels), FP32
+// accumulation.  For FP16 storage each operand is split into FP16 parts
+// x = hi + lo (hi = fp16(x), lo = fp16(x - hi)) and the product is formed as
+// lo*hi + hi*lo + hi*hi (the lo*lo term is below FP32 rounding): about 22
+// significant bits, as the FP32 stem keeps.  For BF16 storage (8 significant
+// bits) the FP16 operands alone (11 bits) suffice.  The output is written with
+// streaming (non-temporal) 16-byte stores: it is far larger than the caches and
+// is next read by the following layer, so keeping it out of L2 leaves the L2 to
+// the frames.  Image widths are multiples of 32, so a 16-pixel block never
+// crosses a row.
 // ---------------------------------------------------------------------------
 constexpr int kStemSeg = 256;
 
@@ -140,45 +147,51 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
                                                         const int* __restrict__ geom, int nframes, int uniform,
                                                         const float* __restrict__ w,
                                                         const float* __restrict__ bias, TO* __restrict__ out,
-                                                        int nseg) {
+                                                        int nseg, int total) {
     constexpr int WIN = kStemSeg + 2, NG = COUT / 16;
-    __shared__ float win[9 * WIN];  // [c][r][column], column j <-> x = x0 + j - 1
-    // workgroup -> (image row, segment), rows contiguous per XCD; row -> (frame, y)
-    const int P = xcd_remap(blockIdx.x, gridDim.x);
-    const int seg = P % nseg;
-    int f = 0, y = P / nseg;
-    if (uniform) {
-        f = y / geom[0];
-        y -= f * geom[0];
-    } else {
-        while (f + 1 < nframes && y >= geom[f * kGeomInts]) {
-            y -= geom[f * kGeomInts];
-            ++f;
+    constexpr bool split = __is_same(TO, f16);
+    __shared__ float win[2][9 * WIN];  // [buffer][c][r][column], column j <-> x = x0 + j - 1
+    // item P -> frame f, row y, first column x0 (x0 >= width: nothing to do)
+    auto locate = [&](int P, int& f, int& y, int& x0) {
+        x0 = (P % nseg) * kStemSeg;
+        y = P / nseg;
+        f = 0;
+        if (uniform) {
+            f = y / geom[0];
+            y -= f * geom[0];
+        } else {
+            while (f + 1 < nframes && y >= geom[f * kGeomInts]) {
+                y -= geom[f * kGeomInts];
+                ++f;
+            }
         }
-    }
-    const int* g = geom + f * kGeomInts;
-    const int h = g[0], wd = g[1];
-    const int x0 = seg * kStemSeg;
-    if (x0 >= wd) return;  // uniform over the workgroup, before any barrier
-    const float* fr = frames + (size_t)g[2] * 3;
-    // all window loads in flight at once, then the LDS stores
+    };
     constexpr int NLD = (9 * WIN + 255) / 256;
     float wv[NLD];
+    auto load = [&](int P) {  // every load of the window in flight at once
+        int f, y, x0;
+        locate(P, f, y, x0);
+        const int* g = geom + f * kGeomInts;
+        const int h = g[0], wd = g[1];
+        const float* fr = frames + (size_t)g[2] * 3;
 #pragma unroll
-    for (int it = 0; it < NLD; ++it) {
-        const int i = threadIdx.x + it * 256;
-        const int cr = i / WIN, j = i - cr * WIN;
-        const int c = cr / 3, r = cr - c * 3;
-        const int iy = y + r - 1, ix = x0 + j - 1;
-        wv[it] = 0.f;
-        if (i < 9 * WIN && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)wd)
-            wv[it] = fr[((size_t)c * h + iy) * wd + ix];
-    }
+        for (int it = 0; it < NLD; ++it) {
+            const int i = threadIdx.x + it * 256;
+            const int cr = i / WIN, j = i - cr * WIN;
+            const int c = cr / 3, r = cr - c * 3;
+            const int iy = y + r - 1, ix = x0 + j - 1;
+            wv[it] = 0.f;
+            if (i < 9 * WIN && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)wd)
+                wv[it] = fr[((size_t)c * h + iy) * wd + ix];
+        }
+    };
+    auto park = [&](int buf) {
 #pragma unroll
-    for (int it = 0; it < NLD; ++it) {
-        const int i = threadIdx.x + it * 256;
-        if (i < 9 * WIN) win[i] = wv[it];
-    }
+        for (int it = 0; it < NLD; ++it) {
+            const int i = threadIdx.x + it * 256;
+            if (i < 9 * WIN) win[buf][i] = wv[it];
+        }
+    };
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = lane & 15, kg = lane >> 4;
     // this lane's 8 values of k: LDS offsets (relative to the block's first pixel)
@@ -204,53 +217,73 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
 #pragma unroll
         for (int i = 0; i < 4; ++i) bv[cg][i] = bias[cg * 16 + kg * 4 + i];
     }
+    int P = blockIdx.x;
+    if (P >= total) return;  // uniform over the workgroup
+    load(P);
+    park(0);
     __syncthreads();
-    const size_t row_m = (size_t)g[2] + (size_t)y * wd;
-    for (int blk = wave; blk < kStemSeg / 16; blk += 4) {
-        const int xb = x0 + blk * 16;
-        if (xb >= wd) break;
-        constexpr bool split = __is_same(TO, f16);
-        f16x8 b, bl;
+    for (int t = 0; P < total; ++t, P += gridDim.x) {
+        const int buf = t & 1;
+        const int Pn = P + gridDim.x;
+        if (Pn < total) load(Pn);
+        int f, y, x0;
+        locate(P, f, y, x0);
+        const int* g = geom + f * kGeomInts;
+        const int wd = g[1];
+        const size_t row_m = (size_t)g[2] + (size_t)y * wd;
+        for (int blk = wave; blk < kStemSeg / 16; blk += 4) {
+            const int xb = x0 + blk * 16;
+            if (xb >= wd) break;
+            f16x8 b, bl;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float v = kval[j] ? win[koff[j] + blk * 16] : 0.f;
-            b[j] = (f16)v;
-            if constexpr (split) bl[j] = (f16)(v - (float)b[j]);
-        }
-        typedef TO T4 __attribute__((ext_vector_type(4)));
-        T4 pk[NG];
-#pragma unroll
-        for (int cg = 0; cg < NG; ++cg) {
-            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-            if constexpr (split) {
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[cg], b, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], bl, acc, 0, 0, 0);
+            for (int j = 0; j < 8; ++j) {
+                const float v = kval[j] ? win[buf][koff[j] + blk * 16] : 0.f;
+                b[j] = (f16)v;
+                if constexpr (split) bl[j] = (f16)(v - (float)b[j]);
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], b, acc, 0, 0, 0);
+            typedef TO T4 __attribute__((ext_vector_type(4)));
+            T4 pk[NG];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) pk[cg][i] = (TO)leaky01(acc[i] + bv[cg][i]);
+            for (int cg = 0; cg < NG; ++cg) {
+                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+                if constexpr (split) {
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[cg], b, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], bl, acc, 0, 0, 0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], b, acc, 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pk[cg][i] = (TO)leaky01(acc[i] + bv[cg][i]);
+            }
+            TO* o = out + (row_m + xb + p) * COUT;
+            if constexpr (NG == 1) {
+                // 16 pixels x 32 bytes: one contiguous 512-byte store
+                typedef unsigned U2 __attribute__((ext_vector_type(2)));
+                U2 u2;
+                __builtin_memcpy(&u2, &pk[0], 8);
+                __builtin_nontemporal_store(u2, (U2*)(o + kg * 4));
+            } else {
+                // Lanes l and l ^ 16 (kg and kg ^ 1) trade halves so that each holds 8
+                // consecutive channels: the even lane channels 4 kg .. 4 kg + 7 of group
+                // 0, the odd lane 16 + 4 (kg - 1) .. + 7 of group 1.  Each lane then
+                // stores 16 bytes and one store covers 16 pixels x 64 bytes contiguously.
+                const bool odd = kg & 1;
+                const T4 give = odd ? pk[0] : pk[1];
+                unsigned g2[2], r2[2];
+                __builtin_memcpy(g2, &give, 8);
+                r2[0] = __shfl_xor(g2[0], 16);
+                r2[1] = __shfl_xor(g2[1], 16);
+                T4 got;
+                __builtin_memcpy(&got, r2, 8);
+                const T4 lo = odd ? got : pk[0], hi = odd ? pk[1] : got;
+                typedef unsigned U4 __attribute__((ext_vector_type(4)));
+                U4 u4;
+                __builtin_memcpy(&u4, &lo, 8);
+                __builtin_memcpy((char*)&u4 + 8, &hi, 8);
+                __builtin_nontemporal_store(u4, (U4*)(o + (odd ? 16 + 4 * (kg - 1) : 4 * kg)));
+            }
         }
-        TO* o = out + (row_m + xb + p) * COUT;
-        if constexpr (NG == 1) {
-            *(T4*)(o + kg * 4) = pk[0];  // 16 pixels x 32 bytes: one contiguous 512-byte store
-        } else {
-            // Lanes l and l ^ 16 (kg and kg ^ 1) trade halves so that each holds 8
-            // consecutive channels: the even lane channels 4 kg .. 4 kg + 7 of group
-            // 0, the odd lane 16 + 4 (kg - 1) .. + 7 of group 1.  Each lane then
-            // stores 16 bytes and one store covers 16 pixels x 64 bytes contiguously.
-            const bool odd = kg & 1;
-            const T4 give = odd ? pk[0] : pk[1];
-            unsigned g2[2], r2[2];
-            __builtin_memcpy(g2, &give, 8);
-            r2[0] = __shfl_xor(g2[0], 16);
-            r2[1] = __shfl_xor(g2[1], 16);
-            T4 got;
-            __builtin_memcpy(&got, r2, 8);
-            typedef TO T8 __attribute__((ext_vector_type(8)));
-            const T4 lo = odd ? got : pk[0], hi = odd ? pk[1] : got;
-            const T8 v8 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-            *(T8*)(o + (odd ? 16 + 4 * (kg - 1) : 4 * kg)) = v8;
-        }
+        if (Pn < total) park(buf ^ 1);
+        __syncthreads();
     }
 }
 
@@ -259,22 +292,24 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
                        hipStream_t s) {
     if (out_type != kF32) {
         // 16-bit storage: the matrix-core stem, one workgroup per kStemSeg-pixel row segment
+        // persistent: 4 workgroups per compute unit (256 of them), all resident at once
         const int nseg = (max_w + kStemSeg - 1) / kStemSeg;
-        dim3 grid2(rows * nseg), block2(256);
+        const int total = rows * nseg;
+        dim3 grid2(total < 1024 ? total : 1024), block2(256);
         if (cout == 32) {
             if (out_type == kF16)
                 stem_mfma_kernel<f16, 32><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias, (f16*)out,
-                                                                   nseg);
+                                                                   nseg, total);
             else
                 stem_mfma_kernel<bf16, 32><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias,
-                                                                    (bf16*)out, nseg);
+                                                                    (bf16*)out, nseg, total);
         } else if (cout == 16) {
             if (out_type == kF16)
                 stem_mfma_kernel<f16, 16><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias, (f16*)out,
-                                                                   nseg);
+                                                                   nseg, total);
             else
                 stem_mfma_kernel<bf16, 16><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias,
-                                                                    (bf16*)out, nseg);
+                                                                    (bf16*)out, nseg, total);
         } else {
             return hipErrorInvalidValue;
         }
@@ -309,7 +344,7 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
 // Cout (both are multiples of 4).  With a.amax set, the largest |value| stored
 // to out0 is folded into *a.amax (float bits as unsigned, non-negative).
 // ---------------------------------------------------------------------------
-template <typename T, int TM, int TN, int WTM, int WTN>
+template <typename T, int TM, int TN, int WTM, int WTN, bool NT = false>
 __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)[TM][TN], int m_base, int n_base,
                                            int lane, const float* __restrict__ dq) {
     typedef T T4 __attribute__((ext_vector_type(4)));
@@ -376,7 +411,14 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)
                     T4 pk;
 #pragma unroll
                     for (int t = 0; t < 4; ++t) pk[t] = cvt_out<T>(v[t]);
-                    *(T4*)((T*)a.out0 + o) = pk;
+                    if constexpr (NT && sizeof(T) == 2) {  // streaming store (not kept in L2)
+                        typedef unsigned U2 __attribute__((ext_vector_type(2)));
+                        U2 u;
+                        __builtin_memcpy(&u, &pk, 8);
+                        __builtin_nontemporal_store(u, (U2*)((T*)a.out0 + o));
+                    } else {
+                        *(T4*)((T*)a.out0 + o) = pk;
+                    }
                 }
 #pragma unroll
                 for (int t = 0; t < 4; ++t) amax = fmaxf(amax, fabsf(v[t]));
@@ -667,7 +709,7 @@ constexpr int waitcnt_imm(int vm, int lgkm) { return (vm & 15) | ((vm >> 4) << 1
 
 __device__ __forceinline__ int dma_swizzle(int r) { return ((r >> 1) & 1) ^ (((r >> 2) & 1) << 1) ^ ((r >> 3) & 1); }
 
-template <typename T, int BM, int BN, int WGM, int WGN, int S>
+template <typename T, int BM, int BN, int WGM, int WGN, int S, bool NT>
 __global__ __launch_bounds__(256) void conv_dma(ConvArgs a) {
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
     constexpr int TM = WTM / 16, TN = WTN / 16;
@@ -815,7 +857,7 @@ __global__ __launch_bounds__(256) void conv_dma(ConvArgs a) {
     // no DMA may still be writing LDS when the workgroup ends
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
 
-    store_tile<T, TM, TN, WTM, WTN>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
+    store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1034,31 +1076,36 @@ hipError_t launch_conv_fp8(const ConvArgs& a, int c, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Tile configurations and dispatch.
 // ---------------------------------------------------------------------------
-// st = 0: register-staged conv_igemm; st = S >= 3: conv_dma with S stages.
-struct TileCfg { int bm, bn, wgm, wgn, bk, st; };
+// st = 0: register-staged conv_igemm; st = S >= 3: conv_dma with S stages;
+// nt = 1: streaming (non-temporal) output stores.
+struct TileCfg { int bm, bn, wgm, wgn, bk, st, nt; };
 static constexpr TileCfg kTiles[] = {
-    {128, 128, 2, 2, 32, 0},  // 0: 64x64 per wave
-    {256, 64, 4, 1, 32, 0},   // 1: 64x64 per wave (Cout 64)
-    {128, 64, 2, 2, 32, 0},   // 2: 64x32 per wave
-    {64, 128, 2, 2, 32, 0},   // 3: 32x64 per wave
-    {256, 32, 4, 1, 32, 0},   // 4: 64x32 per wave (Cout <= 32)
-    {64, 64, 2, 2, 32, 0},    // 5: 32x32 per wave (also the unaligned-Cin path)
-    {128, 32, 4, 1, 32, 0},   // 6: 32x32 per wave
-    {32, 128, 2, 2, 32, 0},   // 7: 16x64 per wave
-    {128, 128, 2, 2, 64, 0},  // 8: as 0, K chunks of 64 (16-bit types)
-    {256, 64, 4, 1, 64, 0},   // 9: as 1, K chunks of 64
-    {128, 64, 2, 2, 64, 0},   // 10: as 2, K chunks of 64
-    {64, 128, 2, 2, 64, 0},   // 11: as 3, K chunks of 64
-    {256, 128, 2, 2, 32, 0},  // 12: 128x64 per wave
-    {128, 256, 2, 2, 32, 0},  // 13: 64x128 per wave
-    {256, 128, 2, 2, 64, 0},  // 14: 128x64 per wave, K chunks of 64
-    {128, 128, 2, 2, 32, 4},  // 15: direct-to-LDS, 4 stages (64 KB)
-    {128, 128, 2, 2, 32, 3},  // 16: direct-to-LDS, 3 stages (48 KB)
-    {256, 128, 2, 2, 32, 3},  // 17: direct-to-LDS, 128x64 per wave (72 KB)
-    {128, 256, 2, 2, 32, 3},  // 18: direct-to-LDS, 64x128 per wave (72 KB)
-    {256, 64, 4, 1, 32, 4},   // 19: direct-to-LDS, Cout 64 (80 KB)
-    {128, 64, 2, 2, 32, 4},   // 20: direct-to-LDS, 64x32 per wave (48 KB)
-    {64, 128, 2, 2, 32, 4},   // 21: direct-to-LDS, 32x64 per wave (48 KB)
+    {128, 128, 2, 2, 32, 0, 0},  // 0: 64x64 per wave
+    {256, 64, 4, 1, 32, 0, 0},   // 1: 64x64 per wave (Cout 64)
+    {128, 64, 2, 2, 32, 0, 0},   // 2: 64x32 per wave
+    {64, 128, 2, 2, 32, 0, 0},   // 3: 32x64 per wave
+    {256, 32, 4, 1, 32, 0, 0},   // 4: 64x32 per wave (Cout <= 32)
+    {64, 64, 2, 2, 32, 0, 0},    // 5: 32x32 per wave (also the unaligned-Cin path)
+    {128, 32, 4, 1, 32, 0, 0},   // 6: 32x32 per wave
+    {32, 128, 2, 2, 32, 0, 0},   // 7: 16x64 per wave
+    {128, 128, 2, 2, 64, 0, 0},  // 8: as 0, K chunks of 64 (16-bit types)
+    {256, 64, 4, 1, 64, 0, 0},   // 9: as 1, K chunks of 64
+    {128, 64, 2, 2, 64, 0, 0},   // 10: as 2, K chunks of 64
+    {64, 128, 2, 2, 64, 0, 0},   // 11: as 3, K chunks of 64
+    {256, 128, 2, 2, 32, 0, 0},  // 12: 128x64 per wave
+    {128, 256, 2, 2, 32, 0, 0},  // 13: 64x128 per wave
+    {256, 128, 2, 2, 64, 0, 0},  // 14: 128x64 per wave, K chunks of 64
+    {128, 128, 2, 2, 32, 4, 0},  // 15: direct-to-LDS, 4 stages (64 KB)
+    {128, 128, 2, 2, 32, 3, 0},  // 16: direct-to-LDS, 3 stages (48 KB)
+    {256, 128, 2, 2, 32, 3, 0},  // 17: direct-to-LDS, 128x64 per wave (72 KB)
+    {128, 256, 2, 2, 32, 3, 0},  // 18: direct-to-LDS, 64x128 per wave (72 KB)
+    {256, 64, 4, 1, 32, 4, 0},   // 19: direct-to-LDS, Cout 64 (80 KB)
+    {128, 64, 2, 2, 32, 4, 0},   // 20: direct-to-LDS, 64x32 per wave (48 KB)
+    {64, 128, 2, 2, 32, 4, 0},   // 21: direct-to-LDS, 32x64 per wave (48 KB)
+    {128, 128, 2, 2, 32, 3, 1},  // 22: as 16, streaming stores
+    {256, 128, 2, 2, 32, 3, 1},  // 23: as 17, streaming stores
+    {128, 64, 2, 2, 32, 4, 1},   // 24: as 20, streaming stores
+    {64, 128, 2, 2, 32, 4, 1},   // 25: as 21, streaming stores
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
@@ -1130,7 +1177,7 @@ static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
         constexpr TileCfg t = kTiles[C];
         dim3 grid(((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn)), block(256);
         if constexpr (t.st > 0)
-            conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st><<<grid, block, 0, s>>>(a);
+            conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0><<<grid, block, 0, s>>>(a);
         else if (aligned)
             conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, true><<<grid, block, 0, s>>>(a);
         else if constexpr (C == 5)
@@ -1166,6 +1213,10 @@ static hipError_t launch_type(const ConvArgs& a, int c, bool aligned, hipStream_
         case 19: return launch_t<T, 19>(a, aligned, s);
         case 20: return launch_t<T, 20>(a, aligned, s);
         case 21: return launch_t<T, 21>(a, aligned, s);
+        case 22: return launch_t<T, 22>(a, aligned, s);
+        case 23: return launch_t<T, 23>(a, aligned, s);
+        case 24: return launch_t<T, 24>(a, aligned, s);
+        case 25: return launch_t<T, 25>(a, aligned, s);
     }
     return hipErrorInvalidValue;
 }
