@@ -28,7 +28,7 @@ K_CAND = 40
 CONF, NMS_IOU = 0.5, 0.4
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_igemm_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_bf16_b16_608x1088_traffic.json")
 
 
 def conv_source_hash(key, tiles):
