@@ -121,12 +121,14 @@ __device__ __forceinline__ int xcd_remap(int L, int W) {
 
 // ---------------------------------------------------------------------------
 // Stem on the matrix cores (16-bit activation storage).  Work items are
-// segments of up to kStemSeg output pixels of one image row; a persistent
-// workgroup walks items P = blockIdx.x + t * gridDim.x (neighbouring workgroups
-// write neighbouring memory at any moment).  For each item the input window it
+// segments of up to kStemSeg output pixels of one image row, walked by
+// persistent workgroups.  For each item the input window it
 // needs (3 channels x 3 rows x kStemSeg + 2 columns, zero outside the frame) is
 // read with coalesced loads -- the next item's window is loaded into registers
 // while the current one is computed -- and parked in LDS (double-buffered).
+// Items are split into 8 contiguous bands, one per XCD, and the workgroups of
+// an XCD walk their band together, so neighbouring rows -- whose windows
+// overlap -- are fetched once into that XCD's L2.
 // Each wave then builds 16-pixel im2col blocks from LDS -- k = (r*3 + s)*3 + c
 // for k < 27, zeros up to 32 -- and runs v_mfma_f32_16x16x32_f16 per 16 output
 // channels (A = folded weights, rows = channels; B = pixels), FP32
@@ -217,15 +219,20 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
 #pragma unroll
         for (int i = 0; i < 4; ++i) bv[cg][i] = bias[cg * 16 + kg * 4 + i];
     }
-    int P = blockIdx.x;
-    if (P >= total) return;  // uniform over the workgroup
+    // band of this workgroup's XCD (gridDim.x is a multiple of 8): items
+    // [lo, hi), walked with stride per = gridDim.x / 8 from lo + blockIdx.x / 8
+    const int per = gridDim.x / kXCDs, xcd = blockIdx.x % kXCDs;
+    const int band = (total + kXCDs - 1) / kXCDs;
+    const int lo = xcd * band, hi = lo + band < total ? lo + band : total;
+    int P = lo + (int)blockIdx.x / kXCDs;
+    if (P >= hi) return;  // uniform over the workgroup
     load(P);
     park(0);
     __syncthreads();
-    for (int t = 0; P < total; ++t, P += gridDim.x) {
+    for (int t = 0; P < hi; ++t, P += per) {
         const int buf = t & 1;
-        const int Pn = P + gridDim.x;
-        if (Pn < total) load(Pn);
+        const int Pn = P + per;
+        if (Pn < hi) load(Pn);
         int f, y, x0;
         locate(P, f, y, x0);
         const int* g = geom + f * kGeomInts;
@@ -282,7 +289,7 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
                 __builtin_nontemporal_store(u4, (U4*)(o + (odd ? 16 + 4 * (kg - 1) : 4 * kg)));
             }
         }
-        if (Pn < total) park(buf ^ 1);
+        if (Pn < hi) park(buf ^ 1);
         __syncthreads();
     }
 }
@@ -292,10 +299,12 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
                        hipStream_t s) {
     if (out_type != kF32) {
         // 16-bit storage: the matrix-core stem, one workgroup per kStemSeg-pixel row segment
-        // persistent: 4 workgroups per compute unit (256 of them), all resident at once
+        // persistent: 4 workgroups per compute unit (256 of them), all resident at
+        // once; a multiple of 8 workgroups (one band per XCD)
         const int nseg = (max_w + kStemSeg - 1) / kStemSeg;
         const int total = rows * nseg;
-        dim3 grid2(total < 1024 ? total : 1024), block2(256);
+        const int g = total < 1024 ? ((total + 7) / 8) * 8 : 1024;
+        dim3 grid2(g), block2(256);
         if (cout == 32) {
             if (out_type == kF16)
                 stem_mfma_kernel<f16, 32><<<grid2, block2, 0, s>>>(frames, geom, nframes, uniform, w, bias, (f16*)out,
@@ -684,10 +693,9 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
 // kernel width for a weight row (so that (r * k + s) * Cin + ci = k index),
 // and a zero halo / out-of-range row gets an out-of-range offset (zeros).
 //
-// Step k (stage k % S holds chunk k): wait until this wave's DMAs of chunk k
-// are done (at most (S - 2) * NPW younger ones may still be in flight), barrier
-// (every wave's part of chunk k has landed, and chunk k - 1 has been read by
-// all), issue chunk k + S - 1 into the stage of chunk k - 1, compute chunk k.
+// Stage k % S holds chunk k.  S chunks are in flight while a chunk is computed:
+// its MFMA operands are read from LDS into registers one step ahead (two
+// register sets), so its stage is refilled as soon as every wave has read it.
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
@@ -813,46 +821,68 @@ __global__ __launch_bounds__(256) void conv_dma(ConvArgs a) {
     // lane-constant LDS read offset: row lane % 16 of a 16-row group, k-slot lane / 16
     const int rd = (lane & 15) * 64 + (((lane >> 4) ^ dma_swizzle(lane & 15)) << 4);
     const int a_rd = (wn * WTN) * 64 + rd, b_rd = (BN + wm * WTM) * 64 + rd;
-    auto compute = [&](auto u_c) {
-        constexpr int u = decltype(u_c)::value;
-        const char* sp = u == 0 ? st0 : u == 1 ? st1 : u == 2 ? st2 : st3;
-        V af[TN], bfr[TM];
+    // MFMA operands of a chunk are read from LDS into one of two register sets
+    // one step ahead, so that the LDS latency hides behind the previous chunk's MFMAs.
+    V fa[2][TN], fb[2][TM];
+    auto read = [&](auto st_c, auto fr_c) {
+        constexpr int st = decltype(st_c)::value, fr = decltype(fr_c)::value;
+        const char* sp = st == 0 ? st0 : st == 1 ? st1 : st == 2 ? st2 : st3;
 #pragma unroll
-        for (int j = 0; j < TN; ++j) af[j] = *(const V*)(sp + a_rd + j * 16 * 64);
+        for (int j = 0; j < TN; ++j) fa[fr][j] = *(const V*)(sp + a_rd + j * 16 * 64);
 #pragma unroll
-        for (int i = 0; i < TM; ++i) bfr[i] = *(const V*)(sp + b_rd + i * 16 * 64);
+        for (int i = 0; i < TM; ++i) fb[fr][i] = *(const V*)(sp + b_rd + i * 16 * 64);
+    };
+    auto mma = [&](auto fr_c) {
+        constexpr int fr = decltype(fr_c)::value;
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
                 if constexpr (__is_same(T, bf16))
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[j], bfr[i], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[fr][j], fb[fr][i], acc[i][j], 0, 0, 0);
                 else
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[j], bfr[i], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[fr][j], fb[fr][i], acc[i][j], 0, 0, 0);
             }
     };
 
+    // Prologue: chunks 0 .. S-2 in flight; once chunk 0 has landed everywhere its
+    // operands are read and chunk S-1 is issued into the last stage.
     issue(std::integral_constant<int, 0>{});
     issue(std::integral_constant<int, 1>{});
     if constexpr (S > 3) issue(std::integral_constant<int, 2>{});
-    auto step = [&](auto u_c) {
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm((S - 2) * NPW, 0));
+    __builtin_amdgcn_s_barrier();
+    read(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+    issue(std::integral_constant<int, S - 1>{});
+    // Step k (chunks k+1 .. k+S-1 in flight, chunk k's operands in registers):
+    // wait until chunk k+1 has landed (at most (S-2) NPW younger DMAs of this wave
+    // outstanding) and this wave's operand reads of chunk k are done; barrier (so
+    // for every wave; chunk k's stage is then free); issue chunk k+S into it; read
+    // chunk k+1's operands; run chunk k's MFMAs.
+    auto step = [&](auto u_c, int k) {
         constexpr int u = decltype(u_c)::value;
         __builtin_amdgcn_s_waitcnt(waitcnt_imm((S - 2) * NPW, 0));
         __builtin_amdgcn_s_barrier();
-        issue(std::integral_constant<int, (u + S - 1) % S>{});
-        compute(u_c);
+        issue(std::integral_constant<int, u % S>{});
+        if (k + 1 < nk) read(std::integral_constant<int, (u + 1) % S>{}, std::integral_constant<int, (u + 1) & 1>{});
+        mma(std::integral_constant<int, u & 1>{});
     };
-    for (int kc = 0;; kc += S) {
-        step(std::integral_constant<int, 0>{});
+    constexpr int L = S == 3 ? 6 : 4;  // steps per loop trip: stage and register set repeat
+    for (int kc = 0;; kc += L) {
+        step(std::integral_constant<int, 0>{}, kc);
         if (kc + 1 >= nk) break;
-        step(std::integral_constant<int, 1>{});
+        step(std::integral_constant<int, 1>{}, kc + 1);
         if (kc + 2 >= nk) break;
-        step(std::integral_constant<int, 2>{});
-        if constexpr (S > 3) {
-            if (kc + 3 >= nk) break;
-            step(std::integral_constant<int, 3>{});
+        step(std::integral_constant<int, 2>{}, kc + 2);
+        if (kc + 3 >= nk) break;
+        step(std::integral_constant<int, 3>{}, kc + 3);
+        if constexpr (L > 4) {
+            if (kc + 4 >= nk) break;
+            step(std::integral_constant<int, 4>{}, kc + 4);
+            if (kc + 5 >= nk) break;
+            step(std::integral_constant<int, 5>{}, kc + 5);
         }
-        if (kc + S >= nk) break;
+        if (kc + L >= nk) break;
     }
     // no DMA may still be writing LDS when the workgroup ends
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
