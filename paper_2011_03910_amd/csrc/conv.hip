@@ -1136,6 +1136,9 @@ static constexpr TileCfg kTiles[] = {
     {256, 128, 2, 2, 32, 3, 1},  // 23: as 17, streaming stores
     {128, 64, 2, 2, 32, 4, 1},   // 24: as 20, streaming stores
     {64, 128, 2, 2, 32, 4, 1},   // 25: as 21, streaming stores
+    {128, 64, 2, 2, 32, 3, 0},   // 26: direct-to-LDS, 3 stages (36 KB: 4 workgroups per CU)
+    {64, 64, 2, 2, 32, 4, 0},    // 27: direct-to-LDS, 32x32 per wave (32 KB: 5 per CU)
+    {64, 64, 2, 2, 32, 3, 0},    // 28: direct-to-LDS, 3 stages (24 KB: 6 per CU)
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
@@ -1247,6 +1250,9 @@ static hipError_t launch_type(const ConvArgs& a, int c, bool aligned, hipStream_
         case 23: return launch_t<T, 23>(a, aligned, s);
         case 24: return launch_t<T, 24>(a, aligned, s);
         case 25: return launch_t<T, 25>(a, aligned, s);
+        case 26: return launch_t<T, 26>(a, aligned, s);
+        case 27: return launch_t<T, 27>(a, aligned, s);
+        case 28: return launch_t<T, 28>(a, aligned, s);
     }
     return hipErrorInvalidValue;
 }

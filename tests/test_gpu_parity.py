@@ -240,6 +240,57 @@ def test_full_reduced_precision_parity(torch, precision):
             assert frac >= 0.99
 
 
+@pytest.mark.slow
+def test_full_bf16_batch16_stored_tiles_parity(torch):
+    """The benchmarked launch configuration: BF16, 16 frames of 608x1088 in one
+    batch, the stored per-launch tile choices (direct-to-LDS kernels included),
+    ~40 candidates per frame.  Frames 0 and 15 are checked against the oracle
+    (head outputs by the BF16 rule; detections reported), the other frames
+    against the same forward run one frame at a time (batching must not change
+    a frame's result beyond accumulation order)."""
+    import json
+    import os
+    from oracle.network import forward, round_bf16
+    _say("case: full bf16 b16 stored tiles")
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2011_03910_amd",
+                        "tiles_mi355x.json")
+    tiles = np.array(json.load(open(path))["bf16_b16"], dtype=np.int32)
+    _say(f"  tiles: {sorted(set(tiles.tolist()))}")
+    m = _model(FULL, "bf16", 16)
+    m.load_weights(weights("full", 40))
+    m.set_tiles(tiles)
+    fr = frames("full", 16)
+    heads = _run(torch, m, fr)
+    v = head_views(heads, [(608, 1088)] * 16)
+    layers = weights("full", 40)
+    sel = fr[[0, 15]]
+    ref = forward(sel, layers, FULL.blocks)
+    lr = [layers[0]] + [(round_bf16(w), b) for w, b in layers[1:]]
+    emul = forward(sel, lr, FULL.blocks, store=round_bf16)
+    def pick(d, i):  # one frame of a head dict, as a batch of one
+        return {key: [d[key][s][i][None] for s in range(3)] for key in ("det", "emb")}
+    for j, f in enumerate((0, 15)):
+        _say(f"  frame {f}:")
+        check_reduced_precision(pick(v, f), pick(ref, j), pick(emul, j), "bf16")
+    d = m.decode(heads, [(608, 1088)] * 16)
+    for j, f in enumerate((0, 15)):
+        g = gpu_dets(d, f, m.cap)
+        r = opost.detections(ref, anchors("full"), 0.5, 0.4, frame=j)
+        frac, _ = match_fraction(g["boxes"], r["boxes"], r["score"])
+        _say(f"  frame {f}: dets gpu {len(g['boxes'])} oracle {len(r['idx'])} matched {frac:.3f}")
+    # every frame equals the same network run on that frame alone (same tiles)
+    m1 = _model(FULL, "bf16", 1)
+    m1.load_weights(weights("full", 40))
+    worst = 0.0
+    for f in (3, 8, 12):
+        h1 = head_views(_run(torch, m1, fr[f:f + 1]), [(608, 1088)])
+        for key in ("det", "emb"):
+            for s in range(3):
+                worst = max(worst, rel_err(v[key][s][f], h1[key][s][0]))
+    _say(f"  batch vs single-frame runs (frames 3, 8, 12): rel err {worst:.2e}")
+    assert worst <= 2e-2
+
+
 @pytest.mark.parametrize("cfg_name,k", [("tiny", 50), pytest.param("full", 40, marks=pytest.mark.slow)])
 def test_fp8_backbone_parity(torch, cfg_name, k):
     """FP8 e4m3 backbone: the device's calibrated input scales equal the oracle's
