@@ -239,6 +239,13 @@ def main():
     fwd_ms = ms.sum() / nfwd
     log(f"forward launches: {len(ms)}; conv {n_launch} launches {conv_ms:.3f} ms/step "
         f"({conv_flop / 1e9:.1f} GFLOP) -> {achieved:.1f} TFLOP/s; all forward launches {fwd_ms:.3f} ms")
+    if (kind == 2).any():
+        # stem fused with the first downsample conv: HBM-bound (FP32 frames in, the
+        # stride-2 level's 64 channels out)
+        t2 = ms[kind == 2].sum() / nfwd
+        nbytes = args.batch * (3 * 608 * 1088 * 4 + 304 * 544 * 64 * (4 if args.precision == "fp32" else 2))
+        log(f"fused stem + downsample: {t2 * 1e3:.1f} us, {nbytes / 1e6:.0f} MB algorithmic -> "
+            f"{nbytes / (t2 * 1e-3) / 1e12:.2f} TB/s of 8")
     for i in range(len(ms)):
         t = ms[i] / nfwd
         log(f"  op {i:2d} kind {kind[i]} {t * 1e3:9.1f} us  {fl[i] / 1e9:8.2f} GFLOP  "

@@ -170,6 +170,13 @@ jde_status jde_calibrate(jde_ctx* ctx, const float* d_frames, const jde_frame_de
 /* Input scale of every forward launch (0 for launches that do not run in FP8);
  * in_scales: host, n_ops = number of forward launches. */
 jde_status jde_fp8_scales(const jde_ctx* ctx, float* in_scales, int n_ops);
+/* With on != 0 (the default), 16-bit contexts run the stem (3 -> c0 = 32) and
+ * the first downsample conv (3x3 stride 2, 32 -> 64) as one launch that keeps the
+ * stem's output in on-chip memory (Sec. 3.1 backbone; the result is the same
+ * network, rounded the same way); on = 0 runs them as two launches.  Other
+ * configurations always run unfused.  In jde_profile_collect the fused launch is
+ * kind 2 at op 0 and op 1 is kind 3 with no time or FLOPs of its own. */
+jde_status jde_fuse_stem(jde_ctx* ctx, int on);
 /* Host helper: x (host, n floats) -> OCP e4m3 codes (host, n bytes), round to
  * nearest even, saturating at +-448, NaN -> 0x7f; the encoding of the weights. */
 void jde_fp8_encode(const float* x, uint8_t* out, size_t n);

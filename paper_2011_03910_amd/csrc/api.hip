@@ -89,6 +89,9 @@ struct jde_ctx {
     bool loaded = false;
     int n_backbone_ops = 0;
     bool fp8 = false, fp8_ready = false, calibrating = false;
+    // The stem and the first downsample conv run as one launch (16-bit storage);
+    // last_fused records whether the latest forward did.
+    bool fuse_stem = true, last_fused = false;
     size_t ws_amax = 0;
     // Per-launch timing: a ring of event pairs, one entry per profiled forward.
     static constexpr int kRing = 8;
@@ -427,6 +430,15 @@ ConvArgs conv_args(const jde_ctx* c, const Op& o, const jde_frame_desc* d, int n
 
 bool runs_fp8(const jde_ctx* c, const Op& o) { return o.fp8 && c->fp8_ready && !c->calibrating; }
 
+// The stem (3 -> 32) and the stage-1 downsample conv (3x3 stride 2, 32 -> 64) run
+// fused for 16-bit storage, except while calibrating (the fused launch records
+// no output range).
+static bool stem_fusable(const jde_ctx* c, const Op& stem, const Op& o1) {
+    return c->fuse_stem && !c->calibrating && c->et != kF32 && stem.cout == 32 && o1.kind == OP_CONV &&
+           o1.in_t == stem.out_t && o1.cin == 32 && o1.cout == 64 && o1.ksz == 3 && o1.stride == 2 && o1.cin1 == 0 &&
+           o1.res_t < 0 && o1.act && o1.n_split == o1.cout && !runs_fp8(c, o1);
+}
+
 }  // namespace
 
 // ---- setup kernel: geometry table + counter reset ---------------------------
@@ -592,7 +604,7 @@ jde_status jde_profile_collect(jde_ctx* c, int max_ops, double* op_ms, double* o
     for (int i = 0; i < n && i < max_ops; ++i) {
         if (op_ms) op_ms[i] = i < (int)c->op_ms.size() ? c->op_ms[i] : 0.0;
         if (op_flop) op_flop[i] = i < (int)c->op_flop.size() ? c->op_flop[i] : 0.0;
-        if (op_kind) op_kind[i] = c->ops[i].kind;
+        if (op_kind) op_kind[i] = (c->last_fused && i == 0) ? 2 : (c->last_fused && i == 1) ? 3 : c->ops[i].kind;
     }
     if (n_ops) *n_ops = n;
     if (n_fwd) *n_fwd = c->n_fwd;
@@ -697,10 +709,29 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
         c->pending[slot] = true;
         c->ring_pos = (slot + 1) % jde_ctx::kRing;
     }
+    c->last_fused = false;
     for (size_t oi = 0; oi < c->ops.size(); ++oi) {
         const Op& o = c->ops[oi];
         const char* wb = c->d_weights;
         if (pev) HIP_TRY(hipEventRecord(pev[2 * oi], s));
+        if (o.kind == OP_STEM && oi + 1 < c->ops.size() && stem_fusable(c, o, c->ops[oi + 1])) {
+            const Op& o1 = c->ops[oi + 1];
+            int tiles = 0;
+            for (int f = 0; f < n; ++f) tiles += stem_down_tiles(d[f].h, d[f].w);
+            HIP_TRY(launch_stem_down(frames, geom, n, tiles, (const float*)(wb + o.dev_w), (const float*)(wb + o.dev_b),
+                                     wb + o1.dev_w, (const float*)(wb + o1.dev_b), tptr(o1.out_t), c->et, s));
+            if (pev) {
+                HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));
+                HIP_TRY(hipEventRecord(pev[2 * oi + 2], s));
+                HIP_TRY(hipEventRecord(pev[2 * oi + 3], s));
+                const double M0 = (double)level_pixels(d, n, 0), M1 = (double)level_pixels(d, n, 1);
+                c->op_flop[oi] = 2.0 * M0 * o.cout * 27 + 2.0 * M1 * o1.cout * o1.ksz * o1.ksz * o1.cin;
+                c->op_flop[oi + 1] = 0.0;
+            }
+            c->last_fused = true;
+            ++oi;
+            continue;
+        }
         if (o.kind == OP_STEM) {
             const int M = (int)level_pixels(d, n, 0);
             int rows = 0, max_w = 0;
@@ -982,6 +1013,12 @@ jde_status jde_calibrate(jde_ctx* c, const float* frames, const jde_frame_desc* 
         o.in_scale = m > 0.f ? m / 448.f : 1.f;
     }
     c->fp8_ready = true;
+    return JDE_OK;
+}
+
+jde_status jde_fuse_stem(jde_ctx* c, int on) {
+    if (!c) return fail(JDE_EINVAL, "null context");
+    c->fuse_stem = on != 0;
     return JDE_OK;
 }
 

@@ -294,6 +294,213 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Stem fused with the first downsample conv (16-bit storage, c0 = 32): the
+// stem's output -- the largest tensor of the network -- never goes to HBM.
+// Work items are 2 x 64 tiles of the stride-2 level output (all 64 channels),
+// walked by persistent workgroups.  Per tile: the frame window it needs (3
+// channels x 7 rows x 131 columns, zero outside the frame; loaded into
+// registers while the previous tile is computed) is parked in LDS; the 5 x 129
+// stem outputs the 3x3 stride-2 conv reads are computed on MFMA (as in
+// stem_mfma_kernel; a stem position outside the image is the conv's zero
+// padding, not a stem value) and kept in LDS in the storage type -- the same
+// rounding as a stored stem output -- with even and odd columns in separate
+// planes (80-byte pixel slots), so that the conv's stride-2 reads are unit-
+// stride and bank-conflict-free; the conv then runs from LDS with K = 9 taps x
+// 32 channels, one MFMA k-step per tap in the same order as the unfused GEMM.
+// Wave w computes output channels 16 w .. 16 w + 15 for the whole tile, so its
+// weights (9 taps x 16 channels x 32) stay in registers for the workgroup's life.
+// ---------------------------------------------------------------------------
+constexpr int kSdTY = 2, kSdTX = 64;  // output tile (stride-2 level)
+
+template <typename TO>
+__global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict__ frames,
+                                                        const int* __restrict__ geom, int nframes, int total,
+                                                        const float* __restrict__ w0, const float* __restrict__ b0,
+                                                        const TO* __restrict__ w1, const float* __restrict__ b1,
+                                                        TO* __restrict__ out) {
+    constexpr int C0 = 32, C1 = 64;
+    constexpr int WR = 2 * kSdTY + 1, WC = 2 * kSdTX + 1;  // stem window: 5 x 129
+    constexpr int FR = WR + 2, FC = WC + 2;                  // frame window: 7 x 131
+    constexpr int NE = kSdTX + 1;                            // pixels per parity plane (even: 65, odd: 64)
+    constexpr int PS = 40;                                   // elements per pixel slot (32 + 8 padding)
+    constexpr int NF = 3 * FR * FC, NLD = (NF + 255) / 256;
+    constexpr int NSB = (WR * WC + 15) / 16;                 // 16-pixel stem blocks (41)
+    constexpr bool split = __is_same(TO, f16);
+    typedef typename V16<TO>::type V;
+    __shared__ float fw[NF];
+    __shared__ __attribute__((aligned(16))) TO sw[WR * 2 * NE * PS];
+
+    // item -> frame, output tile origin (ty0, tx0) on the stride-2 level
+    struct Tile { int f, ty0, tx0, h1, w1; };
+    auto locate = [&](int item) {
+        Tile t{0, 0, 0, 0, 0};
+        for (;; ++t.f) {
+            t.h1 = geom[t.f * kGeomInts] >> 1;
+            t.w1 = geom[t.f * kGeomInts + 1] >> 1;
+            const int n = ((t.h1 + kSdTY - 1) / kSdTY) * ((t.w1 + kSdTX - 1) / kSdTX);
+            if (item < n || t.f + 1 >= nframes) break;
+            item -= n;
+        }
+        const int tw = (t.w1 + kSdTX - 1) / kSdTX;
+        t.ty0 = (item / tw) * kSdTY;
+        t.tx0 = (item % tw) * kSdTX;
+        return t;
+    };
+    float fv[NLD];
+    auto load = [&](const Tile& t) {  // frame window rows 2 ty0 - 2 .., columns 2 tx0 - 2 ..
+        const int* g = geom + t.f * kGeomInts;
+        const int h = g[0], wd = g[1];
+        const float* fr = frames + (size_t)g[2] * 3;
+#pragma unroll
+        for (int it = 0; it < NLD; ++it) {
+            const int i = threadIdx.x + it * 256;
+            const int cr = i / FC, j = i - cr * FC;
+            const int c = cr / FR, r = cr - c * FR;
+            const int iy = 2 * t.ty0 - 2 + r, ix = 2 * t.tx0 - 2 + j;
+            fv[it] = 0.f;
+            if (i < NF && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)wd)
+                fv[it] = fr[((size_t)c * h + iy) * wd + ix];
+        }
+    };
+    auto park = [&]() {
+#pragma unroll
+        for (int it = 0; it < NLD; ++it) {
+            const int i = threadIdx.x + it * 256;
+            if (i < NF) fw[i] = fv[it];
+        }
+    };
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p = lane & 15, kg = lane >> 4;
+    // stem operands of this lane: k = kg * 8 + j -> (r, s, c), weights as FP16 hi (+ lo)
+    int koff[8];
+    bool kval[8];
+    f16x8 wa[2], wl[2];
+    float bv[2][4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int k = kg * 8 + j;
+        const int r = k / 9, s = (k / 3) % 3, c = k % 3;
+        kval[j] = k < 27;
+        koff[j] = kval[j] ? (c * FR + r) * FC + s : 0;
+    }
+#pragma unroll
+    for (int cg = 0; cg < 2; ++cg) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float v = kval[j] ? w0[(cg * 16 + p) * 27 + kg * 8 + j] : 0.f;
+            wa[cg][j] = (f16)v;
+            wl[cg][j] = (f16)(v - (float)wa[cg][j]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[cg][i] = b0[cg * 16 + kg * 4 + i];
+    }
+    // conv weights of this wave's channel block, all 9 taps: lane = (channel p, k-slot kg)
+    V af[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) af[t] = *(const V*)(w1 + (size_t)(wave * 16 + p) * (9 * C0) + t * C0 + kg * 8);
+    float cb1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cb1[q] = b1[wave * 16 + kg * 4 + q];
+
+    int P = blockIdx.x;
+    if (P >= total) return;  // uniform over the workgroup
+    Tile t = locate(P);
+    load(t);
+    park();
+    __syncthreads();
+    for (; P < total; P += gridDim.x) {
+        const int* g = geom + t.f * kGeomInts;
+        const int h = g[0], wd = g[1];
+        // stem window: flat 16-pixel blocks over the 5 x 129 positions
+        for (int bi = wave; bi < NSB; bi += 4) {
+            const int q = bi * 16 + p;
+            const int R = q / WC, C = q - R * WC;
+            const bool valid = q < WR * WC;
+            f16x8 b, bl;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float v = (kval[j] && valid) ? fw[koff[j] + R * FC + C] : 0.f;
+                b[j] = (f16)v;
+                if constexpr (split) bl[j] = (f16)(v - (float)b[j]);
+            }
+            const int sy = 2 * t.ty0 - 1 + R, sx = 2 * t.tx0 - 1 + C;
+            const bool inside = valid && (unsigned)sy < (unsigned)h && (unsigned)sx < (unsigned)wd;
+#pragma unroll
+            for (int cg = 0; cg < 2; ++cg) {
+                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+                if constexpr (split) {
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[cg], b, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], bl, acc, 0, 0, 0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], b, acc, 0, 0, 0);
+                typedef TO T4 __attribute__((ext_vector_type(4)));
+                T4 pk;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pk[i] = (TO)(inside ? leaky01(acc[i] + bv[cg][i]) : 0.f);
+                if (valid) *(T4*)(&sw[((R * 2 + (C & 1)) * NE + (C >> 1)) * PS + cg * 16 + kg * 4]) = pk;
+            }
+        }
+        __syncthreads();  // stem window complete; the frame window is free
+        const int Pn = P + gridDim.x;
+        Tile tn = t;
+        if (Pn < total) {
+            tn = locate(Pn);
+            load(tn);  // in flight during the conv below
+        }
+        // the 3x3 stride-2 conv from LDS: 8 blocks of 16 pixels (2 rows x 64 columns)
+        f32x4 acc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tp = 0; tp < 9; ++tp) {
+            const int r = tp / 3, s = tp % 3;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int ty = i >> 2, tx = (i & 3) * 16 + p;  // output row, column within the tile
+                const V bf = *(const V*)(&sw[(((2 * ty + r) * 2 + (s & 1)) * NE + tx + (s >> 1)) * PS + kg * 8]);
+                if constexpr (__is_same(TO, bf16))
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[tp], bf, acc[i], 0, 0, 0);
+                else
+                    acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[tp], bf, acc[i], 0, 0, 0);
+            }
+        }
+        // epilogue: bias, leaky, store this wave's 16 channels (32 bytes of each 128-byte pixel row)
+        typedef TO T4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int oy = t.ty0 + (i >> 2), ox = t.tx0 + (i & 3) * 16 + p;
+            if (oy >= t.h1 || ox >= t.w1) continue;
+            T4 pk;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pk[q] = (TO)leaky01(acc[i][q] + cb1[q]);
+            *(T4*)(out + ((size_t)g[2 + 1] + (size_t)oy * t.w1 + ox) * C1 + wave * 16 + kg * 4) = pk;
+        }
+        __syncthreads();  // every wave is done with the stem window
+        if (Pn < total) park();
+        __syncthreads();
+        t = tn;
+    }
+}
+
+hipError_t launch_stem_down(const float* frames, const int* geom, int nframes, int tiles, const float* w0,
+                            const float* b0, const void* w1, const float* b1, void* out, int out_type,
+                            hipStream_t s) {
+    // persistent: 2 workgroups per compute unit (63 KB of LDS each), all resident
+    dim3 grid(tiles < 512 ? tiles : 512), block(256);
+    if (out_type == kBF16)
+        stem_down_kernel<bf16><<<grid, block, 0, s>>>(frames, geom, nframes, tiles, w0, b0, (const bf16*)w1, b1,
+                                                      (bf16*)out);
+    else if (out_type == kF16)
+        stem_down_kernel<f16><<<grid, block, 0, s>>>(frames, geom, nframes, tiles, w0, b0, (const f16*)w1, b1,
+                                                     (f16*)out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+int stem_down_tiles(int h, int w) { return ((h / 2 + kSdTY - 1) / kSdTY) * ((w / 2 + kSdTX - 1) / kSdTX); }
+
 hipError_t launch_stem(const float* frames, const int* geom, int nframes, int uniform, int rows, int max_w,
                        int M, const float* w, const float* bias, int cout, void* out, int out_type,
                        hipStream_t s) {

@@ -66,6 +66,12 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
                        int M, const float* w, const float* bias, int cout, void* out, int out_type,
                        hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, int elem_type, int tile_cfg, hipStream_t s);
+// Stem fused with the first 3x3 stride-2 conv (c0 = 32 -> 64, 16-bit storage):
+// frames -> stride-2 level output; `tiles` = sum over frames of stem_down_tiles(h, w).
+hipError_t launch_stem_down(const float* frames, const int* geom, int nframes, int tiles, const float* w0,
+                            const float* b0, const void* w1, const float* b1, void* out, int out_type,
+                            hipStream_t s);
+int stem_down_tiles(int h, int w);
 // FP8 e4m3 convolution: BF16 activations quantised on load with in_scale, FP8
 // weights with per-channel wscale; needs cin % 128 == 0 and no concat.
 hipError_t launch_conv_fp8(const ConvArgs& a, int tile_cfg, hipStream_t s);

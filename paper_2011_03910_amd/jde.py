@@ -364,6 +364,10 @@ class JDE:
               "jde_fp8_scales")
         return out
 
+    def fuse_stem(self, on=True):
+        """Run the stem and the first downsample conv as one launch (16-bit only)."""
+        check(self.lib.jde_fuse_stem(self.ctx, 1 if on else 0), "jde_fuse_stem")
+
     def profile_begin(self, on=True):
         check(self.lib.jde_profile_begin(self.ctx, 1 if on else 0), "jde_profile_begin")
 

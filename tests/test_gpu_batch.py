@@ -155,6 +155,33 @@ def test_ragged_batch_matches_oracle_per_frame(torch):
         np.testing.assert_allclose(a["boxes"], b["boxes"], rtol=1e-5, atol=1e-3)
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_fused_stem_equals_unfused(torch, precision):
+    """The fused stem + first downsample launch computes what the two separate
+    launches compute (same roundings, same accumulation order), on a ragged batch
+    of three full-size resolutions; the fused path is also what the full-size
+    oracle parity tests run."""
+    _say(f"case: fused stem {precision} ragged")
+    sizes = [(608, 1088), (320, 576), (480, 864)]
+    m = _model(FULL, precision, 3)
+    m.load_weights(weights("full", 40))
+    frs = [frames("full", 1, 0, h, w)[0] for h, w in sizes]
+    packed = torch.from_numpy(np.concatenate([f.ravel() for f in frs])).cuda()
+    fused = head_views(m.forward(packed, sizes), sizes)
+    m.fuse_stem(False)
+    plain = head_views(m.forward(packed, sizes), sizes)
+    torch.cuda.synchronize()
+    worst, same = 0.0, True
+    for key in ("det", "emb"):
+        for s in range(3):
+            for i in range(3):
+                worst = max(worst, rel_err(fused[key][s][i], plain[key][s][i]))
+                same = same and np.array_equal(fused[key][s][i], plain[key][s][i])
+    _say(f"  fused vs two launches: rel err {worst:.2e}, bitwise equal {same}")
+    assert worst <= 1e-6
+
+
 def test_graph_replays_equal_eager(torch):
     """A captured forward+decode+cost step, replayed several times with eager
     work between replays and with new frame contents, equals the eager step."""
