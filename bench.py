@@ -102,20 +102,28 @@ class Pipeline:
         self.m.decode(self.heads, self.descs, CONF, NMS_IOU, dets=self.dets)
         self.m.cost_batch(trk_emb, mean, cov, self.track_begin, self.dets, cost=self.cost)
 
+    def capture(self, frames, trk_emb, mean, cov):
+        """The same step captured once as a HIP graph (replayed per step)."""
+        s = self.torch.cuda.Stream()
+        self.graph = self.m.graph_capture(frames, self.descs, self.heads, self.dets, CONF, NMS_IOU,
+                                          tracks=(trk_emb, mean, cov, self.track_begin), cost=self.cost, stream=s)
+        self.torch.cuda.synchronize()
 
-def run(pipe, inputs, steps, warmup, torch, profile=False):
+
+def run(pipe, inputs, steps, warmup, torch, profile=False, graph=False):
+    stream = torch.cuda.current_stream()
+    one = (lambda: pipe.graph.launch(stream)) if graph else (lambda: pipe.step(*inputs))
     for _ in range(warmup):
-        pipe.step(*inputs)
+        one()
     torch.cuda.synchronize()
     if profile:
         pipe.m.profile_begin(True)
-    stream = torch.cuda.current_stream()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         evs[i][0].record(stream)
-        pipe.step(*inputs)
+        one()
         evs[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -185,6 +193,8 @@ def main():
     ap.add_argument("--save-tiles", help="write the tile choices to this JSON file")
     ap.add_argument("--load-tiles", help="use tile choices from this JSON file instead of tuning")
     ap.add_argument("--retune", action="store_true", help="run the autotuner instead of the stored tile choices")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager launches instead of replaying the step as a captured HIP graph")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one plain elementwise copy of this many MiB (FP32 negate, read N + write N "
                          "bytes): the reference dispatch that scales hardware byte counters")
@@ -222,7 +232,15 @@ def main():
                     saved.get(key), calib_frames=inputs_b[0])
     tiles_out = {key: None if pipe.tiles is None else pipe.tiles.tolist()}
     traffic = measured_traffic(key, tiles_out[key])
-    wall, step_ms, prof = run(pipe, inputs_b, args.steps, args.warmup, torch, profile=True)
+    # Throughput and latency from a timed pass with no per-launch events; the
+    # per-launch durations (roofline) from a second timed pass of the same steps in
+    # which the library brackets every launch with a HIP event pair.
+    if not args.eager:
+        pipe.capture(*inputs_b)
+    wall, step_ms, _ = run(pipe, inputs_b, args.steps, args.warmup, torch, graph=not args.eager)
+    wall_p, step_ms_p, prof = run(pipe, inputs_b, args.steps, 1, torch, profile=True)
+    log(f"{'graph replay' if not args.eager else 'eager'}: {1e3 * wall / args.steps:.3f} ms/step; eager with "
+        f"per-launch events: {1e3 * wall_p / args.steps:.3f} ms/step")
     fps = args.batch * args.steps / wall
     counts = pipe.dets["count"].cpu().numpy()
     ncand = pipe.dets["n_cand"].cpu().numpy()

@@ -471,15 +471,30 @@ __global__ __launch_bounds__(256) void cost_kernel(const float* __restrict__ fe,
     }
     const int ty = tid >> 4, tx = tid & 15;  // rows ty*2 + {0,1}, cols tx*2 + {0,1}
     float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
-    for (int e0 = 0; e0 < E; e0 += 64) {
-        __syncthreads();
-        for (int v = tid; v < 32 * 64; v += 256) {
+    // 64-wide slices of the embeddings: all loads of a slice in flight at once, the
+    // next slice loading while the current one is reduced
+    float rf[8], re[8];
+    auto fetch = [&](int e0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int v = tid + k * 256;
             const int r = v >> 6, c = v & 63;
             const int t = t0 + r, d = d0 + r, e = e0 + c;
-            sf[r][c] = (t < T && e < E) ? fe[(size_t)t * E + e] : 0.f;
-            se[r][c] = (d < D && e < E) ? de[(size_t)d * E + e] : 0.f;
+            rf[k] = (t < T && e < E) ? fe[(size_t)t * E + e] : 0.f;
+            re[k] = (d < D && e < E) ? de[(size_t)d * E + e] : 0.f;
+        }
+    };
+    fetch(0);
+    for (int e0 = 0; e0 < E; e0 += 64) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int v = tid + k * 256;
+            sf[v >> 6][v & 63] = rf[k];
+            se[v >> 6][v & 63] = re[k];
         }
         __syncthreads();
+        if (e0 + 64 < E) fetch(e0 + 64);
 #pragma unroll 8
         for (int c = 0; c < 64; ++c) {
             const float f0 = sf[ty * 2][c], f1 = sf[ty * 2 + 1][c];
