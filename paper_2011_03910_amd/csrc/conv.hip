@@ -925,13 +925,14 @@ constexpr int waitcnt_imm(int vm, int lgkm) { return (vm & 15) | ((vm >> 4) << 1
 __device__ __forceinline__ int dma_swizzle(int r) { return ((r >> 1) & 1) ^ (((r >> 2) & 1) << 1) ^ ((r >> 3) & 1); }
 
 template <typename T, int BM, int BN, int WGM, int WGN, int S, bool NT>
-__global__ __launch_bounds__(256) void conv_dma(ConvArgs a) {
+__global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
+    constexpr int NW = WGM * WGN;                  // waves (4 or 8)
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
     constexpr int TM = WTM / 16, TN = WTN / 16;
     constexpr int ROWS = BM + BN, SB = ROWS * 64;  // bytes per stage
-    constexpr int NPW = ROWS / 64;                 // DMA instructions per wave per chunk
-    static_assert(WGM * WGN == 4 && TM >= 1 && TN >= 1, "4 waves");
-    static_assert(BM % 64 == 0 && BN % 64 == 0 && S >= 3 && S <= 4, "tile");
+    constexpr int NPW = ROWS / (16 * NW);          // DMA instructions per wave per chunk
+    static_assert((NW == 4 || NW == 8) && TM >= 1 && TN >= 1, "4 or 8 waves");
+    static_assert(BM % (16 * NW) == 0 && BN % (16 * NW) == 0 && S >= 3 && S <= 4, "tile");
     typedef typename V16<T>::type V;
 
     __shared__ __attribute__((aligned(1024))) char st0[SB];
@@ -949,7 +950,7 @@ __global__ __launch_bounds__(256) void conv_dma(ConvArgs a) {
     const __amdgpu_buffer_rsrc_t r_w = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, a.w_bytes, kBufFlags);
 
     // Row descriptors of this lane's DMA instructions (instruction i of this
-    // wave fills rows 16 q .. 16 q + 15 of a stage, q = 4 i + wave):
+    // wave fills rows 16 q .. 16 q + 15 of a stage, q = NW i + wave):
     //   d_off:  element offset of the row's origin (+ its k-slot);
     //   d_wc:   elements between kernel rows (image width x Cin for a pixel row,
     //           k x Cin for a weight row);
@@ -961,12 +962,12 @@ __global__ __launch_bounds__(256) void conv_dma(ConvArgs a) {
     const int taps = a.ksz * a.ksz;
 #pragma unroll
     for (int i = 0; i < NPW; ++i) {
-        const int q = 4 * i + wave;
+        const int q = NW * i + wave;
         const int row = 16 * q + rloc;
         d_off[i] = 0;
         d_wc[i] = 0;
         d_mask[i] = 0;
-        if (64 * i < BN) {  // weight row: channel n0 + row (BN % 64 == 0: static per i)
+        if (16 * NW * i < BN) {  // weight row: channel n0 + row (BN % (16 NW) == 0: static per i)
             const int n = n0 + row;
             if (n < a.cout) {
                 d_off[i] = n * a.K + kslot;
@@ -1003,11 +1004,11 @@ __global__ __launch_bounds__(256) void conv_dma(ConvArgs a) {
         const int sc = ld_s * a.cin + ld_ci;
 #pragma unroll
         for (int i = 0; i < NPW; ++i) {
-            const int q = 4 * i + wave;
+            const int q = NW * i + wave;
             const bool ok = (d_mask[i] >> tap) & 1;
             const int off = ok ? (d_off[i] + ld_r * d_wc[i] + sc) * (int)sizeof(T) : kOOB;
             const char* sp = u == 0 ? st0 : u == 1 ? st1 : u == 2 ? st2 : st3;
-            dma16(64 * i < BN ? r_w : r_in, sp + q * 1024, off);
+            dma16(16 * NW * i < BN ? r_w : r_in, sp + q * 1024, off);
         }
         ++issued;
         ld_ci += 32;
@@ -1346,6 +1347,9 @@ static constexpr TileCfg kTiles[] = {
     {128, 64, 2, 2, 32, 3, 0},   // 26: direct-to-LDS, 3 stages (36 KB: 4 workgroups per CU)
     {64, 64, 2, 2, 32, 4, 0},    // 27: direct-to-LDS, 32x32 per wave (32 KB: 5 per CU)
     {64, 64, 2, 2, 32, 3, 0},    // 28: direct-to-LDS, 3 stages (24 KB: 6 per CU)
+    {256, 128, 4, 2, 32, 3, 0},  // 29: direct-to-LDS, 8 waves of 64x64 (72 KB)
+    {128, 256, 2, 4, 32, 3, 0},  // 30: direct-to-LDS, 8 waves of 64x64 (72 KB)
+    {256, 128, 4, 2, 32, 3, 1},  // 31: as 29, streaming stores
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
@@ -1415,7 +1419,7 @@ static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
         return hipErrorInvalidValue;
     } else {
         constexpr TileCfg t = kTiles[C];
-        dim3 grid(((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn)), block(256);
+        dim3 grid(((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn)), block(64 * t.wgm * t.wgn);
         if constexpr (t.st > 0)
             conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0><<<grid, block, 0, s>>>(a);
         else if (aligned)
@@ -1460,6 +1464,9 @@ static hipError_t launch_type(const ConvArgs& a, int c, bool aligned, hipStream_
         case 26: return launch_t<T, 26>(a, aligned, s);
         case 27: return launch_t<T, 27>(a, aligned, s);
         case 28: return launch_t<T, 28>(a, aligned, s);
+        case 29: return launch_t<T, 29>(a, aligned, s);
+        case 30: return launch_t<T, 30>(a, aligned, s);
+        case 31: return launch_t<T, 31>(a, aligned, s);
     }
     return hipErrorInvalidValue;
 }

@@ -189,6 +189,26 @@ def test_assign_matches_oracle(rng, t_n, d_n):
             assert len(set(pairs[:, 1])) == len(pairs)
 
 
+def test_assign_with_forbidden_rows_and_columns_matches_oracle(rng):
+    """Tracks or detections with no allowed entry can never be matched; the
+    assignment (which drops them before its search) still equals the oracle's."""
+    import paper_2011_03910_amd as P
+    for T, D in ((30, 12), (12, 30), (25, 25)):
+        for trial in range(4):
+            c = rng.uniform(0, 1.3, (T, D)).astype(np.float32)
+            c[rng.random(T) < 0.5, :] = np.inf          # whole tracks forbidden
+            c[:, rng.random(D) < 0.3] = np.inf          # whole detections forbidden
+            c[rng.random(c.shape) < 0.3] = np.inf
+            pairs, total = P.jde_assign(c, 0.7)
+            rp, rt = otrack.assign(c.astype(np.float64), 0.7)
+            assert len(pairs) == len(rp) and total == pytest.approx(rt, abs=1e-9)
+    assert len(P.jde_assign(np.full((40, 9), np.inf, np.float32), 0.7)[0]) == 0
+    one = np.full((50, 20), np.inf, np.float32)
+    one[17, 3] = 0.25
+    pairs, total = P.jde_assign(one, 0.7)
+    assert pairs.tolist() == [[17, 3]] and total == pytest.approx(0.25)
+
+
 def test_fp8_encoder_matches_library_cast():
     """The weight encoder (host, product) equals torch's float8_e4m3fn cast on
     in-range values, saturates to 448 and maps NaN to 0x7f."""
