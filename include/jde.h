@@ -177,6 +177,15 @@ jde_status jde_fp8_scales(const jde_ctx* ctx, float* in_scales, int n_ops);
  * configurations always run unfused.  In jde_profile_collect the fused launch is
  * kind 2 at op 0 and op 1 is kind 3 with no time or FLOPs of its own. */
 jde_status jde_fuse_stem(jde_ctx* ctx, int on);
+/* With on != 0 (the default), 16-bit contexts run each residual block of 64 or
+ * 128 channels (Sec. 3.1 backbone: 1x1 C -> C/2, 3x3 C/2 -> C, leaky, + input)
+ * as one launch that keeps the C/2-channel intermediate in on-chip memory and
+ * reads the block input once; on = 0 runs the two convs as two launches.  Same
+ * network, same roundings.  Blocks whose convs run in FP8, and calibration
+ * forwards, always run unfused.  In jde_profile_collect the fused launch is kind
+ * 4 at the block's first conv and the second conv is kind 5 with no time or
+ * FLOPs of its own. */
+jde_status jde_fuse_blocks(jde_ctx* ctx, int on);
 /* Host helper: x (host, n floats) -> OCP e4m3 codes (host, n bytes), round to
  * nearest even, saturating at +-448, NaN -> 0x7f; the encoding of the weights. */
 void jde_fp8_encode(const float* x, uint8_t* out, size_t n);
@@ -264,7 +273,8 @@ jde_status jde_profile_begin(jde_ctx* ctx, int on);
 /* Waits for the recorded events and returns, per forward launch i < *n_ops
  * (launch order; at most max_ops entries written): summed duration in ms over
  * the profiled forwards (op_ms), FLOPs of one launch for the last batch
- * (op_flop: 2*M*N*K), kind (op_kind: 0 = stem, 1 = MFMA conv).  *n_fwd gets
+ * (op_flop: 2*M*N*K), kind (op_kind: 0 = stem, 1 = MFMA conv; 2-5 = fused
+ * launches, see jde_fuse_stem and jde_fuse_blocks).  *n_fwd gets
  * the number of forwards summed.  All arrays host. */
 jde_status jde_profile_collect(jde_ctx* ctx, int max_ops, double* op_ms, double* op_flop, int* op_kind,
                                int* n_ops, int* n_fwd);

@@ -89,9 +89,13 @@ struct jde_ctx {
     bool loaded = false;
     int n_backbone_ops = 0;
     bool fp8 = false, fp8_ready = false, calibrating = false;
-    // The stem and the first downsample conv run as one launch (16-bit storage);
-    // last_fused records whether the latest forward did.
-    bool fuse_stem = true, last_fused = false;
+    // The stem and the first downsample conv run as one launch (16-bit storage),
+    // and so do the two convs of each 64- and 128-channel residual block.
+    // launch_kind[i] records how op i ran in the latest forward: 0 = its own
+    // launch, 2 / 4 = head of a fused stem / residual-block launch, 3 / 5 = run
+    // inside the previous op's fused launch.
+    bool fuse_stem = true, fuse_blocks = true;
+    std::vector<int> launch_kind;
     size_t ws_amax = 0;
     // Per-launch timing: a ring of event pairs, one entry per profiled forward.
     static constexpr int kRing = 8;
@@ -171,13 +175,19 @@ void build_plan(jde_ctx* c) {
         const int t = add_tensor(s, ch);
         add_op(OP_CONV, down, x, t, s - 1, s);
         x = t;
+        // Blocks of 64 and 128 channels write a new tensor (the fused block
+        // launch reads a halo of x around each output tile); the others run in
+        // place.  Either way out = leaky(conv) + x.
+        const bool out_of_place = ch == 64 || ch == 128;
         for (int b = 0; b < g.blocks[s - 1]; ++b) {
             const int c1 = add_layer(ch / 2, 1, ch, 1);
             const int c2 = add_layer(ch, 3, ch / 2, 1);
             const int mid = add_tensor(s, ch / 2);
             add_op(OP_CONV, c1, x, mid, s, s);
-            const int o = add_op(OP_CONV, c2, mid, x, s, s);
-            c->ops[o].res_t = x;   // in place: out = leaky(conv) + x
+            const int y = out_of_place ? add_tensor(s, ch) : x;
+            const int o = add_op(OP_CONV, c2, mid, y, s, s);
+            c->ops[o].res_t = x;
+            x = y;
         }
         feat[s] = x;
     }
@@ -439,6 +449,19 @@ static bool stem_fusable(const jde_ctx* c, const Op& stem, const Op& o1) {
            o1.res_t < 0 && o1.act && o1.n_split == o1.cout && !runs_fp8(c, o1);
 }
 
+// A 64- or 128-channel residual block (1x1 C -> C/2, then 3x3 C/2 -> C + x,
+// written out of place) runs as one launch for 16-bit storage, except while
+// calibrating and when either conv runs in FP8.
+static bool block_fusable(const jde_ctx* c, const Op& o1, const Op& o2) {
+    return c->fuse_blocks && !c->calibrating && c->et != kF32 && o1.kind == OP_CONV && o2.kind == OP_CONV &&
+           (o1.cin == 64 || o1.cin == 128) && o1.ksz == 1 && o1.stride == 1 && 2 * o1.cout == o1.cin &&
+           o1.cin1 == 0 && o1.in2_t < 0 && o1.res_t < 0 && o1.act && o1.n_split == o1.cout && o1.layer2 < 0 &&
+           o1.lvl_in == o1.lvl_out && o2.ksz == 3 && o2.stride == 1 && o2.cin == o1.cout && o2.cout == o1.cin &&
+           o2.in_t == o1.out_t && o2.res_t == o1.in_t && o2.out_t >= 0 && o2.out_t != o1.in_t && o2.cin1 == 0 &&
+           o2.in2_t < 0 && o2.act && o2.n_split == o2.cout && o2.layer2 < 0 && o2.lvl_in == o1.lvl_out &&
+           o2.lvl_out == o1.lvl_out && !runs_fp8(c, o1) && !runs_fp8(c, o2);
+}
+
 }  // namespace
 
 // ---- setup kernel: geometry table + counter reset ---------------------------
@@ -604,7 +627,10 @@ jde_status jde_profile_collect(jde_ctx* c, int max_ops, double* op_ms, double* o
     for (int i = 0; i < n && i < max_ops; ++i) {
         if (op_ms) op_ms[i] = i < (int)c->op_ms.size() ? c->op_ms[i] : 0.0;
         if (op_flop) op_flop[i] = i < (int)c->op_flop.size() ? c->op_flop[i] : 0.0;
-        if (op_kind) op_kind[i] = (c->last_fused && i == 0) ? 2 : (c->last_fused && i == 1) ? 3 : c->ops[i].kind;
+        if (op_kind) {
+            const int lk = i < (int)c->launch_kind.size() ? c->launch_kind[i] : 0;
+            op_kind[i] = lk ? lk : c->ops[i].kind;
+        }
     }
     if (n_ops) *n_ops = n;
     if (n_fwd) *n_fwd = c->n_fwd;
@@ -709,7 +735,7 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
         c->pending[slot] = true;
         c->ring_pos = (slot + 1) % jde_ctx::kRing;
     }
-    c->last_fused = false;
+    c->launch_kind.assign(c->ops.size(), 0);
     for (size_t oi = 0; oi < c->ops.size(); ++oi) {
         const Op& o = c->ops[oi];
         const char* wb = c->d_weights;
@@ -728,7 +754,29 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
                 c->op_flop[oi] = 2.0 * M0 * o.cout * 27 + 2.0 * M1 * o1.cout * o1.ksz * o1.ksz * o1.cin;
                 c->op_flop[oi + 1] = 0.0;
             }
-            c->last_fused = true;
+            c->launch_kind[oi] = 2;
+            c->launch_kind[oi + 1] = 3;
+            ++oi;
+            continue;
+        }
+        if (o.kind == OP_CONV && oi + 1 < c->ops.size() && block_fusable(c, o, c->ops[oi + 1])) {
+            const Op& o2 = c->ops[oi + 1];
+            const int C = o.cin, lvl = o.lvl_in;
+            int tiles = 0;
+            for (int f = 0; f < n; ++f) tiles += resblock_tiles(C, d[f].h >> lvl, d[f].w >> lvl);
+            const size_t M = level_pixels(d, n, lvl);
+            HIP_TRY(launch_resblock(tptr(o.in_t), tptr(o2.out_t), wb + o.dev_w, (const float*)(wb + o.dev_b),
+                                    wb + o2.dev_w, (const float*)(wb + o2.dev_b), geom, n, lvl, C, tiles,
+                                    M * C * elem_bytes(c->et), c->et, s));
+            if (pev) {
+                HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));
+                HIP_TRY(hipEventRecord(pev[2 * oi + 2], s));
+                HIP_TRY(hipEventRecord(pev[2 * oi + 3], s));
+                c->op_flop[oi] = 2.0 * M * o.cout * o.cin + 2.0 * M * o2.cout * 9.0 * o2.cin;
+                c->op_flop[oi + 1] = 0.0;
+            }
+            c->launch_kind[oi] = 4;
+            c->launch_kind[oi + 1] = 5;
             ++oi;
             continue;
         }
@@ -1019,6 +1067,12 @@ jde_status jde_calibrate(jde_ctx* c, const float* frames, const jde_frame_desc* 
 jde_status jde_fuse_stem(jde_ctx* c, int on) {
     if (!c) return fail(JDE_EINVAL, "null context");
     c->fuse_stem = on != 0;
+    return JDE_OK;
+}
+
+jde_status jde_fuse_blocks(jde_ctx* c, int on) {
+    if (!c) return fail(JDE_EINVAL, "null context");
+    c->fuse_blocks = on != 0;
     return JDE_OK;
 }
 

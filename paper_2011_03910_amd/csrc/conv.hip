@@ -682,7 +682,11 @@ template <typename T, int BM, int BN, int WGM, int WGN, int BK, bool ALIGNED>
 __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
     constexpr int VEC = 16 / sizeof(T);
     constexpr int VR = BK / VEC;
-    constexpr int LDR = BK + VEC;  // padded LDS row, in elements
+    // Padded LDS row, in elements.  16-bit types: 32 bytes of padding make the
+    // row stride an odd multiple of 32 bytes (96 or 160), so the 16 rows x 2
+    // k-slots one ds_read_b128 serves at a time hit distinct 16-byte units
+    // modulo 512 bytes.  FP32 (the checking path) keeps 16 bytes.
+    constexpr int LDR = BK + (sizeof(T) == 4 ? VEC : 2 * VEC);
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
     constexpr int TM = WTM / 16, TN = WTN / 16;
     constexpr int BVEC = BM * VR, AVEC = BN * VR;
@@ -922,7 +926,14 @@ __device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, const void* lds,
 
 constexpr int waitcnt_imm(int vm, int lgkm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | (lgkm << 8); }
 
-__device__ __forceinline__ int dma_swizzle(int r) { return ((r >> 1) & 1) ^ (((r >> 2) & 1) << 1) ^ ((r >> 3) & 1); }
+// 16-byte slot swizzle of the 64-byte LDS rows.  A wave's ds_read_b128 is served
+// 32 lanes at a time and runs at full rate (256 B/clk per CU) only if those 32
+// lanes -- 16 consecutive rows x 2 k-slots here -- touch distinct 16-byte units
+// modulo 512 bytes.  Rows r and r + 8 share units modulo 512, so row bit 3 flips
+// slot bit 1 (their slot pairs {0,1} and {2,3} become disjoint).  Measured on
+// gfx950: the unswizzled layout and an XOR of row bits 1-3 into both slot bits
+// both run at half rate.
+__device__ __forceinline__ int dma_swizzle(int r) { return ((r >> 3) & 1) << 1; }
 
 template <typename T, int BM, int BN, int WGM, int WGN, int S, bool NT>
 __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
@@ -1312,6 +1323,312 @@ hipError_t launch_conv_fp8(const ConvArgs& a, int c, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Residual block fused into one launch (16-bit storage, C = 64 or 128):
+//   out = leaky(b2 + W2 (*) y) + x,   y = leaky(b1 + W1 x)  (1x1 C -> C/2, then
+// 3x3 C/2 -> C; Sec. 3.1's Darknet-53 blocks).  The C/2-channel intermediate y
+// never goes to HBM, and x is read once (as the 1x1's input and as the
+// residual).  Work items are TY x TX tiles of output pixels (all C channels),
+// walked by persistent workgroups (8 waves, one per compute unit); the items
+// are split into 8 contiguous bands, one per XCD, so that tiles whose windows
+// overlap are fetched into the same L2.  Per tile:
+//   * the (TY + 2) x (TX + 2)-pixel window of x (zero outside the frame) is in
+//     LDS, brought in by direct-to-LDS loads while the previous tile computes
+//     (two window buffers);
+//   * y over the whole window, on MFMA (A = W1 rows, B = window pixels), stored
+//     in LDS in the storage type -- the rounding of a stored y -- with the
+//     conv's zero padding at window positions outside the frame;
+//   * the 3x3 conv from LDS, K = 9 taps x C/2 in the unfused GEMM's order (tap-
+//     major, then 32-channel k-steps), bias, leaky, + x (from the window),
+//     stored to `out` (not x: neighbouring tiles still read x's halo).
+// Wave roles (8 waves, two per SIMD): in the 1x1, a wave owns GA groups of 16 y
+// channels (weights in registers) over a strided set of 16-pixel blocks; in the
+// 3x3 a wave owns JB groups of 16 output channels (JB MFMA blocks share each
+// pixel operand; weights of all 9 taps in registers: 36 JB registers per
+// 32-channel k-step) over a part of the tile's pixels.  C = 128 takes JB = 1 so
+// that the weights fit beside the accumulators.
+// Pixel rows in LDS are padded by 32 bytes (x: 2C + 32, y: C + 32 bytes per
+// pixel: 6, 10 or 18 16-byte units, twice an odd number), so that 16 consecutive
+// pixels at two k-slots -- the 32 lanes a ds_read_b128 serves at once -- hit
+// distinct 16-byte units modulo 512 bytes (full LDS rate), and every operand
+// address is a per-lane base plus an immediate offset.
+// ---------------------------------------------------------------------------
+// f(integral_constant<int, I>) for I = B .. E - 1, in order
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+template <int C> struct RbCfg;
+template <> struct RbCfg<64> { static constexpr int TY = 8, TX = 32, GA = 2, JB = 2, NW = 8; };
+template <> struct RbCfg<128> { static constexpr int TY = 8, TX = 16, GA = 1, JB = 1, NW = 8; };
+
+template <typename T, int C>
+__global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __restrict__ x, T* __restrict__ out,
+                                                       const T* __restrict__ w1, const float* __restrict__ b1,
+                                                       const T* __restrict__ w2, const float* __restrict__ b2,
+                                                       const int* __restrict__ geom, int nframes, int lvl,
+                                                       int total, int x_bytes) {
+    constexpr int C2 = C / 2, NW = RbCfg<C>::NW;
+    constexpr int TY = RbCfg<C>::TY, TX = RbCfg<C>::TX, GA = RbCfg<C>::GA, JB = RbCfg<C>::JB;
+    constexpr int WY = TY + 2, WX = TX + 2, NPX = WY * WX;
+    constexpr int NBA = (NPX + 15) / 16, NPXP = NBA * 16;        // 1x1 blocks over the window
+    constexpr int XS = C * 2 + 32, YS = C2 * 2 + 32;              // LDS bytes per pixel (padded)
+    constexpr int XSL = C / 8;                                    // 16-byte slots of x per pixel
+    constexpr int NDMA = (NPXP * XS + 1023) / 1024, DPW = (NDMA + NW - 1) / NW;  // 1-KB DMAs per window
+    constexpr int XB = NDMA * 1024;                               // bytes per window buffer
+    constexpr int NGA = C2 / 16, GSETS = NGA / GA;                // 1x1: y-channel group sets
+    constexpr int NGB = C / (16 * JB), PG = NW / NGB;             // 3x3: channel groups, pixel groups
+    constexpr int BPR = TX / 16, NBB = TY * BPR, BPW = NBB / PG;   // 3x3: 16-pixel blocks
+    constexpr int KA = C / 32, KB = C2 / 32;                      // k-steps per tap
+    static_assert(NGA % GA == 0 && NW % NGB == 0 && NBB % PG == 0 && BPW % BPR == 0, "tile");
+    static_assert(2 * XB + NPXP * YS <= 160 * 1024, "LDS");
+    typedef typename V16<T>::type V;
+    typedef T T4 __attribute__((ext_vector_type(4)));
+
+    __shared__ __attribute__((aligned(1024))) char xw[2][XB];
+    __shared__ __attribute__((aligned(1024))) char yw[NPXP * YS];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int p = lane & 15, kg = lane >> 4;
+    const __amdgpu_buffer_rsrc_t r_x = __builtin_amdgcn_make_buffer_rsrc((void*)x, 0, x_bytes, kBufFlags);
+
+    // weights of this wave, for the workgroup's life
+    const int gset = wave % GSETS;
+    V a1[GA][KA];
+    float bb1[GA][4];
+#pragma unroll
+    for (int g = 0; g < GA; ++g) {
+        const int ch = (gset * GA + g) * 16;
+#pragma unroll
+        for (int kk = 0; kk < KA; ++kk) a1[g][kk] = *(const V*)(w1 + (size_t)(ch + p) * C + kk * 32 + kg * 8);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bb1[g][q] = b1[ch + kg * 4 + q];
+    }
+    const int cg = wave % NGB, pg = wave / NGB;
+    V a2[JB][9][KB];
+    float bb2[JB][4];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+        const int ch = (cg * JB + j) * 16;
+#pragma unroll
+        for (int tp = 0; tp < 9; ++tp)
+#pragma unroll
+            for (int kk = 0; kk < KB; ++kk)
+                a2[j][tp][kk] = *(const V*)(w2 + (size_t)(ch + p) * (9 * C2) + tp * C2 + kk * 32 + kg * 8);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bb2[j][q] = b2[ch + kg * 4 + q];
+    }
+
+    // item -> frame, tile origin, level size, first packed pixel of the frame
+    struct Tile { int ty0, tx0, h, w, base; };
+    auto locate = [&](int item) {
+        Tile t{0, 0, 0, 0, 0};
+        int f = 0;
+        for (;; ++f) {
+            t.h = geom[f * kGeomInts] >> lvl;
+            t.w = geom[f * kGeomInts + 1] >> lvl;
+            const int n = ((t.h + TY - 1) / TY) * ((t.w + TX - 1) / TX);
+            if (item < n || f + 1 >= nframes) break;
+            item -= n;
+        }
+        const int tw = (t.w + TX - 1) / TX;
+        t.ty0 = (item / tw) * TY;
+        t.tx0 = (item % tw) * TX;
+        t.base = geom[f * kGeomInts + 2 + lvl];
+        return t;
+    };
+    // window DMA: lane i of instruction q fills the 16-byte LDS slot 64 q + i,
+    // i.e. slot s of window pixel px (s >= XSL is the padding: zeros)
+    auto issue = [&](const Tile& t, int buf) {
+#pragma unroll
+        for (int i = 0; i < DPW; ++i) {
+            const int q = wave + NW * i;
+            if (q < NDMA) {  // wave-uniform
+                const int L = q * 64 + lane;
+                const int px = L / (XSL + 2), s = L - px * (XSL + 2);
+                const int wy = px / WX, wx = px - wy * WX;
+                const int iy = t.ty0 - 1 + wy, ix = t.tx0 - 1 + wx;
+                const bool ok = s < XSL && px < NPX && (unsigned)iy < (unsigned)t.h && (unsigned)ix < (unsigned)t.w;
+                const int off = ok ? ((t.base + iy * t.w + ix) * C + s * 8) * (int)sizeof(T) : kOOB;
+                // the LDS address is wave-uniform; buf lives in a vector register
+                const unsigned la = __builtin_amdgcn_readfirstlane(
+                    (unsigned)(unsigned long)(lds_ptr_t)&xw[0][0] + (unsigned)(buf * XB + q * 1024));
+                asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+                             :
+                             : "s"(la), "v"(off), "s"(r_x)
+                             : "memory", "m0");
+            }
+        }
+    };
+
+    const int per = gridDim.x / kXCDs, xcd = blockIdx.x % kXCDs;
+    const int band = (total + kXCDs - 1) / kXCDs;
+    const int lo = xcd * band, hi = lo + band < total ? lo + band : total;
+    int P = lo + (int)blockIdx.x / kXCDs;
+    if (P >= hi) return;  // uniform over the workgroup
+    Tile t = locate(P);
+    issue(t, 0);
+    for (int it = 0; P < hi; ++it, P += per) {
+        const int buf = it & 1;
+        // this tile's window has landed (and the previous tile's stores are done);
+        // every wave has finished the previous tile's 3x3 (y is free)
+        __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
+        __syncthreads();
+        const char* xb = xw[buf];
+        // 1x1 over the window -> y (LDS)
+        for (int blk = wave / GSETS; blk < NBA; blk += NW / GSETS) {
+            const int px = blk * 16 + p;
+            f32x4 acc[GA];
+#pragma unroll
+            for (int g = 0; g < GA; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < KA; ++kk) {
+                const V bf = *(const V*)(xb + px * XS + (kk * 4 + kg) * 16);
+#pragma unroll
+                for (int g = 0; g < GA; ++g) {
+                    if constexpr (__is_same(T, bf16))
+                        acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[g][kk], bf, acc[g], 0, 0, 0);
+                    else
+                        acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1[g][kk], bf, acc[g], 0, 0, 0);
+                }
+            }
+            const int wy = px / WX, wx = px - wy * WX;
+            const int iy = t.ty0 - 1 + wy, ix = t.tx0 - 1 + wx;
+            const bool inside = px < NPX && (unsigned)iy < (unsigned)t.h && (unsigned)ix < (unsigned)t.w;
+#pragma unroll
+            for (int g = 0; g < GA; ++g) {
+                const int yc = (gset * GA + g) * 16 + kg * 4;  // first of this lane's 4 y channels
+                T4 pk;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pk[q] = (T)(inside ? leaky01(acc[g][q] + bb1[g][q]) : 0.f);
+                *(T4*)(yw + px * YS + yc * 2) = pk;
+            }
+        }
+        __syncthreads();  // y complete
+        const int Pn = P + per;
+        Tile tn = t;
+        if (Pn < hi) {
+            tn = locate(Pn);
+            issue(tn, buf ^ 1);  // lands during the 3x3 below
+        }
+        // 3x3 from y, this wave's BPW blocks x 16 JB channels.  Steps are (tap,
+        // k-step) pairs in the unfused GEMM's K order; a step's pixel operands are
+        // read from LDS one step ahead into the other register set, and nothing is
+        // scheduled across steps (this bounds the registers the reads hold).
+        f32x4 acc[BPW][JB];
+#pragma unroll
+        for (int i = 0; i < BPW; ++i)
+#pragma unroll
+            for (int j = 0; j < JB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        V bfr[2][BPW];
+        auto rd_b = [&](auto st_c) {
+            constexpr int st = decltype(st_c)::value, tp = st / KB, kk = st % KB;
+            constexpr int r = tp / 3, s = tp % 3;
+#pragma unroll
+            for (int i = 0; i < BPW; ++i) {
+                const int blk = pg * BPW + i;
+                const int ty = blk / BPR, tx = (blk % BPR) * 16 + p;
+                const int wpx = (ty + r) * WX + tx + s;
+                bfr[st & 1][i] = *(const V*)(yw + wpx * YS + (kk * 4 + kg) * 16);
+            }
+        };
+        auto mm_b = [&](auto st_c) {
+            constexpr int st = decltype(st_c)::value, tp = st / KB, kk = st % KB;
+#pragma unroll
+            for (int i = 0; i < BPW; ++i)
+#pragma unroll
+                for (int j = 0; j < JB; ++j) {
+                    if constexpr (__is_same(T, bf16))
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[j][tp][kk], bfr[st & 1][i], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2[j][tp][kk], bfr[st & 1][i], acc[i][j], 0, 0, 0);
+                }
+        };
+        rd_b(std::integral_constant<int, 0>{});
+        static_for<0, 9 * KB>([&](auto st_c) {
+            constexpr int st = decltype(st_c)::value;
+            if constexpr (st + 1 < 9 * KB) rd_b(std::integral_constant<int, st + 1>{});
+            mm_b(st_c);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        // epilogue: bias, leaky, + x, store
+#pragma unroll
+        for (int i = 0; i < BPW; ++i) {
+            const int blk = pg * BPW + i;
+            const int ty = blk / BPR, tx = (blk % BPR) * 16 + p;
+            const int cpx = (ty + 1) * WX + tx + 1;  // window pixel of this output pixel
+            T4 pk[JB];
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {
+                const int c = (cg * JB + j) * 16 + kg * 4;
+                const T4 rv = *(const T4*)(xb + cpx * XS + c * 2);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pk[j][q] = (T)(leaky01(acc[i][j][q] + bb2[j][q]) + (float)rv[q]);
+            }
+            const int oy = t.ty0 + ty, ox = t.tx0 + tx;
+            const bool in = oy < t.h && ox < t.w;
+            T* op = out + ((size_t)t.base + (size_t)oy * t.w + ox) * C + cg * JB * 16;
+            if constexpr (JB == 1) {
+                if (in) *(T4*)(op + 4 * kg) = pk[0];
+            } else {
+                // Lanes l and l ^ 16 trade halves so that each holds 8 consecutive
+                // channels and stores 16 bytes (64 contiguous bytes per pixel).
+                const bool odd = kg & 1;
+                const T4 give = odd ? pk[0] : pk[1];
+                unsigned g2[2], r2[2];
+                __builtin_memcpy(g2, &give, 8);
+                r2[0] = __shfl_xor(g2[0], 16);
+                r2[1] = __shfl_xor(g2[1], 16);
+                T4 got;
+                __builtin_memcpy(&got, r2, 8);
+                const T4 lo4 = odd ? got : pk[0], hi4 = odd ? pk[1] : got;
+                if (in) {
+                    typedef unsigned U4 __attribute__((ext_vector_type(4)));
+                    U4 u4;
+                    __builtin_memcpy(&u4, &lo4, 8);
+                    __builtin_memcpy((char*)&u4 + 8, &hi4, 8);
+                    *(U4*)(op + (odd ? 16 + 4 * (kg - 1) : 4 * kg)) = u4;
+                }
+            }
+        }
+        t = tn;
+    }
+    // no DMA may still be writing LDS when the workgroup ends
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
+}
+
+int resblock_tiles(int C, int h, int w) {
+    if (C == 64) return ((h + RbCfg<64>::TY - 1) / RbCfg<64>::TY) * ((w + RbCfg<64>::TX - 1) / RbCfg<64>::TX);
+    if (C == 128) return ((h + RbCfg<128>::TY - 1) / RbCfg<128>::TY) * ((w + RbCfg<128>::TX - 1) / RbCfg<128>::TX);
+    return 0;
+}
+
+hipError_t launch_resblock(const void* x, void* out, const void* w1, const float* b1, const void* w2,
+                           const float* b2, const int* geom, int nframes, int lvl, int C, int tiles, size_t x_bytes,
+                           int et, hipStream_t s) {
+    if ((C != 64 && C != 128) || (et != kBF16 && et != kF16) || tiles <= 0 || x_bytes >= (size_t)1 << 31 ||
+        x == out)
+        return hipErrorInvalidValue;
+    // persistent: one workgroup per compute unit, a multiple of 8 (one band per XCD)
+    const int g = tiles < 256 ? ((tiles + 7) / 8) * 8 : 256;
+    dim3 grid(g), block(64 * (C == 64 ? RbCfg<64>::NW : RbCfg<128>::NW));
+#define JDE_RB(TT, CC)                                                                                          \
+    resblock_kernel<TT, CC><<<grid, block, 0, s>>>((const TT*)x, (TT*)out, (const TT*)w1, b1, (const TT*)w2, b2, \
+                                                   geom, nframes, lvl, tiles, (int)x_bytes)
+    if (et == kBF16) {
+        if (C == 64) JDE_RB(bf16, 64); else JDE_RB(bf16, 128);
+    } else {
+        if (C == 64) JDE_RB(f16, 64); else JDE_RB(f16, 128);
+    }
+#undef JDE_RB
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Tile configurations and dispatch.
 // ---------------------------------------------------------------------------
 // st = 0: register-staged conv_igemm; st = S >= 3: conv_dma with S stages;
@@ -1356,7 +1673,7 @@ constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 template <typename T>
 constexpr int lds_bytes(const TileCfg& t) {
     if (t.st) return t.st * (t.bm + t.bn) * 64;
-    return 2 * (t.bm + t.bn) * (t.bk + 16 / (int)sizeof(T)) * (int)sizeof(T);
+    return 2 * (t.bm + t.bn) * (t.bk + (sizeof(T) == 4 ? 4 : 16)) * (int)sizeof(T);
 }
 // 16-bit types may use every tile; FP32 only the register-staged K-32 tiles
 // whose LDS fits.
@@ -1393,7 +1710,6 @@ bool conv_tile_ok(int c, int et, const ConvArgs& a) {
 }
 
 int conv_default_tile(int et, const ConvArgs& a) {
-    (void)et;
     if (!aligned_cin(a, 32)) return 5;
     // Prefer the largest tile that still gives at least ~2 workgroups per CU.
     static const int pref_wide[] = {0, 2, 3, 5, 7};
@@ -1406,6 +1722,7 @@ int conv_default_tile(int et, const ConvArgs& a) {
     else { pref = pref_wide; np = 5; }
     int best = pref[np - 1];
     for (int i = 0; i < np; ++i) {
+        if (!built(pref[i], et)) continue;
         const TileCfg& t = kTiles[pref[i]];
         const long wgs = (long)((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn);
         if (wgs >= 512) { best = pref[i]; break; }

@@ -72,6 +72,13 @@ hipError_t launch_stem_down(const float* frames, const int* geom, int nframes, i
                             const float* b0, const void* w1, const float* b1, void* out, int out_type,
                             hipStream_t s);
 int stem_down_tiles(int h, int w);
+// Residual block (1x1 C -> C/2, 3x3 C/2 -> C, + x) as one launch, 16-bit storage,
+// C = 64 or 128, all at level lvl; out must not alias x.  `tiles` = sum over
+// frames of resblock_tiles(C, h, w) with the level's frame sizes.
+hipError_t launch_resblock(const void* x, void* out, const void* w1, const float* b1, const void* w2,
+                           const float* b2, const int* geom, int nframes, int lvl, int C, int tiles, size_t x_bytes,
+                           int et, hipStream_t s);
+int resblock_tiles(int C, int h, int w);
 // FP8 e4m3 convolution: BF16 activations quantised on load with in_scale, FP8
 // weights with per-channel wscale; needs cin % 128 == 0 and no concat.
 hipError_t launch_conv_fp8(const ConvArgs& a, int tile_cfg, hipStream_t s);

@@ -368,6 +368,10 @@ class JDE:
         """Run the stem and the first downsample conv as one launch (16-bit only)."""
         check(self.lib.jde_fuse_stem(self.ctx, 1 if on else 0), "jde_fuse_stem")
 
+    def fuse_blocks(self, on=True):
+        """Run each 64- and 128-channel residual block as one launch (16-bit only)."""
+        check(self.lib.jde_fuse_blocks(self.ctx, 1 if on else 0), "jde_fuse_blocks")
+
     def profile_begin(self, on=True):
         check(self.lib.jde_profile_begin(self.ctx, 1 if on else 0), "jde_profile_begin")
 

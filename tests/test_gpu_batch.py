@@ -182,6 +182,72 @@ def test_fused_stem_equals_unfused(torch, precision):
     assert worst <= 1e-6
 
 
+def _fused_vs_plain(m, packed, sizes, switch):
+    fused = head_views(m.forward(packed, sizes), sizes)
+    m.profile_begin(True)
+    m.forward(packed, sizes)
+    _, _, kind, _ = m.profile_collect()
+    m.profile_begin(False)
+    switch(False)
+    plain = head_views(m.forward(packed, sizes), sizes)
+    switch(True)
+    worst, same = 0.0, True
+    for key in ("det", "emb"):
+        for s in range(3):
+            for i in range(len(sizes)):
+                worst = max(worst, rel_err(fused[key][s][i], plain[key][s][i]))
+                same = same and np.array_equal(fused[key][s][i], plain[key][s][i])
+    return worst, same, kind
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_fused_blocks_equal_unfused(torch, precision):
+    """The fused residual-block launches (64 and 128 channels: the stride-2 and
+    stride-4 stages of the full network) compute what the two conv launches of
+    each block compute, on a ragged batch of three resolutions whose level sizes
+    leave partial tiles (864 / 2 = 432 columns, 480 / 4 = 120 rows ...)."""
+    _say(f"case: fused residual blocks {precision} ragged")
+    sizes = [(608, 1088), (320, 576), (480, 864)]
+    m = _model(FULL, precision, 3)
+    m.load_weights(weights("full", 40))
+    frs = [frames("full", 1, 0, h, w)[0] for h, w in sizes]
+    packed = torch.from_numpy(np.concatenate([f.ravel() for f in frs])).cuda()
+    worst, same, kind = _fused_vs_plain(m, packed, sizes, m.fuse_blocks)
+    torch.cuda.synchronize()
+    n_fused = int((np.asarray(kind) == 4).sum())
+    _say(f"  fused blocks: {n_fused} launches; vs two launches each: rel err {worst:.2e}, bitwise equal {same}")
+    assert n_fused == 1 + 2  # stage 1 (one block) and stage 2 (two blocks)
+    assert worst <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_fused_blocks_tiny_partial_tiles(torch, precision):
+    """Tiny network (widths 16..256): its 64- and 128-channel blocks sit at the
+    stride-4 and stride-8 levels, 48 x 80 and 24 x 40 for a 192 x 320 frame, so
+    every tile row ends in a partial tile; fused equals unfused, and each frame
+    of the batch matches the frame run alone (whose other convs may pick other
+    tiles)."""
+    _say(f"case: fused residual blocks tiny {precision}")
+    n = 2
+    m = _model(TINY, precision, n)
+    m.load_weights(weights("tiny", 50))
+    fr = frames("tiny", n)
+    sizes = [(192, 320)] * n
+    packed = torch.from_numpy(fr).cuda()
+    worst, same, kind = _fused_vs_plain(m, packed, sizes, m.fuse_blocks)
+    n_fused = int((np.asarray(kind) == 4).sum())
+    _say(f"  fused blocks: {n_fused} launches; rel err {worst:.2e}, bitwise equal {same}")
+    assert n_fused == sum(b for b, ch in zip(TINY.blocks, [32, 64, 128, 256, 512]) if ch in (64, 128))
+    assert worst <= 1e-6
+    both = head_views(m.forward(packed, sizes), sizes)
+    for i in range(n):
+        alone = head_views(m.forward(torch.from_numpy(fr[i:i + 1]).cuda(), sizes[:1]), sizes[:1])
+        for key in ("det", "emb"):
+            for s in range(3):
+                assert rel_err(both[key][s][i], alone[key][s][0]) <= 1e-5, (i, key, s)
+
+
 def test_graph_replays_equal_eager(torch):
     """A captured forward+decode+cost step, replayed several times with eager
     work between replays and with new frame contents, equals the eager step."""
