@@ -1423,37 +1423,46 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
         for (int q = 0; q < 4; ++q) bb2[j][q] = b2[ch + kg * 4 + q];
     }
 
-    // item -> frame, tile origin, level size, first packed pixel of the frame
+    // Work items are visited in increasing order, so the frame of the next item
+    // is found by advancing a cursor (frame f: items [first, first + n)).
     struct Tile { int ty0, tx0, h, w, base; };
-    auto locate = [&](int item) {
-        Tile t{0, 0, 0, 0, 0};
-        int f = 0;
-        for (;; ++f) {
-            t.h = geom[f * kGeomInts] >> lvl;
-            t.w = geom[f * kGeomInts + 1] >> lvl;
-            const int n = ((t.h + TY - 1) / TY) * ((t.w + TX - 1) / TX);
-            if (item < n || f + 1 >= nframes) break;
-            item -= n;
-        }
-        const int tw = (t.w + TX - 1) / TX;
-        t.ty0 = (item / tw) * TY;
-        t.tx0 = (item % tw) * TX;
-        t.base = geom[f * kGeomInts + 2 + lvl];
-        return t;
+    int cf = 0, cfirst = 0, cn = 0, ctw = 1, ch_ = 0, cw_ = 0, cbase = 0;
+    auto load_frame = [&]() {
+        ch_ = geom[cf * kGeomInts] >> lvl;
+        cw_ = geom[cf * kGeomInts + 1] >> lvl;
+        cbase = geom[cf * kGeomInts + 2 + lvl];
+        ctw = (cw_ + TX - 1) / TX;
+        cn = ((ch_ + TY - 1) / TY) * ctw;
     };
-    // window DMA: lane i of instruction q fills the 16-byte LDS slot 64 q + i,
-    // i.e. slot s of window pixel px (s >= XSL is the padding: zeros)
+    auto locate = [&](int item) {
+        while (item >= cfirst + cn && cf + 1 < nframes) {
+            cfirst += cn;
+            ++cf;
+            load_frame();
+        }
+        const int r = item - cfirst, ty = r / ctw;
+        return Tile{ty * TY, (r - ty * ctw) * TX, ch_, cw_, cbase};
+    };
+    // Window DMA: lane i of instruction q fills the 16-byte LDS slot 64 q + i,
+    // i.e. slot s of window pixel (wy, wx) (s >= XSL is the padding: zeros).
+    // The lane's (wy, wx, s) per instruction is fixed: packed once, -1 = padding.
+    int dgeo[DPW];
+#pragma unroll
+    for (int i = 0; i < DPW; ++i) {
+        const int L = (wave + NW * i) * 64 + lane;
+        const int px = L / (XSL + 2), sl = L - px * (XSL + 2);
+        const int wy = px / WX, wx = px - wy * WX;
+        dgeo[i] = (sl < XSL && px < NPX) ? (wy << 16) | (wx << 8) | sl : -1;
+    }
     auto issue = [&](const Tile& t, int buf) {
 #pragma unroll
         for (int i = 0; i < DPW; ++i) {
             const int q = wave + NW * i;
             if (q < NDMA) {  // wave-uniform
-                const int L = q * 64 + lane;
-                const int px = L / (XSL + 2), s = L - px * (XSL + 2);
-                const int wy = px / WX, wx = px - wy * WX;
-                const int iy = t.ty0 - 1 + wy, ix = t.tx0 - 1 + wx;
-                const bool ok = s < XSL && px < NPX && (unsigned)iy < (unsigned)t.h && (unsigned)ix < (unsigned)t.w;
-                const int off = ok ? ((t.base + iy * t.w + ix) * C + s * 8) * (int)sizeof(T) : kOOB;
+                const int g = dgeo[i];
+                const int iy = t.ty0 - 1 + (g >> 16), ix = t.tx0 - 1 + ((g >> 8) & 255);
+                const bool ok = g >= 0 && (unsigned)iy < (unsigned)t.h && (unsigned)ix < (unsigned)t.w;
+                const int off = ok ? ((t.base + iy * t.w + ix) * C + (g & 255) * 8) * (int)sizeof(T) : kOOB;
                 // the LDS address is wave-uniform; buf lives in a vector register
                 const unsigned la = __builtin_amdgcn_readfirstlane(
                     (unsigned)(unsigned long)(lds_ptr_t)&xw[0][0] + (unsigned)(buf * XB + q * 1024));
@@ -1464,20 +1473,32 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
             }
         }
     };
+    const __amdgpu_buffer_rsrc_t r_out = __builtin_amdgcn_make_buffer_rsrc((void*)out, 0, x_bytes, kBufFlags);
 
     const int per = gridDim.x / kXCDs, xcd = blockIdx.x % kXCDs;
     const int band = (total + kXCDs - 1) / kXCDs;
     const int lo = xcd * band, hi = lo + band < total ? lo + band : total;
     int P = lo + (int)blockIdx.x / kXCDs;
     if (P >= hi) return;  // uniform over the workgroup
+    load_frame();
     Tile t = locate(P);
     issue(t, 0);
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
+    // Per tile: barrier (every wave's share of this tile's window has landed, and
+    // every wave is done with the previous tile: its window buffer and y are
+    // free); issue the next tile's window into the other buffer; 1x1 -> y;
+    // barrier; 3x3 + epilogue; wait for this wave's share of the next window.
+    // Vector memory operations complete in order, and each wave issues exactly
+    // BPW stores after its window loads, so vmcnt(BPW) waits for the loads only.
     for (int it = 0; P < hi; ++it, P += per) {
         const int buf = it & 1;
-        // this tile's window has landed (and the previous tile's stores are done);
-        // every wave has finished the previous tile's 3x3 (y is free)
-        __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
         __syncthreads();
+        const int Pn = P + per;
+        Tile tn = t;
+        if (Pn < hi) {
+            tn = locate(Pn);
+            issue(tn, buf ^ 1);
+        }
         const char* xb = xw[buf];
         // 1x1 over the window -> y (LDS)
         for (int blk = wave / GSETS; blk < NBA; blk += NW / GSETS) {
@@ -1509,12 +1530,6 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
             }
         }
         __syncthreads();  // y complete
-        const int Pn = P + per;
-        Tile tn = t;
-        if (Pn < hi) {
-            tn = locate(Pn);
-            issue(tn, buf ^ 1);  // lands during the 3x3 below
-        }
         // 3x3 from y, this wave's BPW blocks x 16 JB channels.  Steps are (tap,
         // k-step) pairs in the unfused GEMM's K order; a step's pixel operands are
         // read from LDS one step ahead into the other register set, and nothing is
@@ -1571,9 +1586,14 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
             }
             const int oy = t.ty0 + ty, ox = t.tx0 + tx;
             const bool in = oy < t.h && ox < t.w;
-            T* op = out + ((size_t)t.base + (size_t)oy * t.w + ox) * C + cg * JB * 16;
+            // byte offset of this pixel's channel block; pixels outside the frame
+            // get an out-of-range offset (the store is dropped but still issued)
+            const int ob = in ? ((t.base + oy * t.w + ox) * C + cg * JB * 16) * (int)sizeof(T) : kOOB;
             if constexpr (JB == 1) {
-                if (in) *(T4*)(op + 4 * kg) = pk[0];
+                unsigned u2[2];
+                __builtin_memcpy(u2, &pk[0], 8);
+                typedef unsigned U2 __attribute__((ext_vector_type(2)));
+                __builtin_amdgcn_raw_buffer_store_b64(U2{u2[0], u2[1]}, r_out, in ? ob + 8 * kg : kOOB, 0, 0);
             } else {
                 // Lanes l and l ^ 16 trade halves so that each holds 8 consecutive
                 // channels and stores 16 bytes (64 contiguous bytes per pixel).
@@ -1586,15 +1606,15 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
                 T4 got;
                 __builtin_memcpy(&got, r2, 8);
                 const T4 lo4 = odd ? got : pk[0], hi4 = odd ? pk[1] : got;
-                if (in) {
-                    typedef unsigned U4 __attribute__((ext_vector_type(4)));
-                    U4 u4;
-                    __builtin_memcpy(&u4, &lo4, 8);
-                    __builtin_memcpy((char*)&u4 + 8, &hi4, 8);
-                    *(U4*)(op + (odd ? 16 + 4 * (kg - 1) : 4 * kg)) = u4;
-                }
+                typedef unsigned U4 __attribute__((ext_vector_type(4)));
+                U4 u4;
+                __builtin_memcpy(&u4, &lo4, 8);
+                __builtin_memcpy((char*)&u4 + 8, &hi4, 8);
+                const int cb = odd ? 16 + 4 * (kg - 1) : 4 * kg;
+                __builtin_amdgcn_raw_buffer_store_b128(u4, r_out, in ? ob + cb * (int)sizeof(T) : kOOB, 0, 0);
             }
         }
+        __builtin_amdgcn_s_waitcnt(waitcnt_imm(BPW, 15));
         t = tn;
     }
     // no DMA may still be writing LDS when the workgroup ends
