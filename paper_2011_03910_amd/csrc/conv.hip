@@ -23,7 +23,9 @@
 
 namespace jde {
 
-__device__ __forceinline__ float leaky01(float x) { return x > 0.f ? x : 0.1f * x; }
+// leaky ReLU 0.1: max(x, 0.1 x) equals (x > 0 ? x : 0.1 x) for every x (signed
+// zeros included) in two vector instructions instead of three
+__device__ __forceinline__ float leaky01(float x) { return __builtin_fmaxf(x, 0.1f * x); }
 
 template <typename T> struct V16;
 template <> struct V16<float> { typedef f32x4 type; };
@@ -1362,8 +1364,10 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 template <int C> struct RbCfg;
-template <> struct RbCfg<64> { static constexpr int TY = 8, TX = 32, GA = 2, JB = 2, NW = 8; };
-template <> struct RbCfg<128> { static constexpr int TY = 8, TX = 16, GA = 1, JB = 1, NW = 8; };
+// DA: window DMAs per wave issued during the 1x1 (the rest go one per 3x3
+// step); measured fastest with all of them in the 1x1.
+template <> struct RbCfg<64> { static constexpr int TY = 8, TX = 32, GA = 2, JB = 2, NW = 8, DA = 7; };
+template <> struct RbCfg<128> { static constexpr int TY = 8, TX = 16, GA = 1, JB = 1, NW = 8, DA = 7; };
 
 template <typename T, int C>
 __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __restrict__ x, T* __restrict__ out,
@@ -1383,6 +1387,13 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
     constexpr int NGB = C / (16 * JB), PG = NW / NGB;             // 3x3: channel groups, pixel groups
     constexpr int BPR = TX / 16, NBB = TY * BPR, BPW = NBB / PG;   // 3x3: 16-pixel blocks
     constexpr int KA = C / 32, KB = C2 / 32;                      // k-steps per tap
+    constexpr int NBW = (NBA + NW / GSETS - 1) / (NW / GSETS);    // 1x1 blocks per wave (at most)
+    constexpr int AB = NBW < 3 ? NBW : 3, NBAT = (NBW + AB - 1) / AB;  // 1x1 batches of AB blocks
+    // The next window's DMAs: the first DA are issued over the 1x1 batches, the
+    // rest one per 3x3 step.  A compute unit's vector memory path moves 32-64
+    // B/clk, so a wave issuing DMAs stalls wherever it issues them.
+    constexpr int DA = RbCfg<C>::DA, DPB = (DA + NBAT - 1) / NBAT;
+    static_assert(DA <= DPW && DPW - DA <= 9 * KB, "DMA steps");
     static_assert(NGA % GA == 0 && NW % NGB == 0 && NBB % PG == 0 && BPW % BPR == 0, "tile");
     static_assert(2 * XB + NPXP * YS <= 160 * 1024, "LDS");
     typedef typename V16<T>::type V;
@@ -1446,7 +1457,9 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
     // Window DMA: lane i of instruction q fills the 16-byte LDS slot 64 q + i,
     // i.e. slot s of window pixel (wy, wx) (s >= XSL is the padding: zeros).
     // The lane's (wy, wx, s) per instruction is fixed: packed once, -1 = padding.
-    int dgeo[DPW];
+    // For a window inside the frame the offset is the window origin's plus a
+    // per-lane term that depends only on the frame width (drel, for width drw).
+    int dgeo[DPW], drel[DPW], drw = -1;
 #pragma unroll
     for (int i = 0; i < DPW; ++i) {
         const int L = (wave + NW * i) * 64 + lane;
@@ -1454,23 +1467,33 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
         const int wy = px / WX, wx = px - wy * WX;
         dgeo[i] = (sl < XSL && px < NPX) ? (wy << 16) | (wx << 8) | sl : -1;
     }
-    auto issue = [&](const Tile& t, int buf) {
+    auto issue_one = [&](const Tile& t, int buf, int i) {
+        const int q = wave + NW * i;
+        if (q < NDMA) {  // wave-uniform
+            const int g = dgeo[i];
+            const bool interior = t.ty0 >= 1 && t.tx0 >= 1 && t.ty0 + TY < t.h && t.tx0 + TX < t.w;  // uniform
+            int off;
+            if (interior) {
+                if (t.w != drw) {  // uniform; once per frame width
+                    drw = t.w;
 #pragma unroll
-        for (int i = 0; i < DPW; ++i) {
-            const int q = wave + NW * i;
-            if (q < NDMA) {  // wave-uniform
-                const int g = dgeo[i];
+                    for (int k = 0; k < DPW; ++k)
+                        drel[k] = (((dgeo[k] >> 16) * drw + ((dgeo[k] >> 8) & 255)) * C + (dgeo[k] & 255) * 8) *
+                                  (int)sizeof(T);
+                }
+                off = g >= 0 ? ((t.base + (t.ty0 - 1) * t.w + t.tx0 - 1) * C) * (int)sizeof(T) + drel[i] : kOOB;
+            } else {
                 const int iy = t.ty0 - 1 + (g >> 16), ix = t.tx0 - 1 + ((g >> 8) & 255);
                 const bool ok = g >= 0 && (unsigned)iy < (unsigned)t.h && (unsigned)ix < (unsigned)t.w;
-                const int off = ok ? ((t.base + iy * t.w + ix) * C + (g & 255) * 8) * (int)sizeof(T) : kOOB;
-                // the LDS address is wave-uniform; buf lives in a vector register
-                const unsigned la = __builtin_amdgcn_readfirstlane(
-                    (unsigned)(unsigned long)(lds_ptr_t)&xw[0][0] + (unsigned)(buf * XB + q * 1024));
-                asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
-                             :
-                             : "s"(la), "v"(off), "s"(r_x)
-                             : "memory", "m0");
+                off = ok ? ((t.base + iy * t.w + ix) * C + (g & 255) * 8) * (int)sizeof(T) : kOOB;
             }
+            // the LDS address is wave-uniform; buf lives in a vector register
+            const unsigned la = __builtin_amdgcn_readfirstlane(
+                (unsigned)(unsigned long)(lds_ptr_t)&xw[0][0] + (unsigned)(buf * XB + q * 1024));
+            asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+                         :
+                         : "s"(la), "v"(off), "s"(r_x)
+                         : "memory", "m0");
         }
     };
     const __amdgpu_buffer_rsrc_t r_out = __builtin_amdgcn_make_buffer_rsrc((void*)out, 0, x_bytes, kBufFlags);
@@ -1482,53 +1505,74 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
     if (P >= hi) return;  // uniform over the workgroup
     load_frame();
     Tile t = locate(P);
-    issue(t, 0);
+#pragma unroll
+    for (int i = 0; i < DPW; ++i) issue_one(t, 0, i);
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
     // Per tile: barrier (every wave's share of this tile's window has landed, and
     // every wave is done with the previous tile: its window buffer and y are
-    // free); issue the next tile's window into the other buffer; 1x1 -> y;
+    // free); 1x1 -> y, issuing the next tile's window into the other buffer;
     // barrier; 3x3 + epilogue; wait for this wave's share of the next window.
     // Vector memory operations complete in order, and each wave issues exactly
-    // BPW stores after its window loads, so vmcnt(BPW) waits for the loads only.
+    // BPW JB stores after its window loads, so vmcnt(BPW JB) waits for the loads
+    // only.
     for (int it = 0; P < hi; ++it, P += per) {
         const int buf = it & 1;
         __syncthreads();
         const int Pn = P + per;
-        Tile tn = t;
-        if (Pn < hi) {
-            tn = locate(Pn);
-            issue(tn, buf ^ 1);
-        }
+        const bool more = Pn < hi;
+        const Tile tn = more ? locate(Pn) : t;
         const char* xb = xw[buf];
-        // 1x1 over the window -> y (LDS)
-        for (int blk = wave / GSETS; blk < NBA; blk += NW / GSETS) {
-            const int px = blk * 16 + p;
-            f32x4 acc[GA];
+        // 1x1 over the window -> y (LDS), in batches of AB blocks per wave (operand
+        // reads, then MFMAs, then epilogues); the next tile's window DMAs are
+        // issued between batches.
+        static_for<0, NBAT>([&](auto bt_c) {
+            constexpr int bt = decltype(bt_c)::value;
+            if (more) {
 #pragma unroll
-            for (int g = 0; g < GA; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int i = bt * DPB; i < (bt + 1) * DPB && i < DA; ++i) issue_one(tn, buf ^ 1, i);
+            }
+            V bfa[AB][KA];
+            int pxs[AB];
 #pragma unroll
-            for (int kk = 0; kk < KA; ++kk) {
-                const V bf = *(const V*)(xb + px * XS + (kk * 4 + kg) * 16);
+            for (int b = 0; b < AB; ++b) {
+                const int blk = wave / GSETS + (bt * AB + b) * (NW / GSETS);
+                pxs[b] = (blk < NBA ? blk : NBA - 1) * 16 + p;  // past the window: recomputed, not stored
+#pragma unroll
+                for (int kk = 0; kk < KA; ++kk) bfa[b][kk] = *(const V*)(xb + pxs[b] * XS + (kk * 4 + kg) * 16);
+            }
+            f32x4 acc[AB][GA];
+#pragma unroll
+            for (int b = 0; b < AB; ++b)
 #pragma unroll
                 for (int g = 0; g < GA; ++g) {
-                    if constexpr (__is_same(T, bf16))
-                        acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[g][kk], bf, acc[g], 0, 0, 0);
-                    else
-                        acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1[g][kk], bf, acc[g], 0, 0, 0);
+                    acc[b][g] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kk = 0; kk < KA; ++kk) {
+                        if constexpr (__is_same(T, bf16))
+                            acc[b][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[g][kk], bfa[b][kk], acc[b][g], 0, 0, 0);
+                        else
+                            acc[b][g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1[g][kk], bfa[b][kk], acc[b][g], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+            for (int b = 0; b < AB; ++b) {
+                const int blk = wave / GSETS + (bt * AB + b) * (NW / GSETS);
+                if (blk < NBA) {  // wave-uniform
+                    const int px = pxs[b];
+                    const int wy = px / WX, wx = px - wy * WX;
+                    const int iy = t.ty0 - 1 + wy, ix = t.tx0 - 1 + wx;
+                    const bool inside = px < NPX && (unsigned)iy < (unsigned)t.h && (unsigned)ix < (unsigned)t.w;
+#pragma unroll
+                    for (int g = 0; g < GA; ++g) {
+                        const int yc = (gset * GA + g) * 16 + kg * 4;  // first of this lane's 4 y channels
+                        T4 pk;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) pk[q] = (T)leaky01(acc[b][g][q] + bb1[g][q]);
+                        *(T4*)(yw + px * YS + yc * 2) = inside ? pk : T4{};
+                    }
                 }
             }
-            const int wy = px / WX, wx = px - wy * WX;
-            const int iy = t.ty0 - 1 + wy, ix = t.tx0 - 1 + wx;
-            const bool inside = px < NPX && (unsigned)iy < (unsigned)t.h && (unsigned)ix < (unsigned)t.w;
-#pragma unroll
-            for (int g = 0; g < GA; ++g) {
-                const int yc = (gset * GA + g) * 16 + kg * 4;  // first of this lane's 4 y channels
-                T4 pk;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) pk[q] = (T)(inside ? leaky01(acc[g][q] + bb1[g][q]) : 0.f);
-                *(T4*)(yw + px * YS + yc * 2) = pk;
-            }
-        }
+        });
         __syncthreads();  // y complete
         // 3x3 from y, this wave's BPW blocks x 16 JB channels.  Steps are (tap,
         // k-step) pairs in the unfused GEMM's K order; a step's pixel operands are
@@ -1567,6 +1611,9 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
         static_for<0, 9 * KB>([&](auto st_c) {
             constexpr int st = decltype(st_c)::value;
             if constexpr (st + 1 < 9 * KB) rd_b(std::integral_constant<int, st + 1>{});
+            if constexpr (DA + st < DPW) {
+                if (more) issue_one(tn, buf ^ 1, DA + st);
+            }
             mm_b(st_c);
             __builtin_amdgcn_sched_barrier(0);
         });
@@ -1586,35 +1633,18 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
             }
             const int oy = t.ty0 + ty, ox = t.tx0 + tx;
             const bool in = oy < t.h && ox < t.w;
-            // byte offset of this pixel's channel block; pixels outside the frame
-            // get an out-of-range offset (the store is dropped but still issued)
-            const int ob = in ? ((t.base + oy * t.w + ox) * C + cg * JB * 16) * (int)sizeof(T) : kOOB;
-            if constexpr (JB == 1) {
-                unsigned u2[2];
-                __builtin_memcpy(u2, &pk[0], 8);
-                typedef unsigned U2 __attribute__((ext_vector_type(2)));
-                __builtin_amdgcn_raw_buffer_store_b64(U2{u2[0], u2[1]}, r_out, in ? ob + 8 * kg : kOOB, 0, 0);
-            } else {
-                // Lanes l and l ^ 16 trade halves so that each holds 8 consecutive
-                // channels and stores 16 bytes (64 contiguous bytes per pixel).
-                const bool odd = kg & 1;
-                const T4 give = odd ? pk[0] : pk[1];
-                unsigned g2[2], r2[2];
-                __builtin_memcpy(g2, &give, 8);
-                r2[0] = __shfl_xor(g2[0], 16);
-                r2[1] = __shfl_xor(g2[1], 16);
-                T4 got;
-                __builtin_memcpy(&got, r2, 8);
-                const T4 lo4 = odd ? got : pk[0], hi4 = odd ? pk[1] : got;
-                typedef unsigned U4 __attribute__((ext_vector_type(4)));
-                U4 u4;
-                __builtin_memcpy(&u4, &lo4, 8);
-                __builtin_memcpy((char*)&u4 + 8, &hi4, 8);
-                const int cb = odd ? 16 + 4 * (kg - 1) : 4 * kg;
-                __builtin_amdgcn_raw_buffer_store_b128(u4, r_out, in ? ob + cb * (int)sizeof(T) : kOOB, 0, 0);
+            // 8 bytes per lane and channel block; pixels outside the frame get an
+            // out-of-range offset (the store is dropped but still issued)
+            const int ob = ((t.base + oy * t.w + ox) * C + cg * JB * 16 + kg * 4) * (int)sizeof(T);
+            typedef unsigned U2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {
+                U2 u2;
+                __builtin_memcpy(&u2, &pk[j], 8);
+                __builtin_amdgcn_raw_buffer_store_b64(u2, r_out, in ? ob + j * 16 * (int)sizeof(T) : kOOB, 0, 0);
             }
         }
-        __builtin_amdgcn_s_waitcnt(waitcnt_imm(BPW, 15));
+        __builtin_amdgcn_s_waitcnt(waitcnt_imm(BPW * JB, 15));
         t = tn;
     }
     // no DMA may still be writing LDS when the workgroup ends
