@@ -186,6 +186,16 @@ jde_status jde_fuse_stem(jde_ctx* ctx, int on);
  * 4 at the block's first conv and the second conv is kind 5 with no time or
  * FLOPs of its own. */
 jde_status jde_fuse_blocks(jde_ctx* ctx, int on);
+/* With on != 0 (default off), 16-bit contexts run each 3x3 stride-1 conv with
+ * Cin % 64 == 0 and Cout % 128 == 0 (Sec. 3.1: the residual blocks of the deep
+ * stages and the head convs) from an LDS window loaded once per 32-channel input
+ * slice for all nine taps, when every frame's width at that level is <= 190;
+ * on = 0 runs them as implicit GEMMs.  Same network; the FP32 accumulation runs
+ * in another order (slice-major instead of tap-major), so results agree to
+ * rounding, not bitwise.  FP8 launches are unaffected.  Off by default: with its
+ * 144 KB of LDS one workgroup fills a compute unit, and its per-step barrier then
+ * idles the matrix cores; the implicit GEMM is faster on MI355X. */
+jde_status jde_window_convs(jde_ctx* ctx, int on);
 /* Host helper: x (host, n floats) -> OCP e4m3 codes (host, n bytes), round to
  * nearest even, saturating at +-448, NaN -> 0x7f; the encoding of the weights. */
 void jde_fp8_encode(const float* x, uint8_t* out, size_t n);

@@ -86,6 +86,7 @@ SIGNATURES = {
     "jde_fp8_scales": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int]),
     "jde_fuse_stem": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_fuse_blocks": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "jde_window_convs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_fp8_encode": (None, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t]),
     "jde_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p, c_int_p, c_int_p,

@@ -95,6 +95,9 @@ struct jde_ctx {
     // launch, 2 / 4 = head of a fused stem / residual-block launch, 3 / 5 = run
     // inside the previous op's fused launch.
     bool fuse_stem = true, fuse_blocks = true;
+    // 3x3 stride-1 convs run from an LDS window (conv3_win) where they qualify;
+    // off by default: measured slower than the implicit GEMM on MI355X.
+    bool window_convs = false;
     std::vector<int> launch_kind;
     size_t ws_amax = 0;
     // Per-launch timing: a ring of event pairs, one entry per profiled forward.
@@ -796,7 +799,20 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
             continue;
         }
         const ConvArgs a = conv_args(c, o, d, n, uniform, W, geom, out, (int)oi);
-        if (runs_fp8(c, o)) {
+        int w3 = 0;  // pixel tiles of the window kernel, 0 = implicit GEMM
+        if (c->window_convs && !runs_fp8(c, o) && conv3w_ok(a, c->et)) {
+            for (int f = 0; f < n; ++f) {
+                const int t = conv3w_tiles(d[f].h >> o.lvl_out, d[f].w >> o.lvl_out);
+                if (t == 0) {
+                    w3 = 0;
+                    break;
+                }
+                w3 += t;
+            }
+        }
+        if (w3 > 0) {
+            HIP_TRY(launch_conv3w(a, c->et, w3, s));
+        } else if (runs_fp8(c, o)) {
             HIP_TRY(launch_conv_fp8(a, o.tile8, s));
         } else {
             const int tile = (o.tile >= 0 && conv_tile_ok(o.tile, c->et, a)) ? o.tile : conv_default_tile(c->et, a);
@@ -1073,6 +1089,12 @@ jde_status jde_fuse_stem(jde_ctx* c, int on) {
 jde_status jde_fuse_blocks(jde_ctx* c, int on) {
     if (!c) return fail(JDE_EINVAL, "null context");
     c->fuse_blocks = on != 0;
+    return JDE_OK;
+}
+
+jde_status jde_window_convs(jde_ctx* c, int on) {
+    if (!c) return fail(JDE_EINVAL, "null context");
+    c->window_convs = on != 0;
     return JDE_OK;
 }
 

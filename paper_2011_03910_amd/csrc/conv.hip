@@ -23,6 +23,15 @@
 
 namespace jde {
 
+// f(integral_constant<int, I>) for I = B .. E - 1, in order
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 // leaky ReLU 0.1: max(x, 0.1 x) equals (x > 0 ? x : 0.1 x) for every x (signed
 // zeros included) in two vector instructions instead of three
 __device__ __forceinline__ float leaky01(float x) { return __builtin_fmaxf(x, 0.1f * x); }
@@ -1112,6 +1121,205 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// 3x3 stride-1 convolution from an LDS window (16-bit storage; Cin % 64 == 0,
+// Cout % 128 == 0, no concat input, level width <= 190).
+//
+// The implicit GEMM above gathers every input pixel once per tap: nine loads of
+// each activation per K slice, which keeps a compute unit's texture-address path
+// ~80 % busy on the deep 3x3 layers (hardware counters) -- the load path, not the
+// matrix cores, bounds them.  Here a workgroup owns a tile of whole output rows
+// of one frame (TY rows x W, at most 272 pixels) and 128 output channels.  Per
+// 32-channel input slice it loads the (TY + 2) x (W + 2) window once into LDS
+// and runs all nine taps from it, the pixel operand of tap (r, s) being the
+// window shifted by (r - 1, s - 1); only the 128 x 32 weight slice is loaded per
+// tap.  K order: slice-major, tap-minor (a different FP32 summation order from
+// the implicit GEMM's tap-major order).
+//
+// Pipeline (8 waves: 2 pixel halves x 4 groups of 32 channels; one workgroup
+// per compute unit): weight slices of steps k + 1 .. k + 3 are in flight in four
+// LDS stages while step k computes, the next slice's window streams into the
+// second window buffer over the first seven taps, and a step's MFMA operands are
+// read from LDS one step ahead into the other register set.  Every wave issues
+// the same DMAs in the same order at every step (past the end: out-of-range
+// offsets, which load zeros into free buffers), so the wait before each step's
+// barrier is a static vmcnt per tap position.  The epilogue is store_tile's
+// (bias, leaky, residual, split FP32 output) with the tile's pixel range as M.
+// ---------------------------------------------------------------------------
+constexpr int kW3Px = 272;   // output pixels per tile at most (17 blocks of 16)
+constexpr int kW3Win = 576;  // window pixels at most
+
+// Tile height for a level of width w (1 <= w <= kW3MaxW).
+__host__ __device__ inline int w3_rows(int w) {
+    const int a = kW3Px / w, b = kW3Win / (w + 2) - 2;
+    return a < b ? a : b;
+}
+
+template <typename T, bool NT>
+__global__ __launch_bounds__(512) void conv3_win(ConvArgs a, int ntc, int total) {
+    constexpr int NW = 8, BN = 128, TM = 9, TN = 2, PS = 96;       // PS: LDS bytes per window pixel
+    constexpr int NWD = (kW3Win * (PS / 16) + 64 * NW - 1) / (64 * NW);  // window DMAs per wave per slice
+    constexpr int WB = NWD * NW * 1024, WS = BN * 64;              // window buffer, weight stage bytes
+    static_assert(NWD <= 7, "window DMAs must finish by tap 6");
+    typedef typename V16<T>::type V;
+
+    __shared__ __attribute__((aligned(1024))) char win[2][WB];
+    __shared__ __attribute__((aligned(1024))) char wst[4][WS];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave & 1, wn = wave >> 1;
+    const int p = lane & 15, kg = lane >> 4;
+
+    // tile: pixel tile pt (channel tiles innermost, XCD-aware), frame f, rows y0..
+    const int Lt = xcd_remap(blockIdx.x, total);
+    int pt = Lt / ntc;
+    const int n0 = (Lt - pt * ntc) * BN;
+    int f = 0, H = 0, W = 1, TY = 1;
+    for (;;) {
+        H = a.geom[f * kGeomInts] >> a.lvl_out;
+        W = a.geom[f * kGeomInts + 1] >> a.lvl_out;
+        TY = w3_rows(W);
+        const int n = (H + TY - 1) / TY;
+        if (pt < n || f + 1 >= a.nframes) break;
+        pt -= n;
+        ++f;
+    }
+    const int y0 = pt * TY, rows = H - y0 < TY ? H - y0 : TY, P = rows * W;
+    const int fbase = a.geom[f * kGeomInts + 2 + a.lvl_out];
+    const int mt0 = fbase + y0 * W;
+    const int WX = W + 2, npx = (rows + 2) * WX;
+    const int nc = a.cin / 32, nk = 9 * nc;
+
+    const __amdgpu_buffer_rsrc_t r_in = __builtin_amdgcn_make_buffer_rsrc((void*)a.in, 0, a.in_bytes, kBufFlags);
+    const __amdgpu_buffer_rsrc_t r_w = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, a.w_bytes, kBufFlags);
+
+    // window DMA i of this wave: lane -> (window pixel, 16-byte unit); element
+    // offset of the slice-0 data, or -1 (padding unit, outside the window/frame)
+    int dgeo[NWD];
+#pragma unroll
+    for (int i = 0; i < NWD; ++i) {
+        const int L = (wave + NW * i) * 64 + lane;
+        const int px = L / (PS / 16), u = L - px * (PS / 16);
+        const int wy = px / WX, wx = px - wy * WX;
+        const int iy = y0 - 1 + wy, ix = wx - 1;
+        const bool ok = u < 4 && px < npx && (unsigned)iy < (unsigned)H && (unsigned)ix < (unsigned)W;
+        dgeo[i] = ok ? ((fbase + iy * W + ix) * a.cin + u * 8) : -1;
+    }
+    auto win_dma = [&](int c, int i) {  // slice c into window buffer c & 1
+        const int off = (dgeo[i] >= 0 && c < nc) ? (dgeo[i] + c * 32) * (int)sizeof(T) : kOOB;
+        dma16(r_in, &win[c & 1][(wave + NW * i) * 1024], off);
+    };
+    // weight DMA of step k (slice k / 9, tap k % 9): rows n0 + 16 wave .., 64 bytes each
+    const int wrow = n0 + 16 * wave + (lane >> 2);
+    const int wslot = ((lane & 3) ^ dma_swizzle(lane >> 2)) * 8;
+    auto w_dma = [&](int k) {
+        const int c = k / 9, t = k - 9 * c;
+        const int off = k < nk ? (wrow * a.K + t * a.cin + c * 32 + wslot) * (int)sizeof(T) : kOOB;
+        dma16(r_w, &wst[k & 3][wave * 1024], off);
+    };
+
+    // B operand bases: window centre of this lane's pixel in block i (+ its k-slot)
+    int cb[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int q = (wm * TM + i) * 16 + p;
+        int ctr = WX + 1;  // past the tile: any window pixel (not stored)
+        if (q < P) {
+            const int ty = q / W, tx = q - ty * W;
+            ctr = (ty + 1) * WX + tx + 1;
+        }
+        cb[i] = ctr * PS + kg * 16;
+    }
+    const int a_rd = (wn * 32 + p) * 64 + ((kg ^ dma_swizzle(p)) << 4);
+
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    V fa[2][TN], fb[2][TM];
+    auto read = [&](int k, int set) {
+        const int c = k / 9, t = k - 9 * c;
+        const char* ws = wst[k & 3];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) fa[set][j] = *(const V*)(ws + a_rd + j * 16 * 64);
+        const int toff = ((t / 3 - 1) * WX + (t % 3 - 1)) * PS;
+        const char* wb = win[c & 1] + toff;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) fb[set][i] = *(const V*)(wb + cb[i]);
+    };
+    auto mma = [&](int set) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                if constexpr (__is_same(T, bf16))
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[set][j], fb[set][i], acc[i][j], 0, 0, 0);
+                else
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[set][j], fb[set][i], acc[i][j], 0, 0, 0);
+            }
+    };
+
+    // prologue: slice 0's window and the weights of steps 0..2
+#pragma unroll
+    for (int i = 0; i < NWD; ++i) win_dma(0, i);
+    w_dma(0);
+    w_dma(1);
+    w_dma(2);
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
+    __syncthreads();
+    read(0, 0);
+    // Step k = 9 c + t.  Issue order per step: weights of k + 3, then (t < NWD)
+    // window DMA t of slice c + 1.  Before the barrier of step k the weights of
+    // k + 1 must have landed (issued at step k - 2) and, at t = 8, slice c + 1's
+    // whole window: the ops issued after those are what vmcnt may leave.
+    auto step = [&](auto u_c, int k) {
+        constexpr int u = decltype(u_c)::value, t = u % 9;
+        constexpr int wprev2 = ((t + 7) % 9) < NWD, wprev1 = ((t + 8) % 9) < NWD;
+        constexpr int vm = t == 8 ? 1 : wprev2 + 1 + wprev1;
+        __builtin_amdgcn_s_waitcnt(waitcnt_imm(vm, 0));
+        __builtin_amdgcn_s_barrier();
+        w_dma(k + 3);
+        if constexpr (t < NWD) win_dma(k / 9 + 1, t);
+        if (k + 1 < nk) read(k + 1, (u + 1) & 1);
+        mma(u & 1);
+        __builtin_amdgcn_sched_barrier(0);  // keeps the register sets bounded
+    };
+    for (int kc = 0; kc < nk; kc += 18) {
+        static_for<0, 18>([&](auto u_c) { step(u_c, kc + decltype(u_c)::value); });
+    }
+    // no DMA may still be writing LDS when the workgroup ends
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
+
+    ConvArgs at = a;
+    at.M = mt0 + P;  // the tile's pixels end here (rows past the frame are not computed)
+    store_tile<T, TM, TN, TM * 16, TN * 16, NT>(at, acc, mt0 + wm * TM * 16, n0 + wn * 32, lane, nullptr);
+}
+
+// Tiles of one frame level (h x w) for conv3_win, 0 if the width does not fit.
+int conv3w_tiles(int h, int w) {
+    if (w < 1 || w > kW3MaxW || h < 1) return 0;
+    const int ty = w3_rows(w);
+    return (h + ty - 1) / ty;
+}
+
+bool conv3w_ok(const ConvArgs& a, int et) {
+    return (et == kBF16 || et == kF16) && a.ksz == 3 && a.stride == 1 && a.pad == 1 && a.cin % 64 == 0 &&
+           a.cout % 128 == 0 && a.cin1 == 0 && a.lvl_in == a.lvl_out && !a.wscale;
+}
+
+hipError_t launch_conv3w(const ConvArgs& a, int et, int pixel_tiles, hipStream_t s) {
+    if (!conv3w_ok(a, et) || pixel_tiles <= 0) return hipErrorInvalidValue;
+    const int ntc = a.cout / 128, total = pixel_tiles * ntc;
+    dim3 grid(total), block(512);
+    if (et == kBF16)
+        conv3_win<bf16, false><<<grid, block, 0, s>>>(a, ntc, total);
+    else
+        conv3_win<f16, false><<<grid, block, 0, s>>>(a, ntc, total);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // FP8 (OCP e4m3) implicit GEMM for the deep backbone convolutions.
 //   K chunks of 128 = one v_mfma_scale_f32_16x16x128_f8f6f4 (unit block scales)
 //   per 16x16 output block; each lane feeds 32 consecutive k of its row (two
@@ -1354,15 +1562,6 @@ hipError_t launch_conv_fp8(const ConvArgs& a, int c, hipStream_t s) {
 // distinct 16-byte units modulo 512 bytes (full LDS rate), and every operand
 // address is a per-lane base plus an immediate offset.
 // ---------------------------------------------------------------------------
-// f(integral_constant<int, I>) for I = B .. E - 1, in order
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
 template <int C> struct RbCfg;
 // DA: window DMAs per wave issued during the 1x1 (the rest go one per 3x3
 // step); measured fastest with all of them in the 1x1.

@@ -79,6 +79,13 @@ hipError_t launch_resblock(const void* x, void* out, const void* w1, const float
                            const float* b2, const int* geom, int nframes, int lvl, int C, int tiles, size_t x_bytes,
                            int et, hipStream_t s);
 int resblock_tiles(int C, int h, int w);
+// 3x3 stride-1 convolution from an LDS window (16-bit storage): applies when
+// conv3w_ok and every frame's level width is <= kW3MaxW; `pixel_tiles` = sum over
+// frames of conv3w_tiles(h, w) at the level.
+constexpr int kW3MaxW = 190;
+bool conv3w_ok(const ConvArgs& a, int et);
+int conv3w_tiles(int h, int w);
+hipError_t launch_conv3w(const ConvArgs& a, int et, int pixel_tiles, hipStream_t s);
 // FP8 e4m3 convolution: BF16 activations quantised on load with in_scale, FP8
 // weights with per-channel wscale; needs cin % 128 == 0 and no concat.
 hipError_t launch_conv_fp8(const ConvArgs& a, int tile_cfg, hipStream_t s);

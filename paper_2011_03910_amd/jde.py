@@ -372,6 +372,10 @@ class JDE:
         """Run each 64- and 128-channel residual block as one launch (16-bit only)."""
         check(self.lib.jde_fuse_blocks(self.ctx, 1 if on else 0), "jde_fuse_blocks")
 
+    def window_convs(self, on=True):
+        """Run qualifying 3x3 stride-1 convs from an LDS window (16-bit only)."""
+        check(self.lib.jde_window_convs(self.ctx, 1 if on else 0), "jde_window_convs")
+
     def profile_begin(self, on=True):
         check(self.lib.jde_profile_begin(self.ctx, 1 if on else 0), "jde_profile_begin")
 
