@@ -1916,6 +1916,8 @@ static constexpr TileCfg kTiles[] = {
     {256, 128, 4, 2, 32, 3, 0},  // 29: direct-to-LDS, 8 waves of 64x64 (72 KB)
     {128, 256, 2, 4, 32, 3, 0},  // 30: direct-to-LDS, 8 waves of 64x64 (72 KB)
     {256, 128, 4, 2, 32, 3, 1},  // 31: as 29, streaming stores
+    {256, 256, 2, 4, 32, 3, 0},  // 32: direct-to-LDS, 8 waves of 128x64 (96 KB: half the loads per FLOP of 29/30)
+    {256, 256, 4, 2, 32, 3, 0},  // 33: direct-to-LDS, 8 waves of 64x128 (96 KB)
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
@@ -2033,6 +2035,8 @@ static hipError_t launch_type(const ConvArgs& a, int c, bool aligned, hipStream_
         case 29: return launch_t<T, 29>(a, aligned, s);
         case 30: return launch_t<T, 30>(a, aligned, s);
         case 31: return launch_t<T, 31>(a, aligned, s);
+        case 32: return launch_t<T, 32>(a, aligned, s);
+        case 33: return launch_t<T, 33>(a, aligned, s);
     }
     return hipErrorInvalidValue;
 }
