@@ -307,7 +307,7 @@ def main():
         "speedup_vs_fp32_b1": None if fp32 is None else round(fps / fp32["fps"], 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "kernel": f"conv_igemm ({n_launch} launches/step, {conv_flop / 1e9:.1f} GFLOP/step, "
+                     "kernel": f"implicit-GEMM convs conv_dma/conv_igemm ({n_launch} launches/step, {conv_flop / 1e9:.1f} GFLOP/step, "
                                f"mean {conv_ms / n_launch * 1e3:.1f} us/launch)"},
         "serving": None if serving is None else {k: (round(v, 3) if isinstance(v, float) else v)
                                                   for k, v in serving.items()},
