@@ -131,6 +131,64 @@ __device__ __forceinline__ int xcd_remap(int L, int W) {
 }
 
 // ---------------------------------------------------------------------------
+// Stem operands on the matrix cores.  The 3 x 3 x 3 receptive field of a stem
+// output is laid out over two 32-wide k-steps as k = 16 r + 4 s + c (row r and
+// column s of the 3x3, channel c; the s = 3 and c = 3 slots and k >= 48 carry
+// zero weights).  The input window sits in LDS as FP16 positions of 4 channel
+// slots (8 bytes: c0, c1, c2, 0), so a lane's eight k-values of a k-step -- two
+// horizontally adjacent positions x 4 slots -- are 16 contiguous bytes: one LDS
+// read per k-step instead of eight reads and eight conversions.  FP16 storage
+// also keeps a window of the low parts x - fp16(x).
+// ---------------------------------------------------------------------------
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+// A operand of output channel co, k-step m, lane group kg: FP16 hi and lo parts
+__device__ __forceinline__ void stem_wfrag(const float* __restrict__ w, int co, int m, int kg, f16x8& hi,
+                                           f16x8& lo) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int k = 32 * m + 8 * kg + j, r = k >> 4, s = (k >> 2) & 3, c = k & 3;
+        const float v = (r < 3 && s < 3 && c < 3) ? w[co * 27 + (r * 3 + s) * 3 + c] : 0.f;
+        hi[j] = (f16)v;
+        lo[j] = (f16)(v - (float)hi[j]);
+    }
+}
+
+// B operand of k-step m for a pixel whose 3x3 window starts at position `pos`
+// (row 0, column 0 of the receptive field) in a window of row stride `ws`.
+__device__ __forceinline__ f16x8 stem_bfrag(const f16x4* __restrict__ win, int pos, int ws, int m, int kg) {
+    const int r = 2 * m + (kg >> 1);
+    if (r > 2) return f16x8{};
+    const f16x4* q = win + pos + r * ws + 2 * (kg & 1);
+    const f16x4 a = q[0], b = q[1];
+    return f16x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+}
+
+// One 16-pixel block of stem outputs for channel groups 0..NG-1 (FP32 accumulation;
+// with split, lo x hi + hi x lo + hi x hi per k-step).
+template <int NG, bool split>
+__device__ __forceinline__ void stem_block(const f16x4* __restrict__ wh, const f16x4* __restrict__ wlo, int pos,
+                                           int ws, int kg, const f16x8 (&wa)[NG][2], const f16x8 (&wl)[NG][2],
+                                           f32x4 (&acc)[NG]) {
+#pragma unroll
+    for (int cg = 0; cg < NG; ++cg) acc[cg] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const f16x8 b = stem_bfrag(wh, pos, ws, m, kg);
+        f16x8 bl{};
+        if constexpr (split) bl = stem_bfrag(wlo, pos, ws, m, kg);
+#pragma unroll
+        for (int cg = 0; cg < NG; ++cg) {
+            if constexpr (split) {
+                acc[cg] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[cg][m], b, acc[cg], 0, 0, 0);
+                acc[cg] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg][m], bl, acc[cg], 0, 0, 0);
+            }
+            acc[cg] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg][m], b, acc[cg], 0, 0, 0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Stem on the matrix cores (16-bit activation storage).  Work items are
 // segments of up to kStemSeg output pixels of one image row, walked by
 // persistent workgroups.  For each item the input window it
@@ -140,10 +198,10 @@ __device__ __forceinline__ int xcd_remap(int L, int W) {
 // Items are split into 8 contiguous bands, one per XCD, and the workgroups of
 // an XCD walk their band together, so neighbouring rows -- whose windows
 // overlap -- are fetched once into that XCD's L2.
-// Each wave then builds 16-pixel im2col blocks from LDS -- k = (r*3 + s)*3 + c
-// for k < 27, zeros up to 32 -- and runs v_mfma_f32_16x16x32_f16 per 16 output
-// channels (A = folded weights, rows = channels; B = pixels), FP32
-// accumulation.  For FP16 storage each operand is split into FP16 parts
+// Each wave then runs 16-pixel blocks from LDS (stem_block: two k-steps of
+// v_mfma_f32_16x16x32_f16 per 16 output channels; A = folded weights, rows =
+// channels; B = pixels), FP32 accumulation.  For FP16 storage each operand is
+// split into FP16 parts
 // x = hi + lo (hi = fp16(x), lo = fp16(x - hi)) and the product is formed as
 // lo*hi + hi*lo + hi*hi (the lo*lo term is below FP32 rounding): about 22
 // significant bits, as the FP32 stem keeps.  For BF16 storage (8 significant
@@ -161,9 +219,12 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
                                                         const float* __restrict__ w,
                                                         const float* __restrict__ bias, TO* __restrict__ out,
                                                         int nseg, int total) {
-    constexpr int WIN = kStemSeg + 2, NG = COUT / 16;
+    // window: 3 rows x WS positions, position j <-> x = x0 + j - 1 (the last one
+    // only feeds zero-weight slots)
+    constexpr int WS = kStemSeg + 3, NP = 3 * WS, NG = COUT / 16;
     constexpr bool split = __is_same(TO, f16);
-    __shared__ float win[2][9 * WIN];  // [buffer][c][r][column], column j <-> x = x0 + j - 1
+    __shared__ f16x4 wh[2][NP];
+    __shared__ f16x4 wlo[split ? 2 : 1][split ? NP : 1];
     // item P -> frame f, row y, first column x0 (x0 >= width: nothing to do)
     auto locate = [&](int P, int& f, int& y, int& x0) {
         x0 = (P % nseg) * kStemSeg;
@@ -179,8 +240,8 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
             }
         }
     };
-    constexpr int NLD = (9 * WIN + 255) / 256;
-    float wv[NLD];
+    constexpr int NLD = (NP + 255) / 256;
+    float wv[NLD][3];
     auto load = [&](int P) {  // every load of the window in flight at once
         int f, y, x0;
         locate(P, f, y, x0);
@@ -190,43 +251,38 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
 #pragma unroll
         for (int it = 0; it < NLD; ++it) {
             const int i = threadIdx.x + it * 256;
-            const int cr = i / WIN, j = i - cr * WIN;
-            const int c = cr / 3, r = cr - c * 3;
+            const int r = i / WS, j = i - r * WS;
             const int iy = y + r - 1, ix = x0 + j - 1;
-            wv[it] = 0.f;
-            if (i < 9 * WIN && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)wd)
-                wv[it] = fr[((size_t)c * h + iy) * wd + ix];
+            const bool ok = i < NP && j < WS - 1 && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)wd;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) wv[it][c] = ok ? fr[((size_t)c * h + iy) * wd + ix] : 0.f;
         }
     };
     auto park = [&](int buf) {
 #pragma unroll
         for (int it = 0; it < NLD; ++it) {
             const int i = threadIdx.x + it * 256;
-            if (i < 9 * WIN) win[buf][i] = wv[it];
+            if (i < NP) {
+                f16x4 hv, lv;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    hv[c] = (f16)wv[it][c];
+                    lv[c] = (f16)(wv[it][c] - (float)hv[c]);
+                }
+                hv[3] = lv[3] = (f16)0.f;
+                wh[buf][i] = hv;
+                if constexpr (split) wlo[buf][i] = lv;
+            }
         }
     };
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = lane & 15, kg = lane >> 4;
-    // this lane's 8 values of k: LDS offsets (relative to the block's first pixel)
-    int koff[8];
-    bool kval[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int k = kg * 8 + j;
-        const int r = k / 9, s = (k / 3) % 3, c = k % 3;
-        kval[j] = k < 27;
-        koff[j] = kval[j] ? (c * 3 + r) * WIN + s + p : 0;
-    }
-    f16x8 wa[NG], wl[NG];
+    f16x8 wa[NG][2], wl[NG][2];
     float bv[NG][4];
 #pragma unroll
     for (int cg = 0; cg < NG; ++cg) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float v = kval[j] ? w[(cg * 16 + p) * 27 + kg * 8 + j] : 0.f;
-            wa[cg][j] = (f16)v;
-            wl[cg][j] = (f16)(v - (float)wa[cg][j]);
-        }
+        for (int m = 0; m < 2; ++m) stem_wfrag(w, cg * 16 + p, m, kg, wa[cg][m], wl[cg][m]);
 #pragma unroll
         for (int i = 0; i < 4; ++i) bv[cg][i] = bias[cg * 16 + kg * 4 + i];
     }
@@ -252,26 +308,14 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
         for (int blk = wave; blk < kStemSeg / 16; blk += 4) {
             const int xb = x0 + blk * 16;
             if (xb >= wd) break;
-            f16x8 b, bl;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float v = kval[j] ? win[buf][koff[j] + blk * 16] : 0.f;
-                b[j] = (f16)v;
-                if constexpr (split) bl[j] = (f16)(v - (float)b[j]);
-            }
+            f32x4 acc[NG];
+            stem_block<NG, split>(wh[buf], wlo[split ? buf : 0], blk * 16 + p, WS, kg, wa, wl, acc);
             typedef TO T4 __attribute__((ext_vector_type(4)));
             T4 pk[NG];
 #pragma unroll
-            for (int cg = 0; cg < NG; ++cg) {
-                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-                if constexpr (split) {
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[cg], b, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], bl, acc, 0, 0, 0);
-                }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], b, acc, 0, 0, 0);
+            for (int cg = 0; cg < NG; ++cg)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) pk[cg][i] = (TO)leaky01(acc[i] + bv[cg][i]);
-            }
+                for (int i = 0; i < 4; ++i) pk[cg][i] = (TO)leaky01(acc[cg][i] + bv[cg][i]);
             TO* o = out + (row_m + xb + p) * COUT;
             if constexpr (NG == 1) {
                 // 16 pixels x 32 bytes: one contiguous 512-byte store
@@ -333,13 +377,15 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
     constexpr int C0 = 32, C1 = 64;
     constexpr int WR = 2 * kSdTY + 1, WC = 2 * kSdTX + 1;  // stem window: 5 x 129
     constexpr int FR = WR + 2, FC = WC + 2;                  // frame window: 7 x 131
+    constexpr int FS = FC + 1;                               // positions per window row (+1: zero-weight slots)
     constexpr int NE = kSdTX + 1;                            // pixels per parity plane (even: 65, odd: 64)
     constexpr int PS = 40;                                   // elements per pixel slot (32 + 8 padding)
-    constexpr int NF = 3 * FR * FC, NLD = (NF + 255) / 256;
+    constexpr int NPF = FR * FS, NLD = (NPF + 255) / 256;
     constexpr int NSB = (WR * WC + 15) / 16;                 // 16-pixel stem blocks (41)
     constexpr bool split = __is_same(TO, f16);
     typedef typename V16<TO>::type V;
-    __shared__ float fw[NF];
+    __shared__ f16x4 fwh[NPF];                               // FP16 positions x 4 channel slots
+    __shared__ f16x4 fwl[split ? NPF : 1];                   // low parts (FP16 storage)
     __shared__ __attribute__((aligned(16))) TO sw[WR * 2 * NE * PS];
 
     // item -> frame, output tile origin (ty0, tx0) on the stride-2 level
@@ -358,7 +404,7 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
         t.tx0 = (item % tw) * kSdTX;
         return t;
     };
-    float fv[NLD];
+    float fv[NLD][3];
     auto load = [&](const Tile& t) {  // frame window rows 2 ty0 - 2 .., columns 2 tx0 - 2 ..
         const int* g = geom + t.f * kGeomInts;
         const int h = g[0], wd = g[1];
@@ -366,44 +412,40 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
 #pragma unroll
         for (int it = 0; it < NLD; ++it) {
             const int i = threadIdx.x + it * 256;
-            const int cr = i / FC, j = i - cr * FC;
-            const int c = cr / FR, r = cr - c * FR;
+            const int r = i / FS, j = i - r * FS;
             const int iy = 2 * t.ty0 - 2 + r, ix = 2 * t.tx0 - 2 + j;
-            fv[it] = 0.f;
-            if (i < NF && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)wd)
-                fv[it] = fr[((size_t)c * h + iy) * wd + ix];
+            const bool ok = i < NPF && j < FC && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)wd;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fv[it][c] = ok ? fr[((size_t)c * h + iy) * wd + ix] : 0.f;
         }
     };
     auto park = [&]() {
 #pragma unroll
         for (int it = 0; it < NLD; ++it) {
             const int i = threadIdx.x + it * 256;
-            if (i < NF) fw[i] = fv[it];
+            if (i < NPF) {
+                f16x4 hv, lv;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    hv[c] = (f16)fv[it][c];
+                    lv[c] = (f16)(fv[it][c] - (float)hv[c]);
+                }
+                hv[3] = lv[3] = (f16)0.f;
+                fwh[i] = hv;
+                if constexpr (split) fwl[i] = lv;
+            }
         }
     };
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = lane & 15, kg = lane >> 4;
-    // stem operands of this lane: k = kg * 8 + j -> (r, s, c), weights as FP16 hi (+ lo)
-    int koff[8];
-    bool kval[8];
-    f16x8 wa[2], wl[2];
+    // stem weights of this lane as FP16 hi (+ lo), two k-steps per channel group
+    f16x8 wa[2][2], wl[2][2];
     float bv[2][4];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int k = kg * 8 + j;
-        const int r = k / 9, s = (k / 3) % 3, c = k % 3;
-        kval[j] = k < 27;
-        koff[j] = kval[j] ? (c * FR + r) * FC + s : 0;
-    }
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float v = kval[j] ? w0[(cg * 16 + p) * 27 + kg * 8 + j] : 0.f;
-            wa[cg][j] = (f16)v;
-            wl[cg][j] = (f16)(v - (float)wa[cg][j]);
-        }
+        for (int m = 0; m < 2; ++m) stem_wfrag(w0, cg * 16 + p, m, kg, wa[cg][m], wl[cg][m]);
 #pragma unroll
         for (int i = 0; i < 4; ++i) bv[cg][i] = b0[cg * 16 + kg * 4 + i];
     }
@@ -429,27 +471,16 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
             const int q = bi * 16 + p;
             const int R = q / WC, C = q - R * WC;
             const bool valid = q < WR * WC;
-            f16x8 b, bl;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float v = (kval[j] && valid) ? fw[koff[j] + R * FC + C] : 0.f;
-                b[j] = (f16)v;
-                if constexpr (split) bl[j] = (f16)(v - (float)b[j]);
-            }
+            f32x4 acc[2];
+            stem_block<2, split>(fwh, fwl, valid ? R * FS + C : 0, FS, kg, wa, wl, acc);
             const int sy = 2 * t.ty0 - 1 + R, sx = 2 * t.tx0 - 1 + C;
             const bool inside = valid && (unsigned)sy < (unsigned)h && (unsigned)sx < (unsigned)wd;
 #pragma unroll
             for (int cg = 0; cg < 2; ++cg) {
-                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-                if constexpr (split) {
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[cg], b, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], bl, acc, 0, 0, 0);
-                }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg], b, acc, 0, 0, 0);
                 typedef TO T4 __attribute__((ext_vector_type(4)));
                 T4 pk;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) pk[i] = (TO)(inside ? leaky01(acc[i] + bv[cg][i]) : 0.f);
+                for (int i = 0; i < 4; ++i) pk[i] = (TO)(inside ? leaky01(acc[cg][i] + bv[cg][i]) : 0.f);
                 if (valid) *(T4*)(&sw[((R * 2 + (C & 1)) * NE + (C >> 1)) * PS + cg * 16 + kg * 4]) = pk;
             }
         }
