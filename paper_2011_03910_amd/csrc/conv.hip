@@ -164,14 +164,15 @@ __device__ __forceinline__ f16x8 stem_bfrag(const f16x4* __restrict__ win, int p
     return f16x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
 }
 
-// One 16-pixel block of stem outputs for channel groups 0..NG-1 (FP32 accumulation;
-// with split, lo x hi + hi x lo + hi x hi per k-step).
+// One 16-pixel block of stem outputs for channel groups 0..NG-1: FP32
+// accumulation started at the bias (bv: this lane's 4 channels per group); with
+// split, lo x hi + hi x lo + hi x hi per k-step.
 template <int NG, bool split>
 __device__ __forceinline__ void stem_block(const f16x4* __restrict__ wh, const f16x4* __restrict__ wlo, int pos,
                                            int ws, int kg, const f16x8 (&wa)[NG][2], const f16x8 (&wl)[NG][2],
-                                           f32x4 (&acc)[NG]) {
+                                           const float (&bv)[NG][4], f32x4 (&acc)[NG]) {
 #pragma unroll
-    for (int cg = 0; cg < NG; ++cg) acc[cg] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int cg = 0; cg < NG; ++cg) acc[cg] = f32x4{bv[cg][0], bv[cg][1], bv[cg][2], bv[cg][3]};
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const f16x8 b = stem_bfrag(wh, pos, ws, m, kg);
@@ -309,13 +310,13 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
             const int xb = x0 + blk * 16;
             if (xb >= wd) break;
             f32x4 acc[NG];
-            stem_block<NG, split>(wh[buf], wlo[split ? buf : 0], blk * 16 + p, WS, kg, wa, wl, acc);
+            stem_block<NG, split>(wh[buf], wlo[split ? buf : 0], blk * 16 + p, WS, kg, wa, wl, bv, acc);
             typedef TO T4 __attribute__((ext_vector_type(4)));
             T4 pk[NG];
 #pragma unroll
             for (int cg = 0; cg < NG; ++cg)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) pk[cg][i] = (TO)leaky01(acc[cg][i] + bv[cg][i]);
+                for (int i = 0; i < 4; ++i) pk[cg][i] = (TO)leaky01(acc[cg][i]);
             TO* o = out + (row_m + xb + p) * COUT;
             if constexpr (NG == 1) {
                 // 16 pixels x 32 bytes: one contiguous 512-byte store
@@ -466,13 +467,16 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
     for (; P < total; P += gridDim.x) {
         const int* g = geom + t.f * kGeomInts;
         const int h = g[0], wd = g[1];
-        // stem window: flat 16-pixel blocks over the 5 x 129 positions
+        // stem window: flat 16-pixel blocks over the 5 x 129 positions; in an
+        // interior tile every stem position lies inside the frame
+        const bool interior = 2 * t.ty0 - 1 >= 0 && 2 * t.tx0 - 1 >= 0 && 2 * t.ty0 - 1 + WR <= h &&
+                              2 * t.tx0 - 1 + WC <= wd;
         for (int bi = wave; bi < NSB; bi += 4) {
             const int q = bi * 16 + p;
             const int R = q / WC, C = q - R * WC;
             const bool valid = q < WR * WC;
             f32x4 acc[2];
-            stem_block<2, split>(fwh, fwl, valid ? R * FS + C : 0, FS, kg, wa, wl, acc);
+            stem_block<2, split>(fwh, fwl, valid ? R * FS + C : 0, FS, kg, wa, wl, bv, acc);
             const int sy = 2 * t.ty0 - 1 + R, sx = 2 * t.tx0 - 1 + C;
             const bool inside = valid && (unsigned)sy < (unsigned)h && (unsigned)sx < (unsigned)wd;
 #pragma unroll
@@ -480,7 +484,8 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
                 typedef TO T4 __attribute__((ext_vector_type(4)));
                 T4 pk;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) pk[i] = (TO)(inside ? leaky01(acc[cg][i] + bv[cg][i]) : 0.f);
+                for (int i = 0; i < 4; ++i) pk[i] = (TO)leaky01(acc[cg][i]);
+                if (!interior && !inside) pk = T4{};  // the conv's zero padding
                 if (valid) *(T4*)(&sw[((R * 2 + (C & 1)) * NE + (C >> 1)) * PS + cg * 16 + kg * 4]) = pk;
             }
         }
