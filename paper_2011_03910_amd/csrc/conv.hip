@@ -381,7 +381,7 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
     constexpr int FS = FC + 1;                               // positions per window row (+1: zero-weight slots)
     constexpr int NE = kSdTX + 1;                            // pixels per parity plane (even: 65, odd: 64)
     constexpr int PS = 40;                                   // elements per pixel slot (32 + 8 padding)
-    constexpr int NPF = FR * FS, NLD = (NPF + 255) / 256;
+    constexpr int NPF = FR * FS;
     constexpr int NSB = (WR * WC + 15) / 16;                 // 16-pixel stem blocks (41)
     constexpr bool split = __is_same(TO, f16);
     typedef typename V16<TO>::type V;
@@ -405,35 +405,41 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
         t.tx0 = (item % tw) * kSdTX;
         return t;
     };
-    float fv[NLD][3];
-    auto load = [&](const Tile& t) {  // frame window rows 2 ty0 - 2 .., columns 2 tx0 - 2 ..
+    // The frame window is loaded as 16-byte groups of 4 columns from x = 2 tx0 - 4
+    // (16-byte aligned: widths are multiples of 32), so a group lies wholly inside
+    // or wholly outside the frame; thread i < 7 x 34 loads group i % 34 of row i / 34
+    // for the 3 channels (next tile's window: in flight during the current conv).
+    constexpr int NGR = (FS + 2 + 3) / 4;  // groups per row: positions -2 .. 4 NGR - 3
+    static_assert(FR * NGR <= 256, "one group per thread");
+    typedef float f32x4v __attribute__((ext_vector_type(4)));
+    f32x4v fv[3];
+    const int gr = threadIdx.x / NGR, gq = threadIdx.x - gr * NGR;
+    auto load = [&](const Tile& t) {
         const int* g = geom + t.f * kGeomInts;
         const int h = g[0], wd = g[1];
         const float* fr = frames + (size_t)g[2] * 3;
+        const int iy = 2 * t.ty0 - 2 + gr, x = 2 * t.tx0 - 4 + 4 * gq;
+        const bool ok = gr < FR && (unsigned)iy < (unsigned)h && x >= 0 && x + 4 <= wd;
 #pragma unroll
-        for (int it = 0; it < NLD; ++it) {
-            const int i = threadIdx.x + it * 256;
-            const int r = i / FS, j = i - r * FS;
-            const int iy = 2 * t.ty0 - 2 + r, ix = 2 * t.tx0 - 2 + j;
-            const bool ok = i < NPF && j < FC && (unsigned)iy < (unsigned)h && (unsigned)ix < (unsigned)wd;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) fv[it][c] = ok ? fr[((size_t)c * h + iy) * wd + ix] : 0.f;
-        }
+        for (int c = 0; c < 3; ++c)
+            fv[c] = ok ? *(const f32x4v*)(fr + ((size_t)c * h + iy) * wd + x) : f32x4v{0.f, 0.f, 0.f, 0.f};
     };
     auto park = [&]() {
+        if (gr < FR) {
 #pragma unroll
-        for (int it = 0; it < NLD; ++it) {
-            const int i = threadIdx.x + it * 256;
-            if (i < NPF) {
-                f16x4 hv, lv;
+            for (int k = 0; k < 4; ++k) {
+                const int j = 4 * gq - 2 + k;  // window position of column x + k
+                if (j >= 0 && j < FS) {
+                    f16x4 hv, lv;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    hv[c] = (f16)fv[it][c];
-                    lv[c] = (f16)(fv[it][c] - (float)hv[c]);
+                    for (int c = 0; c < 3; ++c) {
+                        hv[c] = (f16)fv[c][k];
+                        lv[c] = (f16)(fv[c][k] - (float)hv[c]);
+                    }
+                    hv[3] = lv[3] = (f16)0.f;
+                    fwh[gr * FS + j] = hv;
+                    if constexpr (split) fwl[gr * FS + j] = lv;
                 }
-                hv[3] = lv[3] = (f16)0.f;
-                fwh[i] = hv;
-                if constexpr (split) fwl[i] = lv;
             }
         }
     };
@@ -471,22 +477,31 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
         // interior tile every stem position lies inside the frame
         const bool interior = 2 * t.ty0 - 1 >= 0 && 2 * t.tx0 - 1 >= 0 && 2 * t.ty0 - 1 + WR <= h &&
                               2 * t.tx0 - 1 + WC <= wd;
-        for (int bi = wave; bi < NSB; bi += 4) {
-            const int q = bi * 16 + p;
-            const int R = q / WC, C = q - R * WC;
-            const bool valid = q < WR * WC;
-            f32x4 acc[2];
-            stem_block<2, split>(fwh, fwl, valid ? R * FS + C : 0, FS, kg, wa, wl, bv, acc);
-            const int sy = 2 * t.ty0 - 1 + R, sx = 2 * t.tx0 - 1 + C;
-            const bool inside = valid && (unsigned)sy < (unsigned)h && (unsigned)sx < (unsigned)wd;
+        // batches of SB blocks per wave, unrolled so that the blocks' LDS reads,
+        // MFMAs and epilogues overlap; slots past the last block recompute it
+        // without storing
+        constexpr int SB = 4;
+        for (int b0 = 0; b0 < (NSB + 3) / 4; b0 += SB) {
 #pragma unroll
-            for (int cg = 0; cg < 2; ++cg) {
-                typedef TO T4 __attribute__((ext_vector_type(4)));
-                T4 pk;
+            for (int b = 0; b < SB; ++b) {
+                const int bi = wave + 4 * (b0 + b);
+                const bool live = bi < NSB;  // wave-uniform
+                const int q = (live ? bi : NSB - 1) * 16 + p;
+                const int R = q / WC, C = q - R * WC;
+                const bool valid = live && q < WR * WC;
+                f32x4 acc[2];
+                stem_block<2, split>(fwh, fwl, q < WR * WC ? R * FS + C : 0, FS, kg, wa, wl, bv, acc);
+                const int sy = 2 * t.ty0 - 1 + R, sx = 2 * t.tx0 - 1 + C;
+                const bool inside = (unsigned)sy < (unsigned)h && (unsigned)sx < (unsigned)wd;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) pk[i] = (TO)leaky01(acc[cg][i]);
-                if (!interior && !inside) pk = T4{};  // the conv's zero padding
-                if (valid) *(T4*)(&sw[((R * 2 + (C & 1)) * NE + (C >> 1)) * PS + cg * 16 + kg * 4]) = pk;
+                for (int cg = 0; cg < 2; ++cg) {
+                    typedef TO T4 __attribute__((ext_vector_type(4)));
+                    T4 pk;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) pk[i] = (TO)leaky01(acc[cg][i]);
+                    if (!interior && !inside) pk = T4{};  // the conv's zero padding
+                    if (valid) *(T4*)(&sw[((R * 2 + (C & 1)) * NE + (C >> 1)) * PS + cg * 16 + kg * 4]) = pk;
+                }
             }
         }
         __syncthreads();  // stem window complete; the frame window is free
