@@ -48,6 +48,8 @@ template <typename T> __device__ __forceinline__ T cvt_out(float x) { return (T)
 constexpr int kBufFlags = 0x00020000;
 constexpr int kXCDs = 8;     // accelerator complex dies of an MI355X, each with its own L2
 constexpr int kOOB = 0x80000000;
+// s_waitcnt immediate (gfx9 encoding): vmcnt vm, lgkmcnt lgkm, expcnt not waited
+constexpr int waitcnt_imm(int vm, int lgkm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | (lgkm << 8); }
 
 // Row m of a level-`lvl` packed tensor -> (frame, y, x).
 __device__ __forceinline__ void map_pixel(const int* __restrict__ geom, int nframes, int uniform, int lvl,
@@ -141,6 +143,23 @@ __device__ __forceinline__ int xcd_remap(int L, int W) {
 // also keeps a window of the low parts x - fp16(x).
 // ---------------------------------------------------------------------------
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+// Marks registers as read here (an empty asm statement taking them as inputs),
+// so that the waits for the loads that wrote them are placed here rather than
+// inside a later loop.
+template <typename X>
+__device__ __forceinline__ void touch_regs1(const X& x) {
+    if constexpr (sizeof(X) <= 16 && !__is_array(X)) {
+        asm volatile("" ::"v"(x));
+    } else {
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(x) / sizeof(x[0])); ++i) touch_regs1(x[i]);
+    }
+}
+template <typename... X>
+__device__ __forceinline__ void touch_regs(const X&... x) {
+    (touch_regs1(x), ...);
+}
 
 // A operand of output channel co, k-step m, lane group kg: FP16 hi and lo parts
 __device__ __forceinline__ void stem_wfrag(const float* __restrict__ w, int co, int m, int kg, f16x8& hi,
@@ -287,6 +306,7 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
 #pragma unroll
         for (int i = 0; i < 4; ++i) bv[cg][i] = bias[cg * 16 + kg * 4 + i];
     }
+    touch_regs(wa, wl, bv);  // weights landed before the loop (see stem_down_kernel)
     // band of this workgroup's XCD (gridDim.x is a multiple of 8): items
     // [lo, hi), walked with stride per = gridDim.x / 8 from lo + blockIdx.x / 8
     const int per = gridDim.x / kXCDs, xcd = blockIdx.x % kXCDs;
@@ -408,7 +428,7 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
     // The frame window is loaded as 16-byte groups of 4 columns from x = 2 tx0 - 4
     // (16-byte aligned: widths are multiples of 32), so a group lies wholly inside
     // or wholly outside the frame; thread i < 7 x 34 loads group i % 34 of row i / 34
-    // for the 3 channels (next tile's window: in flight during the current conv).
+    // for the 3 channels.
     constexpr int NGR = (FS + 2 + 3) / 4;  // groups per row: positions -2 .. 4 NGR - 3
     static_assert(FR * NGR <= 256, "one group per thread");
     typedef float f32x4v __attribute__((ext_vector_type(4)));
@@ -463,6 +483,14 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
     float cb1[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) cb1[q] = b1[wave * 16 + kg * 4 + q];
+    // Use the weights once here: otherwise the compiler, merging loop entry and
+    // back edge, counts their loads as outstanding inside the loop and waits for
+    // the next tile's frame loads (issued later) before the conv's MFMAs and the
+    // epilogue.
+    touch_regs(af, cb1, wa, bv);
+    // output buffer: every level-1 pixel of the batch x 64 channels
+    const int out_bytes = geom[(nframes - 1) * kGeomInts + 8 + 1] * C1 * (int)sizeof(TO);
+    const __amdgpu_buffer_rsrc_t r_out = __builtin_amdgcn_make_buffer_rsrc((void*)out, 0, out_bytes, kBufFlags);
 
     int P = blockIdx.x;
     if (P >= total) return;  // uniform over the workgroup
@@ -473,6 +501,13 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
     for (; P < total; P += gridDim.x) {
         const int* g = geom + t.f * kGeomInts;
         const int h = g[0], wd = g[1];
+        // the next tile's frame window: in flight during this tile's stem and conv
+        const int Pn = P + gridDim.x;
+        Tile tn = t;
+        if (Pn < total) {
+            tn = locate(Pn);
+            load(tn);
+        }
         // stem window: flat 16-pixel blocks over the 5 x 129 positions; in an
         // interior tile every stem position lies inside the frame
         const bool interior = 2 * t.ty0 - 1 >= 0 && 2 * t.tx0 - 1 >= 0 && 2 * t.ty0 - 1 + WR <= h &&
@@ -505,12 +540,7 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
             }
         }
         __syncthreads();  // stem window complete; the frame window is free
-        const int Pn = P + gridDim.x;
-        Tile tn = t;
-        if (Pn < total) {
-            tn = locate(Pn);
-            load(tn);  // in flight during the conv below
-        }
+        const int obase1 = g[2 + 1];  // first level-1 pixel of the frame
         // the 3x3 stride-2 conv from LDS: 8 blocks of 16 pixels (2 rows x 64 columns)
         f32x4 acc[8];
 #pragma unroll
@@ -528,16 +558,26 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
                     acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[tp], bf, acc[i], 0, 0, 0);
             }
         }
-        // epilogue: bias, leaky, store this wave's 16 channels (32 bytes of each 128-byte pixel row)
+        // epilogue: bias, leaky, store this wave's 16 channels (32 bytes of each
+        // 128-byte pixel row); the frame's base pixel is read before the stores (a
+        // scalar load after vector stores to memory it may alias waits for them)
+        // Buffer stores, issued by every lane (outside the frame: an out-of-range
+        // offset, dropped), so the wait for the next window's loads before the
+        // park below can leave this wave's 8 stores in flight.
         typedef TO T4 __attribute__((ext_vector_type(4)));
+        typedef unsigned U2 __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int oy = t.ty0 + (i >> 2), ox = t.tx0 + (i & 3) * 16 + p;
-            if (oy >= t.h1 || ox >= t.w1) continue;
             T4 pk;
 #pragma unroll
             for (int q = 0; q < 4; ++q) pk[q] = (TO)leaky01(acc[i][q] + cb1[q]);
-            *(T4*)(out + ((size_t)g[2 + 1] + (size_t)oy * t.w1 + ox) * C1 + wave * 16 + kg * 4) = pk;
+            U2 u2;
+            __builtin_memcpy(&u2, &pk, 8);
+            const int off = (oy < t.h1 && ox < t.w1)
+                                ? ((obase1 + oy * t.w1 + ox) * C1 + wave * 16 + kg * 4) * (int)sizeof(TO)
+                                : kOOB;
+            __builtin_amdgcn_raw_buffer_store_b64(u2, r_out, off, 0, 0);
         }
         __syncthreads();  // every wave is done with the stem window
         if (Pn < total) park();
@@ -986,7 +1026,6 @@ __device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, const void* lds,
                  : "memory", "m0");
 }
 
-constexpr int waitcnt_imm(int vm, int lgkm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | (lgkm << 8); }
 
 // 16-byte slot swizzle of the 64-byte LDS rows.  A wave's ds_read_b128 is served
 // 32 lanes at a time and runs at full rate (256 B/clk per CU) only if those 32
