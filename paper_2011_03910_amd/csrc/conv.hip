@@ -1035,16 +1035,27 @@ __device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, const void* lds,
 // gfx950: the unswizzled layout and an XOR of row bits 1-3 into both slot bits
 // both run at half rate.
 __device__ __forceinline__ int dma_swizzle(int r) { return ((r >> 3) & 1) << 1; }
+// For 128-byte rows (8 slots): slot bit 2 ^= row bit 1, slot bit 1 ^= row bit 2 --
+// one of the linear XOR swizzles a lane-pattern probe found to keep the 16 rows x
+// 4 slots of an MFMA operand read at full rate (unswizzled: quarter rate).
+template <int RB>
+__device__ __forceinline__ int lds_swizzle(int r) {
+    if constexpr (RB == 64) return dma_swizzle(r);
+    else return (((r >> 1) & 1) << 2) | (((r >> 2) & 1) << 1);
+}
 
-template <typename T, int BM, int BN, int WGM, int WGN, int S, bool NT>
+template <typename T, int BM, int BN, int WGM, int WGN, int S, bool NT, int BK>
 __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
     constexpr int NW = WGM * WGN;                  // waves (4 or 8)
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
     constexpr int TM = WTM / 16, TN = WTN / 16;
-    constexpr int ROWS = BM + BN, SB = ROWS * 64;  // bytes per stage
-    constexpr int NPW = ROWS / (16 * NW);          // DMA instructions per wave per chunk
-    static_assert((NW == 4 || NW == 8) && TM >= 1 && TN >= 1, "4 or 8 waves");
-    static_assert(BM % (16 * NW) == 0 && BN % (16 * NW) == 0 && S >= 3 && S <= 4, "tile");
+    constexpr int RB = BK * 2;                     // bytes per LDS row (one K chunk of a row)
+    constexpr int KK = BK / 32;                    // MFMA k-steps per chunk
+    constexpr int RPI = 1024 / RB;                 // rows per DMA instruction
+    constexpr int ROWS = BM + BN, SB = ROWS * RB;  // bytes per stage
+    constexpr int NPW = ROWS / (RPI * NW);         // DMA instructions per wave per chunk
+    static_assert((NW == 4 || NW == 8) && TM >= 1 && TN >= 1 && (BK == 32 || BK == 64), "tile");
+    static_assert(BM % (RPI * NW) == 0 && BN % (RPI * NW) == 0 && S >= 3 && S <= 4, "tile");
     typedef typename V16<T>::type V;
 
     __shared__ __attribute__((aligned(1024))) char st0[SB];
@@ -1062,24 +1073,26 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
     const __amdgpu_buffer_rsrc_t r_w = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, a.w_bytes, kBufFlags);
 
     // Row descriptors of this lane's DMA instructions (instruction i of this
-    // wave fills rows 16 q .. 16 q + 15 of a stage, q = NW i + wave):
+    // wave fills rows RPI q .. RPI q + RPI - 1 of a stage, q = NW i + wave):
     //   d_off:  element offset of the row's origin (+ its k-slot);
     //   d_wc:   elements between kernel rows (image width x Cin for a pixel row,
     //           k x Cin for a weight row);
     //   d_mask: bit r * k + s set iff tap (r, s) lies inside the image (every tap of
     //           a weight row; none for a row past M or Cout).
     int d_off[NPW], d_wc[NPW], d_mask[NPW];
-    const int rloc = lane >> 2;
-    const int kslot = ((lane & 3) ^ dma_swizzle(rloc)) * 8;
+    const int rloc = lane / (RB / 16);
+    // (rows of a 128-byte-row instruction start at multiples of 8: rloc carries
+    // the row bits 1 and 2 the swizzle uses)
+    const int kslot = ((lane % (RB / 16)) ^ lds_swizzle<RB>(rloc)) * 8;
     const int taps = a.ksz * a.ksz;
 #pragma unroll
     for (int i = 0; i < NPW; ++i) {
         const int q = NW * i + wave;
-        const int row = 16 * q + rloc;
+        const int row = RPI * q + rloc;
         d_off[i] = 0;
         d_wc[i] = 0;
         d_mask[i] = 0;
-        if (16 * NW * i < BN) {  // weight row: channel n0 + row (BN % (16 NW) == 0: static per i)
+        if (RPI * NW * i < BN) {  // weight row: channel n0 + row (BN % (RPI NW) == 0: static per i)
             const int n = n0 + row;
             if (n < a.cout) {
                 d_off[i] = n * a.K + kslot;
@@ -1109,7 +1122,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
     // Tap (r, s) and channel ci of the next chunk to issue, advanced without
     // branches; chunks past the end read nothing (out-of-range offsets).
     int ld_ci = 0, ld_r = 0, ld_s = 0, issued = 0;
-    const int nk = a.K / 32;
+    const int nk = a.K / BK;
     auto issue = [&](auto u_c) {
         constexpr int u = decltype(u_c)::value;
         const int tap = issued < nk ? ld_r * a.ksz + ld_s : 31;  // bit 31 is never set
@@ -1120,10 +1133,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
             const bool ok = (d_mask[i] >> tap) & 1;
             const int off = ok ? (d_off[i] + ld_r * d_wc[i] + sc) * (int)sizeof(T) : kOOB;
             const char* sp = u == 0 ? st0 : u == 1 ? st1 : u == 2 ? st2 : st3;
-            dma16(16 * NW * i < BN ? r_w : r_in, sp + q * 1024, off);
+            dma16(RPI * NW * i < BN ? r_w : r_in, sp + q * 1024, off);
         }
         ++issued;
-        ld_ci += 32;
+        ld_ci += BK;
         const int wrap = ld_ci >= a.cin;
         ld_ci = wrap ? 0 : ld_ci;
         ld_s += wrap;
@@ -1138,31 +1151,42 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // lane-constant LDS read offset: row lane % 16 of a 16-row group, k-slot lane / 16
-    const int rd = (lane & 15) * 64 + (((lane >> 4) ^ dma_swizzle(lane & 15)) << 4);
-    const int a_rd = (wn * WTN) * 64 + rd, b_rd = (BN + wm * WTM) * 64 + rd;
+    // lane-constant LDS read offsets (per k-step kk of a chunk): row lane % 16 of a
+    // 16-row group, k-slot 4 kk + lane / 16
+    int rd[KK];
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+        rd[kk] = (lane & 15) * RB + (((4 * kk + (lane >> 4)) ^ lds_swizzle<RB>(lane & 15)) << 4);
+    const int a_rd = (wn * WTN) * RB, b_rd = (BN + wm * WTM) * RB;
     // MFMA operands of a chunk are read from LDS into one of two register sets
     // one step ahead, so that the LDS latency hides behind the previous chunk's MFMAs.
-    V fa[2][TN], fb[2][TM];
+    V fa[2][KK][TN], fb[2][KK][TM];
     auto read = [&](auto st_c, auto fr_c) {
         constexpr int st = decltype(st_c)::value, fr = decltype(fr_c)::value;
         const char* sp = st == 0 ? st0 : st == 1 ? st1 : st == 2 ? st2 : st3;
 #pragma unroll
-        for (int j = 0; j < TN; ++j) fa[fr][j] = *(const V*)(sp + a_rd + j * 16 * 64);
+        for (int kk = 0; kk < KK; ++kk) {
 #pragma unroll
-        for (int i = 0; i < TM; ++i) fb[fr][i] = *(const V*)(sp + b_rd + i * 16 * 64);
+            for (int j = 0; j < TN; ++j) fa[fr][kk][j] = *(const V*)(sp + a_rd + rd[kk] + j * 16 * RB);
+#pragma unroll
+            for (int i = 0; i < TM; ++i) fb[fr][kk][i] = *(const V*)(sp + b_rd + rd[kk] + i * 16 * RB);
+        }
     };
     auto mma = [&](auto fr_c) {
         constexpr int fr = decltype(fr_c)::value;
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                if constexpr (__is_same(T, bf16))
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[fr][j], fb[fr][i], acc[i][j], 0, 0, 0);
-                else
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[fr][j], fb[fr][i], acc[i][j], 0, 0, 0);
-            }
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    if constexpr (__is_same(T, bf16))
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[fr][kk][j], fb[fr][kk][i], acc[i][j],
+                                                                            0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[fr][kk][j], fb[fr][kk][i], acc[i][j],
+                                                                           0, 0, 0);
+                }
     };
 
     // Prologue: chunks 0 .. S-2 in flight; once chunk 0 has landed everywhere its
@@ -2008,19 +2032,22 @@ static constexpr TileCfg kTiles[] = {
     {256, 128, 4, 2, 32, 3, 1},  // 31: as 29, streaming stores
     {256, 256, 2, 4, 32, 3, 0},  // 32: direct-to-LDS, 8 waves of 128x64 (96 KB: half the loads per FLOP of 29/30)
     {256, 256, 4, 2, 32, 3, 0},  // 33: direct-to-LDS, 8 waves of 64x128 (96 KB)
+    {256, 128, 4, 2, 64, 3, 0},  // 34: direct-to-LDS, 64-channel K chunks (128-byte rows), 8 waves (144 KB)
+    {128, 256, 2, 4, 64, 3, 0},  // 35: as 34, 8 waves (144 KB)
+    {128, 128, 2, 2, 64, 3, 0},  // 36: as 34, 4 waves (96 KB)
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 template <typename T>
 constexpr int lds_bytes(const TileCfg& t) {
-    if (t.st) return t.st * (t.bm + t.bn) * 64;
+    if (t.st) return t.st * (t.bm + t.bn) * t.bk * 2;
     return 2 * (t.bm + t.bn) * (t.bk + (sizeof(T) == 4 ? 4 : 16)) * (int)sizeof(T);
 }
 // 16-bit types may use every tile; FP32 only the register-staged K-32 tiles
 // whose LDS fits.
 template <typename T>
 constexpr bool tile_built(int c) {
-    if (kTiles[c].st) return sizeof(T) == 2 && lds_bytes<T>(kTiles[c]) <= 128 * 1024;
+    if (kTiles[c].st) return sizeof(T) == 2 && lds_bytes<T>(kTiles[c]) <= 160 * 1024;
     return (sizeof(T) == 2 || kTiles[c].bk == 32) && lds_bytes<T>(kTiles[c]) <= 96 * 1024;
 }
 
@@ -2045,7 +2072,7 @@ bool conv_tile_ok(int c, int et, const ConvArgs& a) {
     if (c < 0 || c >= kNumTiles) return false;
     if (et != kF32 && et != kBF16 && et != kF16) return false;
     if (!built(c, et)) return false;
-    if (kTiles[c].st) return a.cin % 32 == 0 && a.cin1 == 0;
+    if (kTiles[c].st) return a.cin % kTiles[c].bk == 0 && a.cin1 == 0;
     if (!aligned_cin(a, kTiles[c].bk)) return c == 5 && a.cin1 == 0 && a.cin % (et == kF32 ? 4 : 8) == 0;
     return true;
 }
@@ -2079,7 +2106,7 @@ static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
         constexpr TileCfg t = kTiles[C];
         dim3 grid(((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn)), block(64 * t.wgm * t.wgn);
         if constexpr (t.st > 0)
-            conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0><<<grid, block, 0, s>>>(a);
+            conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk><<<grid, block, 0, s>>>(a);
         else if (aligned)
             conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, true><<<grid, block, 0, s>>>(a);
         else if constexpr (C == 5)
@@ -2127,6 +2154,9 @@ static hipError_t launch_type(const ConvArgs& a, int c, bool aligned, hipStream_
         case 31: return launch_t<T, 31>(a, aligned, s);
         case 32: return launch_t<T, 32>(a, aligned, s);
         case 33: return launch_t<T, 33>(a, aligned, s);
+        case 34: return launch_t<T, 34>(a, aligned, s);
+        case 35: return launch_t<T, 35>(a, aligned, s);
+        case 36: return launch_t<T, 36>(a, aligned, s);
     }
     return hipErrorInvalidValue;
 }
