@@ -248,7 +248,7 @@ def main():
         f"p99 {pct(step_ms, 99):.2f} ms; candidates/frame {ncand.mean():.1f}, kept {counts.mean():.1f}")
 
     ms, fl, kind, nfwd = prof
-    conv = kind == 1
+    conv = (kind == 1) | (kind == 6)  # implicit-GEMM and persistent pointwise conv launches
     conv_ms = ms[conv].sum() / nfwd
     conv_flop = fl[conv].sum()
     n_launch = int(conv.sum())
@@ -307,7 +307,7 @@ def main():
         "speedup_vs_fp32_b1": None if fp32 is None else round(fps / fp32["fps"], 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "kernel": f"implicit-GEMM convs conv_dma/conv_igemm ({n_launch} launches/step, {conv_flop / 1e9:.1f} GFLOP/step, "
+                     "kernel": f"conv launches conv_dma/conv_igemm/conv_pw_stream ({n_launch} launches/step, {conv_flop / 1e9:.1f} GFLOP/step, "
                                f"mean {conv_ms / n_launch * 1e3:.1f} us/launch)"},
         "serving": None if serving is None else {k: (round(v, 3) if isinstance(v, float) else v)
                                                   for k, v in serving.items()},

@@ -153,7 +153,10 @@ jde_status jde_autotune(jde_ctx* ctx, const float* d_frames, const jde_frame_des
 /* Reads (set = 0) or writes (set = 1) the tile choice of every forward launch:
  * tiles[n_ops] host, n_ops = number of forward launches (jde_profile_collect's
  * *n_ops); -1 = the built-in default.  Entries of non-MFMA launches are ignored
- * on write. */
+ * on write; a tile that does not fit its launch falls back to the default.
+ * Tile 37 is the persistent pointwise kernel (1x1 convs of 256 -> 128 and
+ * 512 -> 256 channels, BF16 / FP16: weights held in registers, pixel tiles
+ * streamed through LDS; same summation order as the implicit GEMM). */
 jde_status jde_tiles(jde_ctx* ctx, int* tiles, int n_ops, int set);
 
 /* FP8 calibration (mixed precision, Sec. 4.1, taken to the e4m3 format of
@@ -284,7 +287,8 @@ jde_status jde_profile_begin(jde_ctx* ctx, int on);
  * (launch order; at most max_ops entries written): summed duration in ms over
  * the profiled forwards (op_ms), FLOPs of one launch for the last batch
  * (op_flop: 2*M*N*K), kind (op_kind: 0 = stem, 1 = MFMA conv; 2-5 = fused
- * launches, see jde_fuse_stem and jde_fuse_blocks).  *n_fwd gets
+ * launches, see jde_fuse_stem and jde_fuse_blocks; 6 = MFMA conv run by the
+ * persistent pointwise kernel, tile 37 of jde_tiles).  *n_fwd gets
  * the number of forwards summed.  All arrays host. */
 jde_status jde_profile_collect(jde_ctx* ctx, int max_ops, double* op_ms, double* op_flop, int* op_kind,
                                int* n_ops, int* n_fwd);

@@ -93,7 +93,8 @@ struct jde_ctx {
     // and so do the two convs of each 64- and 128-channel residual block.
     // launch_kind[i] records how op i ran in the latest forward: 0 = its own
     // launch, 2 / 4 = head of a fused stem / residual-block launch, 3 / 5 = run
-    // inside the previous op's fused launch.
+    // inside the previous op's fused launch, 6 = its own launch of the persistent
+    // pointwise kernel.
     bool fuse_stem = true, fuse_blocks = true;
     // 3x3 stride-1 convs run from an LDS window (conv3_win) where they qualify;
     // off by default: measured slower than the implicit GEMM on MI355X.
@@ -817,6 +818,7 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
         } else {
             const int tile = (o.tile >= 0 && conv_tile_ok(o.tile, c->et, a)) ? o.tile : conv_default_tile(c->et, a);
             HIP_TRY(launch_conv(a, c->et, tile, s));
+            if (conv_tile_pw(tile)) c->launch_kind[oi] = 6;
         }
         if (pev) {
             HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));

@@ -1992,11 +1992,203 @@ hipError_t launch_resblock(const void* x, void* out, const void* w1, const float
 }
 
 // ---------------------------------------------------------------------------
+// Pointwise (1x1, stride 1) conv as a persistent streaming GEMM, 16-bit storage:
+// out[m][:] = act(b + W x[m][:]) for the batch's M pixels (the 1x1 halves of
+// the Darknet-53 residual blocks of Sec. 3.1 and the FPN's 1x1 convs with no
+// concatenated input).  With K = Cin <= 512 the work per pixel is small (2 Cout
+// FLOP per input byte), so the launch is bound by moving x in and out to HBM;
+// the implicit GEMM pays a pipeline fill per short K loop instead.  Here every
+// wave keeps its 16 G output channels' weights for all of K in registers for the
+// workgroup's life, and one workgroup per compute unit walks BN-pixel tiles
+// of x, brought into a ring of NBUF LDS buffers by direct-to-LDS loads NBUF - 1
+// tiles ahead of the one computing.  Workgroup g takes the pixels [g M / grid,
+// (g + 1) M / grid) in tiles from the range's start (the last one partial), so
+// that every workgroup moves the same bytes (equal tiles dealt round robin
+// would leave up to a whole tile's imbalance: 16 % at 5 tiles per workgroup).
+//   * tile layout in LDS: pixel rows of 2 Cin + 32 bytes (16-byte slots, the two
+//     last are padding, loaded as zeros), so that the 16 pixels x 2 k-slots a
+//     ds_read_b128 serves at once hit distinct 16-byte units modulo 512 bytes;
+//   * each wave issues exactly DPW 1-KB loads per tile (loads past the tile or
+//     the batch read zeros), so the wait for the next tile is a fixed vmcnt;
+//   * K is summed in the implicit GEMM's order (32-channel k-steps from 0, the
+//     bias after the last), so the outputs equal its outputs bit for bit.
+// ---------------------------------------------------------------------------
+// BN pixels per tile, G 16-channel groups per wave, NBUF ring buffers; on MI355X
+// 32 / 16 pixels with four buffers measured about 6 % faster than 64 / 32 with
+// three, and 128 / 64 with two about 12 % slower.
+template <int CIN, int COUT> struct PwCfg;
+template <> struct PwCfg<256, 128> { static constexpr int BN = 32, G = 1, NBUF = 4; };
+template <> struct PwCfg<512, 256> { static constexpr int BN = 16, G = 2, NBUF = 4; };
+
+template <typename T, int CIN, int COUT>
+__global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T* __restrict__ out,
+                                                      const T* __restrict__ w, const float* __restrict__ bias, int M,
+                                                      int ld, int act, int x_bytes, int out_bytes) {
+    constexpr int NW = 8, BN = PwCfg<CIN, COUT>::BN, G = PwCfg<CIN, COUT>::G;
+    static_assert(NW * G * 16 == COUT, "one wave per 16 G output channels");
+    constexpr int KA = CIN / 32, NB = BN / 16;
+    constexpr int XSL = CIN / 8, XS = (XSL + 2) * 16;              // slots of x per pixel, bytes per LDS row
+    constexpr int NSL = BN * (XSL + 2);                             // 16-byte slots per tile
+    constexpr int DPW = (NSL + 64 * NW - 1) / (64 * NW);            // 1-KB loads per wave per tile
+    constexpr int XB = DPW * NW * 1024, NBUF = PwCfg<CIN, COUT>::NBUF;  // bytes per buffer, buffers
+    constexpr int NST = NB * G;                                     // stores per wave per tile
+    static_assert(NBUF >= 2 && NBUF * XB <= 160 * 1024 && (NBUF - 2) * DPW + NB * G <= 63, "LDS, vmcnt");
+    typedef typename V16<T>::type V;
+    typedef T T4 __attribute__((ext_vector_type(4)));
+
+    __shared__ __attribute__((aligned(1024))) char xw[NBUF * XB];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int p = lane & 15, kg = lane >> 4;
+    const __amdgpu_buffer_rsrc_t r_x = __builtin_amdgcn_make_buffer_rsrc((void*)x, 0, x_bytes, kBufFlags);
+    const __amdgpu_buffer_rsrc_t r_out = __builtin_amdgcn_make_buffer_rsrc((void*)out, 0, out_bytes, kBufFlags);
+
+    V a[G][KA];
+    float bb[G][4];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int ch = (wave * G + g) * 16;
+#pragma unroll
+        for (int kk = 0; kk < KA; ++kk) a[g][kk] = *(const V*)(w + (size_t)(ch + p) * CIN + kk * 32 + kg * 8);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bb[g][q] = bias[ch + kg * 4 + q];
+    }
+    touch_regs(a, bb);  // the weights have landed before the loop's first wait
+
+    // Load i of this wave fills tile slots (wave + NW i) 64 + lane: pixel px,
+    // slot sl of that pixel's row; rel = its byte offset from the tile's first
+    // pixel, -1 for padding slots and slots past the tile.
+    int rel[DPW], pxi[DPW];
+#pragma unroll
+    for (int i = 0; i < DPW; ++i) {
+        const int L = (wave + NW * i) * 64 + lane;
+        const int px = L / (XSL + 2), sl = L - px * (XSL + 2);
+        pxi[i] = px;
+        rel[i] = (L < NSL && sl < XSL) ? (px * CIN + sl * 8) * (int)sizeof(T) : -1;
+    }
+    const unsigned lbase = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long)(lds_ptr_t)&xw[0]);
+    // this workgroup's pixels [lo, hi) and tiles
+    const int lo = (int)((long long)blockIdx.x * M / gridDim.x);
+    const int hi = (int)((long long)(blockIdx.x + 1) * M / gridDim.x);
+    const int nt = (hi - lo + BN - 1) / BN;
+    auto issue = [&](int j, int buf) {  // tile j >= nt: zeros (the count stays fixed)
+        const int p0 = lo + (j < nt ? j : 0) * BN;
+#pragma unroll
+        for (int i = 0; i < DPW; ++i) {
+            const int off = (j < nt && rel[i] >= 0 && p0 + pxi[i] < hi)
+                                ? (int)((unsigned)p0 * (unsigned)(CIN * sizeof(T)) + (unsigned)rel[i])
+                                : kOOB;
+            const unsigned la = lbase + (unsigned)(buf * XB + (wave + NW * i) * 1024);
+            asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+                         :
+                         : "s"(la), "v"(off), "s"(r_x)
+                         : "memory", "m0");
+        }
+    };
+
+    // gridDim.x <= ceil(M / BN): every workgroup has at least one pixel
+    static_for<0, NBUF - 1>([&](auto j_c) { issue(decltype(j_c)::value, decltype(j_c)::value); });
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm((NBUF - 2) * DPW, 15));  // this wave's loads of the first tile
+    // Per tile (ring slot it % NBUF): barrier (every wave's loads of this tile
+    // have landed; every wave is done with the previous tile, whose slot is
+    // refilled now with the tile NBUF - 1 ahead); MFMAs from LDS; epilogue
+    // stores; wait for this wave's loads of the next tile: in issue order they are
+    // followed by the loads of the NBUF - 2 tiles after it and by this tile's NST
+    // stores (and possibly earlier tiles' stores, which only waits longer), and
+    // vector memory operations complete in order.
+    for (int it = 0; it < nt; ++it) {
+        const int buf = it % NBUF;
+        __builtin_amdgcn_s_barrier();
+        issue(it + NBUF - 1, (it + NBUF - 1) % NBUF);
+        const char* xb = xw + buf * XB;
+        f32x4 acc[NB][G];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[b][g] = f32x4{0.f, 0.f, 0.f, 0.f};
+        V bf[2][NB];
+        auto rd = [&](auto kk_c) {
+            constexpr int kk = decltype(kk_c)::value;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) bf[kk & 1][b] = *(const V*)(xb + (b * 16 + p) * XS + (kk * 4 + kg) * 16);
+        };
+        rd(std::integral_constant<int, 0>{});
+        static_for<0, KA>([&](auto kk_c) {
+            constexpr int kk = decltype(kk_c)::value;
+            if constexpr (kk + 1 < KA) rd(std::integral_constant<int, kk + 1>{});
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    if constexpr (__is_same(T, bf16))
+                        acc[b][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[g][kk], bf[kk & 1][b], acc[b][g], 0, 0, 0);
+                    else
+                        acc[b][g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[g][kk], bf[kk & 1][b], acc[b][g], 0, 0, 0);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        // epilogue: + bias, leaky (act), cast; 8 bytes per lane and 16-channel
+        // group; pixels past the range get an out-of-range offset (dropped, issued)
+        typedef unsigned U2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int m = lo + it * BN + b * 16 + p;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                T4 pk;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float v = acc[b][g][q] + bb[g][q];
+                    if (act) v = leaky01(v);
+                    pk[q] = cvt_out<T>(v);
+                }
+                U2 u2;
+                __builtin_memcpy(&u2, &pk, 8);
+                const int ob = (m * ld + (wave * G + g) * 16 + kg * 4) * (int)sizeof(T);
+                __builtin_amdgcn_raw_buffer_store_b64(u2, r_out, m < hi ? ob : kOOB, 0, 0);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(waitcnt_imm((NBUF - 2) * DPW + NST, 15));
+    }
+    // no load may still be writing LDS when the workgroup ends
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
+}
+
+static bool conv_pw_ok(const ConvArgs& a, int et) {
+    if (et != kBF16 && et != kF16) return false;
+    if (a.ksz != 1 || a.stride != 1 || a.pad != 0 || a.cin1 != 0 || a.lvl_in != a.lvl_out) return false;
+    if (a.res || a.out1 || a.n_split != a.cout || a.out0_f32 || a.wscale || a.amax) return false;
+    if (!((a.cin == 256 && a.cout == 128) || (a.cin == 512 && a.cout == 256))) return false;
+    if (a.ld0 < a.cout || a.ld0 % 4 || a.M <= 0) return false;
+    return (size_t)a.M * a.cin * 2 <= (size_t)a.in_bytes && (size_t)a.M * a.ld0 * 2 < ((size_t)1 << 31);
+}
+
+template <typename T, int CIN, int COUT>
+static hipError_t launch_pw_t(const ConvArgs& a, hipStream_t s) {
+    constexpr int BN = PwCfg<CIN, COUT>::BN;
+    const int ntiles = (a.M + BN - 1) / BN;
+    const int g = ntiles < 256 ? ntiles : 256;  // one workgroup per compute unit (96 KB of LDS)
+    conv_pw_stream<T, CIN, COUT><<<dim3(g), dim3(512), 0, s>>>((const T*)a.in, (T*)a.out0, (const T*)a.w, a.bias,
+                                                                a.M, a.ld0, a.act, a.in_bytes, a.M * a.ld0 * 2);
+    return hipGetLastError();
+}
+
+static hipError_t launch_pw(const ConvArgs& a, int et, hipStream_t s) {
+    if (!conv_pw_ok(a, et)) return hipErrorInvalidValue;
+    if (et == kBF16)
+        return a.cin == 256 ? launch_pw_t<bf16, 256, 128>(a, s) : launch_pw_t<bf16, 512, 256>(a, s);
+    return a.cin == 256 ? launch_pw_t<f16, 256, 128>(a, s) : launch_pw_t<f16, 512, 256>(a, s);
+}
+
+// ---------------------------------------------------------------------------
 // Tile configurations and dispatch.
 // ---------------------------------------------------------------------------
 // st = 0: register-staged conv_igemm; st = S >= 3: conv_dma with S stages;
 // nt = 1: streaming (non-temporal) output stores.
-struct TileCfg { int bm, bn, wgm, wgn, bk, st, nt; };
+// pw = 1: the persistent pointwise kernel (conv_pw_stream; 1x1 convs of 256 -> 128
+// and 512 -> 256 channels only, the other fields unused).
+struct TileCfg { int bm, bn, wgm, wgn, bk, st, nt, pw = 0; };
 static constexpr TileCfg kTiles[] = {
     {128, 128, 2, 2, 32, 0, 0},  // 0: 64x64 per wave
     {256, 64, 4, 1, 32, 0, 0},   // 1: 64x64 per wave (Cout 64)
@@ -2035,6 +2227,7 @@ static constexpr TileCfg kTiles[] = {
     {256, 128, 4, 2, 64, 3, 0},  // 34: direct-to-LDS, 64-channel K chunks (128-byte rows), 8 waves (144 KB)
     {128, 256, 2, 4, 64, 3, 0},  // 35: as 34, 8 waves (144 KB)
     {128, 128, 2, 2, 64, 3, 0},  // 36: as 34, 4 waves (96 KB)
+    {64, 128, 1, 1, 32, 0, 0, 1},  // 37: persistent pointwise stream (120 KB)
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
@@ -2047,11 +2240,13 @@ constexpr int lds_bytes(const TileCfg& t) {
 // whose LDS fits.
 template <typename T>
 constexpr bool tile_built(int c) {
+    if (kTiles[c].pw) return sizeof(T) == 2;
     if (kTiles[c].st) return sizeof(T) == 2 && lds_bytes<T>(kTiles[c]) <= 160 * 1024;
     return (sizeof(T) == 2 || kTiles[c].bk == 32) && lds_bytes<T>(kTiles[c]) <= 96 * 1024;
 }
 
 int conv_num_tile_cfgs() { return kNumTiles; }
+bool conv_tile_pw(int c) { return c >= 0 && c < kNumTiles && kTiles[c].pw; }
 void conv_tile_shape(int c, int* bm, int* bn) {
     *bm = kTiles[c].bm;
     *bn = kTiles[c].bn;
@@ -2072,6 +2267,7 @@ bool conv_tile_ok(int c, int et, const ConvArgs& a) {
     if (c < 0 || c >= kNumTiles) return false;
     if (et != kF32 && et != kBF16 && et != kF16) return false;
     if (!built(c, et)) return false;
+    if (kTiles[c].pw) return conv_pw_ok(a, et);
     if (kTiles[c].st) return a.cin % kTiles[c].bk == 0 && a.cin1 == 0;
     if (!aligned_cin(a, kTiles[c].bk)) return c == 5 && a.cin1 == 0 && a.cin % (et == kF32 ? 4 : 8) == 0;
     return true;
@@ -2100,7 +2296,7 @@ int conv_default_tile(int et, const ConvArgs& a) {
 
 template <typename T, int C>
 static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
-    if constexpr (!tile_built<T>(C)) {
+    if constexpr (!tile_built<T>(C) || kTiles[C].pw) {  // pointwise tiles: launch_pw
         return hipErrorInvalidValue;
     } else {
         constexpr TileCfg t = kTiles[C];
@@ -2157,12 +2353,14 @@ static hipError_t launch_type(const ConvArgs& a, int c, bool aligned, hipStream_
         case 34: return launch_t<T, 34>(a, aligned, s);
         case 35: return launch_t<T, 35>(a, aligned, s);
         case 36: return launch_t<T, 36>(a, aligned, s);
+        case 37: return launch_t<T, 37>(a, aligned, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_conv(const ConvArgs& a, int et, int c, hipStream_t s) {
     if (!conv_tile_ok(c, et, a)) return hipErrorInvalidValue;
+    if (kTiles[c].pw) return launch_pw(a, et, s);
     const bool aligned = aligned_cin(a, kTiles[c].bk);
     if (et == kF32) return launch_type<float>(a, c, aligned, s);
     if (et == kBF16) return launch_type<bf16>(a, c, aligned, s);

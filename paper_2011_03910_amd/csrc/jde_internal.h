@@ -95,6 +95,8 @@ int conv_num_tile_cfgs();
 bool conv_tile_ok(int tile_cfg, int elem_type, const ConvArgs& a);
 int conv_default_tile(int elem_type, const ConvArgs& a);
 void conv_tile_shape(int tile_cfg, int* bm, int* bn);
+// Tile config that selects the persistent pointwise (1x1) kernel.
+bool conv_tile_pw(int tile_cfg);
 
 // Post-processing launchers (post.hip).
 struct DecodeArgs {

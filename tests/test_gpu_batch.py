@@ -332,3 +332,40 @@ def test_graph_replays_equal_eager(torch):
             D = len(a["anchor_idx"])
             np.testing.assert_array_equal(cost[6 * f:6 * f + 6, :D].cpu().numpy(), ec[6 * f:6 * f + 6, :D].cpu().numpy())
         _say(f"  replay {rep} ok: {[int(x) for x in dets['count'].cpu()]} detections")
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("cfg_name", ["tiny", "full"])
+def test_pointwise_stream_equals_implicit_gemm(torch, precision, cfg_name):
+    """Tile 37 (the persistent pointwise kernel: 1x1 convs of 256 -> 128 and
+    512 -> 256 channels) sums K in the implicit GEMM's order, so forcing it
+    wherever it applies leaves the heads unchanged (bit for bit up to the 1e-6
+    bound), on ragged batches whose pixel counts end in partial tiles; the launch
+    kinds show which convs took it."""
+    _say(f"case: pointwise stream {cfg_name} {precision}")
+    cfg = TINY if cfg_name == "tiny" else FULL
+    sizes = ([(192, 320), (128, 256), (192, 320)] if cfg_name == "tiny"
+             else [(608, 1088), (320, 576), (480, 864)])
+    m = _model(cfg, precision, len(sizes))
+    m.load_weights(weights(cfg_name, 50 if cfg_name == "tiny" else 40))
+    frs = [frames(cfg_name, 1, 0, h, w)[0] for h, w in sizes]
+    packed = torch.from_numpy(np.concatenate([f.ravel() for f in frs])).cuda()
+    n_ops = len(m.tiles())
+    m.set_tiles(np.full(n_ops, -1, dtype=np.int32))
+    plain = head_views(m.forward(packed, sizes), sizes)
+    m.set_tiles(np.full(n_ops, 37, dtype=np.int32))  # ops it does not fit keep their default tile
+    m.profile_begin(True)
+    pw = head_views(m.forward(packed, sizes), sizes)
+    _, _, kind, _ = m.profile_collect()
+    m.profile_begin(False)
+    torch.cuda.synchronize()
+    worst, same = 0.0, True
+    for key in ("det", "emb"):
+        for s in range(3):
+            for i in range(len(sizes)):
+                worst = max(worst, rel_err(pw[key][s][i], plain[key][s][i]))
+                same = same and np.array_equal(pw[key][s][i], plain[key][s][i])
+    n_pw = int((np.asarray(kind) == 6).sum())
+    _say(f"  pointwise launches: {n_pw}; vs implicit GEMM: rel err {worst:.2e}, bitwise equal {same}")
+    assert n_pw >= (1 if cfg_name == "tiny" else 16)
+    assert worst <= 1e-6
