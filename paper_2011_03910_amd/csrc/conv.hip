@@ -2274,6 +2274,9 @@ bool conv_tile_ok(int c, int et, const ConvArgs& a) {
 }
 
 int conv_default_tile(int et, const ConvArgs& a) {
+    // the persistent pointwise kernel wherever it fits (same sums, faster)
+    for (int t = 0; t < kNumTiles; ++t)
+        if (kTiles[t].pw && conv_tile_ok(t, et, a)) return t;
     if (!aligned_cin(a, 32)) return 5;
     // Prefer the largest tile that still gives at least ~2 workgroups per CU.
     static const int pref_wide[] = {0, 2, 3, 5, 7};

@@ -338,10 +338,10 @@ def test_graph_replays_equal_eager(torch):
 @pytest.mark.parametrize("cfg_name", ["tiny", "full"])
 def test_pointwise_stream_equals_implicit_gemm(torch, precision, cfg_name):
     """Tile 37 (the persistent pointwise kernel: 1x1 convs of 256 -> 128 and
-    512 -> 256 channels) sums K in the implicit GEMM's order, so forcing it
-    wherever it applies leaves the heads unchanged (bit for bit up to the 1e-6
-    bound), on ragged batches whose pixel counts end in partial tiles; the launch
-    kinds show which convs took it."""
+    512 -> 256 channels, the default wherever it fits) sums K in the implicit
+    GEMM's order, so the heads equal those with the same launches on the
+    implicit GEMM (bit for bit up to the 1e-6 bound), on ragged batches whose
+    pixel counts end in partial tiles; the launch kinds show which convs took it."""
     _say(f"case: pointwise stream {cfg_name} {precision}")
     cfg = TINY if cfg_name == "tiny" else FULL
     sizes = ([(192, 320), (128, 256), (192, 320)] if cfg_name == "tiny"
@@ -351,21 +351,31 @@ def test_pointwise_stream_equals_implicit_gemm(torch, precision, cfg_name):
     frs = [frames(cfg_name, 1, 0, h, w)[0] for h, w in sizes]
     packed = torch.from_numpy(np.concatenate([f.ravel() for f in frs])).cuda()
     n_ops = len(m.tiles())
-    m.set_tiles(np.full(n_ops, -1, dtype=np.int32))
-    plain = head_views(m.forward(packed, sizes), sizes)
-    m.set_tiles(np.full(n_ops, 37, dtype=np.int32))  # ops it does not fit keep their default tile
-    m.profile_begin(True)
-    pw = head_views(m.forward(packed, sizes), sizes)
-    _, _, kind, _ = m.profile_collect()
-    m.profile_begin(False)
-    torch.cuda.synchronize()
+
+    def run(tiles):
+        m.set_tiles(tiles)
+        m.profile_begin(True)
+        out = head_views(m.forward(packed, sizes), sizes)
+        _, _, kind, _ = m.profile_collect()
+        m.profile_begin(False)
+        torch.cuda.synchronize()
+        return out, np.asarray(kind)[:n_ops]
+
+    pw, kind = run(np.full(n_ops, 37, dtype=np.int32))  # ops it does not fit take their default tile
+    _, kind_default = run(np.full(n_ops, -1, dtype=np.int32))
+    # the built-in default picks it wherever it fits
+    np.testing.assert_array_equal(kind_default == 6, kind == 6)
+    # the same launches through the implicit GEMM (register-staged tile 0), the
+    # others on their default tile as above
+    plain, kind_plain = run(np.where(kind == 6, 0, -1).astype(np.int32))
+    assert not (kind_plain == 6).any()
     worst, same = 0.0, True
     for key in ("det", "emb"):
         for s in range(3):
             for i in range(len(sizes)):
                 worst = max(worst, rel_err(pw[key][s][i], plain[key][s][i]))
                 same = same and np.array_equal(pw[key][s][i], plain[key][s][i])
-    n_pw = int((np.asarray(kind) == 6).sum())
+    n_pw = int((kind == 6).sum())
     _say(f"  pointwise launches: {n_pw}; vs implicit GEMM: rel err {worst:.2e}, bitwise equal {same}")
     assert n_pw >= (1 if cfg_name == "tiny" else 16)
     assert worst <= 1e-6
