@@ -2134,6 +2134,7 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int m = lo + it * BN + b * 16 + p;
+            const int mo = m < hi ? m : lo;  // offsets computed for in-range pixels only
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 T4 pk;
@@ -2145,7 +2146,7 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
                 }
                 U2 u2;
                 __builtin_memcpy(&u2, &pk, 8);
-                const int ob = (m * ld + (wave * G + g) * 16 + kg * 4) * (int)sizeof(T);
+                const int ob = (mo * ld + (wave * G + g) * 16 + kg * 4) * (int)sizeof(T);
                 __builtin_amdgcn_raw_buffer_store_b64(u2, r_out, m < hi ? ob : kOOB, 0, 0);
             }
         }
