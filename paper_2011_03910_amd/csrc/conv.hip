@@ -2008,8 +2008,9 @@ hipError_t launch_resblock(const void* x, void* out, const void* w1, const float
 //   * tile layout in LDS: pixel rows of 2 Cin + 32 bytes (16-byte slots, the two
 //     last are padding, loaded as zeros), so that the 16 pixels x 2 k-slots a
 //     ds_read_b128 serves at once hit distinct 16-byte units modulo 512 bytes;
-//   * each wave issues exactly DPW 1-KB loads per tile (loads past the tile or
-//     the batch read zeros), so the wait for the next tile is a fixed vmcnt;
+//   * each wave issues a fixed number of 1-KB loads per tile (DPW or DPW - 1;
+//     loads past the range read zeros), so the wait for the next tile is one of
+//     two fixed vmcnts;
 //   * K is summed in the implicit GEMM's order (32-channel k-steps from 0, the
 //     bias after the last), so the outputs equal its outputs bit for bit.
 // ---------------------------------------------------------------------------
@@ -2029,8 +2030,8 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
     constexpr int KA = CIN / 32, NB = BN / 16;
     constexpr int XSL = CIN / 8, XS = (XSL + 2) * 16;              // slots of x per pixel, bytes per LDS row
     constexpr int NSL = BN * (XSL + 2);                             // 16-byte slots per tile
-    constexpr int DPW = (NSL + 64 * NW - 1) / (64 * NW);            // 1-KB loads per wave per tile
-    constexpr int XB = DPW * NW * 1024, NBUF = PwCfg<CIN, COUT>::NBUF;  // bytes per buffer, buffers
+    constexpr int NDMA = (NSL + 63) / 64, DPW = (NDMA + NW - 1) / NW;  // 1-KB loads per tile, per wave (at most)
+    constexpr int XB = NDMA * 1024, NBUF = PwCfg<CIN, COUT>::NBUF;  // bytes per buffer, buffers
     constexpr int NST = NB * G;                                     // stores per wave per tile
     static_assert(NBUF >= 2 && NBUF * XB <= 160 * 1024 && (NBUF - 2) * DPW + NB * G <= 63, "LDS, vmcnt");
     typedef typename V16<T>::type V;
@@ -2072,10 +2073,12 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
     const int lo = (int)((long long)blockIdx.x * M / gridDim.x);
     const int hi = (int)((long long)(blockIdx.x + 1) * M / gridDim.x);
     const int nt = (hi - lo + BN - 1) / BN;
-    auto issue = [&](int j, int buf) {  // tile j >= nt: zeros (the count stays fixed)
-        const int p0 = lo + (j < nt ? j : 0) * BN;
-#pragma unroll
-        for (int i = 0; i < DPW; ++i) {
+    // Load i of tile j into ring slot buf (tile j >= nt: zeros, so that the count
+    // per wave stays fixed); waves whose last load index is past the tile's NDMA
+    // loads issue DPW - 1 per tile (`full` is false for them).
+    auto issue_one = [&](int j, int buf, int i) {
+        if (wave + NW * i < NDMA) {  // wave-uniform
+            const int p0 = lo + (j < nt ? j : 0) * BN;
             const int off = (j < nt && rel[i] >= 0 && p0 + pxi[i] < hi)
                                 ? (int)((unsigned)p0 * (unsigned)(CIN * sizeof(T)) + (unsigned)rel[i])
                                 : kOOB;
@@ -2086,21 +2089,30 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
                          : "memory", "m0");
         }
     };
+    const bool full = wave + NW * (DPW - 1) < NDMA;
 
     // gridDim.x <= ceil(M / BN): every workgroup has at least one pixel
-    static_for<0, NBUF - 1>([&](auto j_c) { issue(decltype(j_c)::value, decltype(j_c)::value); });
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm((NBUF - 2) * DPW, 15));  // this wave's loads of the first tile
+    static_for<0, NBUF - 1>([&](auto j_c) {
+#pragma unroll
+        for (int i = 0; i < DPW; ++i) issue_one(decltype(j_c)::value, decltype(j_c)::value, i);
+    });
+    // this wave's loads of the first tile
+    if (full)
+        __builtin_amdgcn_s_waitcnt(waitcnt_imm((NBUF - 2) * DPW, 15));
+    else
+        __builtin_amdgcn_s_waitcnt(waitcnt_imm((NBUF - 2) * (DPW - 1), 15));
     // Per tile (ring slot it % NBUF): barrier (every wave's loads of this tile
     // have landed; every wave is done with the previous tile, whose slot is
-    // refilled now with the tile NBUF - 1 ahead); MFMAs from LDS; epilogue
-    // stores; wait for this wave's loads of the next tile: in issue order they are
-    // followed by the loads of the NBUF - 2 tiles after it and by this tile's NST
-    // stores (and possibly earlier tiles' stores, which only waits longer), and
-    // vector memory operations complete in order.
+    // refilled with the tile NBUF - 1 ahead, its loads spread over the k-steps so
+    // that the compute unit's load path works while the matrix cores do); MFMAs
+    // from LDS; epilogue stores; wait for this wave's loads of the next tile: in
+    // issue order they are followed by the loads of the NBUF - 2 tiles after it
+    // and by this tile's NST stores (and possibly earlier tiles' stores, which only
+    // waits longer), and vector memory operations complete in order.
     for (int it = 0; it < nt; ++it) {
         const int buf = it % NBUF;
         __builtin_amdgcn_s_barrier();
-        issue(it + NBUF - 1, (it + NBUF - 1) % NBUF);
+        const int jn = it + NBUF - 1, bn = jn % NBUF;
         const char* xb = xw + buf * XB;
         f32x4 acc[NB][G];
 #pragma unroll
@@ -2116,6 +2128,9 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
         rd(std::integral_constant<int, 0>{});
         static_for<0, KA>([&](auto kk_c) {
             constexpr int kk = decltype(kk_c)::value;
+            static_for<0, DPW>([&](auto i_c) {  // load i at k-step i KA / DPW
+                if constexpr ((decltype(i_c)::value * KA) / DPW == kk) issue_one(jn, bn, decltype(i_c)::value);
+            });
             if constexpr (kk + 1 < KA) rd(std::integral_constant<int, kk + 1>{});
 #pragma unroll
             for (int b = 0; b < NB; ++b)
@@ -2150,7 +2165,10 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
                 __builtin_amdgcn_raw_buffer_store_b64(u2, r_out, m < hi ? ob : kOOB, 0, 0);
             }
         }
-        __builtin_amdgcn_s_waitcnt(waitcnt_imm((NBUF - 2) * DPW + NST, 15));
+        if (full)
+            __builtin_amdgcn_s_waitcnt(waitcnt_imm((NBUF - 2) * DPW + NST, 15));
+        else
+            __builtin_amdgcn_s_waitcnt(waitcnt_imm((NBUF - 2) * (DPW - 1) + NST, 15));
     }
     // no load may still be writing LDS when the workgroup ends
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
