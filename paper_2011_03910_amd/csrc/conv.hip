@@ -2187,7 +2187,7 @@ template <typename T, int CIN, int COUT>
 static hipError_t launch_pw_t(const ConvArgs& a, hipStream_t s) {
     constexpr int BN = PwCfg<CIN, COUT>::BN;
     const int ntiles = (a.M + BN - 1) / BN;
-    const int g = ntiles < 256 ? ntiles : 256;  // one workgroup per compute unit (96 KB of LDS)
+    const int g = ntiles < 256 ? ntiles : 256;  // one workgroup per compute unit (68 KB of LDS)
     conv_pw_stream<T, CIN, COUT><<<dim3(g), dim3(512), 0, s>>>((const T*)a.in, (T*)a.out0, (const T*)a.w, a.bias,
                                                                 a.M, a.ld0, a.act, a.in_bytes, a.M * a.ld0 * 2);
     return hipGetLastError();
@@ -2246,7 +2246,7 @@ static constexpr TileCfg kTiles[] = {
     {256, 128, 4, 2, 64, 3, 0},  // 34: direct-to-LDS, 64-channel K chunks (128-byte rows), 8 waves (144 KB)
     {128, 256, 2, 4, 64, 3, 0},  // 35: as 34, 8 waves (144 KB)
     {128, 128, 2, 2, 64, 3, 0},  // 36: as 34, 4 waves (96 KB)
-    {64, 128, 1, 1, 32, 0, 0, 1},  // 37: persistent pointwise stream (120 KB)
+    {64, 128, 1, 1, 32, 0, 0, 1},  // 37: persistent pointwise stream (68 KB)
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
