@@ -167,3 +167,74 @@ def test_tracker_keeps_identities_on_clean_synthetic_scene(rng):
                 assert owner[i] == tr["id"]
     assert len(owner) == n
     assert len(trk.tracks) == n - 1
+
+
+def test_box_to_z_hand_computed():
+    """(x1, y1, x2, y2) = (10, 20, 40, 110): centre (25, 65), width 30, height 90,
+    so the aspect a = w / h = 1/3 (not h / w = 3)."""
+    z = tk.box_to_z(np.array([[10.0, 20.0, 40.0, 110.0], [-5.0, 0.0, 15.0, 80.0]]))
+    np.testing.assert_array_equal(z[0], [25.0, 65.0, 30.0 / 90.0, 90.0])
+    np.testing.assert_array_equal(z[1], [5.0, 40.0, 0.25, 80.0])
+
+
+def test_smooth_embedding_closed_form():
+    """Orthogonal unit f (track) and e (detection): f' = (0.9 f + 0.1 e) / sqrt(0.82),
+    so <f', f> = 0.9 / sqrt(0.82) and <f', e> = 0.1 / sqrt(0.82); the old state
+    carries the momentum.  A scaled-up e does not change the direction of the
+    weights beyond the stated mix (e enters unnormalised)."""
+    f = np.zeros(16)
+    f[3] = 1.0
+    e = np.zeros(16)
+    e[7] = 1.0
+    g = tk.smooth_embedding(f, e)
+    assert abs(np.linalg.norm(g) - 1.0) < 1e-15
+    assert g @ f == pytest.approx(0.9 / math.sqrt(0.82), rel=1e-14)
+    assert g @ e == pytest.approx(0.1 / math.sqrt(0.82), rel=1e-14)
+    g2 = tk.smooth_embedding(f, 3.0 * e)
+    assert g2 @ e / (g2 @ f) == pytest.approx(0.3 / 0.9, rel=1e-14)
+
+
+def test_kalman_predict_covariance_closed_form():
+    """P = diag(p), F = [[I, I], [0, I]]: F P F^T has P[i, i] = p_i + p_{i+4},
+    P[i, i+4] = P[i+4, i] = p_{i+4}, P[i+4, i+4] = p_{i+4}; the process noise Q is
+    added on the diagonal with stds scaled by the height before the prediction
+    (position h/20, velocity h/160; a: 1e-2, va: 1e-5)."""
+    p = np.arange(1.0, 9.0) * 0.37
+    h = 120.0
+    mean = np.array([300.0, 200.0, 0.4, h, 1.5, -2.0, 0.01, 6.0])     # vh != 0: h changes on predict
+    m2, c2 = tk.kf_predict(mean, np.diag(p))
+    q = np.array([(h / 20) ** 2, (h / 20) ** 2, 1e-4, (h / 20) ** 2,
+                  (h / 160) ** 2, (h / 160) ** 2, 1e-10, (h / 160) ** 2])
+    want = np.zeros((8, 8))
+    for i in range(4):
+        want[i, i] = p[i] + p[i + 4] + q[i]
+        want[i, i + 4] = want[i + 4, i] = p[i + 4]
+        want[i + 4, i + 4] = p[i + 4] + q[i + 4]
+    np.testing.assert_allclose(c2, want, rtol=1e-14, atol=0)
+    np.testing.assert_array_equal(m2, np.concatenate([mean[:4] + mean[4:], mean[4:]]))
+
+
+def test_kalman_steady_state_matches_discrete_riccati():
+    """With a constant height the filter splits into four independent 1-D
+    constant-velocity filters with constant Q and R; after many predict/update
+    steps the predicted 2x2 covariance of each coordinate is the solution of the
+    discrete algebraic Riccati equation X = F X F^T - F X H^T (H X H^T + r)^-1 H X F^T + Q
+    (scipy.linalg.solve_discrete_are with A = F^T, B = H^T)."""
+    from scipy.linalg import solve_discrete_are
+    h = 90.0
+    z = np.array([200.0, 150.0, 0.35, h])
+    mean, cov = tk.kf_initiate(z)
+    for _ in range(400):
+        mean, cov = tk.kf_predict(mean, cov)
+        pred = cov.copy()
+        mean, cov = tk.kf_update(mean, cov, z)
+    assert mean[3] == h
+    f1 = np.array([[1.0, 1.0], [0.0, 1.0]])
+    h1 = np.array([[1.0], [0.0]])
+    # cx, cy and h share the height-scaled noises (the aspect's 1e-10 velocity
+    # noise makes its filter converge over thousands of steps, so it is left out)
+    q = np.diag([(h / 20) ** 2, (h / 160) ** 2])
+    x = solve_discrete_are(f1.T, h1, q, np.array([[(h / 20) ** 2]]))
+    for i in (0, 1, 3):
+        got = pred[np.ix_([i, i + 4], [i, i + 4])]
+        np.testing.assert_allclose(got, x, rtol=1e-10)
