@@ -222,6 +222,19 @@ jde_status jde_nms(jde_ctx* ctx, const float* d_boxes, const float* d_margins, c
                    int K, float nms_iou, void* d_ws, size_t ws_bytes, int* d_keep, int* d_nkeep,
                    void* stream);
 
+/* jde_nms without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same inputs, outputs and keep list as jde_nms, no context.  Its
+ * scratch (8.3 MiB: keys, positions, sorted boxes, keep list and the K x K/64
+ * suppression mask) is a static device array that the library holds on each GPU
+ * it runs on until the process ends; the call allocates nothing.  K <= 8192,
+ * else JDE_ECAPACITY before any work is enqueued.  Runs on the current device;
+ * `stream` must belong to it.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other host threads) race and
+ * must be serialised by the caller. */
+jde_status jde_nms_noalloc(const float* d_boxes, const float* d_margins, const int* d_idx, int K,
+                           float nms_iou, int* d_keep, int* d_nkeep, void* stream);
+
 /* Tracks x detections cost (Appendix A items 5-6).  All pointers device.
  * track_emb [T,E] FP32, mean [T,8] FP64 (cx, cy, a, h, vcx, vcy, va, vh),
  * cov [T,8,8] FP64 (predicted state), det_boxes [D,4] FP32 (x1, y1, x2, y2),

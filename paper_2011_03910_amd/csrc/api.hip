@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -531,6 +532,50 @@ uint16_t f32_to_f16_rne(float x) {
 }
 }  // namespace jde
 
+// ---- NMS without caller-provided device memory -----------------------------
+// jde_nms_noalloc runs jde_nms's kernels on a file-scope device array instead of
+// a workspace.  Layout (byte offsets): sort keys u64[kNoallocK], positions
+// int[kNoallocK], three counters in 256-byte slots, sorted boxes float4[kNoallocK],
+// keep positions int[kNoallocK], suppression mask u64[kNoallocK][kNoallocK / 64].
+namespace {
+constexpr int kNoallocK = 8192;
+constexpr size_t kNaKeys = 0;
+constexpr size_t kNaVals = kNaKeys + (size_t)kNoallocK * 8;
+constexpr size_t kNaCount = kNaVals + (size_t)kNoallocK * 4;
+constexpr size_t kNaKcount = kNaCount + 256;
+constexpr size_t kNaNkeep = kNaKcount + 256;
+constexpr size_t kNaBoxes = kNaNkeep + 256;
+constexpr size_t kNaKeep = kNaBoxes + (size_t)kNoallocK * 16;
+constexpr size_t kNaMask = kNaKeep + (size_t)kNoallocK * 4;
+constexpr size_t kNaBytes = kNaMask + (size_t)kNoallocK * (kNoallocK / 64) * 8;
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+char* g_na_ptr[kNaMaxDevices] = {};
+}  // namespace
+
+// One copy per GPU, held until the process ends.  Host code never passes this
+// name to a kernel: it is a host-side stand-in; the device address of each GPU's
+// copy comes from hipGetSymbolAddress (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// Device address of the current device's copy of `scratch`, looked up once per
+// device with that device current.
+static jde_status noalloc_scratch(char** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(JDE_EDEVICE, "device %d outside [0, %d)", dev, kNaMaxDevices);
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(JDE_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_na_ptr[dev] = (char*)p;
+    }
+    *out = g_na_ptr[dev];
+    return JDE_OK;
+}
+
 // ---- C ABI -----------------------------------------------------------------
 extern "C" {
 
@@ -998,6 +1043,35 @@ jde_status jde_nms(jde_ctx* c, const float* boxes, const float* margins, const i
     HIP_TRY(launch_sort(keys, vals, counts, c->keycap, 1, s));
     HIP_TRY(launch_nms_gather(boxes, keys, vals, K, sboxes, kcount, s));
     HIP_TRY(launch_nms(sboxes, kcount, c->cap, iou, (unsigned long long*)(W + c->ws_mask), keep, nkeep, 1, s));
+    HIP_TRY(launch_nms_finish(keep, nkeep, vals, keep_out, nkeep_out, K, s));
+    return JDE_OK;
+}
+
+jde_status jde_nms_noalloc(const float* boxes, const float* margins, const int* idx, int K, float iou, int* keep_out,
+                           int* nkeep_out, void* stream) {
+    if (!keep_out || !nkeep_out) return fail(JDE_EINVAL, "null argument");
+    if (K < 0) return fail(JDE_EINVAL, "K=%d is negative", K);
+    if (K > kNoallocK)
+        return fail(JDE_ECAPACITY, "K=%d exceeds the %d candidates the static scratch array holds", K, kNoallocK);
+    if (K > 0 && (!boxes || !margins || !idx)) return fail(JDE_EINVAL, "null candidate arrays");
+    if (!(iou >= 0.f)) return fail(JDE_EINVAL, "nms_iou must be >= 0");
+    char* S = nullptr;
+    if (jde_status st = noalloc_scratch(&S)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* keys = (unsigned long long*)(S + kNaKeys);
+    int* vals = (int*)(S + kNaVals);
+    int* counts = (int*)(S + kNaCount);
+    float* sboxes = (float*)(S + kNaBoxes);
+    int* kcount = (int*)(S + kNaKcount);
+    int* keep = (int*)(S + kNaKeep);
+    int* nkeep = (int*)(S + kNaNkeep);
+    // Every scratch word a kernel reads is written earlier in this sequence (the
+    // counters by prepare / gather / scan, the mask words of rows < K by the mask
+    // kernel), so nothing needs clearing between calls.
+    HIP_TRY(launch_nms_prepare(boxes, margins, idx, K, keys, vals, counts, s));
+    HIP_TRY(launch_sort(keys, vals, counts, kNoallocK, 1, s));
+    HIP_TRY(launch_nms_gather(boxes, keys, vals, K, sboxes, kcount, s));
+    HIP_TRY(launch_nms(sboxes, kcount, kNoallocK, iou, (unsigned long long*)(S + kNaMask), keep, nkeep, 1, s));
     HIP_TRY(launch_nms_finish(keep, nkeep, vals, keep_out, nkeep_out, K, s));
     return JDE_OK;
 }

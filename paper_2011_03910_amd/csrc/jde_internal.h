@@ -20,7 +20,7 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 constexpr int kMaxFrames = 64;     // frames per batch
 constexpr int kLevels = 6;         // strides 1, 2, 4, 8, 16, 32
 constexpr int kMaxCap = 8192;      // per-frame candidate cap entering NMS
-constexpr int kSortLds = 8192;     // keys sorted in LDS; larger lists sort in global memory
+constexpr int kSortLds = 4096;     // keys sorted in LDS; larger lists sort in global memory
 
 // Per-frame geometry of a batch, stored in device memory (int32 each):
 //   [0] h, [1] w of the frame (pixels),

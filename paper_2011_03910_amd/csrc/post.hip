@@ -91,7 +91,7 @@ hipError_t launch_decode(const DecodeArgs& a, int max_anchors, hipStream_t s) {
 // (the key buffer has a power-of-two capacity per frame).
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 1024;
-constexpr int kSortLdsKV = 4096;
+constexpr int kSortLdsKV = kSortLds;
 
 __global__ __launch_bounds__(kSortThreads) void sort_kernel(u64* keys, int* vals, const int* counts, int keycap) {
     __shared__ u64 sk[kSortLdsKV];

@@ -86,6 +86,21 @@ def jde_cost_matrix(trk_emb, mean, cov, det_boxes, det_emb, gate=9.4877, cost=No
     return cost
 
 
+def jde_nms_noalloc(boxes, margins, idx, nms_iou=0.4, keep=None, nkeep=None, stream=None):
+    """Greedy NMS of one candidate list on the library's static scratch (no
+    workspace).  Device tensors in; keep positions [max(K, 1)] int32 and the
+    kept count [1] int32 out (allocated here unless given)."""
+    torch = _torch()
+    K = int(boxes.shape[0])
+    if keep is None:
+        keep = torch.empty(max(K, 1), dtype=torch.int32, device=boxes.device)
+    if nkeep is None:
+        nkeep = torch.empty(1, dtype=torch.int32, device=boxes.device)
+    check(load().jde_nms_noalloc(_ptr(boxes), _ptr(margins), _ptr(idx), K, float(nms_iou), _ptr(keep),
+                                 _ptr(nkeep), _stream(stream)), "jde_nms_noalloc")
+    return keep, nkeep
+
+
 def jde_track_emb_update(pairs, det_emb, trk_emb, momentum=0.9, stream=None):
     P = pairs.shape[0]
     check(load().jde_track_emb_update(_ptr(pairs), P, _ptr(det_emb), det_emb.shape[0], _ptr(trk_emb),

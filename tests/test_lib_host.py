@@ -224,3 +224,14 @@ def test_fp8_encoder_matches_library_cast():
     np.testing.assert_array_equal(got[inr], ref[inr])
     big = np.array([449.0, 1e9, -600.0, np.nan], dtype=np.float32)
     np.testing.assert_array_equal(jde_fp8_encode(big), [0x7E, 0x7E, 0xFE, 0x7F])
+
+
+def test_nms_noalloc_rejects_lists_beyond_its_scratch(lib):
+    """The static-scratch NMS refuses K > 8192 before any device work."""
+    from paper_2011_03910_amd import _lib
+    st = lib.jde_nms_noalloc(None, None, None, 8193, ctypes.c_float(0.4), ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), None)
+    assert st == _lib.JDE_ECAPACITY
+    assert "8192" in lib.jde_last_error().decode()
+    assert lib.jde_nms_noalloc(None, None, None, -1, ctypes.c_float(0.4), ctypes.c_void_p(16),
+                               ctypes.c_void_p(16), None) == _lib.JDE_EINVAL
