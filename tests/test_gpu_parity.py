@@ -2,7 +2,8 @@
 
 Tolerances: FP32 path, every head output within normwise max relative error
 1e-4; reduced precision within 2e-2 and >= 99% of the oracle's detections
-matched at IoU >= 0.9.  NMS keep-indices are bit-exact on the oracle's
+matched at IoU >= 0.9 (asserted for every precision; BF16 and FP8 miss it and
+are marked as expected failures with the measured numbers).  NMS keep-indices are bit-exact on the oracle's
 candidates.  Cost entries within 2e-6 with an identical +inf pattern.
 """
 
@@ -59,27 +60,104 @@ def test_tiny_fp32_forward_parity(torch):
             assert e <= 1e-4, (key, s, e)
 
 
-def check_reduced_precision(v, ref, emul, precision, frame=0):
-    """FP16: every head output within 2e-2 of the FP64 oracle.  BF16: its 8-bit
-    mantissa alone puts this random-weight network's outputs further than 2e-2
-    from FP64 (the rounding-emulated oracle shows it), so the bound is the
-    emulated oracle's own error: the kernels may not add error beyond what
-    storing weights and activations in BF16 implies."""
-    worst = 0.0
+# The spec bar for the reduced-precision path: every head output within
+# 2e-2 (normwise max relative error) of the FP64 oracle and >= 99 % of the
+# oracle's detections matched at IoU >= 0.9 (per frame, one-to-one greedy
+# matching in oracle-score order).  Both halves are asserted for every
+# precision; where a half is measured to fail, the test is marked as an expected
+# failure with the measured numbers, and the other half still has to pass.
+BAR_ERR = 2e-2
+BAR_MATCH = 0.99
+
+
+class HeadBarError(Exception):
+    """A head output beyond BAR_ERR (kept apart from AssertionError so that an
+    expected failure of the matching half cannot hide a head regression)."""
+
+
+class MatchBarError(Exception):
+    """Matched fraction below BAR_MATCH."""
+
+
+# BF16 storage cannot meet either half on this random-weight network: the FP64
+# oracle with only its conv weights rounded to BF16 already moves the full
+# frame's heads by 2.5e-2 .. 7.8e-2, with only its stored activations rounded by
+# 3.4e-2 .. 8.9e-2, with both by 3.6e-2 .. 1.11e-1 (FP32 residual stream:
+# 1.17e-1).
+BF16_MISSES_BAR = pytest.mark.xfail(
+    strict=True, raises=(HeadBarError, MatchBarError),
+    reason="BF16 storage alone moves this network's heads 3.6e-2..1.1e-1 from FP64 (> 2e-2); the GPU measures "
+           "3.7e-2..1.07e-1 and 81-93 % of detections matched")
+FP8_MISSES_BAR = pytest.mark.xfail(
+    strict=True, raises=(HeadBarError, MatchBarError),
+    reason="the e4m3 backbone moves the heads 0.2-0.47 from FP64 and matches ~27 % of detections")
+# FP16 meets the head half everywhere (5e-3 .. 1.44e-2) but single decisions
+# flip: a candidate whose margin lies within the FP16 error of the threshold, or
+# an overlapping pair whose NMS outcome changes.  With 8-70 detections per frame
+# one flip already drops the fraction below 99 %.
+FP16_MATCH_MISS = pytest.mark.xfail(
+    strict=True, raises=MatchBarError,
+    reason="FP16 heads meet 2e-2, but threshold / NMS flips leave 1-4 oracle detections of 8-70 unmatched "
+           "(87.5-98.6 %)")
+
+
+def head_errors(v, ref, frame=0, ref_frame=0, emul=None):
+    """Per-head normwise errors of GPU heads v against the FP64 oracle; prints
+    them (and, as a diagnostic only, the error of a rounding-emulated oracle)."""
+    errs = {}
     for key in ("det", "emb"):
         for s in range(3):
-            e = rel_err(v[key][s][frame], ref[key][s][frame])
-            e_emul = rel_err(emul[key][s][frame], ref[key][s][frame])
-            e_vs_emul = rel_err(v[key][s][frame], emul[key][s][frame])
-            _say(f"  {key}{8 << s}: rel err {e:.2e} (rounding-emulated oracle {e_emul:.2e}; gpu vs emulated "
-                 f"{e_vs_emul:.2e})")
-            bound = 2e-2 if precision == "fp16" else max(2e-2, 1.5 * e_emul)
-            assert e <= bound, (key, s, e, bound)
-            worst = max(worst, e)
-    return worst
+            e = rel_err(v[key][s][frame], ref[key][s][ref_frame])
+            msg = f"  {key}{8 << s}: rel err vs fp64 {e:.2e}"
+            if emul is not None:
+                msg += f" (diagnostic: rounding-emulated oracle {rel_err(emul[key][s][ref_frame], ref[key][s][ref_frame]):.2e})"
+            _say(msg)
+            errs[f"{key}{8 << s}"] = e
+    return errs
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def classify_misses(v, d, r, frame=0, thr_margin=0.0):
+    """For each oracle detection the GPU did not match: 'threshold' if the GPU's
+    own margin at that anchor is below the threshold (it never became a GPU
+    candidate), else 'nms' (a candidate the GPU's NMS resolved differently)."""
+    frac, pairs = match_fraction(d["boxes"], r["boxes"], r["score"])
+    matched = {q for q, _ in pairs}
+    kinds = {"threshold": 0, "nms": 0}
+    for q in range(len(r["idx"])):
+        if q in matched:
+            continue
+        idx = int(r["idx"][q])
+        for s in range(3):
+            det = v["det"][s][frame]
+            n = det.shape[0] * det.shape[1] * 4
+            if idx < n:
+                cell, a = divmod(idx, 4)
+                i, j = divmod(cell, det.shape[1])
+                m = float(det[i, j, 6 * a + 5]) - float(det[i, j, 6 * a + 4])
+                kinds["threshold" if m < thr_margin else "nms"] += 1
+                break
+            idx -= n
+    return frac, pairs, kinds
+
+
+def check_bar(v, ref, d, r, frame=0, ref_frame=0, emul=None):
+    """Asserts the reduced-precision bar: heads first (HeadBarError), then the
+    detection matching (MatchBarError).  Returns (worst head error, matched fraction)."""
+    errs = head_errors(v, ref, frame, ref_frame, emul)
+    frac, pairs, kinds = classify_misses(v, d, r, frame)
+    cos = [float(d["emb"][g] @ r["emb"][q]) for q, g in pairs]
+    _say(f"  dets gpu {len(d['boxes'])} oracle {len(r['idx'])} matched {frac:.4f} (misses: {kinds}); "
+         f"min emb cos {min(cos) if cos else float('nan'):.4f}")
+    worst = max(errs.values())
+    if worst > BAR_ERR:
+        raise HeadBarError(f"head error {worst:.3e} > {BAR_ERR}: {errs}")
+    if frac < BAR_MATCH:
+        raise MatchBarError(f"matched {frac:.4f} < {BAR_MATCH} (misses {kinds})")
+    return worst, frac
+
+
+@pytest.mark.parametrize("precision", [pytest.param("bf16", marks=BF16_MISSES_BAR),
+                                       pytest.param("fp16", marks=FP16_MATCH_MISS)])
 def test_tiny_reduced_precision_parity(torch, precision):
     _say(f"case: tiny {precision} b1 forward+decode")
     m = _model(TINY, precision, 1)
@@ -88,13 +166,9 @@ def test_tiny_reduced_precision_parity(torch, precision):
     ref = oracle_forward("tiny", 50, 1)
     emul = oracle_forward_rounded("tiny", 50, 1, precision)
     v = head_views(heads, [(192, 320)])
-    check_reduced_precision(v, ref, emul, precision)
     d = gpu_dets(m.decode(heads, [(192, 320)]), 0, m.cap)
     r = opost.detections(ref, anchors("tiny"), 0.5, 0.4)
-    frac, _ = match_fraction(d["boxes"], r["boxes"], r["score"])
-    _say(f"  matched {frac:.3f} of {len(r['idx'])}")
-    if precision == "fp16":
-        assert frac >= 0.95
+    check_bar(v, ref, d, r, emul=emul)
 
 
 def test_tiny_decode_nms_normalise_on_gpu_heads(torch):
@@ -215,70 +289,93 @@ def test_full_fp32_b1_forward_parity(torch):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("precision", ["bf16", "fp16"])
-def test_full_reduced_precision_parity(torch, precision):
-    """Full network at the workload's density (~40 candidates per frame): head
-    outputs within tolerance, >= 99% of the oracle's detections matched at IoU
-    >= 0.9 (FP16; reported for BF16); the dense 1000-candidate setting is reported."""
-    _say(f"case: full {precision} b1 forward")
-    for k, strict in ((40, True), (1000, False)):
-        m = _model(FULL, precision, 1)
-        m.load_weights(weights("full", k))
-        heads = _run(torch, m, frames("full", 1))
-        ref = oracle_forward("full", k, 1)
-        v = head_views(heads, [(608, 1088)])
-        if strict:
-            emul = oracle_forward_rounded("full", k, 1, precision)
-            check_reduced_precision(v, ref, emul, precision)
-        d = gpu_dets(m.decode(heads, [(608, 1088)]), 0, m.cap)
-        r = opost.detections(ref, anchors("full"), 0.5, 0.4)
-        frac, pairs = match_fraction(d["boxes"], r["boxes"], r["score"])
-        cos = [float(d["emb"][g] @ r["emb"][q]) for q, g in pairs]
-        _say(f"  K={k}: dets gpu {len(d['boxes'])} oracle {len(r['idx'])} matched {frac:.4f} "
-             f"min emb cos {min(cos) if cos else float('nan'):.4f}")
-        if strict and precision == "fp16":
-            assert frac >= 0.99
+@pytest.mark.parametrize("k", [pytest.param(10, marks=FP16_MATCH_MISS), 40,
+                               pytest.param(100, marks=FP16_MATCH_MISS), 1000])
+def test_full_fp16_parity_at_densities(torch, k):
+    """Full network, FP16 (the paper's mixed precision), batch 1, confidence
+    offsets for 10 / 40 / 100 / 1000 candidates per frame: the bar at every density."""
+    _say(f"case: full fp16 b1 K={k}")
+    m = _model(FULL, "fp16", 1, cap=2048)
+    m.load_weights(weights("full", k))
+    heads = _run(torch, m, frames("full", 1))
+    ref = oracle_forward("full", k, 1)
+    v = head_views(heads, [(608, 1088)])
+    d = gpu_dets(m.decode(heads, [(608, 1088)]), 0, m.cap)
+    r = opost.detections(ref, anchors("full"), 0.5, 0.4)
+    _say(f"  candidates gpu {d['n_cand']} oracle {r['n_cand']}")
+    check_bar(v, ref, d, r)
 
 
 @pytest.mark.slow
-def test_full_bf16_batch16_stored_tiles_parity(torch):
-    """The benchmarked launch configuration: BF16, 16 frames of 608x1088 in one
-    batch, the stored per-launch tile choices (direct-to-LDS kernels included),
-    ~40 candidates per frame.  Frames 0 and 15 are checked against the oracle
-    (head outputs by the BF16 rule; detections reported), the other frames
-    against the same forward run one frame at a time (batching must not change
-    a frame's result beyond accumulation order)."""
+@BF16_MISSES_BAR
+def test_full_bf16_parity(torch):
+    """Full network, BF16, batch 1, ~40 candidates: held to the same bar."""
+    _say("case: full bf16 b1 K=40")
+    m = _model(FULL, "bf16", 1)
+    m.load_weights(weights("full", 40))
+    heads = _run(torch, m, frames("full", 1))
+    ref = oracle_forward("full", 40, 1)
+    v = head_views(heads, [(608, 1088)])
+    d = gpu_dets(m.decode(heads, [(608, 1088)]), 0, m.cap)
+    r = opost.detections(ref, anchors("full"), 0.5, 0.4)
+    check_bar(v, ref, d, r, emul=oracle_forward_rounded("full", 40, 1, "bf16"))
+
+
+def _stored_tiles(name):
     import json
     import os
-    from oracle.network import forward, round_bf16
-    _say("case: full bf16 b16 stored tiles")
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2011_03910_amd",
                         "tiles_mi355x.json")
-    tiles = np.array(json.load(open(path))["bf16_b16"], dtype=np.int32)
+    return np.array(json.load(open(path))[name], dtype=np.int32)
+
+
+def _batch16_vs_oracle(torch, precision):
+    """16 frames of 608x1088 in one batch with the stored BF16 batch-16 tile
+    choices (the benchmarked launches, direct-to-LDS kernels included); frames 0
+    and 15 against the FP64 oracle."""
+    tiles = _stored_tiles("bf16_b16")
     _say(f"  tiles: {sorted(set(tiles.tolist()))}")
-    m = _model(FULL, "bf16", 16)
+    m = _model(FULL, precision, 16)
     m.load_weights(weights("full", 40))
     m.set_tiles(tiles)
     fr = frames("full", 16)
     heads = _run(torch, m, fr)
     v = head_views(heads, [(608, 1088)] * 16)
-    layers = weights("full", 40)
-    sel = fr[[0, 15]]
-    ref = forward(sel, layers, FULL.blocks)
-    lr = [layers[0]] + [(round_bf16(w), b) for w, b in layers[1:]]
-    emul = forward(sel, lr, FULL.blocks, store=round_bf16)
-    def pick(d, i):  # one frame of a head dict, as a batch of one
-        return {key: [d[key][s][i][None] for s in range(3)] for key in ("det", "emb")}
-    for j, f in enumerate((0, 15)):
-        _say(f"  frame {f}:")
-        check_reduced_precision(pick(v, f), pick(ref, j), pick(emul, j), "bf16")
     d = m.decode(heads, [(608, 1088)] * 16)
-    for j, f in enumerate((0, 15)):
-        g = gpu_dets(d, f, m.cap)
-        r = opost.detections(ref, anchors("full"), 0.5, 0.4, frame=j)
-        frac, _ = match_fraction(g["boxes"], r["boxes"], r["score"])
-        _say(f"  frame {f}: dets gpu {len(g['boxes'])} oracle {len(r['idx'])} matched {frac:.3f}")
-    # every frame equals the same network run on that frame alone (same tiles)
+    for f in (0, 15):
+        _say(f"  frame {f}:")
+        ref = oracle_forward("full", 40, 1, t0=f)        # frame f of the batch = frame f of the stream
+        r = opost.detections(ref, anchors("full"), 0.5, 0.4)
+        check_bar(v, ref, gpu_dets(d, f, m.cap), r, frame=f, ref_frame=0)
+    return m, fr, v
+
+
+@pytest.mark.slow
+@BF16_MISSES_BAR
+def test_full_bf16_batch16_stored_tiles_parity(torch):
+    _say("case: full bf16 b16 stored tiles vs oracle")
+    _batch16_vs_oracle(torch, "bf16")
+
+
+@pytest.mark.slow
+@FP16_MATCH_MISS
+def test_full_fp16_batch16_stored_tiles_parity(torch):
+    """The same launches (stored tiles: conv_dma, conv_pw_stream, fused stem and
+    blocks) in FP16 meet the bar."""
+    _say("case: full fp16 b16 stored tiles vs oracle")
+    _batch16_vs_oracle(torch, "fp16")
+
+
+@pytest.mark.slow
+def test_full_bf16_batch16_frames_equal_single_frame_runs(torch):
+    """Batching does not change a frame's result: frames 3, 8 and 12 of the
+    benchmarked BF16 batch of 16 (stored tiles) equal each frame run alone."""
+    _say("case: full bf16 b16 vs single-frame runs")
+    m = _model(FULL, "bf16", 16)
+    m.load_weights(weights("full", 40))
+    m.set_tiles(_stored_tiles("bf16_b16"))
+    fr = frames("full", 16)
+    v = head_views(_run(torch, m, fr), [(608, 1088)] * 16)
     m1 = _model(FULL, "bf16", 1)
     m1.load_weights(weights("full", 40))
     worst = 0.0
@@ -287,43 +384,96 @@ def test_full_bf16_batch16_stored_tiles_parity(torch):
         for key in ("det", "emb"):
             for s in range(3):
                 worst = max(worst, rel_err(v[key][s][f], h1[key][s][0]))
-    _say(f"  batch vs single-frame runs (frames 3, 8, 12): rel err {worst:.2e}")
-    assert worst <= 2e-2
+    _say(f"  batch vs single-frame runs: rel err {worst:.2e}")
+    assert worst <= 1e-6
+
+
+def _fp64_input_amax(cfg_name, k, convs):
+    """max |x| of the input of each conv in `convs`, in the FP64 oracle's forward."""
+    from oracle.network import forward
+    cfg = TINY if cfg_name == "tiny" else FULL
+    amax = {}
+
+    def record(i, x):
+        if i in convs:
+            amax[i] = float(np.abs(x).max())
+        return x
+
+    forward(frames(cfg_name, 1), weights(cfg_name, k), cfg.blocks, in_hook=record)
+    return amax
 
 
 @pytest.mark.parametrize("cfg_name,k", [("tiny", 50), pytest.param("full", 40, marks=pytest.mark.slow)])
+def test_fp8_calibration_scales(torch, cfg_name, k):
+    """FP8 e4m3 backbone: the device sets each FP8 conv's input scale to max|x| /
+    448 of that input over the calibration batch (measured on the BF16 network,
+    so it may differ from the FP64 network's max|x| by the BF16 error), and no
+    other launch gets a scale."""
+    from tests.helpers import fp8_layer_set
+    cfg = TINY if cfg_name == "tiny" else FULL
+    _say(f"case: {cfg_name} fp8 calibration")
+    m = _model(cfg, "fp8", 1)
+    m.load_weights(weights(cfg_name, k))
+    dev_scales = m.calibrate(torch.from_numpy(frames(cfg_name, 1)).cuda())
+    torch.cuda.synchronize()
+    f8 = sorted(fp8_layer_set(cfg))
+    amax = _fp64_input_amax(cfg_name, k, set(f8))
+    # op index = layer index in the backbone (one launch per conv there)
+    got = np.array([dev_scales[i] for i in f8])
+    want = np.array([amax[i] / 448.0 for i in f8])
+    _say(f"  {len(f8)} fp8 convs; scale rel diff vs fp64 max|x|/448: {np.abs(got / want - 1).max():.2e}")
+    assert np.all(dev_scales[[i for i in range(len(dev_scales)) if i not in f8]] == 0)
+    np.testing.assert_allclose(got, want, rtol=0.15)
+
+
+@pytest.mark.parametrize("cfg_name,k", [("tiny", 50), pytest.param("full", 40, marks=pytest.mark.slow)])
+@FP8_MISSES_BAR
 def test_fp8_backbone_parity(torch, cfg_name, k):
-    """FP8 e4m3 backbone: the device's calibrated input scales equal the oracle's
-    (same rule on the BF16 network), and every head output stays within 1.5x the
-    error of the FP8-emulated oracle (weights and inputs rounded the same way)."""
-    from tests.helpers import oracle_forward_fp8, fp8_layer_set
+    """FP8 e4m3 backbone held to the reduced-precision bar (the FP8-emulated
+    oracle's error is printed as a diagnostic)."""
+    from tests.helpers import oracle_forward_fp8
     cfg = TINY if cfg_name == "tiny" else FULL
     _say(f"case: {cfg_name} fp8 b1")
     m = _model(cfg, "fp8", 1)
     m.load_weights(weights(cfg_name, k))
     x = torch.from_numpy(frames(cfg_name, 1)).cuda()
-    dev_scales = m.calibrate(x)
-    torch.cuda.synchronize()
-    emul, scales = oracle_forward_fp8(cfg_name, k, 1)
-    f8 = sorted(fp8_layer_set(cfg))
-    # op index = layer index in the backbone (one launch per conv there)
-    got = np.array([dev_scales[i] for i in f8])
-    want = np.array([scales[i] for i in f8])
-    _say(f"  {len(f8)} fp8 convs; scale rel diff {np.abs(got / want - 1).max():.2e}")
-    assert np.all(dev_scales[[i for i in range(len(dev_scales)) if i not in f8]] == 0)
-    np.testing.assert_allclose(got, want, rtol=2e-2)
+    m.calibrate(x)
     heads = m.forward(x)
     torch.cuda.synchronize()
     ref = oracle_forward(cfg_name, k, 1)
+    emul, _ = oracle_forward_fp8(cfg_name, k, 1)
     v = head_views(heads, [(cfg.height, cfg.width)])
-    for key in ("det", "emb"):
-        for s in range(3):
-            e = rel_err(v[key][s][0], ref[key][s][0])
-            e_emul = rel_err(emul[key][s][0], ref[key][s][0])
-            _say(f"  {key}{8 << s}: rel err {e:.2e} (fp8-emulated oracle {e_emul:.2e}; "
-                 f"gpu vs emulated {rel_err(v[key][s][0], emul[key][s][0]):.2e})")
-            assert e <= max(2e-2, 1.5 * e_emul), (key, s, e, e_emul)
     d = gpu_dets(m.decode(heads, [(cfg.height, cfg.width)]), 0, m.cap)
     r = opost.detections(ref, anchors(cfg_name), 0.5, 0.4)
-    frac, _ = match_fraction(d["boxes"], r["boxes"], r["score"])
-    _say(f"  dets gpu {len(d['boxes'])} oracle {len(r['idx'])} matched {frac:.3f}")
+    check_bar(v, ref, d, r, emul=emul)
+
+
+@pytest.mark.slow
+def test_decode_on_gpu_full_heads_dense_overflow_and_global_sort(torch):
+    """Decode, sort, NMS and normalisation of the GPU's own full-frame FP32 heads
+    (confidence offset for 1000 candidates) against the oracle's post-processing
+    of the same values, element by element, in four regimes: 1000 candidates
+    (sorted in LDS), 1000 over a cap of 512 (overflow: the top 512 by key), 7093
+    at threshold 0.1 (more than the 4096 keys the LDS sort holds: sorted in
+    global memory) and 14214 at 0.05 over a cap of 8192 (global sort + overflow)."""
+    _say("case: full fp32 decode regimes on gpu heads")
+    out = None
+    for thr, cap in ((0.5, 2048), (0.5, 512), (0.1, 8192), (0.05, 8192)):
+        m = _model(FULL, "fp32", 1, cap=cap)
+        m.load_weights(weights("full", 1000))
+        heads = _run(torch, m, frames("full", 1))
+        if out is None:
+            v = head_views(heads, [(608, 1088)])
+            out = {"det": [x[0][None] for x in v["det"]], "emb": [x[0][None] for x in v["emb"]]}
+        d = gpu_dets(m.decode(heads, [(608, 1088)], conf_thr=thr), 0, m.cap)
+        torch.cuda.synchronize()
+        r = opost.detections(out, anchors("full"), thr, 0.4, cap=cap)
+        _say(f"  thr {thr} cap {cap}: candidates gpu {d['n_cand']} oracle {r['n_cand']}, overflow gpu "
+             f"{d['overflow']} oracle {int(r['overflow'])}, kept gpu {len(d['anchor_idx'])} oracle {len(r['idx'])}")
+        assert d["n_cand"] == r["n_cand"] and d["overflow"] == int(r["overflow"])
+        np.testing.assert_array_equal(d["anchor_idx"], r["idx"])
+        np.testing.assert_array_equal(d["margins"], r["margin"])
+        np.testing.assert_allclose(d["boxes"], r["boxes"], rtol=2e-6, atol=2e-4)
+        np.testing.assert_allclose(d["scores"], r["score"], rtol=1e-6)
+        np.testing.assert_allclose(d["emb"], r["emb"], atol=1e-6)
+        del m
