@@ -46,7 +46,8 @@ typedef enum {
     JDE_EDEVICE = -3,       /* a HIP call failed                                     */
     JDE_ECAPACITY = -4,     /* batch exceeds the capacity given at jde_create        */
     JDE_EUNSUPPORTED = -5,  /* configuration the library does not implement          */
-    JDE_ESTATE = -6         /* call out of order (e.g. forward before load_weights)  */
+    JDE_ESTATE = -6,        /* call out of order (e.g. forward before load_weights)  */
+    JDE_EBUDGET = -7        /* admission refused: the device-memory budget is spent  */
 } jde_status;
 
 /* Arithmetic of the convolutions (Sec. 4.1 runs the model in mixed precision).
@@ -66,6 +67,10 @@ typedef struct {
     int max_frames;          /* largest batch (frames) any call will pass               */
     int max_h, max_w;        /* largest frame; every frame's h, w divisible by 32       */
     int max_candidates;      /* per-frame cap on candidates entering NMS (<= 8192)      */
+    size_t max_pixels;       /* most pixels of one batch (sum of h*w over its frames); the
+                                workspace is planned for it.  0 = max_frames*max_h*max_w.
+                                Lets a batch hold many frames of mixed sizes without
+                                reserving max_frames frames of the largest size.       */
 } jde_config;
 
 typedef struct { int h, w; } jde_frame_desc;
@@ -126,11 +131,29 @@ jde_status jde_load_weights(jde_ctx* ctx, const float* host_blob, size_t n_float
 
 /* Bytes of device workspace that jde_forward, jde_decode and jde_nms need for
  * any batch within the context's capacity (total pixels of a batch <=
- * max_frames * max_h * max_w, frames <= max_frames). */
+ * max_pixels, or max_frames * max_h * max_w when that is 0; frames <=
+ * max_frames). */
 size_t jde_workspace_bytes(const jde_ctx* ctx);
 /* Float counts of each head output for a batch: det[s] and emb[s] lengths. */
 jde_status jde_head_sizes(const jde_ctx* ctx, const jde_frame_desc* descs, int n,
                           size_t det_floats[3], size_t emb_floats[3]);
+
+/* Device bytes one frame of h x w occupies while it is in flight through
+ * jde_forward and jde_decode in this context: its FP32 pixels, its head outputs
+ * (det and emb, FP32), its detection rows (cap rows of box, score, margin,
+ * index and E-wide embedding) and its share, by pixels, of the workspace.
+ * 0 when h, w are not positive multiples of 32 or exceed the context's frame
+ * size.  Host-only. */
+size_t jde_frame_bytes(const jde_ctx* ctx, int h, int w);
+/* Admission of waiting frames by device-memory budget (the serving pipeline of
+ * Sec. 4.3-4.4, with frames of many video streams in flight at once): the
+ * longest prefix of descs[0..n) -- at most max_frames frames -- whose
+ * jde_frame_bytes, added to in_flight_bytes, stay within budget_bytes.
+ * *n_admit (host) receives its length.  JDE_OK when at least one frame fits,
+ * JDE_EBUDGET with *n_admit = 0 when the first frame does not, JDE_EINVAL on a
+ * frame the context cannot hold.  Host-only. */
+jde_status jde_admit(const jde_ctx* ctx, const jde_frame_desc* descs, int n, size_t in_flight_bytes,
+                     size_t budget_bytes, int* n_admit);
 
 /* ---- hot path ------------------------------------------------------------ */
 
@@ -205,14 +228,18 @@ void jde_fp8_encode(const float* x, uint8_t* out, size_t n);
 
 /* Post-processing of Appendix A items 1-3 plus embedding normalisation, for
  * every frame of the batch: anchor decode, keep iff score >= conf_thr
- * (evaluated as c_fg - c_bg >= ln(conf_thr / (1 - conf_thr)) in FP32), sort
- * by (margin desc, index asc), keep the top cap, greedy NMS (suppress iff IoU
+ * (evaluated as (c_fg + off_f) - c_bg >= ln(conf_thr / (1 - conf_thr)) in FP32,
+ * off_f = d_logit_offset[f], or 0 when d_logit_offset is NULL), sort by
+ * (margin desc, index asc), keep the top cap, greedy NMS (suppress iff IoU
  * with an earlier kept box > nms_iou, FP32 predicate inter > thr * union), and
- * gather + L2-normalise the embedding at each kept anchor's cell.  heads as
- * written by jde_forward; out: host struct of device pointers. */
+ * gather + L2-normalise the embedding at each kept anchor's cell.  The margin
+ * and score written out include the offset.  d_logit_offset: device [n] FP32 or
+ * NULL (a per-frame confidence offset, e.g. to set a video stream's density of
+ * candidates).  heads as written by jde_forward; out: host struct of device
+ * pointers. */
 jde_status jde_decode(jde_ctx* ctx, const jde_head_out* heads, const jde_frame_desc* descs, int n,
-                      float conf_thr, float nms_iou, void* d_ws, size_t ws_bytes,
-                      const jde_dets* out, void* stream);
+                      float conf_thr, float nms_iou, const float* d_logit_offset, void* d_ws,
+                      size_t ws_bytes, const jde_dets* out, void* stream);
 
 /* Greedy NMS alone (Appendix A item 3) on one list of K <= max_candidates
  * candidates (device): boxes [K,4], margins [K], idx [K] (distinct).  Writes
@@ -282,7 +309,8 @@ typedef struct jde_graph jde_graph;
  * nodes.  Fails with JDE_ESTATE while per-launch profiling is on. */
 jde_status jde_graph_capture(jde_ctx* ctx, const float* d_frames, const jde_frame_desc* descs, int n,
                              void* d_ws, size_t ws_bytes, const jde_head_out* heads, float conf_thr,
-                             float nms_iou, const jde_dets* dets, const float* d_track_emb,
+                             float nms_iou, const float* d_logit_offset, const jde_dets* dets,
+                             const float* d_track_emb,
                              const double* d_mean, const double* d_cov, const int* track_begin,
                              float* d_cost, void* stream, jde_graph** out);
 /* Replays the captured step on `stream`. */
@@ -328,6 +356,11 @@ jde_status jde_kf_update(double mean[8], double cov[64], const double z[4]);
  * other pair is still applied). */
 jde_status jde_kf_update_n(int n, const int* track_idx, const int* det_idx, double* mean, double* cov,
                            const double* z);
+
+/* Kalman measurement of each detection box (Appendix A item 4 tracks boxes
+ * with a Kalman filter): z = (cx, cy, w / h, h) in FP64 from the FP32 box
+ * x1, y1, x2, y2 (w = x2 - x1, h = y2 - y1).  boxes [n,4], z [n,4], host. */
+void jde_box_to_z(int n, const float* boxes, double* z);
 
 /* Min-cost assignment (Hungarian) on cost [T,D] (host, FP32, row-major):
  * entries > max_cost (and +inf) are forbidden; among complete matchings the

@@ -15,3 +15,4 @@ from .frames import tiny_frame, scene_frame, scene_batch, scene_objects  # noqa:
 from .weights import (weight_specs, raw_weights, model_weights, load_calib,  # noqa: F401
                       anchors_px, CALIB_DIR)
 from .tracks import synthetic_dets_tracks  # noqa: F401
+from .mixes import ragged_mix, mix_frames, MIX_SIZES  # noqa: F401

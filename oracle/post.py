@@ -43,10 +43,12 @@ def logit_threshold(thr, dtype=np.float64):
     return dtype(math.log(thr / (1.0 - thr)))
 
 
-def decode_frame(det_maps, anchors, thr, strides=(8, 16, 32)):
+def decode_frame(det_maps, anchors, thr, strides=(8, 16, 32), logit_offset=0.0):
     """Decode + threshold one frame.
 
     det_maps: list of [Hs, Ws, 6A] arrays (strides 8, 16, 32); anchors [3, A, 2] px.
+    logit_offset: a per-frame confidence offset added to every foreground logit
+    c_fg before the margin is formed (0: none).
     The margin test runs in the dtype of det_maps; box arithmetic in FP64.
     Returns dict of candidates in canonical-index order: idx (int64), margin
     (det dtype), score, boxes [K, 4] (x1, y1, x2, y2) FP64, and cell =
@@ -61,7 +63,8 @@ def decode_frame(det_maps, anchors, thr, strides=(8, 16, 32)):
         hs, ws, c = d.shape
         na = c // 6
         v = d.reshape(hs, ws, na, 6)
-        margin = v[..., 5] - v[..., 4]                    # in the head's precision
+        cfg = v[..., 5] if logit_offset == 0.0 else v[..., 5] + dt(logit_offset)
+        margin = cfg - v[..., 4]                          # in the head's precision
         keep = margin >= lthr
         ii, jj, aa = np.nonzero(keep)
         vv = v[ii, jj, aa].astype(np.float64)
@@ -140,16 +143,16 @@ def l2_normalize(e):
     return e / np.maximum(n, NORM_EPS)
 
 
-def detections(out, anchors, conf_thr=0.5, nms_thr=0.4, frame=0, cap=None):
+def detections(out, anchors, conf_thr=0.5, nms_thr=0.4, frame=0, cap=None, logit_offset=0.0):
     """Threshold -> sort -> NMS -> normalised embeddings for one frame.
 
     out: the forward's dict.  Returns dict with (in keep order) idx, margin,
     score, boxes (FP64), emb (FP64, unit rows), plus the pre-NMS candidate
     count 'n_cand' and 'overflow' when a candidate cap is given (the top ``cap``
-    by (margin, idx) are kept).
+    by (margin, idx) are kept).  ``logit_offset`` as in ``decode_frame``.
     """
     dets = [d[frame] for d in out["det"]]
-    c = decode_frame(dets, anchors, conf_thr)
+    c = decode_frame(dets, anchors, conf_thr, logit_offset=logit_offset)
     n_cand = len(c["idx"])
     overflow = False
     if cap is not None and n_cand > cap:

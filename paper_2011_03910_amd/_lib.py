@@ -8,7 +8,8 @@ import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libjde.so")
 
-JDE_OK, JDE_EINVAL, JDE_ENOMEM, JDE_EDEVICE, JDE_ECAPACITY, JDE_EUNSUPPORTED, JDE_ESTATE = 0, -1, -2, -3, -4, -5, -6
+JDE_OK, JDE_EINVAL, JDE_ENOMEM, JDE_EDEVICE, JDE_ECAPACITY, JDE_EUNSUPPORTED, JDE_ESTATE, JDE_EBUDGET = \
+    0, -1, -2, -3, -4, -5, -6, -7
 JDE_FP32, JDE_BF16, JDE_FP16, JDE_FP8 = 0, 1, 2, 3
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
@@ -21,7 +22,7 @@ class JdeConfig(ctypes.Structure):
     _fields_ = [("base_ch", ctypes.c_int), ("blocks", ctypes.c_int * 5), ("emb_dim", ctypes.c_int),
                 ("num_anchors", ctypes.c_int), ("anchors", ((ctypes.c_float * 2) * 4) * 3),
                 ("precision", ctypes.c_int), ("max_frames", ctypes.c_int), ("max_h", ctypes.c_int),
-                ("max_w", ctypes.c_int), ("max_candidates", ctypes.c_int)]
+                ("max_w", ctypes.c_int), ("max_candidates", ctypes.c_int), ("max_pixels", ctypes.c_size_t)]
 
 
 class JdeFrameDesc(ctypes.Structure):
@@ -56,8 +57,12 @@ SIGNATURES = {
     "jde_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(JdeFrameDesc), ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(JdeHeadOut), ctypes.c_void_p]),
     "jde_decode": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(JdeHeadOut), ctypes.POINTER(JdeFrameDesc),
-                                  ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t,
-                                  ctypes.POINTER(JdeDets), ctypes.c_void_p]),
+                                  ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_size_t, ctypes.POINTER(JdeDets), ctypes.c_void_p]),
+    "jde_frame_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "jde_admit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(JdeFrameDesc), ctypes.c_int, ctypes.c_size_t,
+                                 ctypes.c_size_t, c_int_p]),
+    "jde_box_to_z": (None, [ctypes.c_int, c_float_p, c_double_p]),
     "jde_nms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p]),
@@ -78,7 +83,8 @@ SIGNATURES = {
     "jde_tiles": (ctypes.c_int, [ctypes.c_void_p, c_int_p, ctypes.c_int, ctypes.c_int]),
     "jde_graph_capture": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(JdeFrameDesc),
                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(JdeHeadOut),
-                                         ctypes.c_float, ctypes.c_float, ctypes.POINTER(JdeDets), ctypes.c_void_p,
+                                         ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.POINTER(JdeDets),
+                                         ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, c_int_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "jde_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -127,7 +133,7 @@ def load():
 
 _host = None
 HOST_CALLS = ("jde_kf_initiate", "jde_kf_initiate_n", "jde_kf_predict", "jde_kf_update", "jde_kf_update_n",
-              "jde_assign", "jde_fp8_encode")
+              "jde_assign", "jde_fp8_encode", "jde_box_to_z")
 
 
 def load_host():

@@ -75,6 +75,7 @@ struct Tensor {
 
 struct jde_ctx {
     jde_config cfg;
+    size_t cap_pix = 0;              // most pixels a batch may hold (max_pixels or frames x max size)
     int et;                          // element type of activations / conv operands
     std::vector<Layer> layers;
     std::vector<Op> ops;
@@ -250,7 +251,7 @@ void build_plan(jde_ctx* c) {
 
 // Liveness-based first-fit arena over the op sequence, sized for the capacity.
 void plan_arena(jde_ctx* c) {
-    const size_t pix0 = (size_t)c->cfg.max_frames * c->cfg.max_h * c->cfg.max_w;
+    const size_t pix0 = c->cap_pix;
     const size_t eb = elem_bytes(c->et);
     for (auto& t : c->tens) {
         t.first = -1;
@@ -366,8 +367,8 @@ jde_status batch_ok(const jde_ctx* c, const jde_frame_desc* d, int n, bool* unif
         pix += (size_t)d[i].h * d[i].w;
         if (d[i].h != d[0].h || d[i].w != d[0].w) *uniform = false;
     }
-    if (pix > (size_t)c->cfg.max_frames * c->cfg.max_h * c->cfg.max_w)
-        return fail(JDE_ECAPACITY, "batch pixels exceed capacity");
+    if (pix > c->cap_pix)
+        return fail(JDE_ECAPACITY, "batch of %zu pixels exceeds the capacity of %zu", pix, c->cap_pix);
     return JDE_OK;
 }
 
@@ -588,6 +589,7 @@ const char* jde_status_str(int s) {
         case JDE_ECAPACITY: return "capacity exceeded";
         case JDE_EUNSUPPORTED: return "unsupported";
         case JDE_ESTATE: return "bad call order";
+        case JDE_EBUDGET: return "device-memory budget spent";
     }
     return "unknown status";
 }
@@ -613,9 +615,13 @@ jde_status jde_create(const jde_config* cfg, jde_ctx** out) {
     // (max pixels x c0) is the largest tensor, its bytes must stay below 2^31 (buffer
     // loads use 32-bit byte offsets with 2^31 as the out-of-range marker); the
     // upsample/halo rows need 16-bit y, x.
+    const size_t full_pix = (size_t)g.max_frames * g.max_h * g.max_w;
+    if (g.max_pixels > 0 && g.max_pixels < (size_t)g.max_h * g.max_w)
+        return fail(JDE_EINVAL, "max_pixels must hold at least one frame of max_h x max_w");
+    const size_t cap_pix = g.max_pixels > 0 && g.max_pixels < full_pix ? g.max_pixels : full_pix;
     {
         const size_t eb = g.precision == JDE_FP32 ? 4 : 2;
-        if ((size_t)g.max_frames * g.max_h * g.max_w * g.base_ch * eb >= ((size_t)1 << 31) - 4096 ||
+        if (cap_pix * g.base_ch * eb >= ((size_t)1 << 31) - 4096 ||
             g.max_h >= 32768 || g.max_w >= 32768)
             return fail(JDE_EINVAL, "capacity too large: the largest activation must stay below 2 GiB");
     }
@@ -623,6 +629,7 @@ jde_status jde_create(const jde_config* cfg, jde_ctx** out) {
         return fail(JDE_EINVAL, "max_candidates must be a multiple of 64 in [64, %d]", kMaxCap);
     jde_ctx* c = new jde_ctx();
     c->cfg = g;
+    c->cap_pix = cap_pix;
     c->et = g.precision == JDE_FP32 ? kF32 : (g.precision == JDE_FP16 ? kF16 : kBF16);
     c->fp8 = g.precision == JDE_FP8;
     build_plan(c);
@@ -711,6 +718,36 @@ jde_status jde_head_sizes(const jde_ctx* c, const jde_frame_desc* d, int n, size
         det[s] = p * 6 * c->cfg.num_anchors;
         emb[s] = p * c->cfg.emb_dim;
     }
+    return JDE_OK;
+}
+
+size_t jde_frame_bytes(const jde_ctx* c, int h, int w) {
+    if (!c || h <= 0 || w <= 0 || h % 32 || w % 32 || h > c->cfg.max_h || w > c->cfg.max_w) return 0;
+    const jde_config& g = c->cfg;
+    size_t b = (size_t)3 * h * w * 4;
+    for (int s = 0; s < 3; ++s)
+        b += (size_t)(h >> (3 + s)) * (w >> (3 + s)) * (6 * g.num_anchors + g.emb_dim) * 4;
+    b += (size_t)c->cap * (4 + 1 + 1 + 1 + g.emb_dim) * 4 + 3 * 4;
+    b += (size_t)ceil((double)c->ws_total * ((double)h * w / (double)c->cap_pix));
+    return b;
+}
+
+jde_status jde_admit(const jde_ctx* c, const jde_frame_desc* d, int n, size_t in_flight, size_t budget,
+                     int* n_admit) {
+    if (!c || !n_admit || (n > 0 && !d) || n < 0) return fail(JDE_EINVAL, "bad arguments");
+    *n_admit = 0;
+    size_t used = in_flight;
+    int k = 0;
+    for (; k < n && k < c->cfg.max_frames; ++k) {
+        const size_t fb = jde_frame_bytes(c, d[k].h, d[k].w);
+        if (fb == 0) return fail(JDE_EINVAL, "frame %d: %dx%d does not fit the context", k, d[k].h, d[k].w);
+        if (used > budget || fb > budget - used) break;
+        used += fb;
+    }
+    *n_admit = k;
+    if (k == 0 && n > 0)
+        return fail(JDE_EBUDGET, "%zu bytes in flight + %zu for the next frame exceed the budget of %zu", in_flight,
+                    jde_frame_bytes(c, d[0].h, d[0].w), budget);
     return JDE_OK;
 }
 
@@ -941,7 +978,8 @@ jde_status jde_tiles(jde_ctx* c, int* tiles, int n_ops, int set) {
 }
 
 jde_status jde_decode(jde_ctx* c, const jde_head_out* heads, const jde_frame_desc* d, int n, float conf_thr,
-                      float nms_iou, void* ws, size_t wsb, const jde_dets* out, void* stream) {
+                      float nms_iou, const float* logit_offset, void* ws, size_t wsb, const jde_dets* out,
+                      void* stream) {
     if (!c || !heads || !ws || !out) return fail(JDE_EINVAL, "null argument");
     if (wsb < c->ws_total) return fail(JDE_ENOMEM, "workspace %zu < %zu bytes", wsb, c->ws_total);
     if (out->cap != c->cap) return fail(JDE_EINVAL, "dets.cap %d != max_candidates %d", out->cap, c->cap);
@@ -981,6 +1019,7 @@ jde_status jde_decode(jde_ctx* c, const jde_head_out* heads, const jde_frame_des
     da.nframes = n;
     da.A = c->cfg.num_anchors;
     da.lthr = lthr;
+    da.logit_offset = logit_offset;
     da.keycap = c->keycap;
     da.keys = keys;
     da.vals = nullptr;
@@ -1191,9 +1230,9 @@ struct jde_graph {
 };
 
 jde_status jde_graph_capture(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws, size_t wsb,
-                             const jde_head_out* heads, float conf, float iou, const jde_dets* dets,
-                             const float* fe, const double* mean, const double* cov, const int* tb, float* cost,
-                             void* stream, jde_graph** out) {
+                             const jde_head_out* heads, float conf, float iou, const float* logit_offset,
+                             const jde_dets* dets, const float* fe, const double* mean, const double* cov,
+                             const int* tb, float* cost, void* stream, jde_graph** out) {
     if (!c || !out) return fail(JDE_EINVAL, "null argument");
     *out = nullptr;
     if (c->prof) return fail(JDE_ESTATE, "graph capture while profiling");
@@ -1201,7 +1240,7 @@ jde_status jde_graph_capture(jde_ctx* c, const float* frames, const jde_frame_de
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     jde_status st = jde_forward(c, frames, d, n, ws, wsb, heads, stream);
-    if (st == JDE_OK) st = jde_decode(c, heads, d, n, conf, iou, ws, wsb, dets, stream);
+    if (st == JDE_OK) st = jde_decode(c, heads, d, n, conf, iou, logit_offset, ws, wsb, dets, stream);
     if (st == JDE_OK && tb) st = jde_cost_matrix_batch(fe, mean, cov, tb, dets, n, c->cfg.emb_dim, 9.4877, cost, stream);
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(s, &g);

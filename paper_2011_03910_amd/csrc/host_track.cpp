@@ -49,6 +49,17 @@ void chol4_solve(const double L[4][4], const double b[4], double x[4]) {
 
 extern "C" {
 
+void jde_box_to_z(int n, const float* boxes, double* z) {
+    for (int i = 0; i < n; ++i) {
+        const double x1 = boxes[4 * i], y1 = boxes[4 * i + 1], x2 = boxes[4 * i + 2], y2 = boxes[4 * i + 3];
+        const double w = x2 - x1, h = y2 - y1;
+        z[4 * i] = (x1 + x2) / 2.0;
+        z[4 * i + 1] = (y1 + y2) / 2.0;
+        z[4 * i + 2] = w / h;
+        z[4 * i + 3] = h;
+    }
+}
+
 void jde_kf_initiate(const double z[4], double mean[8], double cov[64]) {
     const double h = z[3];
     for (int i = 0; i < 4; ++i) {

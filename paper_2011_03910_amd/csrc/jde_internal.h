@@ -106,6 +106,7 @@ struct DecodeArgs {
     int A;
     float anchors[3][4][2];
     float lthr;              // ln(thr / (1 - thr)) in FP32
+    const float* logit_offset;  // [nframes] added to every c_fg of the frame, or null
     int keycap;              // key slots per frame
     unsigned long long* keys;  // [n][keycap]
     int* vals;               // [n][keycap]

@@ -59,7 +59,9 @@ __global__ __launch_bounds__(256) void decode_kernel(DecodeArgs a) {
     if (t < total) {
         const AnchorLoc L = locate((unsigned)t, g, A);
         const float* d = a.det[L.s] + ((size_t)g[2 + 3 + L.s] + L.cell) * (6 * A) + 6 * L.an;
-        const float margin = (d[5] - d[4]) + 0.0f;   // +0.0 folds -0 into +0
+        // per-frame offset added to the foreground logit (FP32 add, then the margin)
+        const float cfg = a.logit_offset ? d[5] + a.logit_offset[f] : d[5];
+        const float margin = (cfg - d[4]) + 0.0f;   // +0.0 folds -0 into +0
         keep = margin >= a.lthr;
         key = make_key(margin, (unsigned)t);
     }

@@ -39,7 +39,7 @@ def _descs(descs):
 
 
 def jde_create(c0, blocks, emb_dim, anchors, precision="fp32", max_frames=1, max_h=608, max_w=1088,
-               max_candidates=1024):
+               max_candidates=1024, max_pixels=0):
     """Create a context (host plan); returns an opaque handle (ctypes.c_void_p)."""
     lib = load()
     cfg = JdeConfig()
@@ -58,6 +58,7 @@ def jde_create(c0, blocks, emb_dim, anchors, precision="fp32", max_frames=1, max
     cfg.max_h = max_h
     cfg.max_w = max_w
     cfg.max_candidates = max_candidates
+    cfg.max_pixels = int(max_pixels)
     h = ctypes.c_void_p()
     check(lib.jde_create(ctypes.byref(cfg), ctypes.byref(h)), "jde_create")
     return h
@@ -161,6 +162,15 @@ def jde_kf_update_n(track_idx, det_idx, mean, cov, z):
     return mean, cov
 
 
+def jde_box_to_z(boxes):
+    """Host boxes [n, 4] (x1, y1, x2, y2) -> Kalman measurements [n, 4] FP64 (cx, cy, w/h, h)."""
+    b = np.ascontiguousarray(boxes, dtype=np.float32).reshape(-1, 4)
+    z = np.zeros((b.shape[0], 4))
+    load_host().jde_box_to_z(b.shape[0], b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                             z.ctypes.data_as(_lib.c_double_p))
+    return z
+
+
 def jde_fp8_encode(x):
     """Host OCP e4m3 encoding (RNE, saturating) of a float array -> uint8 codes."""
     x = np.ascontiguousarray(x, dtype=np.float32)
@@ -193,10 +203,11 @@ class JDE:
     """
 
     def __init__(self, c0, blocks, emb_dim, anchors, precision="fp32", max_frames=1, max_h=608, max_w=1088,
-                 max_candidates=1024, device="cuda"):
+                 max_candidates=1024, device="cuda", max_pixels=0):
         torch = _torch()
         self.lib = load()
-        self.ctx = jde_create(c0, blocks, emb_dim, anchors, precision, max_frames, max_h, max_w, max_candidates)
+        self.ctx = jde_create(c0, blocks, emb_dim, anchors, precision, max_frames, max_h, max_w, max_candidates,
+                              max_pixels)
         self.E = emb_dim
         self.cap = max_candidates
         self.device = torch.device(device)
@@ -269,15 +280,33 @@ class JDE:
         ds.cap = self.cap
         return ds
 
-    def decode(self, heads, descs, conf_thr=0.5, nms_iou=0.4, dets=None, stream=None):
+    def decode(self, heads, descs, conf_thr=0.5, nms_iou=0.4, dets=None, stream=None, logit_offset=None):
+        """logit_offset: device FP32 [n] added to every c_fg of frame f, or None."""
         if dets is None:
             dets = self.dets_buffers(len(descs))
+        if logit_offset is not None:
+            assert logit_offset.dtype == _torch().float32 and logit_offset.numel() >= len(descs)
         ds = self._dets_struct(dets)
         hs = self._head_struct(heads)
         check(self.lib.jde_decode(self.ctx, ctypes.byref(hs), _descs(descs), len(descs), float(conf_thr),
-                                  float(nms_iou), _ptr(self.ws), self.ws.numel(), ctypes.byref(ds),
-                                  _stream(stream)), "jde_decode")
+                                  float(nms_iou), _ptr(logit_offset), _ptr(self.ws), self.ws.numel(),
+                                  ctypes.byref(ds), _stream(stream)), "jde_decode")
         return dets
+
+    def frame_bytes(self, h, w):
+        """Device bytes one h x w frame occupies while in flight (jde_frame_bytes)."""
+        return int(self.lib.jde_frame_bytes(self.ctx, int(h), int(w)))
+
+    def admit(self, descs, in_flight_bytes, budget_bytes):
+        """Number of leading frames of `descs` the device-memory budget admits (0 when
+        the budget refuses the first one: JDE_EBUDGET)."""
+        n = ctypes.c_int(0)
+        st = self.lib.jde_admit(self.ctx, _descs(descs), len(descs), int(in_flight_bytes), int(budget_bytes),
+                                ctypes.byref(n))
+        if st == _lib.JDE_EBUDGET:
+            return 0
+        check(st, "jde_admit")
+        return n.value
 
     def nms(self, boxes, margins, idx, nms_iou=0.4, stream=None):
         torch = _torch()
@@ -343,7 +372,7 @@ class JDE:
         check(self.lib.jde_tiles(self.ctx, t.ctypes.data_as(_lib.c_int_p), t.size, 1), "jde_tiles")
 
     def graph_capture(self, frames, descs, heads, dets, conf_thr=0.5, nms_iou=0.4, tracks=None, cost=None,
-                      stream=None):
+                      stream=None, logit_offset=None):
         """Capture forward + decode (+ batched cost when tracks = (trk_emb, mean, cov, track_begin))
         on `stream` (a torch.cuda.Stream, not the default stream); returns a Graph."""
         hs = self._head_struct(heads)
@@ -356,10 +385,10 @@ class JDE:
         g = ctypes.c_void_p()
         check(self.lib.jde_graph_capture(self.ctx, _ptr(frames), _descs(descs), len(descs), _ptr(self.ws),
                                          self.ws.numel(), ctypes.byref(hs), float(conf_thr), float(nms_iou),
-                                         ctypes.byref(ds), _ptr(fe), _ptr(mean), _ptr(cov),
+                                         _ptr(logit_offset), ctypes.byref(ds), _ptr(fe), _ptr(mean), _ptr(cov),
                                          None if tb is None else tb.ctypes.data_as(_lib.c_int_p), _ptr(cost),
                                          _stream(stream), ctypes.byref(g)), "jde_graph_capture")
-        return Graph(self.lib, g, (frames, heads, dets, tracks, cost, tb))
+        return Graph(self.lib, g, (frames, heads, dets, tracks, cost, tb, logit_offset))
 
     def calibrate(self, frames, descs=None, heads=None, stream=None):
         """FP8 contexts: set the static activation scales from one BF16 forward of this batch."""

@@ -9,8 +9,12 @@ post-processing (Sec. 4.3).  This module is that pipeline for one GPU:
   rate and resolution); they wait in arrival order;
 * continuous batching: whenever a batch slot is free, every waiting frame that
   fits is admitted -- at most `max_batch` frames, and only while the frames in
-  flight stay within the HBM budget (per-frame activation footprint x frames);
-  frames of different resolutions share one ragged batch;
+  flight stay within the device-memory budget (the library's jde_admit, which
+  charges each frame its pixels, head outputs, detection rows and workspace
+  share); frames of different resolutions share one ragged batch;
+* each stream has its own density of objects; its frames carry a confidence
+  offset (the library's per-frame logit offset) that sets its candidates per
+  frame;
 * each slot owns a library context (workspace, head and detection buffers) and
   a HIP stream; its forward + decode overlap the other slot's work;
 * a post-processing thread takes finished batches in order and, per frame in
@@ -32,7 +36,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .jde import (JDE, jde_kf_initiate_n, jde_kf_predict, jde_kf_update_n, jde_assign,
-                  jde_track_emb_update)
+                  jde_track_emb_update, jde_box_to_z)
 
 CHI2_GATE = 9.4877
 
@@ -44,7 +48,18 @@ class StreamSpec:
     width: int
     fps: float
     phase: float                 # seconds after start of frame 0
-    frames: np.ndarray           # [F, 3, H, W] FP32 host frames cycled through
+    frames: np.ndarray           # [F, 3, H, W] FP32 host frames, played forward then backward
+    logit_offset: float = 0.0    # added to every c_fg of the stream's frames (its density)
+    n_obj: int = 0               # objects in the stream's scene
+
+    def frame_index(self, t):
+        """Frame t of the stream: the F rendered frames played 0..F-1, F-2..1, 0.. so
+        that objects keep moving continuously (they reverse at the ends)."""
+        F = len(self.frames)
+        if F <= 1:
+            return 0
+        k = t % (2 * F - 2)
+        return k if k < F else 2 * F - 2 - k
 
 
 @dataclass
@@ -97,10 +112,14 @@ class Server:
             if tiles is not None:
                 m.set_tiles(tiles)
             self.slots.append({"m": m, "stream": torch.cuda.Stream(), "busy": False})
-        # per-frame activation footprint: a slot's workspace covers max_batch frames of the largest size
-        self.frame_bytes = self.slots[0]["m"].ws.numel() / max_batch
-        self.hbm_budget = hbm_budget if hbm_budget is not None else 2 * self.slots[0]["m"].ws.numel()
-        self.in_flight_bytes = 0.0
+        # Admission by device-memory budget: each frame in flight is charged what the
+        # library says it occupies (pixels, heads, detection rows, workspace share).
+        # The default budget is what the two slots can hold at once.
+        m0 = self.slots[0]["m"]
+        self.hbm_budget = int(hbm_budget) if hbm_budget is not None else 2 * max_batch * m0.frame_bytes(max_h, max_w)
+        self.in_flight_bytes = 0
+        self.budget_stalls = 0           # free slot and waiting frames, but the budget admitted none
+        self.budget_cut = 0              # batches the budget cut below what was waiting (and max_batch)
         self.post_stream = torch.cuda.Stream()
         # Device-resident track embeddings of every stream in one pool: stream k owns
         # rows [k * max_tracks, (k + 1) * max_tracks).
@@ -119,11 +138,56 @@ class Server:
                         "frames": 0}
         for sl in self.slots:
             sl["dev"] = torch.empty(self.max_pix, dtype=torch.float32, device=device)
+            # per-frame confidence offsets: written on the host, copied with the frames (the
+            # slot's previous copy has completed before the slot is free again)
+            sl["off_host"] = torch.zeros(max_batch, dtype=torch.float32).pin_memory()
+            sl["off"] = torch.zeros(max_batch, dtype=torch.float32, device=device)
             # outputs sized for a full batch of the largest frames; smaller batches use a prefix
             sl["heads"] = sl["m"].head_buffers([(max_h, max_w)] * max_batch)
             sl["dets"] = sl["m"].dets_buffers(max_batch)
         self.lock = threading.Lock()
         self.results = []            # per frame: dict(sid, t, boxes, ids, latency)
+        self.cand = {sid: [] for sid in self.streams}   # candidates per frame, per stream
+
+    def calibrate_density(self, iters=28):
+        """Sets each stream's confidence offset so that its first frame gives as many
+        candidates (anchors over the threshold, before NMS) as the stream has
+        objects: the library decodes the frame at trial offsets, and a bisection on
+        its candidate count finds the offsets o_K and o_K+1 at which the count first
+        reaches K and K + 1; the stream gets their midpoint (the threshold then sits
+        mid-gap between the K-th and (K+1)-th margin)."""
+        torch = self.torch
+        m = self.slots[0]["m"]
+        heads, dets = self.slots[0]["heads"], self.slots[0]["dets"]
+        off = self.slots[0]["off"][:1]
+
+        def count(o, desc):
+            off.fill_(o)
+            m.decode(heads, [desc], self.conf_thr, self.nms_iou, dets=dets, logit_offset=off)
+            return int(dets["n_cand"][0].item())
+
+        def first_reaching(k, desc, lo=-40.0, hi=40.0):
+            for _ in range(iters):
+                mid = 0.5 * (lo + hi)
+                if count(mid, desc) >= k:
+                    hi = mid
+                else:
+                    lo = mid
+            return hi
+
+        for st in self.streams.values():
+            sp = st.spec
+            desc = (sp.height, sp.width)
+            x = torch.from_numpy(np.ascontiguousarray(sp.frames[0])).cuda()
+            m.forward(x.reshape(-1), [desc], heads=heads)
+            k = max(int(sp.n_obj), 1)
+            sp.logit_offset = 0.5 * (first_reaching(k, desc) + first_reaching(k + 1, desc))
+        torch.cuda.synchronize()
+
+    def _cand_stats(self):
+        """Per stream: (objects in its scene, mean candidates per frame)."""
+        return {sid: (self.streams[sid].spec.n_obj, round(float(np.mean(c)), 1) if c else None)
+                for sid, c in self.cand.items()}
 
     # ---- producer side -------------------------------------------------------
     def _free_slot(self):
@@ -140,16 +204,19 @@ class Server:
         s = sl["stream"]
         heads, dets = sl["heads"], sl["dets"]
         descs, off = [], 0
+        offs = sl["off_host"][:len(jobs)]
+        offs.numpy()[:] = [self.streams[j.sid].spec.logit_offset for j in jobs]
         with torch.cuda.stream(s):
             for j in jobs:
                 st = self.streams[j.sid]
-                src = st.pinned[j.t % len(st.pinned)]
+                src = st.pinned[st.spec.frame_index(j.t)]
                 n = src.numel()
                 sl["dev"][off:off + n].copy_(src, non_blocking=True)
                 off += n
                 descs.append((st.spec.height, st.spec.width))
+            sl["off"][:len(jobs)].copy_(offs, non_blocking=True)
             m.forward(sl["dev"][:off], descs, heads=heads, stream=s)
-            m.decode(heads, descs, self.conf_thr, self.nms_iou, dets=dets, stream=s)
+            m.decode(heads, descs, self.conf_thr, self.nms_iou, dets=dets, stream=s, logit_offset=sl["off"])
             ev = torch.cuda.Event()
             ev.record(s)
         sl["busy"] = True
@@ -182,15 +249,17 @@ class Server:
             slot = self._free_slot()
             if pending and slot is not None:
                 pending.sort(key=lambda j: j.arrival)
-                batch = []
+                m = self.slots[slot]["m"]
+                want = pending[:self.max_batch]
+                descs = [(self.streams[j.sid].spec.height, self.streams[j.sid].spec.width) for j in want]
                 with self.lock:
-                    for j in pending:
-                        if len(batch) >= self.max_batch:
-                            break
-                        if self.in_flight_bytes + (len(batch) + 1) * self.frame_bytes > self.hbm_budget:
-                            break
-                        batch.append(j)
-                    self.in_flight_bytes += len(batch) * self.frame_bytes
+                    k = m.admit(descs, self.in_flight_bytes, self.hbm_budget)
+                    batch = want[:k]
+                    self.in_flight_bytes += sum(m.frame_bytes(h, w) for h, w in descs[:k])
+                if k == 0:
+                    self.budget_stalls += 1
+                elif k < len(want):
+                    self.budget_cut += 1
                 if batch:
                     for j in batch:
                         j.admitted = time.perf_counter()
@@ -212,6 +281,9 @@ class Server:
                  "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
                  "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
                  "mean_batch": len(self.results) / max(n_batches, 1),
+                 "budget_bytes": self.hbm_budget, "budget_stalls": self.budget_stalls,
+                 "budget_cut_batches": self.budget_cut,
+                 "candidates_per_frame": self._cand_stats(),
                  "host_launch_s": self.t_launch, "host_post_s": self.t_post,
                  "post_parts_s": dict(self.t_parts)}
         return stats
@@ -241,6 +313,9 @@ class Server:
                 dets = item["dets"]
                 n = len(jobs)
                 counts = dets["count"][:n].cpu().numpy()
+                ncand = dets["n_cand"][:n].cpu().numpy()
+                for f, j in enumerate(item["jobs"]):
+                    self.cand[j.sid].append(int(ncand[f]))
                 boxes_all = dets["boxes"].view(-1, m.cap, 4)[:n].cpu().numpy()
                 i0 = len(self.results)
                 for rnd in rounds:
@@ -250,7 +325,7 @@ class Server:
                     r["latency"] = done - r["arrival"]
             self.t_post += time.perf_counter() - t0
             with self.lock:
-                self.in_flight_bytes -= len(item["jobs"]) * self.frame_bytes
+                self.in_flight_bytes -= sum(m.frame_bytes(h, w) for h, w in item["descs"])
                 self.slots[item["slot"]]["busy"] = False
 
     def _associate_round(self, rnd, m, dets, counts, boxes_all):
@@ -288,10 +363,7 @@ class Server:
             boxes = boxes_all[f, :counts[f]]
             D = len(boxes)
             det_ids = np.zeros(D, dtype=np.int64)
-            w = boxes[:, 2] - boxes[:, 0]
-            h = boxes[:, 3] - boxes[:, 1]
-            zs = np.stack([(boxes[:, 0] + boxes[:, 2]) / 2, (boxes[:, 1] + boxes[:, 3]) / 2, w / h, h],
-                          axis=1).astype(np.float64) if D else np.zeros((0, 4))
+            zs = jde_box_to_z(boxes) if D else np.zeros((0, 4))
             matched_t = np.zeros(len(st.ids), dtype=bool)
             matched_d = np.zeros(D, dtype=bool)
             ta = time.perf_counter()
@@ -366,7 +438,9 @@ class Server:
 
 def synthetic_streams(n_streams, seed, frames_per_stream=4, fps=30.0, resolutions=((608, 1088), (480, 864),
                       (320, 576)), objects=(20, 200)):
-    """Seeded stream specs: resolution uniform over `resolutions`, 20-200 objects, random phase."""
+    """Seeded stream specs: resolution uniform over `resolutions`, 20-200 objects,
+    random phase, frames_per_stream consecutive frames of a moving scene (the
+    confidence offset for the stream's density is set by Server.calibrate_density)."""
     from jde_inputs import scene_batch
     rng = np.random.Generator(np.random.PCG64([seed, 23]))
     out = []
@@ -374,5 +448,5 @@ def synthetic_streams(n_streams, seed, frames_per_stream=4, fps=30.0, resolution
         h, w = resolutions[int(rng.integers(len(resolutions)))]
         n_obj = int(rng.integers(objects[0], objects[1] + 1))
         fr = scene_batch(seed, frames_per_stream, h, w, n_obj=n_obj, stream=s)
-        out.append(StreamSpec(s, h, w, fps, float(rng.uniform(0, 1.0 / fps)), fr))
+        out.append(StreamSpec(s, h, w, fps, float(rng.uniform(0, 1.0 / fps)), fr, 0.0, n_obj))
     return out

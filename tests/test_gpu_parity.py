@@ -477,3 +477,29 @@ def test_decode_on_gpu_full_heads_dense_overflow_and_global_sort(torch):
         np.testing.assert_allclose(d["scores"], r["score"], rtol=1e-6)
         np.testing.assert_allclose(d["emb"], r["emb"], atol=1e-6)
         del m
+
+
+def test_decode_per_frame_logit_offset(torch):
+    """A per-frame confidence offset (one per video stream's density) gives, on
+    the GPU's own heads of a 3-frame batch, exactly the oracle's decode with that
+    offset added to every c_fg."""
+    _say("case: tiny fp32 b3 decode with per-frame logit offsets")
+    n = 3
+    m = _model(TINY, "fp32", n)
+    m.load_weights(weights("tiny", 50))
+    descs = [(192, 320)] * n
+    heads = _run(torch, m, frames("tiny", n))
+    off = np.array([0.0, 1.5, -0.75], dtype=np.float32)
+    d = m.decode(heads, descs, logit_offset=torch.from_numpy(off).cuda())
+    torch.cuda.synchronize()
+    v = head_views(heads, descs)
+    for f in range(n):
+        g = gpu_dets(d, f, m.cap)
+        out = {"det": [x[f][None] for x in v["det"]], "emb": [x[f][None] for x in v["emb"]]}
+        r = opost.detections(out, anchors("tiny"), 0.5, 0.4, logit_offset=float(off[f]))
+        _say(f"  frame {f} offset {off[f]:+.2f}: candidates {g['n_cand']} (oracle {r['n_cand']}), kept {len(g['anchor_idx'])}")
+        assert g["n_cand"] == r["n_cand"]
+        np.testing.assert_array_equal(g["anchor_idx"], r["idx"])
+        np.testing.assert_array_equal(g["margins"], r["margin"])
+        np.testing.assert_allclose(g["scores"], r["score"], rtol=1e-6)
+        np.testing.assert_allclose(g["emb"], r["emb"], atol=1e-6)

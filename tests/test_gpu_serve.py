@@ -2,7 +2,9 @@
 
 Each stream's per-frame results (detections after NMS and the track id given
 to each detection) are the same when the stream is served alone and when it
-shares ragged batches with other streams of other resolutions.
+shares ragged batches with other streams of other resolutions and densities
+(each stream has its own confidence offset), under a device-memory budget that
+holds only two frames at a time, in FP32 and in BF16.
 """
 
 import sys
@@ -15,6 +17,9 @@ from tests.helpers import weights, anchors
 
 pytestmark = pytest.mark.gpu
 
+SIZES = {0: (192, 320), 1: (128, 224), 2: (96, 160), 3: (192, 320)}
+OFFSETS = {0: 0.0, 1: 0.8, 2: -0.5, 3: 1.5}
+
 
 def _say(msg):
     print(msg, flush=True)
@@ -23,19 +28,22 @@ def _say(msg):
 
 def _streams(sids):
     from paper_2011_03910_amd.serve import StreamSpec
-    sizes = {0: (192, 320), 1: (128, 224), 2: (96, 160), 3: (192, 320)}
     out = []
     for s in sids:
-        h, w = sizes[s]
+        h, w = SIZES[s]
         fr = np.stack([tiny_frame(TINY.seed, 100 * s + k, h, w) for k in range(3)])
-        out.append(StreamSpec(s, h, w, 60.0, 0.004 * s, fr))
+        # streams 0, 1 and 3 arrive together: three frames that a budget of two
+        # 192x320 frames cannot admit at once
+        out.append(StreamSpec(s, h, w, 60.0, 0.008 if s == 2 else 0.0, fr, OFFSETS[s], 0))
     return out
 
 
-def _serve(sids, duration=0.4):
+def _serve(sids, precision, duration=0.4, budget_frames=None):
     from paper_2011_03910_amd.serve import Server
-    srv = Server(TINY, anchors("tiny"), weights("tiny", 50), _streams(sids), precision="fp32", max_batch=4,
+    srv = Server(TINY, anchors("tiny"), weights("tiny", 50), _streams(sids), precision=precision, max_batch=4,
                  max_tracks=128, cap=256)
+    if budget_frames is not None:
+        srv.hbm_budget = budget_frames * srv.slots[0]["m"].frame_bytes(192, 320)
     stats = srv.run(duration)
     by = {}
     for r in srv.results:
@@ -43,16 +51,18 @@ def _serve(sids, duration=0.4):
     return stats, by
 
 
-def test_stream_results_same_alone_and_in_mix():
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_stream_results_same_alone_and_in_mix(precision):
     import torch
     assert torch.cuda.is_available()
-    _say("case: serve mix of 4 streams")
-    st_mix, mix = _serve([0, 1, 2, 3])
+    _say(f"case: serve mix of 4 streams ({precision}, budget of two 192x320 frames)")
+    st_mix, mix = _serve([0, 1, 2, 3], precision, budget_frames=2)
     _say(f"  mix: {st_mix}")
     assert st_mix["frames"] >= 4 * 20 and st_mix["mean_batch"] > 1.0
+    assert st_mix["budget_stalls"] + st_mix["budget_cut_batches"] > 0
     for sid in (1, 3):
-        _say(f"case: serve stream {sid} alone")
-        st_one, one = _serve([sid])
+        _say(f"case: serve stream {sid} alone ({precision})")
+        st_one, one = _serve([sid], precision)
         keys = sorted(k for k in one if k[0] == sid)
         assert len(keys) >= 20
         for k in keys:

@@ -101,20 +101,20 @@ def test_calls_fail_before_device_work(lib):
                                     None) == _lib.JDE_ENOMEM
         # too many frames / bad frame size / small workspace / cap mismatch
         dets = _lib.JdeDets()
-        assert lib.jde_decode(h, ctypes.byref(heads), d, 3, 0.5, 0.4, fake, ws, ctypes.byref(dets),
+        assert lib.jde_decode(h, ctypes.byref(heads), d, 3, 0.5, 0.4, None, fake, ws, ctypes.byref(dets),
                               None) == _lib.JDE_EINVAL
         dets.cap = 256
         for k in ("boxes", "scores", "margins", "emb", "anchor_idx", "count", "n_cand", "overflow"):
             setattr(dets, k, 0x1000)
-        assert lib.jde_decode(h, ctypes.byref(heads), d, 3, 0.5, 0.4, fake, ws, ctypes.byref(dets),
+        assert lib.jde_decode(h, ctypes.byref(heads), d, 3, 0.5, 0.4, None, fake, ws, ctypes.byref(dets),
                               None) == _lib.JDE_ECAPACITY
         d[0].h = 100
-        assert lib.jde_decode(h, ctypes.byref(heads), d, 1, 0.5, 0.4, fake, ws, ctypes.byref(dets),
+        assert lib.jde_decode(h, ctypes.byref(heads), d, 1, 0.5, 0.4, None, fake, ws, ctypes.byref(dets),
                               None) == _lib.JDE_EINVAL
         d[0].h = 192
-        assert lib.jde_decode(h, ctypes.byref(heads), d, 1, 0.5, 0.4, fake, ws - 1, ctypes.byref(dets),
+        assert lib.jde_decode(h, ctypes.byref(heads), d, 1, 0.5, 0.4, None, fake, ws - 1, ctypes.byref(dets),
                               None) == _lib.JDE_ENOMEM
-        assert lib.jde_decode(h, ctypes.byref(heads), d, 1, 1.5, 0.4, fake, ws, ctypes.byref(dets),
+        assert lib.jde_decode(h, ctypes.byref(heads), d, 1, 1.5, 0.4, None, fake, ws, ctypes.byref(dets),
                               None) == _lib.JDE_EINVAL
         assert lib.jde_nms(h, fake, fake, fake, 257, 0.4, fake, ws, fake, fake, None) == _lib.JDE_ECAPACITY
         assert lib.jde_cost_matrix(None, None, None, 3, None, None, 4, 64, 9.4877, None, None) == _lib.JDE_EINVAL
@@ -235,3 +235,44 @@ def test_nms_noalloc_rejects_lists_beyond_its_scratch(lib):
     assert "8192" in lib.jde_last_error().decode()
     assert lib.jde_nms_noalloc(None, None, None, -1, ctypes.c_float(0.4), ctypes.c_void_p(16),
                                ctypes.c_void_p(16), None) == _lib.JDE_EINVAL
+
+
+def test_box_to_z_matches_oracle(rng):
+    from paper_2011_03910_amd import jde_box_to_z
+    xy = rng.uniform(0, 1000, (50, 2))
+    wh = rng.uniform(5, 300, (50, 2))
+    boxes = np.concatenate([xy, xy + wh], 1).astype(np.float32)
+    got = jde_box_to_z(boxes)
+    want = np.stack([otrack.box_to_z(b) for b in boxes.astype(np.float64)])
+    np.testing.assert_allclose(got, want, rtol=1e-15, atol=0)
+
+
+def test_frame_bytes_and_budget_admission():
+    """jde_frame_bytes adds up a frame's pixels, heads, detection rows and its
+    pixel share of the workspace; jde_admit admits the longest prefix within the
+    budget and refuses with JDE_EBUDGET when even the first frame does not fit."""
+    import paper_2011_03910_amd as P
+    from paper_2011_03910_amd import _lib
+    L = _lib.load()
+    ctx = P.jde_create(FULL.c0, FULL.blocks, FULL.emb_dim, anchors_px(FULL), "bf16", 8, 608, 1088, 512)
+    try:
+        fb = lambda h, w: L.jde_frame_bytes(ctx, h, w)
+        big, mid, small = fb(608, 1088), fb(480, 864), fb(320, 576)
+        heads = sum((608 >> (3 + s)) * (1088 >> (3 + s)) * (24 + 512) * 4 for s in range(3))
+        share = L.jde_workspace_bytes(ctx) / 8
+        assert big >= 3 * 608 * 1088 * 4 + heads + share
+        assert big > mid > small > 0
+        assert fb(600, 1088) == 0 and fb(640, 1088) == 0
+        descs = (_lib.JdeFrameDesc * 4)()
+        for i, (h, w) in enumerate(((608, 1088), (320, 576), (480, 864), (608, 1088))):
+            descs[i].h, descs[i].w = h, w
+        n = ctypes.c_int(-1)
+        assert L.jde_admit(ctx, descs, 4, 0, big + small + mid, ctypes.byref(n)) == 0 and n.value == 3
+        assert L.jde_admit(ctx, descs, 4, 0, big + small + mid - 1, ctypes.byref(n)) == 0 and n.value == 2
+        assert L.jde_admit(ctx, descs, 4, 10 ** 12, 2 * 10 ** 12, ctypes.byref(n)) == 0 and n.value == 4
+        assert L.jde_admit(ctx, descs, 4, 5, big + 4, ctypes.byref(n)) == _lib.JDE_EBUDGET and n.value == 0
+        assert "budget" in L.jde_last_error().decode()
+        descs[1].h = 100
+        assert L.jde_admit(ctx, descs, 4, 0, 10 ** 12, ctypes.byref(n)) == _lib.JDE_EINVAL
+    finally:
+        P.jde_destroy(ctx)

@@ -174,3 +174,23 @@ def test_tiny_calibrated_candidate_count_and_pipeline():
     assert capped["overflow"] and capped["n_cand"] == 50
     top = post.sort_order(c["margin"], c["idx"])[:10]
     assert set(capped["idx"]).issubset(set(c["idx"][top]))
+
+
+def test_logit_offset_equals_shifted_foreground_logits(rng):
+    """A per-frame offset d on c_fg is the same decode as c_fg + d written into
+    the head outputs (the same FP32 add), and at threshold 0.5 it keeps exactly
+    the anchors with c_fg - c_bg >= -d."""
+    from oracle.post import decode_frame
+    an = np.array([[[8.0, 24.0]] * 4, [[16.0, 48.0]] * 4, [[32.0, 96.0]] * 4], dtype=np.float32)
+    det = [rng.normal(0, 2, (h, w, 24)).astype(np.float32) for h, w in ((6, 10), (3, 5), (2, 3))]
+    d = np.float32(1.37)
+    got = decode_frame(det, an, 0.5, logit_offset=float(d))
+    shifted = [x.copy() for x in det]
+    for x in shifted:
+        x[..., 5::6] = x[..., 5::6] + d
+    want = decode_frame(shifted, an, 0.5)
+    np.testing.assert_array_equal(got["idx"], want["idx"])
+    np.testing.assert_array_equal(got["margin"], want["margin"])
+    n = sum(int(((x[..., 5::6] + d) - x[..., 4::6] >= 0).sum()) for x in det)
+    assert len(got["idx"]) == n
+    assert len(decode_frame(det, an, 0.5, logit_offset=-100.0)["idx"]) == 0
