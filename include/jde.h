@@ -222,6 +222,17 @@ jde_status jde_fuse_blocks(jde_ctx* ctx, int on);
  * 144 KB of LDS one workgroup fills a compute unit, and its per-step barrier then
  * idles the matrix cores; the implicit GEMM is faster on MI355X. */
 jde_status jde_window_convs(jde_ctx* ctx, int on);
+/* With on != 0 (default off), the embedding branch of each head (3x3 conv F -> E,
+ * linear + bias, Sec. 3.1) runs only where it is used: jde_forward runs the det
+ * 3x3 conv alone and leaves out->emb unwritten (those pointers may be NULL),
+ * and jde_decode computes each kept detection's embedding from the head's
+ * feature map (kept in the workspace since the forward) at its cell -- the
+ * same conv, K summed in the dense conv's (tap, channel) order in FP32 -- then
+ * L2-normalises it.  The detections are the same as with the dense head; the
+ * forward saves the emb convs' 21.3 GFLOP and 27.8 MB of FP32 output per
+ * 608x1088 frame (Appendix A item 1 needs an embedding per detection only).
+ * The feature maps stay valid until the next jde_forward on the workspace. */
+jde_status jde_sparse_emb(jde_ctx* ctx, int on);
 /* Host helper: x (host, n floats) -> OCP e4m3 codes (host, n bytes), round to
  * nearest even, saturating at +-448, NaN -> 0x7f; the encoding of the weights. */
 void jde_fp8_encode(const float* x, uint8_t* out, size_t n);
@@ -297,6 +308,38 @@ jde_status jde_cost_matrix_batch(const float* d_track_emb, const double* d_mean,
  * d outside [0, D) are skipped.  d_det_emb [D,E], d_track_emb [T,E] FP32. */
 jde_status jde_track_emb_update(const int* d_pairs, int P, const float* d_det_emb, int D,
                                 float* d_track_emb, int T, int E, float momentum, void* stream);
+
+/* ---- device-side association (Appendix A items 4 and 7) ------------------
+ * The same FP64 arithmetic as the host jde_kf_* and jde_assign calls (operation
+ * for operation, no contraction: bit-identical states, the same assignment),
+ * run on the device so that a batch's association needs no host round trip.
+ * Batched layout as for jde_cost_matrix_batch: frame f (0 <= f < n <= 64) owns
+ * tracks [track_begin[f], track_begin[f+1]) (track_begin: host, n+1
+ * non-decreasing ints) and detection rows [f*cap, f*cap + count[f]) of dets. */
+
+/* Predicts T track states in place (device mean [T,8], cov [T,8,8], FP64), as
+ * jde_kf_predict. */
+jde_status jde_kf_predict_dev(int T, double* d_mean, double* d_cov, void* stream);
+/* Kalman update of every track t with det_of_track[t] >= 0 (device [T]) by the
+ * measurement of box f*cap + det_of_track[t] of dets (z = (cx, cy, w/h, h) of
+ * the FP32 box), as jde_kf_update; tracks with -1 are untouched.  d_status
+ * (device [T] or NULL): 1 where S was not positive definite (track untouched),
+ * else 0. */
+jde_status jde_kf_update_dev(const int* track_begin, int n, const int* d_det_of_track, const jde_dets* dets,
+                             double* d_mean, double* d_cov, int* d_status, void* stream);
+/* Min-cost assignment of every frame, as jde_assign, on the cost written by
+ * jde_cost_matrix_batch (d_cost [track_begin[n], cap], row stride cap; D of
+ * frame f read from dets->count[f] on the device).  One workgroup per frame
+ * runs the shortest-augmenting-path method (Kuhn-Munkres, Jonker-Volgenant
+ * form) with its state in LDS: at most 2048 tracks and 2048 detections per
+ * frame (JDE_ECAPACITY for more tracks; a frame whose count exceeds 2048 gets
+ * d_status[f] = 1 and no pairs).  Outputs (device): d_det_of_track [T] (the
+ * detection's row within its frame, or -1), d_track_of_det [n*cap] (the track's
+ * index within its frame, or -1), d_kept [n] pairs kept, d_total [n] FP64 sum of
+ * their costs, d_status [n]. */
+jde_status jde_assign_dev(const float* d_cost, const int* track_begin, int n, const jde_dets* dets,
+                          float max_cost, int* d_det_of_track, int* d_track_of_det, int* d_kept,
+                          double* d_total, int* d_status, void* stream);
 
 /* ---- HIP graph of one step (batch-wise inference replayed as one launch) ---- */
 

@@ -95,6 +95,7 @@ SIGNATURES = {
     "jde_fuse_stem": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_fuse_blocks": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_window_convs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "jde_sparse_emb": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_fp8_encode": (None, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t]),
     "jde_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p, c_int_p, c_int_p,
@@ -102,6 +103,12 @@ SIGNATURES = {
     "jde_track_emb_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                             ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_float,
                                             ctypes.c_void_p]),
+    "jde_kf_predict_dev": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "jde_kf_update_dev": (ctypes.c_int, [c_int_p, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(JdeDets),
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "jde_assign_dev": (ctypes.c_int, [ctypes.c_void_p, c_int_p, ctypes.c_int, ctypes.POINTER(JdeDets),
+                                      ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "jde_kf_initiate": (None, [c_double_p, c_double_p, c_double_p]),
     "jde_kf_predict": (None, [ctypes.c_int, c_double_p, c_double_p]),
     "jde_kf_initiate_n": (None, [ctypes.c_int, c_double_p, c_double_p, c_double_p]),

@@ -63,6 +63,7 @@ struct Op {
     float in_scale;          // per-tensor scale of the input activations (calibrated)
     int producer;            // op whose output this op reads (-1: the stem or none)
     int tile8;               // FP8 tile configuration
+    size_t dev_wt;           // det3+emb ops: the emb conv's weights again as [K][E], for the sparse emb head
 };
 
 struct Tensor {
@@ -101,6 +102,11 @@ struct jde_ctx {
     // 3x3 stride-1 convs run from an LDS window (conv3_win) where they qualify;
     // off by default: measured slower than the implicit GEMM on MI355X.
     bool window_convs = false;
+    // Deferred sparse embedding head: the emb 3x3 convs run in jde_decode at
+    // kept cells only (jde_sparse_emb); their inputs stay live in the arena.
+    bool sparse_emb = false;
+    int emb_op[3] = {-1, -1, -1};    // per scale (stride 8, 16, 32): the det3+emb op
+    size_t ws_work = 0, ws_work_count = 0;
     std::vector<int> launch_kind;
     size_t ws_amax = 0;
     // Per-launch timing: a ring of event pairs, one entry per profiled forward.
@@ -268,6 +274,11 @@ void plan_arena(jde_ctx* c) {
             if (t.first < 0) t.first = i;
             t.last = std::max(t.last, i);
         }
+        // the emb conv's input outlives the forward: the sparse emb head reads it in jde_decode
+        if (o.emb_out >= 0) {
+            c->tens[o.in_t].last = (int)c->ops.size();
+            c->emb_op[o.emb_out] = i;
+        }
     }
     struct Block { size_t off, bytes; int tensor; };
     std::vector<Block> live;
@@ -317,6 +328,10 @@ void plan_weights(jde_ctx* c) {
         off = align256(off + wb);
         o.dev_b = off;
         off = align256(off + (size_t)o.cout * 4);
+        if (o.layer2 >= 0) {
+            o.dev_wt = off;
+            off = align256(off + (size_t)(o.cout - o.n_split) * K * eb);
+        }
         if (o.fp8) {
             o.dev_w8 = off;
             off = align256(off + (size_t)o.cout * K);
@@ -349,6 +364,8 @@ void plan_decode_scratch(jde_ctx* c) {
     c->ws_mask = off;   off = align256(off + n * (size_t)c->cap * (c->cap / 64) * 8);
     c->ws_keep = off;   off = align256(off + n * c->cap * 4);
     c->ws_amax = off;   off = align256(off + c->ops.size() * 4);
+    c->ws_work = off;   off = align256(off + (size_t)3 * n * c->cap * 3 * 4);
+    c->ws_work_count = off; off = align256(off + 3 * 4);
     c->ws_total = off;
 }
 
@@ -778,6 +795,21 @@ jde_status jde_load_weights(jde_ctx* c, const float* blob, size_t nf, void* d_we
                     }
                 }
                 memcpy(host.data() + o.dev_b + row * 4, &b[co], 4);
+                if (q == 1) {
+                    // the emb conv again, [K][E]: k-major so that a wave reads consecutive outputs
+                    const size_t E = (size_t)(o.cout - o.n_split);
+                    unsigned char* dst = host.data() + o.dev_wt;
+                    for (int k = 0; k < K; ++k) {
+                        const float v = w[(size_t)co * K + k];
+                        const size_t at = (size_t)k * E + co;
+                        if (c->et == kF32) {
+                            memcpy(dst + at * 4, &v, 4);
+                        } else {
+                            const uint16_t h = c->et == kBF16 ? f32_to_bf16_rne(v) : f32_to_f16_rne(v);
+                            memcpy(dst + at * 2, &h, 2);
+                        }
+                    }
+                }
                 if (o.fp8) {
                     float amax = 0.f;
                     for (int k = 0; k < K; ++k) amax = std::max(amax, fabsf(w[(size_t)co * K + k]));
@@ -805,7 +837,7 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
     if (c->fp8 && !c->fp8_ready && !c->calibrating) return fail(JDE_ESTATE, "FP8 context not calibrated");
     if (wsb < c->ws_total) return fail(JDE_ENOMEM, "workspace %zu < %zu bytes", wsb, c->ws_total);
     for (int s = 0; s < 3; ++s)
-        if (!out->det[s] || !out->emb[s]) return fail(JDE_EINVAL, "null head output %d", s);
+        if (!out->det[s] || (!c->sparse_emb && !out->emb[s])) return fail(JDE_EINVAL, "null head output %d", s);
     bool uniform;
     if (jde_status st = batch_ok(c, d, n, &uniform)) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -881,7 +913,14 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
             }
             continue;
         }
-        const ConvArgs a = conv_args(c, o, d, n, uniform, W, geom, out, (int)oi);
+        ConvArgs a = conv_args(c, o, d, n, uniform, W, geom, out, (int)oi);
+        if (c->sparse_emb && o.emb_out >= 0) {
+            // det3 alone: the emb rows of the weight block run later, at kept cells only
+            a.cout = o.n_split;
+            a.out1 = nullptr;
+            a.ld1 = 0;
+            a.n_major = (double)a.cout * a.K > (double)a.M * a.cin ? 1 : 0;
+        }
         int w3 = 0;  // pixel tiles of the window kernel, 0 = implicit GEMM
         if (c->window_convs && !runs_fp8(c, o) && conv3w_ok(a, c->et)) {
             for (int f = 0; f < n; ++f) {
@@ -1058,7 +1097,33 @@ jde_status jde_decode(jde_ctx* c, const jde_head_out* heads, const jde_frame_des
     ea.count = out->count;
     ea.n_cand = out->n_cand;
     ea.overflow = out->overflow;
+    ea.work = nullptr;
+    ea.work_count = nullptr;
+    ea.work_cap = n * c->cap;
+    if (c->sparse_emb) {
+        if (!c->loaded) return fail(JDE_ESTATE, "sparse embedding head needs loaded weights");
+        ea.work = (int*)(W + c->ws_work);
+        ea.work_count = (int*)(W + c->ws_work_count);
+        HIP_TRY(launch_setup(geom_params(d, n), geom, ea.work_count, 3, s));
+    }
     HIP_TRY(launch_emit(ea, n, s));
+    if (c->sparse_emb) {
+        SparseEmbArgs sa{};
+        for (int q = 0; q < 3; ++q) {
+            const Op& o = c->ops[c->emb_op[q]];
+            sa.feat[q] = W + c->tens[o.in_t].off;
+            sa.wt[q] = c->d_weights + o.dev_wt;
+            sa.bias[q] = (const float*)(c->d_weights + o.dev_b) + o.n_split;
+            sa.F[q] = o.cin;
+        }
+        sa.E = c->cfg.emb_dim;
+        sa.geom = geom;
+        sa.work = ea.work;
+        sa.count = ea.work_count;
+        sa.work_cap = ea.work_cap;
+        sa.out = out->emb;
+        HIP_TRY(launch_sparse_emb(sa, c->et, n, c->cap, nkeep, s));
+    }
     return JDE_OK;
 }
 
@@ -1165,6 +1230,55 @@ jde_status jde_track_emb_update(const int* pairs, int P, const float* de, int D,
     return JDE_OK;
 }
 
+static jde_status assoc_batch(const int* tb, int n, AssocBatch* b, int* max_t) {
+    if (!tb || n < 0 || n > kMaxFrames) return fail(JDE_EINVAL, "bad batch: n=%d", n);
+    *b = AssocBatch{};
+    b->n = n;
+    *max_t = 0;
+    for (int f = 0; f <= n; ++f) {
+        if (tb[f] < 0 || (f > 0 && tb[f] < tb[f - 1])) return fail(JDE_EINVAL, "track_begin must be non-decreasing");
+        b->begin[f] = tb[f];
+        if (f > 0) *max_t = std::max(*max_t, tb[f] - tb[f - 1]);
+    }
+    return JDE_OK;
+}
+
+jde_status jde_kf_predict_dev(int T, double* mean, double* cov, void* stream) {
+    if (T < 0 || (T > 0 && (!mean || !cov))) return fail(JDE_EINVAL, "bad arguments T=%d", T);
+    HIP_TRY(launch_kf_predict(T, mean, cov, (hipStream_t)stream));
+    return JDE_OK;
+}
+
+jde_status jde_kf_update_dev(const int* tb, int n, const int* det_of_track, const jde_dets* dets, double* mean,
+                             double* cov, int* status, void* stream) {
+    AssocBatch b;
+    int max_t;
+    if (jde_status st = assoc_batch(tb, n, &b, &max_t)) return st;
+    if (max_t > 0 && (!det_of_track || !dets || !dets->boxes || !mean || !cov || dets->cap <= 0))
+        return fail(JDE_EINVAL, "null argument");
+    HIP_TRY(launch_kf_update(b, max_t, det_of_track, max_t ? dets->boxes : nullptr, max_t ? dets->cap : 0, mean, cov,
+                             status, (hipStream_t)stream));
+    return JDE_OK;
+}
+
+jde_status jde_assign_dev(const float* cost, const int* tb, int n, const jde_dets* dets, float max_cost,
+                          int* det_of_track, int* track_of_det, int* kept, double* total, int* status,
+                          void* stream) {
+    AssocBatch b;
+    int max_t;
+    if (jde_status st = assoc_batch(tb, n, &b, &max_t)) return st;
+    if (n == 0) return JDE_OK;
+    if (!dets || !dets->count || dets->cap <= 0 || !track_of_det || !kept || !total || !status ||
+        (max_t > 0 && (!cost || !det_of_track)))
+        return fail(JDE_EINVAL, "null argument");
+    if (max_t > kAssignMax) return fail(JDE_ECAPACITY, "%d tracks in one frame exceed %d", max_t, kAssignMax);
+    if (!(max_cost >= 0.f)) return fail(JDE_EINVAL, "max_cost must be >= 0");
+    const int max_dim = std::min(std::max(max_t, dets->cap), kAssignMax);
+    HIP_TRY(launch_assign(cost, b, max_dim, dets->count, dets->cap, max_cost, det_of_track, track_of_det, kept, total,
+                          status, (hipStream_t)stream));
+    return JDE_OK;
+}
+
 jde_status jde_calibrate(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws, size_t wsb,
                          const jde_head_out* out, void* stream) {
     if (!c || !ws) return fail(JDE_EINVAL, "null argument");
@@ -1204,6 +1318,12 @@ jde_status jde_fuse_stem(jde_ctx* c, int on) {
 jde_status jde_fuse_blocks(jde_ctx* c, int on) {
     if (!c) return fail(JDE_EINVAL, "null context");
     c->fuse_blocks = on != 0;
+    return JDE_OK;
+}
+
+jde_status jde_sparse_emb(jde_ctx* c, int on) {
+    if (!c) return fail(JDE_EINVAL, "null context");
+    c->sparse_emb = on != 0;
     return JDE_OK;
 }
 

@@ -145,7 +145,24 @@ struct EmitArgs {
     const int* cand_count;           // [n]
     float* boxes; float* scores; float* margins; float* emb_out;
     int* anchor_idx; int* count; int* n_cand; int* overflow;
+    int* work;                       // deferred embedding: [3][work_cap][3] (row, frame, cell), or null
+    int* work_count;                 // [3]
+    int work_cap;
 };
+// Deferred sparse embedding head (post.hip): the emb 3x3 conv at kept cells only.
+struct SparseEmbArgs {
+    const void* feat[3];             // head feature maps F[s] channels, NHWC at level 3 + s (storage type)
+    const void* wt[3];               // emb weights [9 F][E] (storage type), K = (tap, channel)
+    const float* bias[3];            // [E]
+    int F[3];
+    int E;
+    const int* geom;
+    const int* work;                 // [3][work_cap][3]
+    const int* count;                // [3]
+    int work_cap;
+    float* out;                      // dets emb rows [n * cap][E] (raw, then normalised)
+};
+hipError_t launch_sparse_emb(const SparseEmbArgs& a, int et, int n, int cap, const int* nkeep, hipStream_t s);
 hipError_t launch_emit(const EmitArgs& a, int n, hipStream_t s);
 hipError_t launch_nms_prepare(const float* boxes, const float* margins, const int* idx, int K,
                               unsigned long long* keys, int* vals, int* count, hipStream_t s);
@@ -160,6 +177,16 @@ struct CostBatch { int n; int begin[kMaxFrames + 1]; };
 hipError_t launch_cost_batch(const float* trk_emb, const double* mean, const double* cov, const CostBatch& b,
                              int max_t, const float* det_boxes, const float* det_emb, const int* dcount, int cap,
                              int E, double gate, float* cost, hipStream_t s);
+// Device association (assoc.hip).  Frame f of a batch owns tracks [begin[f], begin[f+1]).
+typedef CostBatch AssocBatch;
+constexpr int kAssignMax = 2048;   // most rows / columns of one frame's assignment (LDS-resident)
+hipError_t launch_kf_predict(int T, double* mean, double* cov, hipStream_t s);
+hipError_t launch_kf_update(const AssocBatch& b, int max_t, const int* det_of_track, const float* boxes, int cap,
+                            double* mean, double* cov, int* status, hipStream_t s);
+size_t assign_lds_bytes(int max_dim);
+hipError_t launch_assign(const float* cost, const AssocBatch& b, int max_dim, const int* dcount, int cap,
+                         float max_cost, int* det_of_track, int* track_of_det, int* kept, double* total, int* status,
+                         hipStream_t s);
 hipError_t launch_emb_update(const int* pairs, int P, const float* det_emb, int D, float* trk_emb, int T,
                              int E, float momentum, hipStream_t s);
 

@@ -322,17 +322,28 @@ __global__ __launch_bounds__(256) void emit_kernel(EmitArgs a) {
         const unsigned idx = (unsigned)key;
         const size_t r = (size_t)f * a.cap + k;
         const AnchorLoc L = locate(idx, g, a.A);
-        const float* e = a.emb[L.s] + ((size_t)g[2 + 3 + L.s] + L.cell) * a.E;
-        float ss = 0.f;
-        for (int c = lane; c < a.E; c += 64) {
-            const float v = e[c];
-            ss = __builtin_fmaf(v, v, ss);
-        }
+        if (a.work) {
+            // deferred embedding: queue (row, frame, cell) for the sparse emb conv
+            if (lane == 0) {
+                const int q = atomicAdd(a.work_count + L.s, 1);
+                int* w = a.work + ((size_t)L.s * a.work_cap + q) * 3;
+                w[0] = (int)r;
+                w[1] = f;
+                w[2] = L.cell;
+            }
+        } else {
+            const float* e = a.emb[L.s] + ((size_t)g[2 + 3 + L.s] + L.cell) * a.E;
+            float ss = 0.f;
+            for (int c = lane; c < a.E; c += 64) {
+                const float v = e[c];
+                ss = __builtin_fmaf(v, v, ss);
+            }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
-        const float inv = 1.0f / fmaxf(sqrtf(ss), 1e-12f);
-        float* eo = a.emb_out + r * a.E;
-        for (int c = lane; c < a.E; c += 64) eo[c] = e[c] * inv;
+            for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+            const float inv = 1.0f / fmaxf(sqrtf(ss), 1e-12f);
+            float* eo = a.emb_out + r * a.E;
+            for (int c = lane; c < a.E; c += 64) eo[c] = e[c] * inv;
+        }
         if (lane == 0) {
             const float m = key_margin(key);
             *(float4*)(a.boxes + r * 4) = *(const float4*)(a.sboxes + ((size_t)f * a.cap + p) * 4);
@@ -346,6 +357,122 @@ __global__ __launch_bounds__(256) void emit_kernel(EmitArgs a) {
 hipError_t launch_emit(const EmitArgs& a, int n, hipStream_t s) {
     const int gx = (a.cap + 3) / 4 < 64 ? (a.cap + 3) / 4 : 64;
     emit_kernel<<<dim3(gx, n), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Deferred sparse embedding head: the emb 3x3 conv (F -> E, linear + bias) of a
+// head runs only at the cells of kept detections, after NMS, on the head's
+// feature map (kept in the workspace since the forward).
+//   emit (sparse mode) appends each kept detection to its scale's work list:
+//     (output row f * cap + k, frame f, cell);
+//   sparse_emb_kernel: one workgroup per (16 detections, 64 outputs, scale):
+//     a 64-wide K chunk of the 16 detections' 3x3 neighbourhoods is gathered
+//     into LDS (zero outside the frame), every thread owns one output channel
+//     for 4 detections and accumulates over K in FP32, K = (tap, channel) in
+//     the dense conv's order; weights are stored [K][E] so that a wave reads
+//     64 consecutive outputs of one k;
+//   emb_normalize_kernel: L2-normalises each row in place (one wave per row).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ float to_f(T v) { return (float)v; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void sparse_emb_kernel(SparseEmbArgs a) {
+    __shared__ float xs[16][65];
+    __shared__ int s_row[16], s_pix[16], s_i[16], s_j[16], s_h[16], s_w[16];
+    const int sc = blockIdx.z;
+    const int cnt = a.count[sc];
+    const int F = a.F[sc], E = a.E;
+    const int K = 9 * F;
+    const int o = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int g = threadIdx.x >> 6;
+    const T* X = (const T*)a.feat[sc];
+    const T* W = (const T*)a.wt[sc];
+    const int* wl = a.work + (size_t)sc * a.work_cap * 3;
+    for (int tile = blockIdx.x; tile * 16 < cnt; tile += gridDim.x) {
+        __syncthreads();
+        if (threadIdx.x < 16) {
+            const int q = tile * 16 + threadIdx.x;
+            if (q < cnt) {
+                const int f = wl[3 * q + 1], cell = wl[3 * q + 2];
+                const int* gm = a.geom + f * kGeomInts;
+                const int lvl = 3 + sc;
+                const int w = gm[1] >> lvl;
+                s_row[threadIdx.x] = wl[3 * q];
+                s_pix[threadIdx.x] = gm[2 + lvl];
+                s_i[threadIdx.x] = cell / w;
+                s_j[threadIdx.x] = cell - (cell / w) * w;
+                s_h[threadIdx.x] = gm[0] >> lvl;
+                s_w[threadIdx.x] = w;
+            } else {
+                s_row[threadIdx.x] = -1;
+            }
+        }
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < K; k0 += 64) {
+            const int tap = k0 / F, c0 = k0 - tap * F;
+            const int dy = tap / 3 - 1, dx = tap - (tap / 3) * 3 - 1;
+            __syncthreads();
+            {
+                const int d = threadIdx.x >> 4, kk = (threadIdx.x & 15) * 4;
+                float v[4] = {0.f, 0.f, 0.f, 0.f};
+                if (s_row[d] >= 0) {
+                    const int y = s_i[d] + dy, x = s_j[d] + dx;
+                    if (y >= 0 && y < s_h[d] && x >= 0 && x < s_w[d]) {
+                        const T* src = X + ((size_t)s_pix[d] + (size_t)y * s_w[d] + x) * F + c0 + kk;
+                        for (int q = 0; q < 4; ++q) v[q] = to_f(src[q]);
+                    }
+                }
+                for (int q = 0; q < 4; ++q) xs[d][kk + q] = v[q];
+            }
+            __syncthreads();
+            if (o < E) {
+                const T* wp = W + (size_t)k0 * E + o;
+#pragma unroll 8
+                for (int kk = 0; kk < 64; ++kk) {
+                    const float wv = to_f(wp[(size_t)kk * E]);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) acc[d] = __builtin_fmaf(wv, xs[4 * g + d][kk], acc[d]);
+                }
+            }
+        }
+        if (o < E) {
+            const float b = a.bias[sc][o];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int r = s_row[4 * g + d];
+                if (r >= 0) a.out[(size_t)r * E + o] = acc[d] + b;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void emb_normalize_kernel(float* emb, const int* nkeep, int cap, int E) {
+    const int f = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int nk = nkeep[f];
+    for (int k = blockIdx.x * 4 + (threadIdx.x >> 6); k < nk; k += gridDim.x * 4) {
+        float* e = emb + ((size_t)f * cap + k) * E;
+        float ss = 0.f;
+        for (int c = lane; c < E; c += 64) ss = __builtin_fmaf(e[c], e[c], ss);
+#pragma unroll
+        for (int q = 32; q > 0; q >>= 1) ss += __shfl_xor(ss, q);
+        const float inv = 1.0f / fmaxf(sqrtf(ss), 1e-12f);
+        for (int c = lane; c < E; c += 64) e[c] = e[c] * inv;
+    }
+}
+
+hipError_t launch_sparse_emb(const SparseEmbArgs& a, int et, int n, int cap, const int* nkeep, hipStream_t s) {
+    const int max_tiles = (n * cap + 15) / 16;
+    dim3 grid(max_tiles < 64 ? max_tiles : 64, (a.E + 63) / 64, 3);
+    if (et == kF32) sparse_emb_kernel<float><<<grid, 256, 0, s>>>(a);
+    else if (et == kF16) sparse_emb_kernel<f16><<<grid, 256, 0, s>>>(a);
+    else sparse_emb_kernel<bf16><<<grid, 256, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int gx = (cap + 3) / 4 < 64 ? (cap + 3) / 4 : 64;
+    emb_normalize_kernel<<<dim3(gx, n), 256, 0, s>>>(a.out, nkeep, cap, a.E);
     return hipGetLastError();
 }
 

@@ -110,6 +110,57 @@ def jde_track_emb_update(pairs, det_emb, trk_emb, momentum=0.9, stream=None):
     return trk_emb
 
 
+def _dets_of(dets, cap):
+    """JdeDets struct of a dict of device tensors (missing entries -> NULL)."""
+    ds = JdeDets()
+    for k in ("boxes", "scores", "margins", "emb", "anchor_idx", "count", "n_cand", "overflow"):
+        setattr(ds, k, dets[k].data_ptr() if k in dets else 0)
+    ds.cap = int(cap)
+    return ds
+
+
+def _tb(track_begin):
+    tb = np.ascontiguousarray(track_begin, dtype=np.int32)
+    return tb, tb.ctypes.data_as(_lib.c_int_p)
+
+
+def jde_kf_predict_dev(mean, cov, stream=None):
+    """Device Kalman predict in place: mean [T, 8], cov [T, 8, 8] FP64 device tensors."""
+    T = int(mean.shape[0])
+    check(load().jde_kf_predict_dev(T, _ptr(mean), _ptr(cov), _stream(stream)), "jde_kf_predict_dev")
+    return mean, cov
+
+
+def jde_kf_update_dev(track_begin, det_of_track, dets, cap, mean, cov, status=None, stream=None):
+    """Device Kalman update of each track with its assigned detection box (batched layout)."""
+    tb, tbp = _tb(track_begin)
+    ds = _dets_of(dets, cap)
+    check(load().jde_kf_update_dev(tbp, len(tb) - 1, _ptr(det_of_track), ctypes.byref(ds), _ptr(mean), _ptr(cov),
+                                   _ptr(status), _stream(stream)), "jde_kf_update_dev")
+    return mean, cov
+
+
+def jde_assign_dev(cost, track_begin, dets, cap, max_cost, out=None, stream=None):
+    """Device min-cost assignment of every frame of a batched cost [T, cap];
+    returns dict of device tensors det_of_track [T], track_of_det [n*cap], kept [n],
+    total [n] (FP64), status [n]."""
+    torch = _torch()
+    tb, tbp = _tb(track_begin)
+    n = len(tb) - 1
+    dev = dets["count"].device
+    if out is None:
+        out = {"det_of_track": torch.empty(max(int(tb[-1]), 1), dtype=torch.int32, device=dev),
+               "track_of_det": torch.empty(max(n * cap, 1), dtype=torch.int32, device=dev),
+               "kept": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+               "total": torch.empty(max(n, 1), dtype=torch.float64, device=dev),
+               "status": torch.empty(max(n, 1), dtype=torch.int32, device=dev)}
+    ds = _dets_of(dets, cap)
+    check(load().jde_assign_dev(_ptr(cost), tbp, n, ctypes.byref(ds), float(max_cost), _ptr(out["det_of_track"]),
+                                _ptr(out["track_of_det"]), _ptr(out["kept"]), _ptr(out["total"]), _ptr(out["status"]),
+                                _stream(stream)), "jde_assign_dev")
+    return out
+
+
 def jde_kf_initiate(z):
     mean = np.zeros(8)
     cov = np.zeros(64)
@@ -236,21 +287,27 @@ class JDE:
                                         _ptr(self.weights), self.weights.numel(), _stream(stream)),
               "jde_load_weights")
 
-    def head_buffers(self, descs):
+    def head_buffers(self, descs, emb=True):
+        """Head output buffers; emb=False leaves the dense embedding maps out (sparse emb head)."""
         torch = _torch()
         d = _descs(descs)
         det = (ctypes.c_size_t * 3)()
-        emb = (ctypes.c_size_t * 3)()
-        check(self.lib.jde_head_sizes(self.ctx, d, len(descs), det, emb), "jde_head_sizes")
+        embn = (ctypes.c_size_t * 3)()
+        check(self.lib.jde_head_sizes(self.ctx, d, len(descs), det, embn), "jde_head_sizes")
         return {"det": [torch.empty(det[s], dtype=torch.float32, device=self.device) for s in range(3)],
-                "emb": [torch.empty(emb[s], dtype=torch.float32, device=self.device) for s in range(3)]}
+                "emb": [torch.empty(embn[s], dtype=torch.float32, device=self.device) if emb else None
+                        for s in range(3)]}
 
     def _head_struct(self, heads):
         h = JdeHeadOut()
         for s in range(3):
             h.det[s] = heads["det"][s].data_ptr()
-            h.emb[s] = heads["emb"][s].data_ptr()
+            h.emb[s] = heads["emb"][s].data_ptr() if heads["emb"][s] is not None else 0
         return h
+
+    def sparse_emb(self, on=True):
+        """Deferred sparse embedding head (jde_sparse_emb)."""
+        check(self.lib.jde_sparse_emb(self.ctx, int(on)), "jde_sparse_emb")
 
     def forward(self, frames, descs=None, heads=None, stream=None):
         """frames: contiguous FP32 device tensor, [n, 3, H, W] or packed 1-D with `descs`."""
