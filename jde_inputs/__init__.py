@@ -11,7 +11,7 @@ FullHD sequences resized to 1088x608 (Sec. 5, Table 2) and trained JDE weights
 """
 
 from .configs import ModelConfig, TINY, FULL, SEED_BASE, model_config  # noqa: F401
-from .frames import tiny_frame, scene_frame, scene_batch, scene_objects  # noqa: F401
+from .frames import tiny_frame, scene_frame, scene_batch, scene_objects, capture_frame  # noqa: F401
 from .weights import (weight_specs, raw_weights, model_weights, load_calib,  # noqa: F401
                       anchors_px, CALIB_DIR)
 from .tracks import synthetic_dets_tracks  # noqa: F401

@@ -124,3 +124,12 @@ def scene_batch(seed: int, n: int, height: int = 608, width: int = 1088, n_obj: 
                 stream: int = 0, t0: int = 0) -> np.ndarray:
     """[n, 3, H, W] FP32: frames t0 .. t0+n-1 of one stream."""
     return np.stack([scene_frame(seed, stream, t0 + i, height, width, n_obj) for i in range(n)])
+
+
+def capture_frame(seed: int, stream: int, t: int, height: int = 1080, width: int = 1920,
+                  n_obj: int = 40) -> np.ndarray:
+    """[H, W, 3] uint8 RGB frame t of a synthetic stream as a capture device
+    delivers it (FullHD by default): the scene of ``scene_frame`` at that size,
+    quantised to 8 bits."""
+    f = scene_frame(seed, stream, t, height, width, n_obj)
+    return np.ascontiguousarray(np.clip(np.rint(f * 255.0), 0, 255).astype(np.uint8).transpose(1, 2, 0))

@@ -6,7 +6,8 @@ resize method is not stated; the reading used here (and by the product):
 
 * source: 8-bit RGB pixels, row-major [H_in, W_in, 3];
 * letterbox: scale r = min(h / H_in, w / W_in) keeps the aspect ratio, the
-  resized image is round(W_in r) x round(H_in r) pixels, placed at column
+  resized image is round(W_in r) x round(H_in r) pixels (nearest integer,
+  halves rounded up), placed at column
   floor((w - new_w) / 2) and row floor((h - new_h) / 2); the border is 0.5;
 * bilinear resampling with pixel centres aligned: output pixel u of the resized
   image samples the source at s = (u + 1/2) (W_in / new_w) - 1/2, clamped to
@@ -24,10 +25,10 @@ PAD = 0.5
 def letterbox_geometry(src_h, src_w, h, w):
     """(new_h, new_w, top, left) of the resized image inside the h x w frame."""
     r = min(h / src_h, w / src_w)
-    new_w = int(round(src_w * r))
-    new_h = int(round(src_h * r))
-    new_w = min(new_w, w)
-    new_h = min(new_h, h)
+    new_w = int(math.floor(src_w * r + 0.5))        # nearest, halves up
+    new_h = int(math.floor(src_h * r + 0.5))
+    new_w = max(min(new_w, w), 1)
+    new_h = max(min(new_h, h), 1)
     return new_h, new_w, (h - new_h) // 2, (w - new_w) // 2
 
 

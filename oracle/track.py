@@ -119,6 +119,44 @@ def gate_distances(mean, cov, det_boxes):
         if len(mean) else np.zeros((0, len(zs)))
 
 
+def fused_cost_matrix(trk_emb, mean, cov, det_boxes, det_emb, motion_weight, gate=CHI2_4_95):
+    """Appearance and motion in one cost (an association variant beyond the
+    paper's appendix): C = (1 - w) cos + w d^2_M where the gate passes, +inf where
+    d^2_M > gate; w = 0 is the appearance-only cost of ``cost_matrix``.  FP64."""
+    w = float(motion_weight)
+    f = np.asarray(trk_emb, dtype=np.float64)
+    e = np.asarray(det_emb, dtype=np.float64)
+    cos = np.clip(1.0 - f @ e.T, 0.0, 2.0)
+    zs = box_to_z(np.asarray(det_boxes).reshape(-1, 4))
+    c = np.zeros_like(cos)
+    for t in range(len(f)):
+        d2 = mahalanobis_sq(mean[t], cov[t], zs)
+        c[t] = (1.0 - w) * cos[t] + w * d2
+        c[t, d2 > gate] = np.inf
+    return c
+
+
+def state_to_box(mean):
+    """Kalman state (cx, cy, a, h, ...) -> box (x1, y1, x2, y2) with w = a h."""
+    m = np.asarray(mean, dtype=np.float64)
+    w = m[..., 2] * m[..., 3]
+    h = m[..., 3]
+    return np.stack([m[..., 0] - w / 2, m[..., 1] - h / 2, m[..., 0] + w / 2, m[..., 1] + h / 2], axis=-1)
+
+
+def iou_cost_matrix(mean, det_boxes):
+    """Second association stage on box overlap: C[t, d] = 1 - IoU(predicted box of
+    track t, detection d), FP64 (1 for disjoint or empty boxes)."""
+    a = state_to_box(np.asarray(mean).reshape(-1, 8))[:, None, :]
+    b = np.asarray(det_boxes, dtype=np.float64).reshape(-1, 4)[None, :, :]
+    iw = np.clip(np.minimum(a[..., 2], b[..., 2]) - np.maximum(a[..., 0], b[..., 0]), 0, None)
+    ih = np.clip(np.minimum(a[..., 3], b[..., 3]) - np.maximum(a[..., 1], b[..., 1]), 0, None)
+    inter = iw * ih
+    uni = (a[..., 2] - a[..., 0]) * (a[..., 3] - a[..., 1]) + (b[..., 2] - b[..., 0]) * (b[..., 3] - b[..., 1]) - inter
+    iou = np.where(uni > 0, inter / np.where(uni > 0, uni, 1.0), 0.0)
+    return 1.0 - iou
+
+
 def assign(cost, max_cost):
     """Min-cost assignment, then rejection of pairs above max_cost.
 

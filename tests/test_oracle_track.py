@@ -238,3 +238,30 @@ def test_kalman_steady_state_matches_discrete_riccati():
     for i in (0, 1, 3):
         got = pred[np.ix_([i, i + 4], [i, i + 4])]
         np.testing.assert_allclose(got, x, rtol=1e-10)
+
+
+def test_fused_cost_reduces_to_its_parts(rng):
+    """Motion weight 0 is the appearance cost; weight 1 is the Mahalanobis
+    distance itself where the gate passes; the gate pattern never changes."""
+    from jde_inputs import synthetic_dets_tracks
+    s = synthetic_dets_tracks(12, 20, 30, 64)
+    args = (s["trk_emb"], s["mean"], s["cov"], s["boxes"], s["det_emb"])
+    base = otrack.cost_matrix(*args)
+    c0 = otrack.fused_cost_matrix(*args, 0.0)
+    np.testing.assert_array_equal(np.isinf(c0), np.isinf(base))
+    np.testing.assert_allclose(c0[np.isfinite(base)], base[np.isfinite(base)], rtol=0, atol=1e-15)
+    c1 = otrack.fused_cost_matrix(*args, 1.0)
+    d2 = otrack.gate_distances(s["mean"], s["cov"], s["boxes"])
+    fin = np.isfinite(base)
+    np.testing.assert_allclose(c1[fin], d2[fin], rtol=1e-15)
+    cw = otrack.fused_cost_matrix(*args, 0.02)
+    np.testing.assert_allclose(cw[fin], 0.98 * base[fin] + 0.02 * d2[fin], rtol=1e-14)
+
+
+def test_iou_cost_closed_forms():
+    # a track state (cx, cy, a, h) whose box is (0, 0, 2, 1): cx 1, cy 0.5, h 1, a 2
+    m = np.array([[1.0, 0.5, 2.0, 1.0, 0, 0, 0, 0]])
+    boxes = np.array([[0, 0, 2, 1], [1, 0, 3, 1], [5, 5, 6, 6], [0, 0, 1, 1]], dtype=np.float64)
+    c = otrack.iou_cost_matrix(m, boxes)[0]
+    np.testing.assert_allclose(c, [0.0, 1.0 - 1.0 / 3.0, 1.0, 1.0 - 0.5], atol=1e-15)
+    np.testing.assert_allclose(otrack.state_to_box(m)[0], [0, 0, 2, 1])
