@@ -246,6 +246,7 @@ def test_fused_cost_reduces_to_its_parts(rng):
     from jde_inputs import synthetic_dets_tracks
     s = synthetic_dets_tracks(12, 20, 30, 64)
     args = (s["trk_emb"], s["mean"], s["cov"], s["boxes"], s["det_emb"])
+    from oracle import track as otrack
     base = otrack.cost_matrix(*args)
     c0 = otrack.fused_cost_matrix(*args, 0.0)
     np.testing.assert_array_equal(np.isinf(c0), np.isinf(base))
@@ -259,6 +260,7 @@ def test_fused_cost_reduces_to_its_parts(rng):
 
 
 def test_iou_cost_closed_forms():
+    from oracle import track as otrack
     # a track state (cx, cy, a, h) whose box is (0, 0, 2, 1): cx 1, cy 0.5, h 1, a 2
     m = np.array([[1.0, 0.5, 2.0, 1.0, 0, 0, 0, 0]])
     boxes = np.array([[0, 0, 2, 1], [1, 0, 3, 1], [5, 5, 6, 6], [0, 0, 1, 1]], dtype=np.float64)
