@@ -157,6 +157,19 @@ jde_status jde_admit(const jde_ctx* ctx, const jde_frame_desc* descs, int n, siz
 
 /* ---- hot path ------------------------------------------------------------ */
 
+/* Frame ingest (the capture stage of Sec. 4.4 feeds the model FullHD video;
+ * Sec. 5.1 resizes it to 1088x608): n 8-bit RGB frames of src_h x src_w
+ * (d_src: device, [n][src_h][src_w][3] bytes, back to back) -> the model input
+ * of jde_forward (d_dst: device FP32 NCHW in [0, 1], frames packed back to back
+ * at the sizes descs[0..n) (host)).  Letterbox: scale r = min(h / src_h,
+ * w / src_w), the resized image (round(src_w r) x round(src_h r)) centred at
+ * column (w - new_w) / 2 and row (h - new_h) / 2 (integer division), border 0.5;
+ * bilinear resampling with aligned pixel centres (output column u samples
+ * (u + 1/2) src_w / new_w - 1/2, clamped to the image), then / 255.  One pass
+ * over the source and the output; n <= 64. */
+jde_status jde_ingest(const uint8_t* d_src, int n, int src_h, int src_w, const jde_frame_desc* descs,
+                      float* d_dst, void* stream);
+
 /* Model forward over a batch (Sec. 3.1, Sec. 4.2).  d_frames: device FP32
  * NCHW pixels, frames packed back to back (frame f: 3*h_f*w_f floats).  descs:
  * host, n entries.  d_ws: device workspace (>= jde_workspace_bytes).  out:
@@ -301,6 +314,23 @@ jde_status jde_cost_matrix_dets(const float* d_track_emb, const double* d_mean, 
 jde_status jde_cost_matrix_batch(const float* d_track_emb, const double* d_mean, const double* d_cov,
                                  const int* track_begin, const jde_dets* dets, int n, int E,
                                  double gate_chi2, float* d_cost, void* stream);
+
+/* jde_cost_matrix_batch with motion fused into the cost (an association
+ * variant beyond Appendix A, which uses the embedding distance gated by the
+ * Kalman distance): where the gate passes, cost = (1 - w) clamp(1 - <f, e>, 0, 2)
+ * + w d2 (evaluated in FP64, stored FP32), +inf where d2 > gate_chi2;
+ * motion_weight w in [0, 1] (0 = jde_cost_matrix_batch). */
+jde_status jde_cost_matrix_batch_fused(const float* d_track_emb, const double* d_mean, const double* d_cov,
+                                       const int* track_begin, const jde_dets* dets, int n, int E,
+                                       double gate_chi2, float motion_weight, float* d_cost, void* stream);
+/* Box-overlap cost for a second association stage on the tracks and detections
+ * the first stage left unmatched: d_cost [track_begin[n], cap] (row stride cap)
+ * = 1 - IoU(track box, detection box) in FP64, stored FP32, where the track box
+ * comes from its Kalman state (cx, cy, a, h): width a*h.  Batched layout as
+ * jde_cost_matrix_batch; D of frame f from dets->count[f] on the device;
+ * columns >= count[f] are left untouched. */
+jde_status jde_iou_cost_batch(const double* d_mean, const int* track_begin, const jde_dets* dets, int n,
+                              float* d_cost, void* stream);
 
 /* Track embedding smoothing for matched pairs: f_t <- normalise(m f_t + (1-m) e_d)
  * (the track's appearance state follows its matched detections).  d_pairs

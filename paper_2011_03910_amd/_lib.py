@@ -60,6 +60,8 @@ SIGNATURES = {
                                   ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_size_t, ctypes.POINTER(JdeDets), ctypes.c_void_p]),
     "jde_frame_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "jde_ingest": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(JdeFrameDesc), ctypes.c_void_p, ctypes.c_void_p]),
     "jde_admit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(JdeFrameDesc), ctypes.c_int, ctypes.c_size_t,
                                  ctypes.c_size_t, c_int_p]),
     "jde_box_to_z": (None, [ctypes.c_int, c_float_p, c_double_p]),
@@ -77,6 +79,12 @@ SIGNATURES = {
     "jde_cost_matrix_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, c_int_p,
                                              ctypes.POINTER(JdeDets), ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                              ctypes.c_void_p, ctypes.c_void_p]),
+    "jde_cost_matrix_batch_fused": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, c_int_p,
+                                                   ctypes.POINTER(JdeDets), ctypes.c_int, ctypes.c_int,
+                                                   ctypes.c_double, ctypes.c_float, ctypes.c_void_p,
+                                                   ctypes.c_void_p]),
+    "jde_iou_cost_batch": (ctypes.c_int, [ctypes.c_void_p, c_int_p, ctypes.POINTER(JdeDets), ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "jde_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(JdeFrameDesc), ctypes.c_int,
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(JdeHeadOut), ctypes.c_int,
                                     ctypes.c_void_p]),

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libjde.so")
 OBJ_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["conv.hip", "post.hip", "assoc.hip", "api.hip", "host_track.cpp"]
+SOURCES = ["conv.hip", "post.hip", "assoc.hip", "ingest.hip", "api.hip", "host_track.cpp"]
 ARCH = os.environ.get("JDE_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-function",

@@ -1189,8 +1189,40 @@ jde_status jde_cost_matrix(const float* fe, const double* mean, const double* co
     return JDE_OK;
 }
 
+static jde_status assoc_batch(const int* tb, int n, AssocBatch* b, int* max_t) {
+    if (!tb || n < 0 || n > kMaxFrames) return fail(JDE_EINVAL, "bad batch: n=%d", n);
+    *b = AssocBatch{};
+    b->n = n;
+    *max_t = 0;
+    for (int f = 0; f <= n; ++f) {
+        if (tb[f] < 0 || (f > 0 && tb[f] < tb[f - 1])) return fail(JDE_EINVAL, "track_begin must be non-decreasing");
+        b->begin[f] = tb[f];
+        if (f > 0) *max_t = std::max(*max_t, tb[f] - tb[f - 1]);
+    }
+    return JDE_OK;
+}
+
 jde_status jde_cost_matrix_batch(const float* fe, const double* mean, const double* cov, const int* tb,
                                  const jde_dets* dets, int n, int E, double gate, float* cost, void* stream) {
+    return jde_cost_matrix_batch_fused(fe, mean, cov, tb, dets, n, E, gate, 0.f, cost, stream);
+}
+
+jde_status jde_iou_cost_batch(const double* mean, const int* tb, const jde_dets* dets, int n, float* cost,
+                              void* stream) {
+    AssocBatch b;
+    int max_t;
+    if (jde_status st = assoc_batch(tb, n, &b, &max_t)) return st;
+    if (max_t > 0 && (!mean || !cost || !dets || !dets->boxes || !dets->count || dets->cap <= 0))
+        return fail(JDE_EINVAL, "null argument");
+    HIP_TRY(launch_iou_cost(mean, b, max_t, max_t ? dets->boxes : nullptr, max_t ? dets->count : nullptr,
+                            max_t ? dets->cap : 0, cost, (hipStream_t)stream));
+    return JDE_OK;
+}
+
+jde_status jde_cost_matrix_batch_fused(const float* fe, const double* mean, const double* cov, const int* tb,
+                                       const jde_dets* dets, int n, int E, double gate, float motion_w, float* cost,
+                                       void* stream) {
+    if (!(motion_w >= 0.f && motion_w <= 1.f)) return fail(JDE_EINVAL, "motion weight outside [0, 1]");
     if (!dets || !tb || n < 0 || n > kMaxFrames || E <= 0 || E % 4 || dets->cap <= 0)
         return fail(JDE_EINVAL, "bad arguments n=%d E=%d", n, E);
     CostBatch b{};
@@ -1205,7 +1237,7 @@ jde_status jde_cost_matrix_batch(const float* fe, const double* mean, const doub
         return fail(JDE_EINVAL, "null argument");
     if (!(gate >= 0.0)) return fail(JDE_EINVAL, "gate must be >= 0");
     HIP_TRY(launch_cost_batch(fe, mean, cov, b, max_t, dets->boxes, dets->emb, dets->count, dets->cap, E, gate, cost,
-                              (hipStream_t)stream));
+                              (hipStream_t)stream, motion_w));
     return JDE_OK;
 }
 
@@ -1230,16 +1262,40 @@ jde_status jde_track_emb_update(const int* pairs, int P, const float* de, int D,
     return JDE_OK;
 }
 
-static jde_status assoc_batch(const int* tb, int n, AssocBatch* b, int* max_t) {
-    if (!tb || n < 0 || n > kMaxFrames) return fail(JDE_EINVAL, "bad batch: n=%d", n);
-    *b = AssocBatch{};
-    b->n = n;
-    *max_t = 0;
-    for (int f = 0; f <= n; ++f) {
-        if (tb[f] < 0 || (f > 0 && tb[f] < tb[f - 1])) return fail(JDE_EINVAL, "track_begin must be non-decreasing");
-        b->begin[f] = tb[f];
-        if (f > 0) *max_t = std::max(*max_t, tb[f] - tb[f - 1]);
+
+jde_status jde_ingest(const uint8_t* src, int n, int src_h, int src_w, const jde_frame_desc* d, float* dst,
+                      void* stream) {
+    if (n < 0 || n > kMaxFrames) return fail(JDE_EINVAL, "n=%d outside [0, %d]", n, kMaxFrames);
+    if (n == 0) return JDE_OK;
+    if (!src || !dst || !d) return fail(JDE_EINVAL, "null argument");
+    if (src_h <= 0 || src_w <= 0 || (size_t)src_h * src_w * 3 >= ((size_t)1 << 31))
+        return fail(JDE_EINVAL, "bad source size %dx%d", src_h, src_w);
+    IngestArgs a{};
+    a.src = src;
+    a.n = n;
+    a.src_h = src_h;
+    a.src_w = src_w;
+    a.dst = dst;
+    size_t off = 0;
+    int max_pix = 0;
+    for (int f = 0; f < n; ++f) {
+        const int h = d[f].h, w = d[f].w;
+        if (h <= 0 || w <= 0) return fail(JDE_EINVAL, "frame %d: bad size %dx%d", f, h, w);
+        const double r = std::min((double)h / src_h, (double)w / src_w);
+        IngestFrame& g = a.fr[f];
+        g.h = h;
+        g.w = w;
+        g.new_w = std::min((int)std::lround(src_w * r), w);
+        g.new_h = std::min((int)std::lround(src_h * r), h);
+        g.new_w = std::max(g.new_w, 1);
+        g.new_h = std::max(g.new_h, 1);
+        g.top = (h - g.new_h) / 2;
+        g.left = (w - g.new_w) / 2;
+        g.dst_off = off;
+        off += (size_t)3 * h * w;
+        max_pix = std::max(max_pix, h * w);
     }
+    HIP_TRY(launch_ingest(a, max_pix, (hipStream_t)stream));
     return JDE_OK;
 }
 

@@ -176,7 +176,24 @@ hipError_t launch_cost(const float* trk_emb, const double* mean, const double* c
 struct CostBatch { int n; int begin[kMaxFrames + 1]; };
 hipError_t launch_cost_batch(const float* trk_emb, const double* mean, const double* cov, const CostBatch& b,
                              int max_t, const float* det_boxes, const float* det_emb, const int* dcount, int cap,
-                             int E, double gate, float* cost, hipStream_t s);
+                             int E, double gate, float* cost, hipStream_t s, float motion_w = 0.f);
+hipError_t launch_iou_cost(const double* mean, const CostBatch& b, int max_t, const float* boxes, const int* dcount,
+                           int cap, float* cost, hipStream_t s);
+// Frame ingest (ingest.hip): 8-bit RGB [n][src_h][src_w][3] -> packed NCHW FP32.
+struct IngestFrame {
+    int h, w;                // model input size of the frame
+    int new_h, new_w;        // resized image inside it
+    int top, left;           // its position (the rest is the 0.5 border)
+    size_t dst_off;          // first float of the frame in the packed output
+};
+struct IngestArgs {
+    const unsigned char* src;
+    int n, src_h, src_w;
+    float* dst;
+    IngestFrame fr[kMaxFrames];
+};
+hipError_t launch_ingest(const IngestArgs& a, int max_pix, hipStream_t s);
+
 // Device association (assoc.hip).  Frame f of a batch owns tracks [begin[f], begin[f+1]).
 typedef CostBatch AssocBatch;
 constexpr int kAssignMax = 2048;   // most rows / columns of one frame's assignment (LDS-resident)

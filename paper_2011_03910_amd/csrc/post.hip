@@ -529,7 +529,7 @@ __global__ __launch_bounds__(256) void cost_kernel(const float* __restrict__ fe,
                                                    const float* __restrict__ boxes, const float* __restrict__ de,
                                                    int D, const int* __restrict__ dcount, int ldc, int E,
                                                    double gate, float* __restrict__ cost,
-                                                   CostBatch batch) {
+                                                   CostBatch batch, float motion_w) {
     __shared__ float sf[32][65], se[32][65];
     __shared__ double sL[32][10], sHx[32][4], sZ[32][4];
     __shared__ int sPD[32];
@@ -651,6 +651,8 @@ __global__ __launch_bounds__(256) void cost_kernel(const float* __restrict__ fe,
             const double u3 = (y3 - L[6] * u0 - L[7] * u1 - L[8] * u2) / L[9];
             const double d2 = u0 * u0 + u1 * u1 + u2 * u2 + u3 * u3;
             float c = fminf(fmaxf(1.0f - acc[i][j], 0.f), 2.f);
+            // motion-fused variant: (1 - w) cos + w d2, in FP64
+            if (motion_w != 0.f) c = (float)((1.0 - (double)motion_w) * (double)c + (double)motion_w * d2);
             if (!sPD[tl] || !(d2 <= gate)) c = __builtin_inff();
             cost[(size_t)t * ldc + d] = c;
         }
@@ -662,16 +664,56 @@ hipError_t launch_cost(const float* trk_emb, const double* mean, const double* c
     if (T == 0 || D == 0) return hipSuccess;
     dim3 grid((D + 31) / 32, (T + 31) / 32);
     CostBatch none{};
-    cost_kernel<<<grid, 256, 0, s>>>(trk_emb, mean, cov, T, det_boxes, det_emb, D, dcount, ldc, E, gate, cost, none);
+    cost_kernel<<<grid, 256, 0, s>>>(trk_emb, mean, cov, T, det_boxes, det_emb, D, dcount, ldc, E, gate, cost, none,
+                                     0.f);
     return hipGetLastError();
 }
 
 hipError_t launch_cost_batch(const float* trk_emb, const double* mean, const double* cov, const CostBatch& b,
                              int max_t, const float* det_boxes, const float* det_emb, const int* dcount, int cap,
-                             int E, double gate, float* cost, hipStream_t s) {
+                             int E, double gate, float* cost, hipStream_t s, float motion_w) {
     if (b.n == 0 || max_t == 0) return hipSuccess;
     dim3 grid((cap + 31) / 32, (max_t + 31) / 32, b.n);
-    cost_kernel<<<grid, 256, 0, s>>>(trk_emb, mean, cov, 0, det_boxes, det_emb, cap, dcount, cap, E, gate, cost, b);
+    cost_kernel<<<grid, 256, 0, s>>>(trk_emb, mean, cov, 0, det_boxes, det_emb, cap, dcount, cap, E, gate, cost, b,
+                                     motion_w);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Box-overlap cost of a second association stage: C[t, d] = 1 - IoU(track t's
+// predicted box, detection d) in FP64, the track box from its Kalman state
+// (cx, cy, a, h): w = a h.  One thread per (track, detection), frame on z.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void iou_cost_kernel(const double* __restrict__ mean, CostBatch b,
+                                                       const float* __restrict__ boxes,
+                                                       const int* __restrict__ dcount, int cap,
+                                                       float* __restrict__ cost) {
+    const int f = blockIdx.z;
+    const int t = b.begin[f] + blockIdx.y;
+    if (t >= b.begin[f + 1]) return;
+    int D = dcount[f];
+    D = D < cap ? D : cap;
+    const double* m = mean + (size_t)t * 8;
+    const double w = m[2] * m[3], h = m[3];
+    const double ax1 = m[0] - w / 2, ay1 = m[1] - h / 2, ax2 = m[0] + w / 2, ay2 = m[1] + h / 2;
+    const double area_a = (ax2 - ax1) * (ay2 - ay1);
+    for (int d = blockIdx.x * 256 + threadIdx.x; d < D; d += gridDim.x * 256) {
+        const float* bx = boxes + ((size_t)f * cap + d) * 4;
+        const double bx1 = bx[0], by1 = bx[1], bx2 = bx[2], by2 = bx[3];
+        const double iw = fmax(0.0, fmin(ax2, bx2) - fmax(ax1, bx1));
+        const double ih = fmax(0.0, fmin(ay2, by2) - fmax(ay1, by1));
+        const double inter = iw * ih;
+        const double uni = area_a + (bx2 - bx1) * (by2 - by1) - inter;
+        const double iou = uni > 0.0 ? inter / uni : 0.0;
+        cost[(size_t)t * cap + d] = (float)(1.0 - iou);
+    }
+}
+
+hipError_t launch_iou_cost(const double* mean, const CostBatch& b, int max_t, const float* boxes, const int* dcount,
+                           int cap, float* cost, hipStream_t s) {
+    if (b.n == 0 || max_t == 0) return hipSuccess;
+    dim3 grid((cap + 255) / 256 < 8 ? (cap + 255) / 256 : 8, max_t, b.n);
+    iou_cost_kernel<<<grid, 256, 0, s>>>(mean, b, boxes, dcount, cap, cost);
     return hipGetLastError();
 }
 

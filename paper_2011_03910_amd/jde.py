@@ -87,6 +87,20 @@ def jde_cost_matrix(trk_emb, mean, cov, det_boxes, det_emb, gate=9.4877, cost=No
     return cost
 
 
+def jde_ingest(src_u8, descs, out=None, stream=None):
+    """8-bit RGB frames (device uint8 [n, H, W, 3]) -> packed NCHW FP32 model input
+    at the sizes `descs` (letterbox + bilinear resize + /255)."""
+    torch = _torch()
+    n, H, W, C = src_u8.shape
+    assert C == 3 and src_u8.dtype == torch.uint8 and src_u8.is_contiguous()
+    total = sum(3 * h * w for h, w in descs)
+    if out is None:
+        out = torch.empty(total, dtype=torch.float32, device=src_u8.device)
+    check(load().jde_ingest(_ptr(src_u8), int(n), int(H), int(W), _descs(descs), _ptr(out), _stream(stream)),
+          "jde_ingest")
+    return out
+
+
 def jde_nms_noalloc(boxes, margins, idx, nms_iou=0.4, keep=None, nkeep=None, stream=None):
     """Greedy NMS of one candidate list on the library's static scratch (no
     workspace).  Device tensors in; keep positions [max(K, 1)] int32 and the
@@ -122,6 +136,33 @@ def _dets_of(dets, cap):
 def _tb(track_begin):
     tb = np.ascontiguousarray(track_begin, dtype=np.int32)
     return tb, tb.ctypes.data_as(_lib.c_int_p)
+
+
+def jde_cost_matrix_batch_fused(trk_emb, mean, cov, track_begin, dets, cap, motion_weight, gate=9.4877, cost=None,
+                                stream=None):
+    """Motion-fused batched cost [T, cap] (see jde_cost_matrix_batch_fused)."""
+    torch = _torch()
+    tb, tbp = _tb(track_begin)
+    E = int(trk_emb.shape[1]) if trk_emb.dim() == 2 else int(dets["emb"].shape[-1])
+    if cost is None:
+        cost = torch.full((max(int(tb[-1]), 1), cap), float("nan"), dtype=torch.float32, device=dets["count"].device)
+    ds = _dets_of(dets, cap)
+    check(load().jde_cost_matrix_batch_fused(_ptr(trk_emb), _ptr(mean), _ptr(cov), tbp, ctypes.byref(ds),
+                                             len(tb) - 1, E, float(gate), float(motion_weight), _ptr(cost),
+                                             _stream(stream)), "jde_cost_matrix_batch_fused")
+    return cost
+
+
+def jde_iou_cost_batch(mean, track_begin, dets, cap, cost=None, stream=None):
+    """Box-overlap cost [T, cap] = 1 - IoU(track box from its state, detection box)."""
+    torch = _torch()
+    tb, tbp = _tb(track_begin)
+    if cost is None:
+        cost = torch.full((max(int(tb[-1]), 1), cap), float("nan"), dtype=torch.float32, device=dets["count"].device)
+    ds = _dets_of(dets, cap)
+    check(load().jde_iou_cost_batch(_ptr(mean), tbp, ctypes.byref(ds), len(tb) - 1, _ptr(cost), _stream(stream)),
+          "jde_iou_cost_batch")
+    return cost
 
 
 def jde_kf_predict_dev(mean, cov, stream=None):

@@ -145,3 +145,60 @@ def test_assign_dev_equals_host_and_oracle(torch, shapes):
             ref, ref_total = otrack.assign(costs[f].astype(np.float64), max_cost)
             assert len(ref) == kept[f] and abs(ref_total - total[f]) <= 1e-9 * max(1.0, abs(ref_total))
         _say(f"  frame {f} {T}x{D}: kept {kept[f]} total {total[f]:.6f}")
+
+
+def _batched_inputs(torch, shapes, E=512, seed=3):
+    cap = 64 * ((max(max(d for _, d in shapes), 1) + 63) // 64)
+    Ts = [t for t, _ in shapes]
+    tb = np.concatenate([[0], np.cumsum(Ts)]).astype(np.int32)
+    syn = [synthetic_dets_tracks(seed + f, max(T, 1), max(D, 1), E) for f, (T, D) in enumerate(shapes)]
+    cat = lambda k: np.concatenate([s[k][:T] for s, (T, _) in zip(syn, shapes)])
+    boxes = np.zeros((len(shapes) * cap, 4), np.float32)
+    emb = np.zeros((len(shapes) * cap, E), np.float32)
+    for f, (s, (T, D)) in enumerate(zip(syn, shapes)):
+        boxes[f * cap:f * cap + D] = s["boxes"][:D]
+        emb[f * cap:f * cap + D] = s["det_emb"][:D]
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dets = {"boxes": cu(boxes), "emb": cu(emb), "count": cu(np.array([d for _, d in shapes], np.int32))}
+    return syn, tb, cap, cat, dets, cu
+
+
+@pytest.mark.parametrize("w", [0.0, 0.02, 1.0])
+def test_fused_cost_batch_vs_oracle(torch, w):
+    from paper_2011_03910_amd import jde_cost_matrix_batch_fused
+    shapes = [(33, 97), (0, 5), (40, 1), (64, 64)]
+    _say(f"case: fused cost w={w} {shapes}")
+    syn, tb, cap, cat, dets, cu = _batched_inputs(torch, shapes)
+    got = jde_cost_matrix_batch_fused(cu(cat("trk_emb")), cu(cat("mean")), cu(cat("cov")), tb, dets, cap, w)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    for f, (s, (T, D)) in enumerate(zip(syn, shapes)):
+        if not (T and D):
+            continue
+        ref = otrack.fused_cost_matrix(s["trk_emb"][:T], s["mean"][:T], s["cov"][:T], s["boxes"][:D],
+                                       s["det_emb"][:D], w)
+        g = got[tb[f]:tb[f + 1], :D]
+        d2 = otrack.gate_distances(s["mean"][:T], s["cov"][:T], s["boxes"][:D])
+        clear = np.abs(d2 - otrack.CHI2_4_95) > 1e-9 * otrack.CHI2_4_95
+        np.testing.assert_array_equal(np.isinf(g)[clear], np.isinf(ref)[clear])
+        fin = np.isfinite(ref) & np.isfinite(g)
+        err = np.abs(g[fin] - ref[fin]) / np.maximum(1.0, np.abs(ref[fin]))
+        assert err.max(initial=0) <= 2e-6, err.max()
+
+
+def test_iou_cost_batch_vs_oracle(torch):
+    from paper_2011_03910_amd import jde_iou_cost_batch
+    shapes = [(33, 97), (7, 0), (50, 50)]
+    _say(f"case: iou cost {shapes}")
+    syn, tb, cap, cat, dets, cu = _batched_inputs(torch, shapes, seed=8)
+    got = jde_iou_cost_batch(cu(cat("mean")), tb, dets, cap).cpu().numpy()
+    n_overlap = 0
+    for f, (s, (T, D)) in enumerate(zip(syn, shapes)):
+        if not (T and D):
+            continue
+        ref = otrack.iou_cost_matrix(s["mean"][:T], s["boxes"][:D])
+        g = got[tb[f]:tb[f + 1], :D]
+        np.testing.assert_allclose(g, ref, rtol=0, atol=1e-6)
+        n_overlap += int((ref < 1).sum())
+        assert np.isnan(got[tb[f]:tb[f + 1], D:]).all()
+    assert n_overlap > 0
