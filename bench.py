@@ -73,7 +73,7 @@ class Pipeline:
     """Preallocated buffers and one step of the hot path for a fixed batch."""
 
     def __init__(self, precision, batch, layers, torch, tune_frames=None, tiles=None, calib_frames=None,
-                 descs=None):
+                 descs=None, sparse_emb=True):
         from jde_inputs import FULL, anchors_px
         from paper_2011_03910_amd import JDE
         self.torch = torch
@@ -83,7 +83,9 @@ class Pipeline:
         self.m = JDE(FULL.c0, FULL.blocks, FULL.emb_dim, anchors_px(FULL), precision, batch, FULL.height,
                      FULL.width, 512, max_pixels=pix if descs is not None else 0)
         self.m.load_weights(layers)
-        self.heads = self.m.head_buffers(self.descs)
+        # the embedding head runs at kept detections only, after NMS (dense maps not written)
+        self.m.sparse_emb(sparse_emb)
+        self.heads = self.m.head_buffers(self.descs, emb=not sparse_emb)
         self.dets = self.m.dets_buffers(batch)
         self.track_begin = [N_TRACKS * f for f in range(batch + 1)]
         self.cost = torch.empty((batch * N_TRACKS, self.m.cap), dtype=torch.float32, device="cuda")
@@ -236,6 +238,8 @@ def accuracy(heads, descs, ref, frame=0):
     det_f = []
     for key in ("det", "emb"):
         for s in range(3):
+            if heads[key][s] is None:
+                continue
             st = 8 << s
             pix = [(h // st) * (w // st) for h, w in descs]
             flat = heads[key][s].float().cpu().numpy()
@@ -249,10 +253,13 @@ def accuracy(heads, descs, ref, frame=0):
     return errs, det_f
 
 
-def match_frac(gpu_boxes, ref_boxes, ref_scores, iou_min=0.9):
+def match_frac(gpu_boxes, ref_boxes, ref_scores, iou_min=0.9, emb=None):
+    """Fraction of oracle detections matched one-to-one (oracle-score order) at
+    IoU >= iou_min, and the smallest cosine between matched embeddings (emb =
+    (gpu rows, oracle rows)) or None."""
     import numpy as np
     if len(ref_boxes) == 0:
-        return 1.0
+        return 1.0, None
     a = np.asarray(ref_boxes, np.float64)[:, None, :]
     b = np.asarray(gpu_boxes, np.float64)[None, :, :]
     iw = np.clip(np.minimum(a[..., 2], b[..., 2]) - np.maximum(a[..., 0], b[..., 0]), 0, None)
@@ -260,13 +267,16 @@ def match_frac(gpu_boxes, ref_boxes, ref_scores, iou_min=0.9):
     inter = iw * ih
     uni = (a[..., 2] - a[..., 0]) * (a[..., 3] - a[..., 1]) + (b[..., 2] - b[..., 0]) * (b[..., 3] - b[..., 1]) - inter
     m = inter / np.maximum(uni, 1e-30)
-    used, hit = set(), 0
+    used, hit, cos = set(), 0, []
     for r in np.argsort(-np.asarray(ref_scores), kind="stable"):
         cand = [(m[r, g], g) for g in range(m.shape[1]) if g not in used and m[r, g] >= iou_min]
         if cand:
-            used.add(max(cand)[1])
+            g = max(cand)[1]
+            used.add(g)
             hit += 1
-    return hit / len(ref_boxes)
+            if emb is not None:
+                cos.append(float(np.dot(emb[0][g], emb[1][r])))
+    return hit / len(ref_boxes), (min(cos) if cos else None)
 
 
 def post_bytes(pipe, ncand, counts):
@@ -311,12 +321,78 @@ def time_post(pipe, inputs, torch, reps=50):
 
 def frame0_dets(pipe):
     n = int(pipe.dets["count"][0])
-    return pipe.dets["boxes"][:n].cpu().numpy()
+    return pipe.dets["boxes"][:n].cpu().numpy(), pipe.dets["emb"][:n].cpu().numpy()
 
 
-def quick_fps(precision, batch, layers, inputs, torch, tiles, steps=10, warmup=3, descs=None):
+def ingest_bench(torch, batch, reps=20):
+    """The fused ingest kernel on a batch of 8-bit RGB FullHD capture frames ->
+    1088x608 model input: time per batch and its rate on the bytes it must move."""
+    import numpy as np
+    from jde_inputs import FULL, capture_frame
+    from paper_2011_03910_amd import jde_ingest
+    src = np.stack([capture_frame(FULL.seed, 0, t) for t in range(2)])
+    src = torch.from_numpy(src).cuda().repeat(batch // 2 + 1, 1, 1, 1)[:batch].contiguous()
+    descs = [(FULL.height, FULL.width)] * batch
+    out = jde_ingest(src, descs)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        jde_ingest(src, descs, out=out)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    nbytes = batch * (1080 * 1920 * 3 + 3 * FULL.height * FULL.width * 4)
+    return {"frames": batch, "source": "1920x1080 RGB uint8", "us_per_batch": round(ms * 1e3, 1),
+            "bytes": nbytes, "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "frac_of_8TBps": round(nbytes / (ms * 1e-3) / 8e12, 3)}
+
+
+def association_bench(pipe, inputs, torch, reps=20):
+    """Device association of the pipeline's last batch (40 tracks per frame): Kalman
+    predict, the per-frame assignment on the batched cost and the Kalman update,
+    against the host FP64 calls on the same data."""
+    import numpy as np
+    from paper_2011_03910_amd import (jde_kf_predict_dev, jde_assign_dev, jde_kf_update_dev, jde_kf_predict,
+                                      jde_assign)
+    mean, cov = inputs[2].clone(), inputs[3].clone()
+    cap = pipe.m.cap
+    stream = torch.cuda.current_stream()
+    out = jde_assign_dev(pipe.cost, pipe.track_begin, pipe.dets, cap, 0.7)
+    timed = {}
+    calls = {"predict": lambda: jde_kf_predict_dev(mean, cov),
+             "assign": lambda: jde_assign_dev(pipe.cost, pipe.track_begin, pipe.dets, cap, 0.7, out=out),
+             "update": lambda: jde_kf_update_dev(pipe.track_begin, out["det_of_track"], pipe.dets, cap, mean, cov)}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        timed[name] = a.elapsed_time(b) / reps * 1e3
+    # host FP64 on the same sizes
+    hm, hc = inputs[2].cpu().numpy().copy(), inputs[3].cpu().numpy().copy()
+    cost = pipe.cost.cpu().numpy()
+    counts = pipe.dets["count"].cpu().numpy()
+    t0 = time.perf_counter()
+    jde_kf_predict(hm, hc)
+    t1 = time.perf_counter()
+    for f in range(pipe.batch):
+        jde_assign(cost[N_TRACKS * f:N_TRACKS * (f + 1), :counts[f]], 0.7)
+    t2 = time.perf_counter()
+    return {"tracks": int(mean.shape[0]), "frames": pipe.batch,
+            "device_us": {k: round(v, 1) for k, v in timed.items()},
+            "host_us": {"predict": round((t1 - t0) * 1e6, 1), "assign": round((t2 - t1) * 1e6, 1)},
+            "pairs_kept": int(out["kept"][:pipe.batch].sum().item())}
+
+
+def quick_fps(precision, batch, layers, inputs, torch, tiles, steps=10, warmup=3, descs=None, sparse_emb=True):
     """frames/s of the graph-replayed step for one configuration (no per-launch events)."""
-    pipe = Pipeline(precision, batch, layers, torch, None, tiles, calib_frames=inputs[0], descs=descs)
+    pipe = Pipeline(precision, batch, layers, torch, None, tiles, calib_frames=inputs[0], descs=descs,
+                    sparse_emb=sparse_emb)
     pipe.capture(*inputs)
     wall, step_ms, _ = run(pipe, inputs, steps, warmup, torch, graph=True)
     ncand = pipe.dets["n_cand"][:batch].cpu().numpy()
@@ -433,7 +509,13 @@ def main():
                          "bytes": cost_b, "GB_per_s": round(cost_b / (tp["cost"] * 1e-3) / 1e9, 1),
                          "frac_of_8TBps": round(cost_b / (tp["cost"] * 1e-3) / 8e12, 4)}}
         log(f"post-processing: {post}")
-    heads0 = {k: [h.clone() for h in v] for k, v in pipe.heads.items()}
+    extra = {}
+    if not args.no_sweeps:
+        extra["device_association"] = association_bench(pipe, inputs_b, torch)
+        log(f"device association: {extra['device_association']}")
+        extra["ingest"] = ingest_bench(torch, args.batch)
+        log(f"ingest: {extra['ingest']}")
+    heads0 = {k: [None if h is None else h.clone() for h in v] for k, v in pipe.heads.items()}
     boxes0 = frame0_dets(pipe)
     del pipe
     torch.cuda.empty_cache()
@@ -474,13 +556,19 @@ def main():
             torch.cuda.empty_cache()
         sweeps["bf16_b16_density"] = dens
         log(f"density sweep: {dens}")
+        r, p_ = quick_fps("bf16", args.batch, layers, inputs_b, torch, tiles16, sparse_emb=False)
+        sweeps["bf16_b16_dense_emb_head"] = r
+        log(f"dense emb head: {r}")
+        del p_
+        torch.cuda.empty_cache()
         prec = {}
         for pr in ("fp16", "fp8"):
             r, p_ = quick_fps(pr, args.batch, layers, inputs_b, torch, tiles16 if pr == "fp16" else None)
+            hd = ({k: [None if h is None else h.clone() for h in v] for k, v in p_.heads.items()}, frame0_dets(p_))
             if pr == "fp16":
-                fp16_heads0 = ({k: [h.clone() for h in v] for k, v in p_.heads.items()}, frame0_dets(p_))
+                fp16_heads0 = hd
             else:
-                prec_heads8 = ({k: [h.clone() for h in v] for k, v in p_.heads.items()}, frame0_dets(p_))
+                prec_heads8 = hd
             prec[pr] = r
             del p_
             torch.cuda.empty_cache()
@@ -522,11 +610,13 @@ def main():
         if fp16_heads0 is not None:
             rows.append(("fp16", fp16_heads0[0], fp16_heads0[1]))
             rows.append(("fp8", prec_heads8[0], prec_heads8[1]))
-        for name, hd, bx in rows:
+        for name, hd, (bx, be) in rows:
             errs, _ = accuracy(hd, [(FULL.height, FULL.width)] * args.batch, ref)
-            acc[name] = {"err_vs_fp64": {k: float(f"{v:.3e}") for k, v in errs.items()},
-                         "max_err": float(f"{max(errs.values()):.3e}"),
-                         "matched_frac": round(match_frac(bx, r["boxes"], r["score"]), 4),
+            frac, cos = match_frac(bx, r["boxes"], r["score"], emb=(be, r["emb"]))
+            acc[name] = {"head_err_vs_fp64": {k: float(f"{v:.3e}") for k, v in errs.items()},
+                         "max_head_err": float(f"{max(errs.values()):.3e}"),
+                         "matched_frac": round(frac, 4),
+                         "min_emb_cos_matched": None if cos is None else round(cos, 5),
                          "oracle_dets": len(r["idx"]), "gpu_dets": len(bx)}
         log(f"accuracy of frame 0 vs the FP64 oracle: {acc}")
 
@@ -534,7 +624,8 @@ def main():
         "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": f"JDE Darknet-53+FPN+3 heads (E=512), 3x608x1088 synthetic scene frames, "
+        "config": {"workload": f"JDE Darknet-53+FPN+3 heads (E=512, embedding conv at kept detections), "
+                               f"3x608x1088 synthetic scene frames, "
                                f"{args.precision.upper()} batch {args.batch}, confidence offset for {K_CAND} "
                                f"candidates on frame 0 ({ncand.mean():.1f} per frame measured over the batch); "
                                f"forward + decode + NMS + L2-normalise + {N_TRACKS}-track gated cost",
@@ -553,6 +644,7 @@ def main():
                                f"{conv_flop / 1e9:.1f} GFLOP/step, mean {conv_ms / n_launch * 1e3:.1f} us/launch)"},
         "accuracy_frame0": acc,
         "post_processing": post,
+        **extra,
         "ablation_ladder": None if sweeps is None else {
             "fp32_b1_eager": None if fp32 is None else round(fp32["fps"], 1),
             "bf16_b1_graph": sweeps["bf16_batch"]["1"]["fps"],

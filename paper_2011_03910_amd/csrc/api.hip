@@ -63,7 +63,6 @@ struct Op {
     float in_scale;          // per-tensor scale of the input activations (calibrated)
     int producer;            // op whose output this op reads (-1: the stem or none)
     int tile8;               // FP8 tile configuration
-    size_t dev_wt;           // det3+emb ops: the emb conv's weights again as [K][E], for the sparse emb head
 };
 
 struct Tensor {
@@ -328,10 +327,6 @@ void plan_weights(jde_ctx* c) {
         off = align256(off + wb);
         o.dev_b = off;
         off = align256(off + (size_t)o.cout * 4);
-        if (o.layer2 >= 0) {
-            o.dev_wt = off;
-            off = align256(off + (size_t)(o.cout - o.n_split) * K * eb);
-        }
         if (o.fp8) {
             o.dev_w8 = off;
             off = align256(off + (size_t)o.cout * K);
@@ -795,21 +790,6 @@ jde_status jde_load_weights(jde_ctx* c, const float* blob, size_t nf, void* d_we
                     }
                 }
                 memcpy(host.data() + o.dev_b + row * 4, &b[co], 4);
-                if (q == 1) {
-                    // the emb conv again, [K][E]: k-major so that a wave reads consecutive outputs
-                    const size_t E = (size_t)(o.cout - o.n_split);
-                    unsigned char* dst = host.data() + o.dev_wt;
-                    for (int k = 0; k < K; ++k) {
-                        const float v = w[(size_t)co * K + k];
-                        const size_t at = (size_t)k * E + co;
-                        if (c->et == kF32) {
-                            memcpy(dst + at * 4, &v, 4);
-                        } else {
-                            const uint16_t h = c->et == kBF16 ? f32_to_bf16_rne(v) : f32_to_f16_rne(v);
-                            memcpy(dst + at * 2, &h, 2);
-                        }
-                    }
-                }
                 if (o.fp8) {
                     float amax = 0.f;
                     for (int k = 0; k < K; ++k) amax = std::max(amax, fabsf(w[(size_t)co * K + k]));
@@ -1112,7 +1092,8 @@ jde_status jde_decode(jde_ctx* c, const jde_head_out* heads, const jde_frame_des
         for (int q = 0; q < 3; ++q) {
             const Op& o = c->ops[c->emb_op[q]];
             sa.feat[q] = W + c->tens[o.in_t].off;
-            sa.wt[q] = c->d_weights + o.dev_wt;
+            // the emb rows of the det3+emb weight block: rows n_split .. cout of [cout][K]
+            sa.w[q] = c->d_weights + o.dev_w + (size_t)o.n_split * o.ksz * o.ksz * o.cin * elem_bytes(c->et);
             sa.bias[q] = (const float*)(c->d_weights + o.dev_b) + o.n_split;
             sa.F[q] = o.cin;
         }

@@ -152,7 +152,7 @@ struct EmitArgs {
 // Deferred sparse embedding head (post.hip): the emb 3x3 conv at kept cells only.
 struct SparseEmbArgs {
     const void* feat[3];             // head feature maps F[s] channels, NHWC at level 3 + s (storage type)
-    const void* wt[3];               // emb weights [9 F][E] (storage type), K = (tap, channel)
+    const void* w[3];                // emb conv weights [E][9 F] (storage type), K = (tap, channel)
     const float* bias[3];            // [E]
     int F[3];
     int E;

@@ -3,6 +3,8 @@
 // normalisation, the tracks x detections cost with Mahalanobis gating, and the
 // track embedding update.  All per-frame work of a batch runs in one launch
 // per step, with the frame on the grid's y axis.
+#include <type_traits>
+
 #include "jde_internal.h"
 
 namespace jde {
@@ -366,83 +368,163 @@ hipError_t launch_emit(const EmitArgs& a, int n, hipStream_t s) {
 // feature map (kept in the workspace since the forward).
 //   emit (sparse mode) appends each kept detection to its scale's work list:
 //     (output row f * cap + k, frame f, cell);
-//   sparse_emb_kernel: one workgroup per (16 detections, 64 outputs, scale):
-//     a 64-wide K chunk of the 16 detections' 3x3 neighbourhoods is gathered
-//     into LDS (zero outside the frame), every thread owns one output channel
-//     for 4 detections and accumulates over K in FP32, K = (tap, channel) in
-//     the dense conv's order; weights are stored [K][E] so that a wave reads
-//     64 consecutive outputs of one k;
+//   sparse_emb_kernel: a GEMM on the matrix cores per scale, D = detections x
+//     E outputs, K = 9F in the dense conv's (tap, channel) order: one workgroup
+//     (4 waves) per 32 detections x 64 outputs; each 128-wide K chunk of the
+//     detections' 3x3 neighbourhoods (gathered from the NHWC map, zero outside
+//     the frame) and of the conv's own weight rows [E][K] goes through LDS,
+//     the next two chunks loading into registers while one is computed (the
+//     loop is latency-bound: a handful of workgroups per scale walk K); the
+//     MFMAs run in the dense conv's k order, so the rows equal the dense map's
+//     bitwise; FP32 accumulation, bias added, raw rows written;
 //   emb_normalize_kernel: L2-normalises each row in place (one wave per row).
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ float to_f(T v) { return (float)v; }
+template <typename T> struct EmbV;
+template <> struct EmbV<float> { typedef f32x4 type; };
+template <> struct EmbV<bf16> { typedef bf16x8 type; };
+template <> struct EmbV<f16> { typedef f16x8 type; };
+
+constexpr int kEmbDets = 32, kEmbOuts = 64, kEmbBK = 128;
 
 template <typename T>
 __global__ __launch_bounds__(256) void sparse_emb_kernel(SparseEmbArgs a) {
-    __shared__ float xs[16][65];
-    __shared__ int s_row[16], s_pix[16], s_i[16], s_j[16], s_h[16], s_w[16];
+    typedef typename EmbV<T>::type V;
+    constexpr int VEC = 16 / sizeof(T);                       // elements per 16-byte load
+    constexpr int LDR = kEmbBK + (sizeof(T) == 4 ? VEC : 2 * VEC);  // padded LDS row (elements)
+    constexpr int SEG = kEmbBK / VEC;                         // 16-byte segments per row and chunk
+    constexpr int AV = kEmbOuts * SEG / 256;                  // weight loads per thread per chunk
+    constexpr int BVT = kEmbDets * SEG / 256;                 // gather loads per thread per chunk
+    static_assert(AV >= 1 && BVT >= 1, "tile");
+    __shared__ __align__(16) T sA[2][kEmbOuts * LDR];
+    __shared__ __align__(16) T sB[2][kEmbDets * LDR];
+    __shared__ int s_row[kEmbDets], s_pix[kEmbDets], s_i[kEmbDets], s_j[kEmbDets], s_h[kEmbDets], s_w[kEmbDets];
     const int sc = blockIdx.z;
     const int cnt = a.count[sc];
     const int F = a.F[sc], E = a.E;
     const int K = 9 * F;
-    const int o = blockIdx.y * 64 + (threadIdx.x & 63);
-    const int g = threadIdx.x >> 6;
+    const int o0 = blockIdx.y * kEmbOuts;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const T* X = (const T*)a.feat[sc];
-    const T* W = (const T*)a.wt[sc];
+    const T* W = (const T*)a.w[sc];
     const int* wl = a.work + (size_t)sc * a.work_cap * 3;
-    for (int tile = blockIdx.x; tile * 16 < cnt; tile += gridDim.x) {
+    const int nk = (K + kEmbBK - 1) / kEmbBK;
+    for (int tile = blockIdx.x; tile * kEmbDets < cnt; tile += gridDim.x) {
         __syncthreads();
-        if (threadIdx.x < 16) {
-            const int q = tile * 16 + threadIdx.x;
+        if (tid < kEmbDets) {
+            const int q = tile * kEmbDets + tid;
             if (q < cnt) {
                 const int f = wl[3 * q + 1], cell = wl[3 * q + 2];
                 const int* gm = a.geom + f * kGeomInts;
                 const int lvl = 3 + sc;
                 const int w = gm[1] >> lvl;
-                s_row[threadIdx.x] = wl[3 * q];
-                s_pix[threadIdx.x] = gm[2 + lvl];
-                s_i[threadIdx.x] = cell / w;
-                s_j[threadIdx.x] = cell - (cell / w) * w;
-                s_h[threadIdx.x] = gm[0] >> lvl;
-                s_w[threadIdx.x] = w;
+                s_row[tid] = wl[3 * q];
+                s_pix[tid] = gm[2 + lvl];
+                s_i[tid] = cell / w;
+                s_j[tid] = cell - (cell / w) * w;
+                s_h[tid] = gm[0] >> lvl;
+                s_w[tid] = w;
             } else {
-                s_row[threadIdx.x] = -1;
+                s_row[tid] = -1;
             }
         }
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < K; k0 += 64) {
-            const int tap = k0 / F, c0 = k0 - tap * F;
-            const int dy = tap / 3 - 1, dx = tap - (tap / 3) * 3 - 1;
-            __syncthreads();
-            {
-                const int d = threadIdx.x >> 4, kk = (threadIdx.x & 15) * 4;
-                float v[4] = {0.f, 0.f, 0.f, 0.f};
-                if (s_row[d] >= 0) {
-                    const int y = s_i[d] + dy, x = s_j[d] + dx;
-                    if (y >= 0 && y < s_h[d] && x >= 0 && x < s_w[d]) {
-                        const T* src = X + ((size_t)s_pix[d] + (size_t)y * s_w[d] + x) * F + c0 + kk;
-                        for (int q = 0; q < 4; ++q) v[q] = to_f(src[q]);
+        __syncthreads();
+        // chunk kc: weight rows o0 .. o0+63 and the 32 detections' gathered rows, k in [kc*128, +128)
+        auto load = [&](int kc, V* ar, V* br) {
+            const int k0 = kc * kEmbBK;
+#pragma unroll
+            for (int q = 0; q < AV; ++q) {
+                const int v = tid + q * 256;
+                const int r = v / SEG, sg = v % SEG;
+                const int k = k0 + sg * VEC;
+                ar[q] = (o0 + r < E && k < K) ? *(const V*)(W + (size_t)(o0 + r) * K + k) : V{};
+            }
+#pragma unroll
+            for (int q = 0; q < BVT; ++q) {
+                const int v = tid + q * 256;
+                const int d = v / SEG, sg = v % SEG;
+                const int k = k0 + sg * VEC;
+                V x{};
+                if (s_row[d] >= 0 && k < K) {
+                    const int tap = k / F, c = k - tap * F;     // a 16-byte segment never straddles a tap
+                    const int y = s_i[d] + tap / 3 - 1, xx = s_j[d] + (tap - (tap / 3) * 3) - 1;
+                    if (y >= 0 && y < s_h[d] && xx >= 0 && xx < s_w[d])
+                        x = *(const V*)(X + ((size_t)s_pix[d] + (size_t)y * s_w[d] + xx) * F + c);
+                }
+                br[q] = x;
+            }
+        };
+        auto store = [&](int buf, const V* ar, const V* br) {
+#pragma unroll
+            for (int q = 0; q < AV; ++q) {
+                const int v = tid + q * 256;
+                *(V*)(&sA[buf][(v / SEG) * LDR + (v % SEG) * VEC]) = ar[q];
+            }
+#pragma unroll
+            for (int q = 0; q < BVT; ++q) {
+                const int v = tid + q * 256;
+                *(V*)(&sB[buf][(v / SEG) * LDR + (v % SEG) * VEC]) = br[q];
+            }
+        };
+        // each wave: outputs o0 + 16 wave .. +15 x the 32 detections (2 blocks of 16)
+        f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+        const int arow = wave * 16 + (lane & 15), brow = lane & 15;
+        const int kofs = (lane >> 4) * VEC;
+        auto compute = [&](int buf, int kc) {
+            const int kend = K - kc * kEmbBK < kEmbBK ? K - kc * kEmbBK : kEmbBK;
+#pragma unroll
+            for (int kk = 0; kk < kEmbBK; kk += 4 * VEC) {
+                if (kk >= kend) break;
+                const V af = *(const V*)(&sA[buf][arow * LDR + kk + kofs]);
+                V bf_[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) bf_[j] = *(const V*)(&sB[buf][(brow + 16 * j) * LDR + kk + kofs]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t], bf_[j][t], acc[j], 0, 0, 0);
+                    } else if constexpr (__is_same(T, bf16)) {
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf_[j], acc[j], 0, 0, 0);
+                    } else {
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af, bf_[j], acc[j], 0, 0, 0);
                     }
                 }
-                for (int q = 0; q < 4; ++q) xs[d][kk + q] = v[q];
             }
+        };
+        // two register sets: chunks kc + 1 and kc + 2 are in flight while kc is computed
+        V ra[2][AV], rb[2][BVT];
+        load(0, ra[0], rb[0]);
+        if (nk > 1) load(1, ra[1], rb[1]);
+        store(0, ra[0], rb[0]);
+        if (nk > 2) load(2, ra[0], rb[0]);
+        __syncthreads();
+        auto iter = [&](int kc, auto cur_c) {
+            constexpr int cur = decltype(cur_c)::value;
+            if (kc + 1 < nk) store(cur ^ 1, ra[cur ^ 1], rb[cur ^ 1]);
+            if (kc + 3 < nk) load(kc + 3, ra[cur ^ 1], rb[cur ^ 1]);
+            compute(cur, kc);
             __syncthreads();
-            if (o < E) {
-                const T* wp = W + (size_t)k0 * E + o;
-#pragma unroll 8
-                for (int kk = 0; kk < 64; ++kk) {
-                    const float wv = to_f(wp[(size_t)kk * E]);
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) acc[d] = __builtin_fmaf(wv, xs[4 * g + d][kk], acc[d]);
-                }
-            }
+        };
+        int kc = 0;
+        for (; kc + 1 < nk; kc += 2) {
+            iter(kc, std::integral_constant<int, 0>{});
+            iter(kc + 1, std::integral_constant<int, 1>{});
         }
-        if (o < E) {
-            const float b = a.bias[sc][o];
+        if (kc < nk) iter(kc, std::integral_constant<int, 0>{});
+        // lane l of detection block j: outputs 4 (l / 16) + e of the wave's 16, detection l % 16 of block j
+        const int o = o0 + wave * 16 + 4 * (lane >> 4);
+        if (o < E) {                    // E is a multiple of 64: a lane's 4 outputs are all in or all out
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const int r = s_row[4 * g + d];
-                if (r >= 0) a.out[(size_t)r * E + o] = acc[d] + b;
+            for (int j = 0; j < 2; ++j) {
+                const int r = s_row[16 * j + (lane & 15)];
+                if (r < 0) continue;
+                float4 v;
+                v.x = acc[j][0] + a.bias[sc][o];
+                v.y = acc[j][1] + a.bias[sc][o + 1];
+                v.z = acc[j][2] + a.bias[sc][o + 2];
+                v.w = acc[j][3] + a.bias[sc][o + 3];
+                *(float4*)(a.out + (size_t)r * E + o) = v;
             }
         }
     }
@@ -464,8 +546,8 @@ __global__ __launch_bounds__(256) void emb_normalize_kernel(float* emb, const in
 }
 
 hipError_t launch_sparse_emb(const SparseEmbArgs& a, int et, int n, int cap, const int* nkeep, hipStream_t s) {
-    const int max_tiles = (n * cap + 15) / 16;
-    dim3 grid(max_tiles < 64 ? max_tiles : 64, (a.E + 63) / 64, 3);
+    const int max_tiles = (n * cap + kEmbDets - 1) / kEmbDets;
+    dim3 grid(max_tiles < 64 ? max_tiles : 64, (a.E + kEmbOuts - 1) / kEmbOuts, 3);
     if (et == kF32) sparse_emb_kernel<float><<<grid, 256, 0, s>>>(a);
     else if (et == kF16) sparse_emb_kernel<f16><<<grid, 256, 0, s>>>(a);
     else sparse_emb_kernel<bf16><<<grid, 256, 0, s>>>(a);

@@ -18,10 +18,14 @@ post-processing (Sec. 4.3).  This module is that pipeline for one GPU:
 * each slot owns a library context (workspace, head and detection buffers) and
   a HIP stream; its forward + decode overlap the other slot's work;
 * a post-processing thread takes finished batches in order and, per frame in
-  stream order, runs the association: Kalman predict on the host (FP64), the
-  gated cost matrix on the GPU against the stream's device-resident track
-  embeddings, Hungarian assignment on the host, Kalman update, track embedding
-  smoothing on the GPU, and the track lifecycle;
+  stream order, runs the association (Appendix A items 4-9).  With
+  device_assoc (the default) every track's Kalman state and embedding live in
+  device pools: Kalman predict, the gated cost matrix, the assignment and the
+  Kalman update run on the GPU (the library's FP64 kernels, bit-identical to
+  its host calls), and the host only reads back each track's matched
+  detection for the track lifecycle (ids, lost counts, new tracks).  Without
+  it the Kalman filter and the assignment run on the host in FP64 and only the
+  cost matrix and the embeddings are on the device;
 * latency of a frame = its arrival time -> its tracks updated.
 
 Everything on the device runs in the library's kernels; this module only
@@ -36,7 +40,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .jde import (JDE, jde_kf_initiate_n, jde_kf_predict, jde_kf_update_n, jde_assign,
-                  jde_track_emb_update, jde_box_to_z)
+                  jde_track_emb_update, jde_box_to_z, jde_kf_predict_dev, jde_kf_update_dev, jde_assign_dev)
 
 CHI2_GATE = 9.4877
 
@@ -95,9 +99,10 @@ class FrameJob:
 class Server:
     def __init__(self, cfg, anchors, layers, streams, precision="bf16", max_batch=16, hbm_budget=None,
                  max_tracks=512, max_cost=0.7, max_lost=30, conf_thr=0.5, nms_iou=0.4, cap=512, tiles=None,
-                 device="cuda"):
+                 device="cuda", device_assoc=True, sparse_emb=True):
         import torch
         self.torch = torch
+        self.device_assoc = device_assoc
         self.streams = {s.sid: StreamState(s) for s in streams}
         self.max_batch = max_batch
         self.max_cost, self.max_lost = max_cost, max_lost
@@ -109,6 +114,7 @@ class Server:
         for _ in range(2):
             m = JDE(cfg.c0, cfg.blocks, cfg.emb_dim, anchors, precision, max_batch, max_h, max_w, cap, device)
             m.load_weights(layers)
+            m.sparse_emb(sparse_emb)
             if tiles is not None:
                 m.set_tiles(tiles)
             self.slots.append({"m": m, "stream": torch.cuda.Stream(), "busy": False})
@@ -124,6 +130,10 @@ class Server:
         # Device-resident track embeddings of every stream in one pool: stream k owns
         # rows [k * max_tracks, (k + 1) * max_tracks).
         self.pool = torch.zeros((len(self.streams) * max_tracks, self.E), dtype=torch.float32, device=device)
+        # ... and, with device_assoc, their Kalman states (FP64), same rows
+        if device_assoc:
+            self.kmean = torch.zeros((len(self.streams) * max_tracks, 8), dtype=torch.float64, device=device)
+            self.kcov = torch.zeros((len(self.streams) * max_tracks, 8, 8), dtype=torch.float64, device=device)
         for k, st in enumerate(self.streams.values()):
             st.free_rows = list(range(k * max_tracks, (k + 1) * max_tracks))[::-1]
         # Frames arrive in pinned host memory (where a capture process would write
@@ -143,7 +153,7 @@ class Server:
             sl["off_host"] = torch.zeros(max_batch, dtype=torch.float32).pin_memory()
             sl["off"] = torch.zeros(max_batch, dtype=torch.float32, device=device)
             # outputs sized for a full batch of the largest frames; smaller batches use a prefix
-            sl["heads"] = sl["m"].head_buffers([(max_h, max_w)] * max_batch)
+            sl["heads"] = sl["m"].head_buffers([(max_h, max_w)] * max_batch, emb=not sparse_emb)
             sl["dets"] = sl["m"].dets_buffers(max_batch)
         self.lock = threading.Lock()
         self.results = []            # per frame: dict(sid, t, boxes, ids, latency)
@@ -318,8 +328,9 @@ class Server:
                     self.cand[j.sid].append(int(ncand[f]))
                 boxes_all = dets["boxes"].view(-1, m.cap, 4)[:n].cpu().numpy()
                 i0 = len(self.results)
+                assoc = self._associate_round_device if self.device_assoc else self._associate_round
                 for rnd in rounds:
-                    self._associate_round(sorted(rnd, key=lambda x: x[0]), m, dets, counts, boxes_all)
+                    assoc(sorted(rnd, key=lambda x: x[0]), m, dets, counts, boxes_all)
                 done = time.perf_counter()
                 for r in self.results[i0:]:
                     r["latency"] = done - r["arrival"]
@@ -415,6 +426,89 @@ class Server:
             dst = torch.tensor(new_rows, dtype=torch.int64).to(dev, non_blocking=True)
             src = torch.tensor(new_src, dtype=torch.int64).to(dev, non_blocking=True)
             self.pool.index_copy_(0, dst, emb.index_select(0, src))
+        s.synchronize()
+        tm["update_sync"] += time.perf_counter() - t3
+        tm["tracks"] = max(tm["tracks"], T)
+
+    def _associate_round_device(self, rnd, m, dets, counts, boxes_all):
+        """The same round with the Kalman filter and the assignment on the device."""
+        torch = self.torch
+        s = self.post_stream
+        cap = m.cap
+        dev = self.pool.device
+        sts = [self.streams[j.sid] for _, j in rnd]
+        counts_t = [len(st.ids) for st in sts]
+        tb = np.concatenate([[0], np.cumsum(counts_t)]).astype(np.int32)
+        T = int(tb[-1])
+        maxd = int(max((counts[f] for f, _ in rnd), default=0))
+        tm = self.t_parts
+        t0 = time.perf_counter()
+        det_of_track = np.full(T, -1, dtype=np.int32)
+        if T:
+            rows = torch.from_numpy(np.concatenate([st.rows for st in sts])).to(dev, non_blocking=True)
+            dmean = self.kmean.index_select(0, rows)
+            dcov = self.kcov.index_select(0, rows)
+            jde_kf_predict_dev(dmean, dcov, stream=s)
+            if maxd:
+                sub = self._sub_dets(dets, [f for f, _ in rnd], cap)
+                fe = self.pool.index_select(0, rows)
+                cost = m.cost_batch(fe, dmean, dcov, tb, sub, CHI2_GATE, stream=s)
+                out = jde_assign_dev(cost, tb, sub, cap, self.max_cost, stream=s)
+                jde_kf_update_dev(tb, out["det_of_track"], sub, cap, dmean, dcov, stream=s)
+            self.kmean.index_copy_(0, rows, dmean)
+            self.kcov.index_copy_(0, rows, dcov)
+            if maxd:
+                det_of_track = out["det_of_track"][:T].cpu().numpy()
+        t2 = time.perf_counter()
+        tm["cost"] += t2 - t0
+        upd_rows, upd_src, new_rows, new_src = [], [], [], []
+        init_rows, init_z = [], []
+        for i, (f, j) in enumerate(rnd):
+            st = sts[i]
+            boxes = boxes_all[f, :counts[f]]
+            D = len(boxes)
+            dtr = det_of_track[tb[i]:tb[i + 1]]
+            matched_t = dtr >= 0
+            det_ids = np.zeros(D, dtype=np.int64)
+            matched_d = np.zeros(D, dtype=bool)
+            det_ids[dtr[matched_t]] = st.ids[matched_t]
+            matched_d[dtr[matched_t]] = True
+            upd_rows.extend(st.rows[matched_t].tolist())
+            upd_src.extend((f * cap + dtr[matched_t]).tolist())
+            tm["frames"] += 1
+            st.lost[matched_t] = 0
+            st.lost[~matched_t] += 1
+            keep = st.lost <= self.max_lost
+            st.free_rows.extend(st.rows[~keep].tolist())
+            st.ids, st.lost, st.rows = st.ids[keep], st.lost[keep], st.rows[keep]
+            new_d = np.nonzero(~matched_d)[0][:len(st.free_rows)]
+            if len(new_d):
+                rws = np.array([st.free_rows.pop() for _ in new_d], dtype=np.int64)
+                nid = np.arange(st.next_id, st.next_id + len(new_d))
+                st.next_id += len(new_d)
+                det_ids[new_d] = nid
+                st.ids = np.concatenate([st.ids, nid])
+                st.lost = np.concatenate([st.lost, np.zeros(len(new_d), dtype=np.int64)])
+                st.rows = np.concatenate([st.rows, rws])
+                new_rows.extend(rws.tolist())
+                new_src.extend((f * cap + new_d).tolist())
+                init_rows.append(rws)
+                init_z.append(jde_box_to_z(boxes[new_d]))
+            self.results.append({"sid": j.sid, "t": j.t, "boxes": boxes.copy(), "ids": det_ids,
+                                 "arrival": j.arrival, "latency": 0.0})
+        t3 = time.perf_counter()
+        tm["host_assoc"] += t3 - t2
+        emb = dets["emb"]
+        if upd_rows:
+            pr = torch.from_numpy(np.stack([upd_rows, upd_src], axis=1).astype(np.int32)).to(dev, non_blocking=True)
+            jde_track_emb_update(pr, emb, self.pool, 0.9, stream=s)
+        if new_rows:
+            dst = torch.tensor(new_rows, dtype=torch.int64).to(dev, non_blocking=True)
+            src = torch.tensor(new_src, dtype=torch.int64).to(dev, non_blocking=True)
+            self.pool.index_copy_(0, dst, emb.index_select(0, src))
+            m0, c0 = jde_kf_initiate_n(np.concatenate(init_z))
+            self.kmean.index_copy_(0, dst, torch.from_numpy(m0).to(dev, non_blocking=True))
+            self.kcov.index_copy_(0, dst, torch.from_numpy(c0).to(dev, non_blocking=True))
         s.synchronize()
         tm["update_sync"] += time.perf_counter() - t3
         tm["tracks"] = max(tm["tracks"], T)

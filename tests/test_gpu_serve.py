@@ -38,10 +38,10 @@ def _streams(sids):
     return out
 
 
-def _serve(sids, precision, duration=0.4, budget_frames=None):
+def _serve(sids, precision, duration=0.4, budget_frames=None, device_assoc=True):
     from paper_2011_03910_amd.serve import Server
     srv = Server(TINY, anchors("tiny"), weights("tiny", 50), _streams(sids), precision=precision, max_batch=4,
-                 max_tracks=128, cap=256)
+                 max_tracks=128, cap=256, device_assoc=device_assoc)
     if budget_frames is not None:
         srv.hbm_budget = budget_frames * srv.slots[0]["m"].frame_bytes(192, 320)
     stats = srv.run(duration)
@@ -51,18 +51,19 @@ def _serve(sids, precision, duration=0.4, budget_frames=None):
     return stats, by
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_stream_results_same_alone_and_in_mix(precision):
+@pytest.mark.parametrize("precision,device_assoc", [("fp32", False), ("fp32", True), ("bf16", True)])
+def test_stream_results_same_alone_and_in_mix(precision, device_assoc):
     import torch
     assert torch.cuda.is_available()
-    _say(f"case: serve mix of 4 streams ({precision}, budget of two 192x320 frames)")
-    st_mix, mix = _serve([0, 1, 2, 3], precision, budget_frames=2)
+    _say(f"case: serve mix of 4 streams ({precision}, device association {device_assoc}, budget of two 192x320 "
+         f"frames)")
+    st_mix, mix = _serve([0, 1, 2, 3], precision, budget_frames=2, device_assoc=device_assoc)
     _say(f"  mix: {st_mix}")
     assert st_mix["frames"] >= 4 * 20 and st_mix["mean_batch"] > 1.0
     assert st_mix["budget_stalls"] + st_mix["budget_cut_batches"] > 0
     for sid in (1, 3):
         _say(f"case: serve stream {sid} alone ({precision})")
-        st_one, one = _serve([sid], precision)
+        st_one, one = _serve([sid], precision, device_assoc=device_assoc)
         keys = sorted(k for k in one if k[0] == sid)
         assert len(keys) >= 20
         for k in keys:
@@ -72,3 +73,21 @@ def test_stream_results_same_alone_and_in_mix(precision):
             np.testing.assert_array_equal(a["ids"], b["ids"])
         _say(f"  stream {sid}: {len(keys)} frames identical alone and in the mix; "
              f"tracks {max(int(x['ids'].max(initial=0)) for x in one.values())}")
+
+
+def test_device_association_equals_host_association():
+    """The serving loop gives the same detections and track ids with the Kalman
+    filter and the assignment on the device as on the host (the device kernels
+    take the host code's FP64 steps)."""
+    import torch
+    assert torch.cuda.is_available()
+    _say("case: serve mix, device vs host association")
+    _, dev = _serve([0, 1, 2, 3], "fp32", device_assoc=True)
+    _, host = _serve([0, 1, 2, 3], "fp32", device_assoc=False)
+    keys = sorted(set(dev) & set(host))
+    assert len(keys) >= 80
+    for k in keys:
+        np.testing.assert_array_equal(dev[k]["boxes"], host[k]["boxes"])
+        np.testing.assert_array_equal(dev[k]["ids"], host[k]["ids"])
+    _say(f"  {len(keys)} frames: identical boxes and ids; tracks up to "
+         f"{max(int(x['ids'].max(initial=0)) for x in dev.values())}")

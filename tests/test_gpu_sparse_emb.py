@@ -64,7 +64,7 @@ def test_sparse_emb_equals_dense_emb_at_kept_cells(torch, cfg_name, precision, k
             np.testing.assert_allclose(np.linalg.norm(b["emb"], axis=1), 1.0, atol=1e-6)
         total += len(a["emb"])
     _say(f"  {total} detections; max |sparse - dense| of the unit embeddings {worst:.2e}")
-    assert total > 0 and worst <= 2e-5
+    assert total > 0 and worst == 0.0    # same MFMA sequence as the dense conv: bitwise equal
 
 
 def test_sparse_emb_tiny_fp32_vs_oracle(torch):
