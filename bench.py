@@ -147,7 +147,7 @@ SERVE_BUDGET_BYTES = 512 << 20      # device memory the frames in flight may hol
 SERVE_FRAMES = 16                   # rendered frames per stream, played forward and back
 
 
-def serve_bench(layers, precision, seconds, tiles, torch):
+def serve_bench(layers, precision, seconds, tiles, torch, device_assoc=False):
     """16 synthetic streams at 30 FPS (mixed resolutions, 20-200 moving objects, each
     stream's confidence offset set for its object count) through the
     continuous-batching server under a 512 MiB device-memory budget; per-frame
@@ -156,7 +156,7 @@ def serve_bench(layers, precision, seconds, tiles, torch):
     from paper_2011_03910_amd.serve import Server, synthetic_streams
     streams = synthetic_streams(16, FULL.seed, frames_per_stream=SERVE_FRAMES)
     srv = Server(FULL, anchors_px(FULL), layers, streams, precision=precision, max_batch=16, tiles=tiles,
-                 hbm_budget=SERVE_BUDGET_BYTES)
+                 hbm_budget=SERVE_BUDGET_BYTES, device_assoc=device_assoc)
     srv.calibrate_density()
     stats = srv.run(seconds + 0.5, warmup=0.5)
     res = sorted({(s.height, s.width) for s in streams})
@@ -166,7 +166,8 @@ def serve_bench(layers, precision, seconds, tiles, torch):
                   "frame_bytes_mb": {f"{w}x{h}": round(srv.slots[0]["m"].frame_bytes(h, w) / 1e6, 1)
                                      for h, w in res},
                   "objects_vs_candidates": sorted(v for v in cps.values() if v[1] is not None),
-                  "rendered_frames_per_stream": SERVE_FRAMES})
+                  "rendered_frames_per_stream": SERVE_FRAMES,
+                  "association": "device (Kalman + assignment kernels)" if device_assoc else "host FP64"})
     return stats
 
 
@@ -383,10 +384,33 @@ def association_bench(pipe, inputs, torch, reps=20):
     for f in range(pipe.batch):
         jde_assign(cost[N_TRACKS * f:N_TRACKS * (f + 1), :counts[f]], 0.7)
     t2 = time.perf_counter()
+    # larger single-frame problems (synthetic costs, 30 % gated, the rest uniform in [0, 1.2])
+    big = {}
+    rng = np.random.Generator(np.random.PCG64(77))
+    for n in (200, 1000):
+        c = rng.uniform(0.0, 1.2, (n, n)).astype(np.float32)
+        c[rng.random((n, n)) < 0.3] = np.inf
+        capn = (n + 63) // 64 * 64
+        cp = np.full((n, capn), np.inf, np.float32)
+        cp[:, :n] = c
+        dc = torch.from_numpy(cp).cuda()
+        cnt = torch.tensor([n], dtype=torch.int32, device="cuda")
+        o = jde_assign_dev(dc, [0, n], {"count": cnt}, capn, 0.7)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(3):
+            jde_assign_dev(dc, [0, n], {"count": cnt}, capn, 0.7, out=o)
+        b.record(stream)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        jde_assign(c, 0.7)
+        t4 = time.perf_counter()
+        big[f"{n}x{n}"] = {"device_us": round(a.elapsed_time(b) / 3 * 1e3, 1), "host_us": round((t4 - t3) * 1e6, 1)}
     return {"tracks": int(mean.shape[0]), "frames": pipe.batch,
             "device_us": {k: round(v, 1) for k, v in timed.items()},
             "host_us": {"predict": round((t1 - t0) * 1e6, 1), "assign": round((t2 - t1) * 1e6, 1)},
-            "pairs_kept": int(out["kept"][:pipe.batch].sum().item())}
+            "pairs_kept": int(out["kept"][:pipe.batch].sum().item()), "assign_single_frame": big}
 
 
 def quick_fps(precision, batch, layers, inputs, torch, tiles, steps=10, warmup=3, descs=None, sparse_emb=True):
@@ -598,6 +622,13 @@ def main():
         serving = serve_bench(layers, args.precision, args.serve_seconds, tiles_out.get(key), torch)
         log(f"serving: {serving}")
         torch.cuda.empty_cache()
+        if not args.no_sweeps:
+            sd = serve_bench(layers, args.precision, min(args.serve_seconds, 2.0), tiles_out.get(key), torch,
+                             device_assoc=True)
+            extra["serving_device_association"] = {k: sd[k] for k in ("frames", "fps", "p50_ms", "p99_ms",
+                                                                        "mean_batch", "post_parts_s", "association")}
+            log(f"serving, device association: {extra['serving_device_association']}")
+            torch.cuda.empty_cache()
     cpu, acc = None, None
     if not args.no_cpu:
         cpu, ref = cpu_baseline(layers)
