@@ -38,7 +38,7 @@ def conv_source_hash(key, tiles):
     for f in ("conv.hip", "jde_internal.h"):
         with open(os.path.join(ROOT, "paper_2011_03910_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    h.update(json.dumps([key, tiles]).encode())
+    h.update(json.dumps([key, tiles, "sparse emb head"]).encode())
     return h.hexdigest()
 
 
@@ -426,6 +426,80 @@ def quick_fps(precision, batch, layers, inputs, torch, tiles, steps=10, warmup=3
     return rec, pipe
 
 
+# ---- summaries of rocprofv3 output (CPU only; they write the files under profiles/) ----
+
+CONV_KERNELS = ("conv_dma", "conv_igemm", "conv_pw_stream")
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(d, suffix):
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {d}")
+
+
+def summarize_trace(trace_dir, out_md, command):
+    """Markdown table of rocprofv3 --stats kernel durations (largest total first)."""
+    rows = _read_csv(_find(trace_dir, "kernel_stats.csv"))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# Kernel durations: {os.path.basename(out_md)[:-3]}", "", "Command:", "", "```", command, "```", "",
+             "| Kernel | Calls | Avg (us) | Total (ms) | % |", "|---|---|---|---|---|"]
+    conv_n, conv_ns = 0, 0.0
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"] if len(r["Name"]) < 100 else r["Name"][:97] + "..."
+        calls, total = int(r["Calls"]), float(r["TotalDurationNs"])
+        if any(k in r["Name"] for k in CONV_KERNELS):
+            conv_n += calls
+            conv_ns += total
+        lines.append(f"| `{name}` | {calls} | {float(r['AverageNs']) / 1e3:.1f} | {total / 1e6:.2f} | "
+                     f"{100 * total / tot:.2f} |")
+    lines += ["", f"All conv launches ({', '.join(CONV_KERNELS)}): {conv_n} calls, average "
+                  f"{conv_ns / max(conv_n, 1) / 1e3:.1f} us per launch."]
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def summarize_pmc(fetch_dir, write_dir, key, tiles, out_json, commands, probe_mib):
+    """Per-launch HBM bytes of the last forward's conv launches from a FETCH_SIZE and
+    a WRITE_SIZE counter run, each scaled by what the counter reads for the plain
+    copy probe (an elementwise negate over probe_mib MiB, reading and writing
+    probe_mib MiB)."""
+    def per_dispatch(d, counter):
+        out = []
+        for r in _read_csv(_find(d, "counter_collection.csv")):
+            if r.get("Counter_Name") == counter:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        return sorted(out)
+
+    fetch = per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = per_dispatch(write_dir, "WRITE_SIZE")
+    probe_f = [v for _, n, v in fetch if "neg" in n.lower()][0]
+    probe_w = [v for _, n, v in write if "neg" in n.lower()][0]
+    nbytes = probe_mib << 20
+    fscale = nbytes / (probe_f * 1024)
+    wscale = nbytes / (probe_w * 1024)
+    conv_f = [v for _, n, v in fetch if any(k in n for k in CONV_KERNELS)]
+    conv_w = [v for _, n, v in write if any(k in n for k in CONV_KERNELS)]
+    nl = 67                               # conv launches of one forward
+    lf = [round(v * 1024 * fscale) for v in conv_f[-nl:]]
+    lw = [round(v * 1024 * wscale) for v in conv_w[-nl:]]
+    rec = {"workload": key, "source_sha256": conv_source_hash(key, tiles), "launches": nl,
+           "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
+           "fetch_bytes_per_forward": sum(lf), "write_bytes_per_forward": sum(lw),
+           "bytes_per_launch": round((sum(lf) + sum(lw)) / nl),
+           "per_launch_fetch_bytes": lf, "per_launch_write_bytes": lw, "commands": commands,
+           "scale_reference": f"torch.neg over {probe_mib} MiB FP32 (reads and writes {probe_mib} MiB): "
+                              f"FETCH_SIZE {probe_f:.0f} KiB, WRITE_SIZE {probe_w:.0f} KiB"}
+    json.dump(rec, open(out_json, "w"), indent=1)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,10 +519,25 @@ def main():
     ap.add_argument("--retune", action="store_true", help="run the autotuner instead of the stored tile choices")
     ap.add_argument("--eager", action="store_true",
                     help="time eager launches instead of replaying the step as a captured HIP graph")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"),
+                    help="write a markdown summary of a rocprofv3 --stats directory and exit (no GPU)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_MIB", "COMMANDS_JSON"),
+                    help="write the conv launches' HBM traffic from FETCH_SIZE / WRITE_SIZE counter runs to "
+                         "profiles/ and exit (no GPU)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one plain elementwise copy of this many MiB (FP32 negate, read N + write N "
                          "bytes): the reference dispatch that scales hardware byte counters")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_pmc:
+        fdir, wdir, mib, cmds = args.summarize_pmc
+        key = f"{args.precision}_b{args.batch}"
+        tiles = json.load(open(os.path.join(ROOT, "paper_2011_03910_amd", "tiles_mi355x.json"))).get(key)
+        rec = summarize_pmc(fdir, wdir, key, tiles, TRAFFIC_FILE, json.loads(cmds), int(mib))
+        print(json.dumps({k: v for k, v in rec.items() if not k.startswith("per_launch")}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (frames are independent, "
               "so more GPUs would each run this same single-GPU path on their own streams)", file=sys.stderr)
