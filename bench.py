@@ -500,6 +500,65 @@ def summarize_pmc(fetch_dir, write_dir, key, tiles, out_json, commands, probe_mi
     return rec
 
 
+def ragged_bench(layers, tiles, big, torch, totals=(8, 16, 32, 64), steps=10, warmup=3):
+    """Ragged mixes of 608x1088 / 480x864 / 320x576 frames (8 to 64 frames) through
+    ONE graph captured for the whole capacity (jde_graph_capture_any) and replayed
+    per mix, each step followed by the batched cost of the mix's frames."""
+    from jde_inputs import FULL, anchors_px, ragged_mix, mix_frames
+    from paper_2011_03910_amd import JDE
+    mixes = {t: ragged_mix(FULL.seed, t) for t in totals}
+    pix = {t: sum(h * w for h, w in d) for t, d in mixes.items()}
+    tmax = max(totals, key=lambda t: pix[t])
+    m = JDE(FULL.c0, FULL.blocks, FULL.emb_dim, anchors_px(FULL), "bf16", max(totals), FULL.height, FULL.width, 512,
+            max_pixels=pix[tmax])
+    m.load_weights(layers)
+    if tiles is not None:
+        m.set_tiles(tiles)
+    m.sparse_emb(True)
+    heads = m.head_buffers(mixes[tmax], emb=False)   # the largest mix in pixels bounds every level
+    dets = m.dets_buffers(max(totals))
+    frames = torch.empty(3 * pix[tmax], dtype=torch.float32, device="cuda")
+    cost = torch.empty((max(totals) * N_TRACKS, m.cap), dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+    g = m.graph_capture_any(frames, heads, dets, CONF, NMS_IOU, stream=s)
+    out = {"note": "one graph captured once for 64 frames / the largest mix's pixels, replayed for every mix; "
+                   "+ 40-track batched cost per frame"}
+    for t in totals:
+        descs = mixes[t]
+        fr = torch.from_numpy(mix_frames(FULL.seed, descs)).cuda()
+        frames[:fr.numel()].copy_(fr)
+        trk = tuple(x[:N_TRACKS].repeat(t, *([1] * (x.dim() - 1))).contiguous() for x in big[1:])
+        tb = [N_TRACKS * f for f in range(t + 1)]
+        torch.cuda.synchronize()
+
+        def step():
+            g.launch_batch(descs, stream=s)
+            m.cost_batch(trk[0], trk[1], trk[2], tb, dets, cost=cost, stream=s)
+
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                step()
+            s.synchronize()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+            t0 = time.perf_counter()
+            for a, b in evs:
+                a.record(s)
+                step()
+                b.record(s)
+            s.synchronize()
+            wall = time.perf_counter() - t0
+        ms = sorted(a.elapsed_time(b) for a, b in evs)
+        out[str(t)] = {"fps": round(t * steps / wall, 1), "step_p50_ms": round(pct(ms, 50), 3),
+                       "candidates_per_frame": round(float(dets["n_cand"][:t].float().mean()), 1),
+                       "kept_per_frame": round(float(dets["count"][:t].float().mean()), 1),
+                       "mix": {f"{w}x{h}": descs.count((h, w)) for h, w in sorted(set(descs))},
+                       "pixels_vs_608x1088": round(pix[t] / (608 * 1088), 2)}
+        del fr
+    del g, m
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -687,19 +746,8 @@ def main():
             torch.cuda.empty_cache()
         sweeps["b16_precision"] = prec
         log(f"precision rows: {prec}")
-        c3 = {}
-        for total in (8, 16, 32, 64):
-            descs = ragged_mix(FULL.seed, total)
-            fr = torch.from_numpy(mix_frames(FULL.seed, descs)).cuda()
-            trk = tuple(x[:N_TRACKS].repeat(total, *([1] * (x.dim() - 1))).contiguous() for x in big[1:])
-            r, p_ = quick_fps("bf16", total, layers, (fr,) + trk, torch, tiles16, descs=descs)
-            r["mix"] = {f"{w}x{h}": descs.count((h, w)) for h, w in sorted(set(descs))}
-            r["pixels_vs_608x1088"] = round(sum(h * w for h, w in descs) / (608 * 1088), 2)
-            c3[str(total)] = r
-            del p_, fr
-            torch.cuda.empty_cache()
-        sweeps["bf16_ragged_mix"] = c3
-        log(f"ragged mixes: {c3}")
+        sweeps["bf16_ragged_mix"] = ragged_bench(layers, tiles16, big, torch)
+        log(f"ragged mixes: {sweeps['bf16_ragged_mix']}")
         del big
         torch.cuda.empty_cache()
         sweeps["seconds"] = round(time.perf_counter() - t_sw, 1)

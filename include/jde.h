@@ -386,8 +386,29 @@ jde_status jde_graph_capture(jde_ctx* ctx, const float* d_frames, const jde_fram
                              const float* d_track_emb,
                              const double* d_mean, const double* d_cov, const int* track_begin,
                              float* d_cost, void* stream, jde_graph** out);
-/* Replays the captured step on `stream`. */
+/* Replays the captured step on `stream` (graphs of jde_graph_capture). */
 jde_status jde_graph_launch(jde_graph* g, void* stream);
+/* One graph for any batch within the context's capacity (batch-wise inference
+ * of frames of several sizes, Sec. 4.2): captures jde_forward + jde_decode once,
+ * with every launch sized for the capacity (max_frames frames, max_pixels
+ * pixels) and reading the batch it works on from a header in the workspace;
+ * jde_graph_launch_batch writes that header and the frame table for the given
+ * batch (one small kernel on the stream) and replays the graph, so any mix of
+ * frame sizes and counts within the capacity replays the same graph.  BF16 and
+ * FP16 contexts with the fused stem (JDE_EUNSUPPORTED otherwise).  d_frames
+ * holds the batch's frames packed back to back (as for jde_forward); heads
+ * must be sized for the capacity (jde_head_sizes of max_frames frames of
+ * max_h x max_w, or of the largest batch) and dets for max_frames frames;
+ * d_logit_offset: device [max_frames] or NULL.  Detection counts of frames past
+ * the batch read 0.  The batched cost (whose tracks per frame vary) is launched
+ * after the replay. */
+jde_status jde_graph_capture_any(jde_ctx* ctx, const float* d_frames, void* d_ws, size_t ws_bytes,
+                                 const jde_head_out* heads, float conf_thr, float nms_iou,
+                                 const float* d_logit_offset, const jde_dets* dets, void* stream,
+                                 jde_graph** out);
+/* Writes the header of batch descs[0..n) (host) and replays a graph of
+ * jde_graph_capture_any on `stream`.  The batch is validated as for jde_forward. */
+jde_status jde_graph_launch_batch(jde_graph* g, const jde_frame_desc* descs, int n, void* stream);
 void jde_graph_destroy(jde_graph* g);
 
 /* ---- per-launch timing of the forward (Sec. 5.1 profiles where time goes) -- */

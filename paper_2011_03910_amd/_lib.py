@@ -96,6 +96,12 @@ SIGNATURES = {
                                          ctypes.c_void_p, ctypes.c_void_p, c_int_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "jde_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "jde_graph_capture_any": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                             ctypes.POINTER(JdeHeadOut), ctypes.c_float, ctypes.c_float,
+                                             ctypes.c_void_p, ctypes.POINTER(JdeDets), ctypes.c_void_p,
+                                             ctypes.POINTER(ctypes.c_void_p)]),
+    "jde_graph_launch_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(JdeFrameDesc), ctypes.c_int,
+                                              ctypes.c_void_p]),
     "jde_graph_destroy": (None, [ctypes.c_void_p]),
     "jde_calibrate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(JdeFrameDesc), ctypes.c_int,
                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(JdeHeadOut), ctypes.c_void_p]),

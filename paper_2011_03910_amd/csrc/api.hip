@@ -106,6 +106,7 @@ struct jde_ctx {
     bool sparse_emb = false;
     int emb_op[3] = {-1, -1, -1};    // per scale (stride 8, 16, 32): the det3+emb op
     size_t ws_work = 0, ws_work_count = 0;
+    size_t ws_dyn = 0;               // batch header of graphs that serve any batch (kDyn*)
     std::vector<int> launch_kind;
     size_t ws_amax = 0;
     // Per-launch timing: a ring of event pairs, one entry per profiled forward.
@@ -361,6 +362,7 @@ void plan_decode_scratch(jde_ctx* c) {
     c->ws_amax = off;   off = align256(off + c->ops.size() * 4);
     c->ws_work = off;   off = align256(off + (size_t)3 * n * c->cap * 3 * 4);
     c->ws_work_count = off; off = align256(off + 3 * 4);
+    c->ws_dyn = off;    off = align256(off + kDynInts * 4);
     c->ws_total = off;
 }
 
@@ -484,7 +486,7 @@ static bool block_fusable(const jde_ctx* c, const Op& o1, const Op& o2) {
 
 // ---- setup kernel: geometry table + counter reset ---------------------------
 namespace jde {
-__global__ void setup_kernel(GeomParams p, int* geom, int* counters, int ncount) {
+__device__ __forceinline__ void setup_kernel_body(const GeomParams& p, int* geom, int* counters, int ncount) {
     const int t = threadIdx.x;
     if (t < p.n) {
         int pre[kLevels], nxt[kLevels];
@@ -502,8 +504,24 @@ __global__ void setup_kernel(GeomParams p, int* geom, int* counters, int ncount)
     }
     for (int i = t; i < ncount; i += blockDim.x) counters[i] = 0;
 }
+__global__ void setup_kernel(GeomParams p, int* geom, int* counters, int ncount) {
+    setup_kernel_body(p, geom, counters, ncount);
+}
 hipError_t launch_setup(const GeomParams& p, int* geom, int* counters, int ncount, hipStream_t s) {
     setup_kernel<<<1, 256, 0, s>>>(p, geom, counters, ncount);
+    return hipGetLastError();
+}
+
+__global__ void setup_dyn_kernel(GeomParams p, DynHeader h, int* geom, int* dyn, int* counters, int ncount,
+                                 int* counters2, int ncount2) {
+    setup_kernel_body(p, geom, counters, ncount);
+    const int t = threadIdx.x;
+    if (t < kDynInts) dyn[t] = h.v[t];
+    for (int i = t; i < ncount2; i += blockDim.x) counters2[i] = 0;
+}
+hipError_t launch_setup_dyn(const GeomParams& p, const DynHeader& h, int* geom, int* dyn, int* counters, int ncount,
+                            int* counters2, int ncount2, hipStream_t s) {
+    setup_dyn_kernel<<<1, 256, 0, s>>>(p, h, geom, dyn, counters, ncount, counters2, ncount2);
     return hipGetLastError();
 }
 
@@ -810,20 +828,30 @@ jde_status jde_load_weights(jde_ctx* c, const float* blob, size_t nf, void* d_we
     return JDE_OK;
 }
 
-jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws, size_t wsb,
-                       const jde_head_out* out, void* stream) {
+// The forward's launches.  dynamic: for a batch described by the header in the
+// workspace (written before each replay of a graph, see jde_graph_capture_any):
+// grids are sized for the capacity and every launch reads the batch's pixels,
+// frames and tile counts from the header; d, n are then ignored.
+static jde_status forward_impl(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws,
+                               size_t wsb, const jde_head_out* out, void* stream, bool dynamic) {
     if (!c || !frames || !ws || !out) return fail(JDE_EINVAL, "null argument");
     if (!c->loaded) return fail(JDE_ESTATE, "weights not loaded");
     if (c->fp8 && !c->fp8_ready && !c->calibrating) return fail(JDE_ESTATE, "FP8 context not calibrated");
     if (wsb < c->ws_total) return fail(JDE_ENOMEM, "workspace %zu < %zu bytes", wsb, c->ws_total);
     for (int s = 0; s < 3; ++s)
         if (!out->det[s] || (!c->sparse_emb && !out->emb[s])) return fail(JDE_EINVAL, "null head output %d", s);
-    bool uniform;
-    if (jde_status st = batch_ok(c, d, n, &uniform)) return st;
+    bool uniform = false;
+    if (!dynamic) {
+        if (jde_status st = batch_ok(c, d, n, &uniform)) return st;
+    } else {
+        n = c->cfg.max_frames;
+    }
     hipStream_t s = (hipStream_t)stream;
     char* W = (char*)ws;
     int* geom = (int*)(W + c->ws_geom);
-    HIP_TRY(launch_setup(geom_params(d, n), geom, nullptr, 0, s));
+    const int* dynp = dynamic ? (const int*)(W + c->ws_dyn) : nullptr;
+    auto cap_m = [&](int lvl) { return c->cap_pix >> (2 * lvl); };
+    if (!dynamic) HIP_TRY(launch_setup(geom_params(d, n), geom, nullptr, 0, s));
     auto tptr = [&](int t) -> void* { return t < 0 ? nullptr : (void*)(W + c->tens[t].off); };
     hipEvent_t* pev = nullptr;
     if (c->prof) {
@@ -840,10 +868,10 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
         if (pev) HIP_TRY(hipEventRecord(pev[2 * oi], s));
         if (o.kind == OP_STEM && oi + 1 < c->ops.size() && stem_fusable(c, o, c->ops[oi + 1])) {
             const Op& o1 = c->ops[oi + 1];
-            int tiles = 0;
-            for (int f = 0; f < n; ++f) tiles += stem_down_tiles(d[f].h, d[f].w);
+            int tiles = dynamic ? (1 << 30) : 0;  // dynamic: the grid is the persistent maximum
+            for (int f = 0; f < (dynamic ? 0 : n); ++f) tiles += stem_down_tiles(d[f].h, d[f].w);
             HIP_TRY(launch_stem_down(frames, geom, n, tiles, (const float*)(wb + o.dev_w), (const float*)(wb + o.dev_b),
-                                     wb + o1.dev_w, (const float*)(wb + o1.dev_b), tptr(o1.out_t), c->et, s));
+                                     wb + o1.dev_w, (const float*)(wb + o1.dev_b), tptr(o1.out_t), c->et, s, dynp));
             if (pev) {
                 HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));
                 HIP_TRY(hipEventRecord(pev[2 * oi + 2], s));
@@ -860,12 +888,12 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
         if (o.kind == OP_CONV && oi + 1 < c->ops.size() && block_fusable(c, o, c->ops[oi + 1])) {
             const Op& o2 = c->ops[oi + 1];
             const int C = o.cin, lvl = o.lvl_in;
-            int tiles = 0;
-            for (int f = 0; f < n; ++f) tiles += resblock_tiles(C, d[f].h >> lvl, d[f].w >> lvl);
-            const size_t M = level_pixels(d, n, lvl);
+            int tiles = dynamic ? (1 << 30) : 0;
+            for (int f = 0; f < (dynamic ? 0 : n); ++f) tiles += resblock_tiles(C, d[f].h >> lvl, d[f].w >> lvl);
+            const size_t M = dynamic ? cap_m(lvl) : level_pixels(d, n, lvl);
             HIP_TRY(launch_resblock(tptr(o.in_t), tptr(o2.out_t), wb + o.dev_w, (const float*)(wb + o.dev_b),
                                     wb + o2.dev_w, (const float*)(wb + o2.dev_b), geom, n, lvl, C, tiles,
-                                    M * C * elem_bytes(c->et), c->et, s));
+                                    M * C * elem_bytes(c->et), c->et, s, dynp));
             if (pev) {
                 HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));
                 HIP_TRY(hipEventRecord(pev[2 * oi + 2], s));
@@ -879,6 +907,7 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
             continue;
         }
         if (o.kind == OP_STEM) {
+            if (dynamic) return fail(JDE_EUNSUPPORTED, "a graph for any batch needs the fused 16-bit stem");
             const int M = (int)level_pixels(d, n, 0);
             int rows = 0, max_w = 0;
             for (int f = 0; f < n; ++f) {
@@ -893,7 +922,16 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
             }
             continue;
         }
-        ConvArgs a = conv_args(c, o, d, n, uniform, W, geom, out, (int)oi);
+        ConvArgs a = conv_args(c, o, d, dynamic ? 0 : n, uniform, W, geom, out, (int)oi);
+        if (dynamic) {
+            // the capacity sizes the grid; the kernels read this batch's M, frames and layout from the header
+            a.M = (int)cap_m(o.lvl_out);
+            a.nframes = n;
+            a.uniform = 0;
+            a.dyn = dynp;
+            a.n_major = (double)o.cout * a.K > (double)a.M * o.cin ? 1 : 0;
+            if (runs_fp8(c, o)) return fail(JDE_EUNSUPPORTED, "a graph for any batch does not run FP8 convs");
+        }
         if (c->sparse_emb && o.emb_out >= 0) {
             // det3 alone: the emb rows of the weight block run later, at kept cells only
             a.cout = o.n_split;
@@ -902,7 +940,7 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
             a.n_major = (double)a.cout * a.K > (double)a.M * a.cin ? 1 : 0;
         }
         int w3 = 0;  // pixel tiles of the window kernel, 0 = implicit GEMM
-        if (c->window_convs && !runs_fp8(c, o) && conv3w_ok(a, c->et)) {
+        if (c->window_convs && !dynamic && !runs_fp8(c, o) && conv3w_ok(a, c->et)) {
             for (int f = 0; f < n; ++f) {
                 const int t = conv3w_tiles(d[f].h >> o.lvl_out, d[f].w >> o.lvl_out);
                 if (t == 0) {
@@ -927,6 +965,11 @@ jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d,
         }
     }
     return JDE_OK;
+}
+
+jde_status jde_forward(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws, size_t wsb,
+                       const jde_head_out* out, void* stream) {
+    return forward_impl(c, frames, d, n, ws, wsb, out, stream, false);
 }
 
 jde_status jde_autotune(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws, size_t wsb,
@@ -996,9 +1039,11 @@ jde_status jde_tiles(jde_ctx* c, int* tiles, int n_ops, int set) {
     return JDE_OK;
 }
 
-jde_status jde_decode(jde_ctx* c, const jde_head_out* heads, const jde_frame_desc* d, int n, float conf_thr,
-                      float nms_iou, const float* logit_offset, void* ws, size_t wsb, const jde_dets* out,
-                      void* stream) {
+// dynamic: as in forward_impl, for the batch described by the header; the header
+// write (setup_dyn) has zeroed the candidate and work-list counters.
+static jde_status decode_impl(jde_ctx* c, const jde_head_out* heads, const jde_frame_desc* d, int n, float conf_thr,
+                              float nms_iou, const float* logit_offset, void* ws, size_t wsb, const jde_dets* out,
+                              void* stream, bool dynamic) {
     if (!c || !heads || !ws || !out) return fail(JDE_EINVAL, "null argument");
     if (wsb < c->ws_total) return fail(JDE_ENOMEM, "workspace %zu < %zu bytes", wsb, c->ws_total);
     if (out->cap != c->cap) return fail(JDE_EINVAL, "dets.cap %d != max_candidates %d", out->cap, c->cap);
@@ -1008,22 +1053,27 @@ jde_status jde_decode(jde_ctx* c, const jde_head_out* heads, const jde_frame_des
     if (!(conf_thr >= 0.f && conf_thr <= 1.f)) return fail(JDE_EINVAL, "conf_thr outside [0, 1]");
     if (!(nms_iou >= 0.f)) return fail(JDE_EINVAL, "nms_iou must be >= 0");
     bool uniform;
-    if (jde_status st = batch_ok(c, d, n, &uniform)) return st;
+    if (!dynamic) {
+        if (jde_status st = batch_ok(c, d, n, &uniform)) return st;
+    } else {
+        n = c->cfg.max_frames;
+    }
     hipStream_t s = (hipStream_t)stream;
     char* W = (char*)ws;
     int* geom = (int*)(W + c->ws_geom);
     int* counts = (int*)(W + c->ws_counts);
-    HIP_TRY(launch_setup(geom_params(d, n), geom, counts, n, s));
+    if (!dynamic) HIP_TRY(launch_setup(geom_params(d, n), geom, counts, n, s));
     float lthr;
     if (conf_thr <= 0.f) lthr = -INFINITY;
     else if (conf_thr >= 1.f) lthr = INFINITY;
     else lthr = (float)log((double)conf_thr / (1.0 - (double)conf_thr));
-    int max_anchors = 0;
-    for (int i = 0; i < n; ++i) {
+    int max_anchors = dynamic ? c->max_anchors : 0;
+    for (int i = 0; i < (dynamic ? 0 : n); ++i) {
         const int h = d[i].h, w = d[i].w;
         max_anchors = std::max(max_anchors, ((h >> 3) * (w >> 3) + (h >> 4) * (w >> 4) + (h >> 5) * (w >> 5)) * 4);
     }
     DecodeArgs da{};
+    da.dyn = dynamic ? (const int*)(W + c->ws_dyn) : nullptr;
     GatherArgs ga{};
     EmitArgs ea{};
     for (int q = 0; q < 3; ++q) {
@@ -1084,7 +1134,7 @@ jde_status jde_decode(jde_ctx* c, const jde_head_out* heads, const jde_frame_des
         if (!c->loaded) return fail(JDE_ESTATE, "sparse embedding head needs loaded weights");
         ea.work = (int*)(W + c->ws_work);
         ea.work_count = (int*)(W + c->ws_work_count);
-        HIP_TRY(launch_setup(geom_params(d, n), geom, ea.work_count, 3, s));
+        if (!dynamic) HIP_TRY(launch_setup(geom_params(d, n), geom, ea.work_count, 3, s));
     }
     HIP_TRY(launch_emit(ea, n, s));
     if (c->sparse_emb) {
@@ -1106,6 +1156,12 @@ jde_status jde_decode(jde_ctx* c, const jde_head_out* heads, const jde_frame_des
         HIP_TRY(launch_sparse_emb(sa, c->et, n, c->cap, nkeep, s));
     }
     return JDE_OK;
+}
+
+jde_status jde_decode(jde_ctx* c, const jde_head_out* heads, const jde_frame_desc* d, int n, float conf_thr,
+                      float nms_iou, const float* logit_offset, void* ws, size_t wsb, const jde_dets* out,
+                      void* stream) {
+    return decode_impl(c, heads, d, n, conf_thr, nms_iou, logit_offset, ws, wsb, out, stream, false);
 }
 
 jde_status jde_nms(jde_ctx* c, const float* boxes, const float* margins, const int* idx, int K, float iou, void* ws,
@@ -1384,6 +1440,8 @@ void jde_fp8_encode(const float* x, uint8_t* out, size_t n) {
 struct jde_graph {
     hipGraph_t g = nullptr;
     hipGraphExec_t e = nullptr;
+    jde_ctx* ctx = nullptr;          // graphs for any batch: their context and workspace
+    char* ws = nullptr;
 };
 
 jde_status jde_graph_capture(jde_ctx* c, const float* frames, const jde_frame_desc* d, int n, void* ws, size_t wsb,
@@ -1418,8 +1476,65 @@ jde_status jde_graph_capture(jde_ctx* c, const float* frames, const jde_frame_de
     return JDE_OK;
 }
 
+jde_status jde_graph_capture_any(jde_ctx* c, const float* frames, void* ws, size_t wsb, const jde_head_out* heads,
+                                 float conf, float iou, const float* logit_offset, const jde_dets* dets, void* stream,
+                                 jde_graph** out) {
+    if (!c || !out) return fail(JDE_EINVAL, "null argument");
+    *out = nullptr;
+    if (c->prof) return fail(JDE_ESTATE, "graph capture while profiling");
+    if (!stream) return fail(JDE_EINVAL, "capture needs a non-default stream");
+    if (c->et == kF32 || c->fp8) return fail(JDE_EUNSUPPORTED, "a graph for any batch runs BF16 or FP16 contexts");
+    if (!c->fuse_stem) return fail(JDE_EUNSUPPORTED, "a graph for any batch needs the fused stem");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    jde_status st = forward_impl(c, frames, nullptr, 0, ws, wsb, heads, stream, true);
+    if (st == JDE_OK) st = decode_impl(c, heads, nullptr, 0, conf, iou, logit_offset, ws, wsb, dets, stream, true);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(s, &g);
+    if (st != JDE_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (ee != hipSuccess) return fail(JDE_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    jde_graph* G = new jde_graph();
+    G->g = g;
+    G->ctx = c;
+    G->ws = (char*)ws;
+    const hipError_t ie = hipGraphInstantiate(&G->e, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete G;
+        return fail(JDE_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    }
+    *out = G;
+    return JDE_OK;
+}
+
+jde_status jde_graph_launch_batch(jde_graph* g, const jde_frame_desc* d, int n, void* stream) {
+    if (!g || !g->e || !g->ctx) return fail(JDE_EINVAL, "not a graph for any batch");
+    jde_ctx* c = g->ctx;
+    bool uniform;
+    if (jde_status st = batch_ok(c, d, n, &uniform)) return st;
+    DynHeader h{};
+    h.v[kDynN] = n;
+    h.v[kDynUniform] = uniform ? 1 : 0;
+    for (int l = 0; l < kLevels; ++l) h.v[kDynM + l] = (int)level_pixels(d, n, l);
+    for (int f = 0; f < n; ++f) {
+        h.v[kDynStemTiles] += stem_down_tiles(d[f].h, d[f].w);
+        h.v[kDynRb64] += resblock_tiles(64, d[f].h >> 1, d[f].w >> 1);
+        h.v[kDynRb128] += resblock_tiles(128, d[f].h >> 2, d[f].w >> 2);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_setup_dyn(geom_params(d, n), h, (int*)(g->ws + c->ws_geom), (int*)(g->ws + c->ws_dyn),
+                             (int*)(g->ws + c->ws_counts), c->cfg.max_frames, (int*)(g->ws + c->ws_work_count), 3,
+                             s));
+    HIP_TRY(hipGraphLaunch(g->e, s));
+    return JDE_OK;
+}
+
 jde_status jde_graph_launch(jde_graph* g, void* stream) {
     if (!g || !g->e) return fail(JDE_EINVAL, "null graph");
+    if (g->ctx) return fail(JDE_EINVAL, "a graph for any batch is launched with jde_graph_launch_batch");
     HIP_TRY(hipGraphLaunch(g->e, (hipStream_t)stream));
     return JDE_OK;
 }

@@ -394,7 +394,11 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
                                                         const int* __restrict__ geom, int nframes, int total,
                                                         const float* __restrict__ w0, const float* __restrict__ b0,
                                                         const TO* __restrict__ w1, const float* __restrict__ b1,
-                                                        TO* __restrict__ out) {
+                                                        TO* __restrict__ out, const int* __restrict__ dyn) {
+    if (dyn) {  // batch header: frames and tiles of this batch (the grid covers the capacity)
+        nframes = dyn[kDynN];
+        total = dyn[kDynStemTiles];
+    }
     constexpr int C0 = 32, C1 = 64;
     constexpr int WR = 2 * kSdTY + 1, WC = 2 * kSdTX + 1;  // stem window: 5 x 129
     constexpr int FR = WR + 2, FC = WC + 2;                  // frame window: 7 x 131
@@ -588,15 +592,16 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
 
 hipError_t launch_stem_down(const float* frames, const int* geom, int nframes, int tiles, const float* w0,
                             const float* b0, const void* w1, const float* b1, void* out, int out_type,
-                            hipStream_t s) {
+                            hipStream_t s, const int* dyn) {
     // persistent: 2 workgroups per compute unit (63 KB of LDS each), all resident
+    // (with a batch header, `tiles` is the capacity's)
     dim3 grid(tiles < 512 ? tiles : 512), block(256);
     if (out_type == kBF16)
         stem_down_kernel<bf16><<<grid, block, 0, s>>>(frames, geom, nframes, tiles, w0, b0, (const bf16*)w1, b1,
-                                                      (bf16*)out);
+                                                      (bf16*)out, dyn);
     else if (out_type == kF16)
         stem_down_kernel<f16><<<grid, block, 0, s>>>(frames, geom, nframes, tiles, w0, b0, (const f16*)w1, b1,
-                                                     (f16*)out);
+                                                     (f16*)out, dyn);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -769,6 +774,21 @@ __device__ __forceinline__ void tile_origin(const ConvArgs& a, int BM, int BN, i
     }
 }
 
+// The same for logical tile L of W = gm * gn tiles (a workgroup walking tiles
+// L = blockIdx.x, + gridDim.x, ... with gridDim.x a multiple of 8 keeps each tile
+// on the XCD the one-tile-per-workgroup order gives it).
+__device__ __forceinline__ void tile_origin_at(const ConvArgs& a, int BM, int BN, int L, int W, int& m0, int& n0) {
+    const int gm = (a.M + BM - 1) / BM, gn = (a.cout + BN - 1) / BN;
+    const int P = xcd_remap(L, W);
+    if (a.n_major) {
+        m0 = (P % gm) * BM;
+        n0 = (P / gm) * BN;
+    } else {
+        n0 = (P % gn) * BN;
+        m0 = (P / gn) * BM;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // MFMA implicit GEMM.
 //   BM pixels x BN channels per workgroup of 4 waves (WGM x WGN), K chunks of BK.
@@ -780,7 +800,7 @@ __device__ __forceinline__ void tile_origin(const ConvArgs& a, int BM, int BN, i
 //   the same assignment on both operands, so the contraction is unchanged.
 //   Output: lane l holds channels 4(l/16) .. +3 of pixel l%16 of each block.
 // ---------------------------------------------------------------------------
-template <typename T, int BM, int BN, int WGM, int WGN, int BK, bool ALIGNED>
+template <typename T, int BM, int BN, int WGM, int WGN, int BK, bool ALIGNED, bool DYN = false>
 __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
     constexpr int VEC = 16 / sizeof(T);
     constexpr int VR = BK / VEC;
@@ -804,8 +824,19 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
+    // One tile per workgroup; DYN (a graph serving any batch): this batch's pixels,
+    // frames and layout come from the header, and the workgroups (as many as the
+    // capacity needs, at most a few per CU) walk this batch's tiles.
+    int W = gridDim.x;
+    if constexpr (DYN) {
+        a.M = a.dyn[kDynM + a.lvl_out];
+        a.nframes = a.dyn[kDynN];
+        a.uniform = a.dyn[kDynUniform];
+        W = ((a.M + BM - 1) / BM) * ((a.cout + BN - 1) / BN);
+    }
+    for (int tl = blockIdx.x; tl < W; tl += gridDim.x) {
     int m0, n0;
-    tile_origin(a, BM, BN, m0, n0);
+    tile_origin_at(a, BM, BN, tl, W, m0, n0);
     const bool concat = a.cin1 > 0;
     // Buffer resources: a load whose byte offset is out of range returns zeros,
     // which is how the zero halo, rows past M and channels past Cout are read.
@@ -986,6 +1017,9 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
     if (kc < nk) iter(kc, std::integral_constant<int, 0>{});
 
     store_tile<T, TM, TN, WTM, WTN>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
+    if constexpr (!DYN) break;
+    __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1044,7 +1078,7 @@ __device__ __forceinline__ int lds_swizzle(int r) {
     else return (((r >> 1) & 1) << 2) | (((r >> 2) & 1) << 1);
 }
 
-template <typename T, int BM, int BN, int WGM, int WGN, int S, bool NT, int BK>
+template <typename T, int BM, int BN, int WGM, int WGN, int S, bool NT, int BK, bool DYN = false>
 __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
     constexpr int NW = WGM * WGN;                  // waves (4 or 8)
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
@@ -1067,8 +1101,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave % WGM, wn = wave / WGM;
+    // One tile per workgroup; DYN: as in conv_igemm, workgroups walk this batch's tiles.
+    int W = gridDim.x;
+    if constexpr (DYN) {
+        a.M = a.dyn[kDynM + a.lvl_out];
+        a.nframes = a.dyn[kDynN];
+        a.uniform = a.dyn[kDynUniform];
+        W = ((a.M + BM - 1) / BM) * ((a.cout + BN - 1) / BN);
+    }
+    for (int tl = blockIdx.x; tl < W; tl += gridDim.x) {
     int m0, n0;
-    tile_origin(a, BM, BN, m0, n0);
+    tile_origin_at(a, BM, BN, tl, W, m0, n0);
     const __amdgpu_buffer_rsrc_t r_in = __builtin_amdgcn_make_buffer_rsrc((void*)a.in, 0, a.in_bytes, kBufFlags);
     const __amdgpu_buffer_rsrc_t r_w = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, a.w_bytes, kBufFlags);
 
@@ -1228,10 +1271,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
         }
         if (kc + L >= nk) break;
     }
-    // no DMA may still be writing LDS when the workgroup ends
+    // no DMA may still be writing LDS when the workgroup ends (or starts its next tile)
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
 
     store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
+    if constexpr (!DYN) break;
+    // every wave is done reading this tile's stages before the next tile's DMAs refill them
+    __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1687,7 +1734,11 @@ __global__ __launch_bounds__(64 * RbCfg<C>::NW) void resblock_kernel(const T* __
                                                        const T* __restrict__ w1, const float* __restrict__ b1,
                                                        const T* __restrict__ w2, const float* __restrict__ b2,
                                                        const int* __restrict__ geom, int nframes, int lvl,
-                                                       int total, int x_bytes) {
+                                                       int total, int x_bytes, const int* __restrict__ dyn) {
+    if (dyn) {  // batch header: frames and tiles of this batch (the grid covers the capacity)
+        nframes = dyn[kDynN];
+        total = dyn[C == 64 ? kDynRb64 : kDynRb128];
+    }
     constexpr int C2 = C / 2, NW = RbCfg<C>::NW;
     constexpr int TY = RbCfg<C>::TY, TX = RbCfg<C>::TX, GA = RbCfg<C>::GA, JB = RbCfg<C>::JB;
     constexpr int WY = TY + 2, WX = TX + 2, NPX = WY * WX;
@@ -1972,7 +2023,7 @@ int resblock_tiles(int C, int h, int w) {
 
 hipError_t launch_resblock(const void* x, void* out, const void* w1, const float* b1, const void* w2,
                            const float* b2, const int* geom, int nframes, int lvl, int C, int tiles, size_t x_bytes,
-                           int et, hipStream_t s) {
+                           int et, hipStream_t s, const int* dyn) {
     if ((C != 64 && C != 128) || (et != kBF16 && et != kF16) || tiles <= 0 || x_bytes >= (size_t)1 << 31 ||
         x == out)
         return hipErrorInvalidValue;
@@ -1981,7 +2032,7 @@ hipError_t launch_resblock(const void* x, void* out, const void* w1, const float
     dim3 grid(g), block(64 * (C == 64 ? RbCfg<64>::NW : RbCfg<128>::NW));
 #define JDE_RB(TT, CC)                                                                                          \
     resblock_kernel<TT, CC><<<grid, block, 0, s>>>((const TT*)x, (TT*)out, (const TT*)w1, b1, (const TT*)w2, b2, \
-                                                   geom, nframes, lvl, tiles, (int)x_bytes)
+                                                   geom, nframes, lvl, tiles, (int)x_bytes, dyn)
     if (et == kBF16) {
         if (C == 64) JDE_RB(bf16, 64); else JDE_RB(bf16, 128);
     } else {
@@ -2024,7 +2075,8 @@ template <> struct PwCfg<512, 256> { static constexpr int BN = 16, G = 2, NBUF =
 template <typename T, int CIN, int COUT>
 __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T* __restrict__ out,
                                                       const T* __restrict__ w, const float* __restrict__ bias, int M,
-                                                      int ld, int act, int x_bytes, int out_bytes) {
+                                                      int ld, int act, int x_bytes, int out_bytes,
+                                                      const int* __restrict__ dyn_m) {
     constexpr int NW = 8, BN = PwCfg<CIN, COUT>::BN, G = PwCfg<CIN, COUT>::G;
     static_assert(NW * G * 16 == COUT, "one wave per 16 G output channels");
     constexpr int KA = CIN / 32, NB = BN / 16;
@@ -2069,9 +2121,12 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
         rel[i] = (L < NSL && sl < XSL) ? (px * CIN + sl * 8) * (int)sizeof(T) : -1;
     }
     const unsigned lbase = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long)(lds_ptr_t)&xw[0]);
-    // this workgroup's pixels [lo, hi) and tiles
+    // this workgroup's pixels [lo, hi) and tiles (with a batch header, M is this
+    // batch's and the grid the capacity's: a workgroup may get no pixels)
+    if (dyn_m) M = *dyn_m;
     const int lo = (int)((long long)blockIdx.x * M / gridDim.x);
     const int hi = (int)((long long)(blockIdx.x + 1) * M / gridDim.x);
+    if (hi <= lo) return;  // uniform over the workgroup, before any load or barrier
     const int nt = (hi - lo + BN - 1) / BN;
     // Load i of tile j into ring slot buf (tile j >= nt: zeros, so that the count
     // per wave stays fixed); waves whose last load index is past the tile's NDMA
@@ -2189,7 +2244,8 @@ static hipError_t launch_pw_t(const ConvArgs& a, hipStream_t s) {
     const int ntiles = (a.M + BN - 1) / BN;
     const int g = ntiles < 256 ? ntiles : 256;  // one workgroup per compute unit (68 KB of LDS)
     conv_pw_stream<T, CIN, COUT><<<dim3(g), dim3(512), 0, s>>>((const T*)a.in, (T*)a.out0, (const T*)a.w, a.bias,
-                                                                a.M, a.ld0, a.act, a.in_bytes, a.M * a.ld0 * 2);
+                                                                a.M, a.ld0, a.act, a.in_bytes, a.M * a.ld0 * 2,
+                                                                a.dyn ? a.dyn + kDynM + a.lvl_out : nullptr);
     return hipGetLastError();
 }
 
@@ -2208,6 +2264,7 @@ static hipError_t launch_pw(const ConvArgs& a, int et, hipStream_t s) {
 // pw = 1: the persistent pointwise kernel (conv_pw_stream; 1x1 convs of 256 -> 128
 // and 512 -> 256 channels only, the other fields unused).
 struct TileCfg { int bm, bn, wgm, wgn, bk, st, nt, pw = 0; };
+constexpr int kDynConvGrid = 1024;  // workgroups of a conv launch in a graph for any batch (4 per CU)
 static constexpr TileCfg kTiles[] = {
     {128, 128, 2, 2, 32, 0, 0},  // 0: 64x64 per wave
     {256, 64, 4, 1, 32, 0, 0},   // 1: 64x64 per wave (Cout 64)
@@ -2322,7 +2379,27 @@ static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
         return hipErrorInvalidValue;
     } else {
         constexpr TileCfg t = kTiles[C];
-        dim3 grid(((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn)), block(64 * t.wgm * t.wgn);
+        const int tiles = ((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn);
+        dim3 block(64 * t.wgm * t.wgn);
+        if (a.dyn) {
+            // a graph for any batch: a.M is the capacity's; at most kDynConvGrid workgroups walk
+            // the batch's tiles (the header's M), so a small batch pays no empty workgroups
+            if constexpr (sizeof(T) == 2) {
+                dim3 grid(tiles < kDynConvGrid ? tiles : kDynConvGrid);
+                if constexpr (t.st > 0)
+                    conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk, true><<<grid, block, 0, s>>>(a);
+                else if (aligned)
+                    conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, true, true><<<grid, block, 0, s>>>(a);
+                else if constexpr (C == 5)
+                    conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, false, true><<<grid, block, 0, s>>>(a);
+                else
+                    return hipErrorInvalidValue;
+                return hipGetLastError();
+            } else {
+                return hipErrorInvalidValue;  // FP32 contexts do not build graphs for any batch
+            }
+        }
+        dim3 grid(tiles);
         if constexpr (t.st > 0)
             conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk><<<grid, block, 0, s>>>(a);
         else if (aligned)

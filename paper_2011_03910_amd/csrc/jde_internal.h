@@ -30,6 +30,18 @@ constexpr int kGeomInts = 14;
 
 enum ElemType { kF32 = 0, kBF16 = 1, kF16 = 2, kFP8 = 3 };
 
+// Batch header in device memory for launches that serve any batch within the
+// capacity (a captured graph replayed for different mixes of frame sizes): the
+// host writes it, with the geometry table, before each replay; grids are sized
+// for the capacity and work past the batch exits.
+constexpr int kDynN = 0;          // frames in the batch
+constexpr int kDynUniform = 1;    // all frames the same size
+constexpr int kDynM = 2;          // [2 + l]: pixels of the batch at level l (l = 0..5)
+constexpr int kDynStemTiles = 8;  // tiles of the fused stem + first downsample
+constexpr int kDynRb64 = 9;       // tiles of the fused 64-channel residual blocks
+constexpr int kDynRb128 = 10;     // tiles of the fused 128-channel residual blocks
+constexpr int kDynInts = 16;
+
 inline size_t elem_bytes(int t) { return t == kF32 ? 4 : (t == kFP8 ? 1 : 2); }
 
 // Arguments of one convolution launch (implicit GEMM: M = output pixels of the
@@ -59,6 +71,8 @@ struct ConvArgs {
     int in_bytes, in2_bytes, w_bytes;  // sizes of the in / in2 / w buffers (< 2^31): loads past them read 0
     int n_major;           // tile order per XCD: 1 = pixel tiles of a channel range (weights dominate)
     unsigned* amax;        // calibration: max |out0| folded in with atomicMax on the float bits, or null
+    const int* dyn;        // batch header (kDyn*): M, nframes, uniform read from it; M above is then the
+                           // capacity the grid was sized for; null = the values above
 };
 
 // Launchers (conv.hip).
@@ -70,14 +84,14 @@ hipError_t launch_conv(const ConvArgs& a, int elem_type, int tile_cfg, hipStream
 // frames -> stride-2 level output; `tiles` = sum over frames of stem_down_tiles(h, w).
 hipError_t launch_stem_down(const float* frames, const int* geom, int nframes, int tiles, const float* w0,
                             const float* b0, const void* w1, const float* b1, void* out, int out_type,
-                            hipStream_t s);
+                            hipStream_t s, const int* dyn = nullptr);
 int stem_down_tiles(int h, int w);
 // Residual block (1x1 C -> C/2, 3x3 C/2 -> C, + x) as one launch, 16-bit storage,
 // C = 64 or 128, all at level lvl; out must not alias x.  `tiles` = sum over
 // frames of resblock_tiles(C, h, w) with the level's frame sizes.
 hipError_t launch_resblock(const void* x, void* out, const void* w1, const float* b1, const void* w2,
                            const float* b2, const int* geom, int nframes, int lvl, int C, int tiles, size_t x_bytes,
-                           int et, hipStream_t s);
+                           int et, hipStream_t s, const int* dyn = nullptr);
 int resblock_tiles(int C, int h, int w);
 // 3x3 stride-1 convolution from an LDS window (16-bit storage): applies when
 // conv3w_ok and every frame's level width is <= kW3MaxW; `pixel_tiles` = sum over
@@ -107,6 +121,7 @@ struct DecodeArgs {
     float anchors[3][4][2];
     float lthr;              // ln(thr / (1 - thr)) in FP32
     const float* logit_offset;  // [nframes] added to every c_fg of the frame, or null
+    const int* dyn;          // batch header: frames >= its kDynN exit; null = all nframes
     int keycap;              // key slots per frame
     unsigned long long* keys;  // [n][keycap]
     int* vals;               // [n][keycap]
@@ -116,6 +131,10 @@ hipError_t launch_decode(const DecodeArgs& a, int max_anchors, hipStream_t s);
 // Writes the batch geometry table and zeroes `ncount` ints (graph-safe: a kernel, no memset).
 struct GeomParams { int n; int hw[kMaxFrames][2]; };
 hipError_t launch_setup(const GeomParams& p, int* geom, int* counters, int ncount, hipStream_t s);
+// The same plus the batch header (host-computed, kDynInts ints) written to dyn.
+struct DynHeader { int v[kDynInts]; };
+hipError_t launch_setup_dyn(const GeomParams& p, const DynHeader& h, int* geom, int* dyn, int* counters,
+                            int ncount, int* counters2, int ncount2, hipStream_t s);
 hipError_t launch_sort(unsigned long long* keys, int* vals, const int* counts, int keycap, int n,
                        hipStream_t s);
 struct GatherArgs {

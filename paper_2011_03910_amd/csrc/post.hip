@@ -51,6 +51,7 @@ __device__ __forceinline__ AnchorLoc locate(unsigned idx, const int* g, int A) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void decode_kernel(DecodeArgs a) {
     const int f = blockIdx.y;
+    if (a.dyn && f >= a.dyn[kDynN]) return;  // grid covers the capacity; frame past this batch
     const int* g = a.geom + f * kGeomInts;
     const int h = g[0], w = g[1];
     const int A = a.A;

@@ -302,6 +302,7 @@ class JDE:
                               max_pixels)
         self.E = emb_dim
         self.cap = max_candidates
+        self.max_frames, self.max_h, self.max_w = max_frames, max_h, max_w
         self.device = torch.device(device)
         self.weights = torch.empty(self.lib.jde_weights_bytes(self.ctx), dtype=torch.uint8, device=self.device)
         self.ws = torch.empty(self.lib.jde_workspace_bytes(self.ctx), dtype=torch.uint8, device=self.device)
@@ -488,6 +489,22 @@ class JDE:
                                          _stream(stream), ctypes.byref(g)), "jde_graph_capture")
         return Graph(self.lib, g, (frames, heads, dets, tracks, cost, tb, logit_offset))
 
+    def graph_capture_any(self, frames, heads, dets, conf_thr=0.5, nms_iou=0.4, stream=None, logit_offset=None):
+        """One graph of forward + decode for any batch within the capacity
+        (jde_graph_capture_any); replay with Graph.launch_batch(descs)."""
+        hs = self._head_struct(heads)
+        ds = self._dets_struct(dets)
+        g = ctypes.c_void_p()
+        check(self.lib.jde_graph_capture_any(self.ctx, _ptr(frames), _ptr(self.ws), self.ws.numel(),
+                                             ctypes.byref(hs), float(conf_thr), float(nms_iou), _ptr(logit_offset),
+                                             ctypes.byref(ds), _stream(stream), ctypes.byref(g)),
+              "jde_graph_capture_any")
+        return Graph(self.lib, g, (frames, heads, dets, logit_offset, self.ws))
+
+    def capacity_descs(self):
+        """The largest batch of the context as frame sizes (for sizing buffers)."""
+        return [(self.max_h, self.max_w)] * self.max_frames
+
     def calibrate(self, frames, descs=None, heads=None, stream=None):
         """FP8 contexts: set the static activation scales from one BF16 forward of this batch."""
         if descs is None:
@@ -543,6 +560,11 @@ class Graph:
         self.lib = lib
         self.h = handle
         self._keep = keep
+
+    def launch_batch(self, descs, stream=None):
+        """Replays a graph of graph_capture_any for the batch `descs` (frame sizes)."""
+        check(self.lib.jde_graph_launch_batch(self.h, _descs(descs), len(descs), _stream(stream)),
+              "jde_graph_launch_batch")
 
     def launch(self, stream=None):
         check(self.lib.jde_graph_launch(self.h, _stream(stream)), "jde_graph_launch")

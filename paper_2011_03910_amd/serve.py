@@ -15,8 +15,10 @@ post-processing (Sec. 4.3).  This module is that pipeline for one GPU:
 * each stream has its own density of objects; its frames carry a confidence
   offset (the library's per-frame logit offset) that sets its candidates per
   frame;
-* each slot owns a library context (workspace, head and detection buffers) and
-  a HIP stream; its forward + decode overlap the other slot's work;
+* each slot owns a library context (workspace, head and detection buffers), a
+  HIP stream and one captured graph of forward + decode that serves any ragged
+  batch of the slot (replayed with the batch's frame table); its work overlaps
+  the other slot's;
 * a post-processing thread takes finished batches in order and, per frame in
   stream order, runs the association (Appendix A items 4-9).  With
   device_assoc (the default) every track's Kalman state and embedding live in
@@ -39,6 +41,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from ._lib import JdeError
 from .jde import (JDE, jde_kf_initiate_n, jde_kf_predict, jde_kf_update_n, jde_assign,
                   jde_track_emb_update, jde_box_to_z, jde_kf_predict_dev, jde_kf_update_dev, jde_assign_dev)
 
@@ -99,7 +102,7 @@ class FrameJob:
 class Server:
     def __init__(self, cfg, anchors, layers, streams, precision="bf16", max_batch=16, hbm_budget=None,
                  max_tracks=512, max_cost=0.7, max_lost=30, conf_thr=0.5, nms_iou=0.4, cap=512, tiles=None,
-                 device="cuda", device_assoc=True, sparse_emb=True):
+                 device="cuda", device_assoc=True, sparse_emb=True, use_graph=True):
         import torch
         self.torch = torch
         self.device_assoc = device_assoc
@@ -155,6 +158,16 @@ class Server:
             # outputs sized for a full batch of the largest frames; smaller batches use a prefix
             sl["heads"] = sl["m"].head_buffers([(max_h, max_w)] * max_batch, emb=not sparse_emb)
             sl["dets"] = sl["m"].dets_buffers(max_batch)
+            # one graph of forward + decode for any ragged batch of the slot (BF16 / FP16 contexts
+            # with the fused stem; others launch eagerly)
+            sl["graph"] = None
+            if use_graph:
+                try:
+                    sl["graph"] = sl["m"].graph_capture_any(sl["dev"], sl["heads"], sl["dets"], conf_thr, nms_iou,
+                                                            stream=sl["stream"], logit_offset=sl["off"])
+                except JdeError:
+                    sl["graph"] = None
+        torch.cuda.synchronize()
         self.lock = threading.Lock()
         self.results = []            # per frame: dict(sid, t, boxes, ids, latency)
         self.cand = {sid: [] for sid in self.streams}   # candidates per frame, per stream
@@ -225,8 +238,11 @@ class Server:
                 off += n
                 descs.append((st.spec.height, st.spec.width))
             sl["off"][:len(jobs)].copy_(offs, non_blocking=True)
-            m.forward(sl["dev"][:off], descs, heads=heads, stream=s)
-            m.decode(heads, descs, self.conf_thr, self.nms_iou, dets=dets, stream=s, logit_offset=sl["off"])
+            if sl["graph"] is not None:
+                sl["graph"].launch_batch(descs, stream=s)
+            else:
+                m.forward(sl["dev"][:off], descs, heads=heads, stream=s)
+                m.decode(heads, descs, self.conf_thr, self.nms_iou, dets=dets, stream=s, logit_offset=sl["off"])
             ev = torch.cuda.Event()
             ev.record(s)
         sl["busy"] = True

@@ -91,3 +91,31 @@ def test_device_association_equals_host_association():
         np.testing.assert_array_equal(dev[k]["ids"], host[k]["ids"])
     _say(f"  {len(keys)} frames: identical boxes and ids; tracks up to "
          f"{max(int(x['ids'].max(initial=0)) for x in dev.values())}")
+
+
+def test_serving_with_graph_replays_equals_eager_launches():
+    """Full network, BF16: the serving loop replaying each slot's any-batch graph
+    gives the same detections and ids as launching forward + decode eagerly."""
+    import torch
+    from jde_inputs import FULL, scene_batch
+    from paper_2011_03910_amd.serve import Server, StreamSpec
+    assert torch.cuda.is_available()
+    _say("case: serve full bf16, graph replays vs eager launches")
+    sizes = {0: (320, 576), 1: (480, 864), 2: (320, 576)}
+
+    def run(use_graph):
+        streams = [StreamSpec(s, h, w, 30.0, 0.0 if s < 2 else 0.01, scene_batch(FULL.seed, 3, h, w, stream=s),
+                              0.3 * s, 0) for s, (h, w) in sizes.items()]
+        srv = Server(FULL, anchors("full"), weights("full", 100), streams, precision="bf16", max_batch=3,
+                     max_tracks=256, cap=512, use_graph=use_graph)
+        assert (srv.slots[0]["graph"] is not None) == use_graph
+        srv.run(0.5)
+        return {(r["sid"], r["t"]): r for r in srv.results}
+
+    g, e = run(True), run(False)
+    keys = sorted(set(g) & set(e))
+    assert len(keys) >= 30
+    for k in keys:
+        np.testing.assert_array_equal(g[k]["boxes"], e[k]["boxes"])
+        np.testing.assert_array_equal(g[k]["ids"], e[k]["ids"])
+    _say(f"  {len(keys)} frames identical, {sum(len(g[k]['ids']) for k in keys)} detections")
