@@ -774,6 +774,61 @@ __device__ __forceinline__ void tile_origin(const ConvArgs& a, int BM, int BN, i
     }
 }
 
+// The batch a conv launch covers: this launch's grid (one tile per workgroup), or,
+// in a graph for any batch (DYN), the pixels, frames and layout of the batch the
+// header describes, whose tiles the workgroups walk.
+struct DynBatch { int tiles, M, nframes, uniform; };
+
+template <bool DYN>
+__device__ __forceinline__ DynBatch dyn_batch(const ConvArgs& a, int BM, int BN) {
+    if constexpr (!DYN) {
+        return {(int)gridDim.x, a.M, a.nframes, a.uniform};
+    } else {
+        const int M = a.dyn[kDynM + a.lvl_out];
+        return {((M + BM - 1) / BM) * ((a.cout + BN - 1) / BN), M, a.dyn[kDynN], a.dyn[kDynUniform]};
+    }
+}
+
+// The arguments of one tile.  DYN: re-read from the kernel-argument segment at each
+// tile through an offset the compiler cannot see is zero, so that they are not
+// hoisted out of the walk and held in registers across it (which spills and costs
+// the kernels a wave per SIMD of occupancy); the explicit arguments start at offset 0.
+template <bool DYN>
+__device__ __forceinline__ ConvArgs tile_args(const ConvArgs& a0, const DynBatch& db) {
+    if constexpr (!DYN) {
+        return a0;
+    } else {
+#if defined(__HIP_DEVICE_COMPILE__)
+        typedef const __attribute__((address_space(4))) char KChar;
+        typedef const __attribute__((address_space(4))) ConvArgs KArgs;
+        int off = 0;
+        asm volatile("" : "+s"(off));
+        ConvArgs a = *(KArgs*)((KChar*)__builtin_amdgcn_kernarg_segment_ptr() + off);
+#else
+        ConvArgs a = a0;  // the host pass only parses device code
+#endif
+        a.M = db.M;
+        a.nframes = db.nframes;
+        a.uniform = db.uniform;
+        return a;
+    }
+}
+
+// The thread's index; DYN: made opaque at each tile for the same reason (values
+// that depend only on the lane would otherwise be computed once and held in vector
+// registers through every tile's K loop).
+// NT: the workgroup's threads (a power of two; masking with it restores the range
+// the opaque copy hides from the compiler).
+template <bool DYN, int NT>
+__device__ __forceinline__ int tile_tid() {
+    int tid = threadIdx.x;
+    if constexpr (DYN) {
+        asm volatile("" : "+v"(tid));
+        tid &= NT - 1;
+    }
+    return tid;
+}
+
 // The same for logical tile L of W = gm * gn tiles (a workgroup walking tiles
 // L = blockIdx.x, + gridDim.x, ... with gridDim.x a multiple of 8 keeps each tile
 // on the XCD the one-tile-per-workgroup order gives it).
@@ -801,7 +856,7 @@ __device__ __forceinline__ void tile_origin_at(const ConvArgs& a, int BM, int BN
 //   Output: lane l holds channels 4(l/16) .. +3 of pixel l%16 of each block.
 // ---------------------------------------------------------------------------
 template <typename T, int BM, int BN, int WGM, int WGN, int BK, bool ALIGNED, bool DYN = false>
-__global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
+__global__ __launch_bounds__(256) void conv_igemm(ConvArgs a0) {
     constexpr int VEC = 16 / sizeof(T);
     constexpr int VR = BK / VEC;
     // Padded LDS row, in elements.  16-bit types: 32 bytes of padding make the
@@ -821,20 +876,16 @@ __global__ __launch_bounds__(256) void conv_igemm(ConvArgs a) {
     __shared__ __attribute__((aligned(16))) T sA[2][BN * LDR];
     __shared__ __attribute__((aligned(16))) T sB[2][BM * LDR];
 
-    const int tid = threadIdx.x;
+    // One tile per workgroup; DYN (a graph serving any batch): this batch's pixels,
+    // frames and layout come from the header, and the resident workgroups walk this
+    // batch's tiles.
+    const DynBatch db = dyn_batch<DYN>(a0, BM, BN);
+    for (int tl = blockIdx.x; tl < db.tiles; tl += gridDim.x) {
+    const ConvArgs a = tile_args<DYN>(a0, db);
+    const int W = db.tiles;
+    const int tid = tile_tid<DYN, 256>();
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
-    // One tile per workgroup; DYN (a graph serving any batch): this batch's pixels,
-    // frames and layout come from the header, and the workgroups (as many as the
-    // capacity needs, at most a few per CU) walk this batch's tiles.
-    int W = gridDim.x;
-    if constexpr (DYN) {
-        a.M = a.dyn[kDynM + a.lvl_out];
-        a.nframes = a.dyn[kDynN];
-        a.uniform = a.dyn[kDynUniform];
-        W = ((a.M + BM - 1) / BM) * ((a.cout + BN - 1) / BN);
-    }
-    for (int tl = blockIdx.x; tl < W; tl += gridDim.x) {
     int m0, n0;
     tile_origin_at(a, BM, BN, tl, W, m0, n0);
     const bool concat = a.cin1 > 0;
@@ -1079,7 +1130,7 @@ __device__ __forceinline__ int lds_swizzle(int r) {
 }
 
 template <typename T, int BM, int BN, int WGM, int WGN, int S, bool NT, int BK, bool DYN = false>
-__global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
+__global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
     constexpr int NW = WGM * WGN;                  // waves (4 or 8)
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
     constexpr int TM = WTM / 16, TN = WTN / 16;
@@ -1097,19 +1148,15 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
     __shared__ __attribute__((aligned(1024))) char st2[SB];
     __shared__ __attribute__((aligned(1024))) char st3[S > 3 ? SB : 16];
 
-    const int tid = threadIdx.x;
+    // One tile per workgroup; DYN: as in conv_igemm, workgroups walk this batch's tiles.
+    const DynBatch db = dyn_batch<DYN>(a0, BM, BN);
+    for (int tl = blockIdx.x; tl < db.tiles; tl += gridDim.x) {
+    const ConvArgs a = tile_args<DYN>(a0, db);
+    const int W = db.tiles;
+    const int tid = tile_tid<DYN, 64 * NW>();
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave % WGM, wn = wave / WGM;
-    // One tile per workgroup; DYN: as in conv_igemm, workgroups walk this batch's tiles.
-    int W = gridDim.x;
-    if constexpr (DYN) {
-        a.M = a.dyn[kDynM + a.lvl_out];
-        a.nframes = a.dyn[kDynN];
-        a.uniform = a.dyn[kDynUniform];
-        W = ((a.M + BM - 1) / BM) * ((a.cout + BN - 1) / BN);
-    }
-    for (int tl = blockIdx.x; tl < W; tl += gridDim.x) {
     int m0, n0;
     tile_origin_at(a, BM, BN, tl, W, m0, n0);
     const __amdgpu_buffer_rsrc_t r_in = __builtin_amdgcn_make_buffer_rsrc((void*)a.in, 0, a.in_bytes, kBufFlags);
@@ -1204,6 +1251,18 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a) {
     // MFMA operands of a chunk are read from LDS into one of two register sets
     // one step ahead, so that the LDS latency hides behind the previous chunk's MFMAs.
     V fa[2][KK][TN], fb[2][KK][TM];
+    if constexpr (DYN) {
+        // The second set is written only when a chunk follows; left undefined at the
+        // first tile, the compiler carries it from tile to tile in registers that stay
+        // live through every epilogue and prologue (an occupancy step on 128 x 128).
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+#pragma unroll
+            for (int j = 0; j < TN; ++j) fa[1][kk][j] = V{};
+#pragma unroll
+            for (int i = 0; i < TM; ++i) fb[1][kk][i] = V{};
+        }
+    }
     auto read = [&](auto st_c, auto fr_c) {
         constexpr int st = decltype(st_c)::value, fr = decltype(fr_c)::value;
         const char* sp = st == 0 ? st0 : st == 1 ? st1 : st == 2 ? st2 : st3;
@@ -2264,7 +2323,23 @@ static hipError_t launch_pw(const ConvArgs& a, int et, hipStream_t s) {
 // pw = 1: the persistent pointwise kernel (conv_pw_stream; 1x1 convs of 256 -> 128
 // and 512 -> 256 channels only, the other fields unused).
 struct TileCfg { int bm, bn, wgm, wgn, bk, st, nt, pw = 0; };
-constexpr int kDynConvGrid = 1024;  // workgroups of a conv launch in a graph for any batch (4 per CU)
+constexpr int kDynConvGrid = 1024;  // fallback grid of a conv launch in a graph for any batch
+
+// Workgroups of kernel `fn` (of `threads` threads) that the device holds at once.
+// A graph for any batch launches exactly that many (never more: a workgroup that
+// only starts after the resident ones finished their whole walk doubles the
+// launch) and lets each walk the batch's tiles.  A multiple of the 8 XCDs, so that
+// a walk keeps each tile on the XCD the one-tile-per-workgroup order gives it.
+static int resident_grid(const void* fn, int threads) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1 ||
+        cus < 1)
+        return kDynConvGrid;
+    const int n = per_cu * cus;
+    return n >= kXCDs ? n - n % kXCDs : n;
+}
 static constexpr TileCfg kTiles[] = {
     {128, 128, 2, 2, 32, 0, 0},  // 0: 64x64 per wave
     {256, 64, 4, 1, 32, 0, 0},   // 1: 64x64 per wave (Cout 64)
@@ -2382,19 +2457,23 @@ static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
         const int tiles = ((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn);
         dim3 block(64 * t.wgm * t.wgn);
         if (a.dyn) {
-            // a graph for any batch: a.M is the capacity's; at most kDynConvGrid workgroups walk
-            // the batch's tiles (the header's M), so a small batch pays no empty workgroups
+            // a graph for any batch: a.M is the capacity's; the resident workgroups (at most
+            // one per tile) walk the batch's tiles (the header's M), so a small batch pays no
+            // empty workgroups
             if constexpr (sizeof(T) == 2) {
-                dim3 grid(tiles < kDynConvGrid ? tiles : kDynConvGrid);
+                auto go = [&](auto kern) {
+                    const int cap = resident_grid(reinterpret_cast<const void*>(kern), (int)block.x);
+                    kern<<<dim3(tiles < cap ? tiles : cap), block, 0, s>>>(a);
+                    return hipGetLastError();
+                };
                 if constexpr (t.st > 0)
-                    conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk, true><<<grid, block, 0, s>>>(a);
+                    return go(conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk, true>);
                 else if (aligned)
-                    conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, true, true><<<grid, block, 0, s>>>(a);
+                    return go(conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, true, true>);
                 else if constexpr (C == 5)
-                    conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, false, true><<<grid, block, 0, s>>>(a);
+                    return go(conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, false, true>);
                 else
                     return hipErrorInvalidValue;
-                return hipGetLastError();
             } else {
                 return hipErrorInvalidValue;  // FP32 contexts do not build graphs for any batch
             }
