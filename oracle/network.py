@@ -115,6 +115,45 @@ def quantize_fp8_per_channel(w):
     return round_fp8(w / sb) * sb, s
 
 
+def e8m0_exponent(amax):
+    """Power-of-two block scale of FP8 with 32-value blocks (the E8M0 scale the
+    matrix cores apply): the smallest integer s with amax / 2^s <= 448, so that the
+    block's largest magnitude lands in e4m3's top binade without saturating; s = 0
+    for an all-zero block; s is kept within the E8M0 range [-127, 127]."""
+    a = np.asarray(amax, dtype=np.float64)
+    pos = a > 0
+    s = np.ceil(np.log2(np.where(pos, a, FP8_MAX) / FP8_MAX))
+    # log2 is inexact near powers of two: settle s with exact power-of-two scalings
+    s = np.where(np.ldexp(np.where(pos, a, 0.0), -s.astype(np.int64)) > FP8_MAX, s + 1, s)
+    s = np.where(np.ldexp(np.where(pos, a, 0.0), -(s - 1).astype(np.int64)) <= FP8_MAX, s - 1, s)
+    s = np.where(pos, s, 0.0)
+    return np.clip(s, -127, 127).astype(np.int64)
+
+
+def quantize_fp8_blocks(x, block=32):
+    """e4m3 with a power-of-two scale per block of ``block`` consecutive values
+    along the last axis: each block b becomes 2^s_b round_fp8(x / 2^s_b) with
+    s_b = e8m0_exponent(max |x_b|).  The last axis must be a multiple of block.
+    Returns the dequantised values (FP64)."""
+    x = np.asarray(x, dtype=np.float64)
+    assert x.shape[-1] % block == 0, x.shape
+    xb = x.reshape(x.shape[:-1] + (x.shape[-1] // block, block))
+    s = e8m0_exponent(np.abs(xb).max(axis=-1))[..., None]
+    return (np.ldexp(round_fp8(np.ldexp(xb, -s)), s)).reshape(x.shape)
+
+
+def quantize_fp8_per_channel_blocks(w, block=32):
+    """FP8 weights with a per-output-channel scale and, inside it, a power-of-two
+    scale per block of 32 along the flattened (r, s, ci) axis of w [Cout, k, k, Cin]:
+    w ~= s_c * 2^s_cb * round_fp8(w / s_c / 2^s_cb), s_c = max|w_c| / 448.
+    Returns (dequantised weights, per-channel scales)."""
+    w = np.asarray(w, dtype=np.float64)
+    amax = np.abs(w.reshape(w.shape[0], -1)).max(axis=1)
+    s = np.where(amax > 0, amax / FP8_MAX, 1.0)
+    flat = w.reshape(w.shape[0], -1) / s[:, None]
+    return (quantize_fp8_blocks(flat, block) * s[:, None]).reshape(w.shape), s
+
+
 class _Walker:
     """Consumes the weight list in blob order (see jde_inputs.weights)."""
 

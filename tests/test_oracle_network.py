@@ -227,3 +227,70 @@ def test_fp8_rounding_model_matches_library_cast_and_format(rng):
     np.testing.assert_allclose(np.abs(wq).reshape(5, -1).max(1)[[0, 1, 3, 4]],
                                np.abs(w).reshape(5, -1).max(1)[[0, 1, 3, 4]], rtol=1e-12)
     assert np.abs(wq - w).max() <= np.abs(w).max() / 16
+
+
+def test_fp8_block_exponent_closed_forms():
+    """The block exponent is the smallest s with max|x| / 2^s <= 448 (e4m3's
+    largest value 1.75 * 2^8): hand-computed cases at and around the boundaries."""
+    e = net.e8m0_exponent
+    assert e(448.0) == 0 and e(np.nextafter(448.0, 0)) == 0
+    assert e(np.nextafter(448.0, 1000)) == 1 and e(449.0) == 1 and e(896.0) == 1
+    assert e(224.0) == -1 and e(224.5) == 0
+    assert e(1.0) == -8          # 1 / 2^-8 = 256 <= 448, 1 / 2^-9 = 512 > 448
+    assert e(1.75) == -8 and e(1.7500001) == -7
+    assert e(0.0) == 0
+    assert e(1e-300) == -127 and e(1e300) == 127        # the E8M0 range
+    a = np.array([3.0, 0.0, 5e-5, 2.0 ** 20])
+    want = [-7, 0, -23, 12]      # 3 / 2^-7 = 384; 5e-5 / 2^-23 = 419.4; 2^20 / 2^12 = 256
+    np.testing.assert_array_equal(e(a), want)
+
+
+def test_fp8_blocks_scale_each_block_on_its_own(rng):
+    """quantize_fp8_blocks: every 32-value block along the last axis gets its own
+    power of two (its largest magnitude lands in (224, 448] before rounding), a
+    block's result does not depend on the other blocks, values 2^s * (e4m3 code)
+    round-trip exactly, zero blocks stay zero, and the error of each value is at
+    most half a unit of e4m3's top binade relative to its block's maximum."""
+    x = rng.standard_normal((3, 5, 128)) * 10.0 ** rng.uniform(-6, 4, (3, 5, 1))
+    x[1, 2, 32:64] = 0.0
+    x[0, 0, 64:96] *= 1e-3                         # one block far below its neighbours
+    q = net.quantize_fp8_blocks(x)
+    xb, qb = x.reshape(3, 5, 4, 32), q.reshape(3, 5, 4, 32)
+    amax = np.abs(xb).max(-1)
+    s = net.e8m0_exponent(amax)
+    nz = amax > 0
+    top = np.ldexp(amax, -s)
+    assert np.all((top[nz] > 224) & (top[nz] <= 448))
+    assert np.all(qb[1, 2, 1] == 0)
+    # a block's quantisation is the same alone as among others
+    alone = net.quantize_fp8_blocks(x[0, 0, 64:96])
+    np.testing.assert_array_equal(alone, q[0, 0, 64:96])
+    # per-value error: <= 2^-4 of the block maximum (half a step of the top binade: 32 / 448 * 2^s ... bounded)
+    err = np.abs(qb - xb).max(-1)
+    assert np.all(err <= amax / 16 + 1e-300)
+    # exact representables round-trip: 2^5 * e4m3 codes
+    codes = np.array([448.0, -1.5, 0.0, 2.0 ** -9, 3.25, 288.0] + [1.0] * 26)
+    np.testing.assert_array_equal(net.quantize_fp8_blocks(codes * 32.0), codes * 32.0)
+    # the per-tensor e4m3 of the scaled-down block would flush it; the block scale keeps it
+    assert np.abs(q[0, 0, 64:96] - x[0, 0, 64:96]).max() <= np.abs(x[0, 0, 64:96]).max() / 16
+
+
+def test_fp8_weights_per_channel_and_block(rng):
+    """quantize_fp8_per_channel_blocks: blocks run along the flattened (r, s, ci)
+    order of each output channel, inside the channel scale max|w_c| / 448."""
+    w = rng.standard_normal((4, 3, 3, 64))
+    w[1] = 0.0
+    w[2, 1, 1, :32] *= 1e-6                        # one 32-k block (tap (1, 1), ci 0..31) tiny
+    wq, sc = net.quantize_fp8_per_channel_blocks(w)
+    assert sc[1] == 1.0 and np.all(wq[1] == 0)
+    np.testing.assert_allclose(sc[[0, 2, 3]], np.abs(w).reshape(4, -1).max(1)[[0, 2, 3]] / 448.0, rtol=1e-15)
+    # the channel's largest weight is exact (it maps to 448)
+    for c in (0, 2, 3):
+        i = np.abs(w[c]).argmax()
+        assert wq[c].flat[i] == w[c].flat[i]
+    # the tiny block keeps its relative precision: error <= 1/16 of its own maximum
+    blk = w[2, 1, 1, :32]
+    assert np.abs(wq[2, 1, 1, :32] - blk).max() <= np.abs(blk).max() / 16
+    # with one scale per channel only, the same block would lose almost everything
+    wq1, _ = net.quantize_fp8_per_channel(w)
+    assert np.abs(wq1[2, 1, 1, :32] - blk).max() > 10 * np.abs(wq[2, 1, 1, :32] - blk).max()
