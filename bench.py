@@ -73,7 +73,7 @@ class Pipeline:
     """Preallocated buffers and one step of the hot path for a fixed batch."""
 
     def __init__(self, precision, batch, layers, torch, tune_frames=None, tiles=None, calib_frames=None,
-                 descs=None, sparse_emb=True):
+                 descs=None, sparse_emb=True, fp8_blocks=True):
         from jde_inputs import FULL, anchors_px
         from paper_2011_03910_amd import JDE
         self.torch = torch
@@ -91,8 +91,12 @@ class Pipeline:
         self.cost = torch.empty((batch * N_TRACKS, self.m.cap), dtype=torch.float32, device="cuda")
         self.tiles = None
         if precision == "fp8":
-            # static activation scales from one BF16 pass over this batch
-            self.m.calibrate(tune_frames if tune_frames is not None else calib_frames, self.descs, heads=self.heads)
+            # per-pixel, per-32-channel activation exponents; or static per-tensor
+            # activation scales from one BF16 pass over this batch
+            self.m.fp8_block_scales(fp8_blocks)
+            if not fp8_blocks:
+                self.m.calibrate(tune_frames if tune_frames is not None else calib_frames, self.descs,
+                                 heads=self.heads)
         if tiles is not None:
             self.m.set_tiles(tiles)
             self.tiles = self.m.tiles()
@@ -413,10 +417,11 @@ def association_bench(pipe, inputs, torch, reps=20):
             "pairs_kept": int(out["kept"][:pipe.batch].sum().item()), "assign_single_frame": big}
 
 
-def quick_fps(precision, batch, layers, inputs, torch, tiles, steps=10, warmup=3, descs=None, sparse_emb=True):
+def quick_fps(precision, batch, layers, inputs, torch, tiles, steps=10, warmup=3, descs=None, sparse_emb=True,
+              fp8_blocks=True):
     """frames/s of the graph-replayed step for one configuration (no per-launch events)."""
     pipe = Pipeline(precision, batch, layers, torch, None, tiles, calib_frames=inputs[0], descs=descs,
-                    sparse_emb=sparse_emb)
+                    sparse_emb=sparse_emb, fp8_blocks=fp8_blocks)
     pipe.capture(*inputs)
     wall, step_ms, _ = run(pipe, inputs, steps, warmup, torch, graph=True)
     ncand = pipe.dets["n_cand"][:batch].cpu().numpy()
@@ -734,13 +739,16 @@ def main():
         del p_
         torch.cuda.empty_cache()
         prec = {}
-        for pr in ("fp16", "fp8"):
-            r, p_ = quick_fps(pr, args.batch, layers, inputs_b, torch, tiles16 if pr == "fp16" else None)
+        prec_heads8 = {}
+        for pr in ("fp16", "fp8", "fp8_per_tensor"):
+            base = "fp8" if pr.startswith("fp8") else pr
+            r, p_ = quick_fps(base, args.batch, layers, inputs_b, torch, tiles16 if pr == "fp16" else None,
+                              fp8_blocks=pr == "fp8")
             hd = ({k: [None if h is None else h.clone() for h in v] for k, v in p_.heads.items()}, frame0_dets(p_))
             if pr == "fp16":
                 fp16_heads0 = hd
             else:
-                prec_heads8 = hd
+                prec_heads8[pr] = hd
             prec[pr] = r
             del p_
             torch.cuda.empty_cache()
@@ -777,7 +785,8 @@ def main():
         rows = [(args.precision, heads0, boxes0)]
         if fp16_heads0 is not None:
             rows.append(("fp16", fp16_heads0[0], fp16_heads0[1]))
-            rows.append(("fp8", prec_heads8[0], prec_heads8[1]))
+            for name8, hd8 in prec_heads8.items():
+                rows.append((name8, hd8[0], hd8[1]))
         for name, hd, (bx, be) in rows:
             errs, _ = accuracy(hd, [(FULL.height, FULL.width)] * args.batch, ref)
             frac, cos = match_frac(bx, r["boxes"], r["score"], emb=(be, r["emb"]))

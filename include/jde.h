@@ -52,9 +52,9 @@ typedef enum {
 
 /* Arithmetic of the convolutions (Sec. 4.1 runs the model in mixed precision).
  * Accumulation is FP32 in every mode; head outputs, decode and normalisation
- * stay FP32.  JDE_FP8 runs the backbone convolutions in OCP FP8 e4m3 with
- * per-output-channel weight scales and per-tensor activation scales, and the
- * neck/heads in BF16. */
+ * stay FP32.  JDE_FP8 runs the backbone 3x3 convolutions in OCP FP8 e4m3 with
+ * per-channel and per-32-k-block weight scales and per-32-channel activation
+ * scales (see jde_fp8_block_scales), and the rest in BF16. */
 typedef enum { JDE_FP32 = 0, JDE_BF16 = 1, JDE_FP16 = 2, JDE_FP8 = 3 } jde_precision;
 
 typedef struct {
@@ -195,15 +195,23 @@ jde_status jde_autotune(jde_ctx* ctx, const float* d_frames, const jde_frame_des
  * streamed through LDS; same summation order as the implicit GEMM). */
 jde_status jde_tiles(jde_ctx* ctx, int* tiles, int n_ops, int set);
 
-/* FP8 calibration (mixed precision, Sec. 4.1, taken to the e4m3 format of
- * gfx950).  In a JDE_FP8 context the backbone convolutions whose Cin is a
- * multiple of 128 run on e4m3 operands: weights with a per-output-channel
- * scale max|w_c| / 448, input activations (stored BF16) with a static
- * per-tensor scale.  This call runs one BF16 forward of the given batch,
- * records the largest |value| each convolution writes, and sets every FP8
- * launch's input scale to that of its producer / 448.  Arguments as for
- * jde_forward; blocks until done.  Until it has run, jde_forward of a JDE_FP8
- * context returns JDE_ESTATE; jde_load_weights resets it. */
+/* FP8 scaling (mixed precision, Sec. 4.1, taken to the e4m3 format of gfx950).
+ * In a JDE_FP8 context the backbone 3x3 convolutions whose Cin is a multiple of
+ * 128 run on e4m3 operands, and every 32 consecutive k of a row carry a power-of-two
+ * (E8M0) scale that the matrix core applies: weights have a per-output-channel
+ * scale max|w_c| / 448 and, inside it, one exponent per 32-k block (set by
+ * jde_load_weights).  Input activations (stored BF16) are converted when staged:
+ * with on != 0 (the default) each pixel's 32-channel block gets the smallest
+ * power of two 2^s with max|x| / 2^s <= 448; with on = 0 one static per-tensor
+ * scale from jde_calibrate serves the whole tensor.  JDE_EUNSUPPORTED outside a
+ * JDE_FP8 context. */
+jde_status jde_fp8_block_scales(jde_ctx* ctx, int on);
+/* FP8 calibration for per-tensor activation scales (jde_fp8_block_scales off).
+ * Runs one BF16 forward of the given batch, records the largest |value| each
+ * convolution writes, and sets every FP8 launch's input scale to that of its
+ * producer / 448.  Arguments as for jde_forward; blocks until done.  With block
+ * scales off and before this has run, jde_forward of a JDE_FP8 context returns
+ * JDE_ESTATE; jde_load_weights resets it. */
 jde_status jde_calibrate(jde_ctx* ctx, const float* d_frames, const jde_frame_desc* descs, int n,
                          void* d_ws, size_t ws_bytes, const jde_head_out* out, void* stream);
 /* Input scale of every forward launch (0 for launches that do not run in FP8);

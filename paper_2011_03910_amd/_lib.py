@@ -107,6 +107,7 @@ SIGNATURES = {
                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(JdeHeadOut), ctypes.c_void_p]),
     "jde_fp8_scales": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int]),
     "jde_fuse_stem": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "jde_fp8_block_scales": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_fuse_blocks": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_window_convs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_sparse_emb": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),

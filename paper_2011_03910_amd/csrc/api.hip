@@ -60,6 +60,7 @@ struct Op {
     int tile;                // tile configuration (-1: default)
     int fp8;                 // runs as an FP8 e4m3 convolution once calibrated
     size_t dev_w8, dev_ws;   // FP8 weights [Cout][K] and their per-channel scales
+    size_t dev_wbs;          // FP8: E8M0 exponent per output channel and 32-k block [Cout][K/32]
     float in_scale;          // per-tensor scale of the input activations (calibrated)
     int producer;            // op whose output this op reads (-1: the stem or none)
     int tile8;               // FP8 tile configuration
@@ -91,6 +92,7 @@ struct jde_ctx {
     bool loaded = false;
     int n_backbone_ops = 0;
     bool fp8 = false, fp8_ready = false, calibrating = false;
+    bool fp8_blocks = true;   // FP8 activations with an E8M0 scale per pixel and 32 channels
     // The stem and the first downsample conv run as one launch (16-bit storage),
     // and so do the two convs of each 64- and 128-channel residual block.
     // launch_kind[i] records how op i ran in the latest forward: 0 = its own
@@ -313,8 +315,10 @@ void plan_fp8(jde_ctx* c) {
                 o.producer = j;
                 break;
             }
-        o.fp8 = c->fp8 && o.kind == OP_CONV && i < c->n_backbone_ops && o.cin % 128 == 0 && o.cin1 == 0 &&
-                o.producer >= 0;
+        // FP8 where the matrix cores bound the conv: the backbone's 3x3 convs (the 1x1
+        // convs move 2-3 FLOP per byte of BF16 activations, which FP8 operands do not cut)
+        o.fp8 = c->fp8 && o.kind == OP_CONV && i < c->n_backbone_ops && o.ksz == 3 && o.cin % 128 == 0 &&
+                o.cin1 == 0 && o.producer >= 0;
     }
 }
 
@@ -333,6 +337,8 @@ void plan_weights(jde_ctx* c) {
             off = align256(off + (size_t)o.cout * K);
             o.dev_ws = off;
             off = align256(off + (size_t)o.cout * 4);
+            o.dev_wbs = off;
+            off = align256(off + (size_t)o.cout * (K / 32));
         }
     }
     c->weights_bytes = off;
@@ -402,6 +408,12 @@ GeomParams geom_params(const jde_frame_desc* d, int n) {
     return p;
 }
 
+// An FP8 op runs on e4m3 operands once its activation scales are known: always
+// with per-block activation scales, after calibration with per-tensor ones.
+bool runs_fp8(const jde_ctx* c, const Op& o) {
+    return o.fp8 && !c->calibrating && (c->fp8_blocks || c->fp8_ready);
+}
+
 // Arguments of conv op `o` for a batch (d, n) with workspace W and head outputs `out`.
 ConvArgs conv_args(const jde_ctx* c, const Op& o, const jde_frame_desc* d, int n, bool uniform, char* W,
                    const int* geom, const jde_head_out* out, int op_index = -1) {
@@ -448,17 +460,19 @@ ConvArgs conv_args(const jde_ctx* c, const Op& o, const jde_frame_desc* d, int n
         a.out1 = out->emb[o.emb_out];
         a.ld1 = o.cout - o.n_split;
     }
-    if (o.fp8 && c->fp8_ready && !c->calibrating) {
+    if (runs_fp8(c, o)) {
         a.w = wb + o.dev_w8;
         a.wscale = (const float*)(wb + o.dev_ws);
-        a.in_scale = o.in_scale;
+        a.wbscale = (const unsigned char*)(wb + o.dev_wbs);
+        a.act_blocks = c->fp8_blocks ? 1 : 0;
+        a.in_scale = c->fp8_blocks ? 1.f : o.in_scale;
         a.w_bytes = o.cout * a.K;
     }
     if (c->calibrating && op_index >= 0) a.amax = (unsigned*)(W + c->ws_amax) + op_index;
     return a;
 }
 
-bool runs_fp8(const jde_ctx* c, const Op& o) { return o.fp8 && c->fp8_ready && !c->calibrating; }
+
 
 // The stem (3 -> 32) and the stage-1 downsample conv (3x3 stride 2, 32 -> 64) run
 // fused for 16-bit storage, except while calibrating (the fused launch records
@@ -535,6 +549,16 @@ uint16_t f32_to_bf16_rne(float x) {
 }
 // OCP FP8 e4m3 (bias 7, 3 mantissa bits, no infinities, max 448), round to
 // nearest even, saturating at +-448; NaN -> 0x7f.
+// E8M0 exponent byte (127 + s) of the smallest 2^s with m / 2^s <= 448 (m >= 0,
+// 127 for m = 0); the device conversion of activation blocks computes the same.
+int e8m0_for_amax_host(float m) {
+    if (!(m > 0.f)) return 127;
+    int E;
+    const float f = 2.f * frexpf(m, &E);   // m = f * 2^(E - 1), f in [1, 2)
+    const int e = 127 + (E - 1) - 8 + (f > 1.75f ? 1 : 0);
+    return e < 0 ? 0 : (e > 254 ? 254 : e);
+}
+
 uint8_t f32_to_e4m3(float x) {
     if (x != x) return 0x7f;
     const uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
@@ -809,12 +833,23 @@ jde_status jde_load_weights(jde_ctx* c, const float* blob, size_t nf, void* d_we
                 }
                 memcpy(host.data() + o.dev_b + row * 4, &b[co], 4);
                 if (o.fp8) {
+                    // w = sc * 2^(e_b - 127) * q: sc = max |w_c| / 448 per channel, then per
+                    // 32-k block b the E8M0 exponent e_b that brings the block's max |w / sc|
+                    // to at most 448 (e_b <= 127: blocks below the channel's range are
+                    // scaled up into e4m3's normal range).
                     float amax = 0.f;
                     for (int k = 0; k < K; ++k) amax = std::max(amax, fabsf(w[(size_t)co * K + k]));
                     const float sc = amax > 0.f ? amax / 448.f : 1.f;
                     memcpy(host.data() + o.dev_ws + row * 4, &sc, 4);
-                    for (int k = 0; k < K; ++k)
-                        host[o.dev_w8 + row * K + k] = f32_to_e4m3(w[(size_t)co * K + k] / sc);
+                    for (int kb = 0; kb < K / 32; ++kb) {
+                        float bm = 0.f;
+                        for (int k = 32 * kb; k < 32 * kb + 32; ++k)
+                            bm = std::max(bm, fabsf(w[(size_t)co * K + k] / sc));
+                        const int e = e8m0_for_amax_host(bm);
+                        host[o.dev_wbs + row * (K / 32) + kb] = (unsigned char)e;
+                        for (int k = 32 * kb; k < 32 * kb + 32; ++k)
+                            host[o.dev_w8 + row * K + k] = f32_to_e4m3(ldexpf(w[(size_t)co * K + k] / sc, 127 - e));
+                    }
                 }
             }
         }
@@ -836,7 +871,8 @@ static jde_status forward_impl(jde_ctx* c, const float* frames, const jde_frame_
                                size_t wsb, const jde_head_out* out, void* stream, bool dynamic) {
     if (!c || !frames || !ws || !out) return fail(JDE_EINVAL, "null argument");
     if (!c->loaded) return fail(JDE_ESTATE, "weights not loaded");
-    if (c->fp8 && !c->fp8_ready && !c->calibrating) return fail(JDE_ESTATE, "FP8 context not calibrated");
+    if (c->fp8 && !c->fp8_blocks && !c->fp8_ready && !c->calibrating)
+        return fail(JDE_ESTATE, "FP8 context with per-tensor activation scales not calibrated");
     if (wsb < c->ws_total) return fail(JDE_ENOMEM, "workspace %zu < %zu bytes", wsb, c->ws_total);
     for (int s = 0; s < 3; ++s)
         if (!out->det[s] || (!c->sparse_emb && !out->emb[s])) return fail(JDE_EINVAL, "null head output %d", s);
@@ -1399,6 +1435,13 @@ jde_status jde_calibrate(jde_ctx* c, const float* frames, const jde_frame_desc* 
         o.in_scale = m > 0.f ? m / 448.f : 1.f;
     }
     c->fp8_ready = true;
+    return JDE_OK;
+}
+
+jde_status jde_fp8_block_scales(jde_ctx* c, int on) {
+    if (!c) return fail(JDE_EINVAL, "null context");
+    if (!c->fp8) return fail(JDE_EUNSUPPORTED, "block scales apply to FP8 contexts");
+    c->fp8_blocks = on != 0;
     return JDE_OK;
 }
 

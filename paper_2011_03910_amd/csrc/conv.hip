@@ -1541,16 +1541,38 @@ hipError_t launch_conv3w(const ConvArgs& a, int et, int pixel_tiles, hipStream_t
 
 // ---------------------------------------------------------------------------
 // FP8 (OCP e4m3) implicit GEMM for the deep backbone convolutions.
-//   K chunks of 128 = one v_mfma_scale_f32_16x16x128_f8f6f4 (unit block scales)
-//   per 16x16 output block; each lane feeds 32 consecutive k of its row (two
-//   16-byte LDS reads per operand).  Activations stay BF16 in HBM: the B loader
+//   K chunks of 128 = one v_mfma_scale_f32_16x16x128_f8f6f4 per 16x16 output
+//   block; each lane feeds 32 k of its row (two 16-byte LDS reads per operand,
+//   placed so that every 32 consecutive k of the chunk fall in the block whose
+//   E8M0 exponent one lane group passes; the matrix core applies it to the
+//   products).
+//   Weights are e4m3 in HBM with a per-output-channel FP32 scale (max |w_c| / 448)
+//   and, within it, an E8M0 exponent per 32-k block ([Cout][K/32] bytes), staged
+//   through LDS beside the chunk.  Activations stay BF16 in HBM: the B loader
 //   fetches 8 channels (16 bytes) per buffer load and, when staging to LDS,
-//   converts them to e4m3 as round(clamp(x / in_scale, +-448)).  Weights are
-//   e4m3 in HBM with a per-output-channel scale; the epilogue multiplies the
-//   FP32 accumulator by wscale[co] * in_scale.  Requires Cin % 128 == 0 (every
-//   chunk lies within one tap) and no concat input.
+//   converts them to e4m3.  BLK (the default): the four lanes that hold a
+//   pixel's 32 channels of the chunk take their max |x| (a DPP exchange within
+//   the quad), set the block's exponent to the smallest s with max |x| / 2^s
+//   <= 448 and store x / 2^s (exact) rounded to e4m3; the exponent goes to LDS
+//   beside the pixel row.  !BLK: a static per-tensor scale from calibration,
+//   round(clamp(x / in_scale, +-448)), and unit activation exponents.  The
+//   epilogue multiplies the FP32 accumulator by wscale[co] * in_scale (in_scale
+//   is 1 with block scales).  Requires Cin % 128 == 0 (every chunk lies within
+//   one tap) and no concat input.
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int WGM, int WGN>
+// E8M0 exponent byte (127 + s) of the smallest power of two 2^s with m / 2^s <= 448
+// (the largest e4m3 value, 1.75 * 2^8), for m = max |x| >= 0 of a block: with
+// m = f * 2^E, f in [1, 2), s = E - 8 when f <= 1.75, else E - 7.  0 for m = 0.
+__device__ __forceinline__ int e8m0_for_amax(float m) {
+    const unsigned b = __float_as_uint(m);
+    if (m == 0.f) return 127;
+    const int eb = (int)(b >> 23) & 0xff;   // biased exponent (m is finite and >= 0)
+    const int mant = (int)(b & 0x7fffff);
+    const int e = eb - 8 + (mant > 0x600000 ? 1 : 0);
+    return e < 0 ? 0 : (e > 254 ? 254 : e);
+}
+
+template <int BM, int BN, int WGM, int WGN, bool BLK>
 __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
     constexpr int BK = 128;                  // fp8 elements (bytes) per chunk
     constexpr int LDR = BK + 16;             // padded LDS row, bytes
@@ -1566,6 +1588,10 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
 
     __shared__ __attribute__((aligned(16))) unsigned char sA[2][BN * LDR];
     __shared__ __attribute__((aligned(16))) unsigned char sB[2][BM * LDR];
+    // E8M0 exponents of the chunk: 4 bytes (the chunk's four 32-k blocks) per row
+    __shared__ __attribute__((aligned(16))) unsigned sAs[2][BN];
+    __shared__ __attribute__((aligned(16))) unsigned sBs[2][BLK ? BM : 1];
+    static_assert(BN <= 256, "one weight-scale dword per thread");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -1587,7 +1613,12 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
     }
     const __amdgpu_buffer_rsrc_t r_in = __builtin_amdgcn_make_buffer_rsrc((void*)a.in, 0, a.in_bytes, kBufFlags);
     const __amdgpu_buffer_rsrc_t r_w = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, a.w_bytes, kBufFlags);
+    const int kb_row = a.K / 32;   // weight-scale bytes per output channel
+    const __amdgpu_buffer_rsrc_t r_ws =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.wbscale, 0, a.cout * kb_row, kBufFlags);
     const float inv_scale = 1.0f / a.in_scale;
+    // this thread's weight-scale row (thread t < BN stages row n0 + t's 4 bytes per chunk)
+    const int ws_off = (tid < BN && n0 + tid < a.cout) ? (n0 + tid) * kb_row : -1;
 
     int b_off[BPT], b_yx[BPT], b_hw[BPT];
 #pragma unroll
@@ -1619,11 +1650,13 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
 
     int ld_ci = 0, ld_r = 0, ld_s = 0;
     i32x4 ra2[2][APT], rb2[2][BPT];
-    auto load_chunk = [&](int kc, i32x4 (&ra)[APT], i32x4 (&rb)[BPT]) {
+    unsigned rs2[2];
+    auto load_chunk = [&](int kc, i32x4 (&ra)[APT], i32x4 (&rb)[BPT], unsigned& rs) {
         const int k0 = kc * BK;
 #pragma unroll
         for (int i = 0; i < APT; ++i)
             ra[i] = __builtin_amdgcn_raw_buffer_load_b128(r_w, a_off[i] >= 0 ? a_off[i] + k0 : kOOB, 0, 0);
+        rs = (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r_ws, ws_off >= 0 ? ws_off + kc * 4 : kOOB, 0, 0);
 #pragma unroll
         for (int i = 0; i < BPT; ++i) {
             const int iy = (b_yx[i] >> 16) + ld_r, ix = (int)(short)(b_yx[i] & 0xffff) + ld_s;
@@ -1640,16 +1673,31 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
         ld_s = wrap2 ? 0 : ld_s;
         ld_r += wrap2;
     };
-    // 8 BF16 values -> 8 e4m3 bytes (two dwords), scaled and saturated.
-    auto to_fp8 = [&](i32x4 v) {
+    // 8 BF16 values -> 8 e4m3 bytes (two dwords), scaled and saturated.  BLK: every
+    // lane of the quad that holds one pixel's 32-channel block computes the block's
+    // exponent (returned in *e8) and scales by it exactly.
+    auto to_fp8 = [&](i32x4 v, int* e8) {
         float f[8];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             f[2 * q] = __uint_as_float(((unsigned)v[q]) << 16);
             f[2 * q + 1] = __uint_as_float(((unsigned)v[q]) & 0xffff0000u);
         }
+        if constexpr (BLK) {
+            float m = 0.f;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) f[q] = fminf(fmaxf(f[q] * inv_scale, -448.f), 448.f);
+            for (int q = 0; q < 8; ++q) m = fmaxf(m, fabsf(f[q]));
+            // max over the quad (lanes 4j .. 4j+3 of the wave hold one block)
+            m = fmaxf(m, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(m), 0xB1, 0xF, 0xF, true)));
+            m = fmaxf(m, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(m), 0x4E, 0xF, 0xF, true)));
+            const int e = e8m0_for_amax(m);
+            *e8 = e;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) f[q] = fminf(fmaxf(__builtin_amdgcn_ldexpf(f[q], 127 - e), -448.f), 448.f);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) f[q] = fminf(fmaxf(f[q] * inv_scale, -448.f), 448.f);
+        }
         int lo = 0, hi = 0;
         lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[0], f[1], lo, false);
         lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[2], f[3], lo, true);
@@ -1657,16 +1705,24 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
         hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[6], f[7], hi, true);
         return i32x2{lo, hi};
     };
-    auto store_chunk = [&](int buf, const i32x4 (&ra)[APT], const i32x4 (&rb)[BPT]) {
+    static_assert(BVEC % 256 == 0, "every lane converts: the quad exchange needs all four lanes");
+    auto store_chunk = [&](int buf, const i32x4 (&ra)[APT], const i32x4 (&rb)[BPT], unsigned rs) {
 #pragma unroll
         for (int i = 0; i < APT; ++i) {
             const int v = tid + i * 256;
             if (AVEC % 256 == 0 || v < AVEC) *(i32x4*)(&sA[buf][(v / VRA) * LDR + (v % VRA) * 16]) = ra[i];
         }
+        if (tid < BN) sAs[buf][tid] = rs;
 #pragma unroll
         for (int i = 0; i < BPT; ++i) {
             const int v = tid + i * 256;
-            if (BVEC % 256 == 0 || v < BVEC) *(i32x2*)(&sB[buf][(v / VRB) * LDR + (v % VRB) * 8]) = to_fp8(rb[i]);
+            int e8 = 127;
+            const i32x2 q = to_fp8(rb[i], &e8);
+            *(i32x2*)(&sB[buf][(v / VRB) * LDR + (v % VRB) * 8]) = q;
+            if constexpr (BLK) {
+                // lane 4j of the quad writes the block's exponent: row v / VRB, block (v % VRB) / 4
+                if ((v & 3) == 0) ((unsigned char*)sBs[buf])[(v / VRB) * 4 + (v % VRB) / 4] = (unsigned char)e8;
+            }
         }
     };
 
@@ -1676,41 +1732,54 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int arow = wn * WTN + (lane & 15), brow = wm * WTM + (lane & 15);
-    const int kofs = (lane >> 4) * 32;
+    // The matrix core takes a lane's 32 bytes as two 16-value halves: lane group g
+    // (lane / 16) supplies k = 16 g .. 16 g + 15 in bytes 0-15 and k = 64 + 16 g ..
+    // in bytes 16-31, and the block scale of lane group b covers k = 32 b .. 32 b +
+    // 31 (groups 2 (b % 2) and 2 (b % 2) + 1, half b / 2).  Reading the chunk's
+    // bytes 16 g and 64 + 16 g puts chunk k = 32 b .. 32 b + 31 -- one weight or
+    // activation scale block -- exactly where lane group b's scale applies.
+    const int kofs = (lane >> 4) * 16;
+    const int kblk = lane >> 4;   // the 32-k block this lane feeds
     auto compute = [&](int buf) {
         const unsigned char* A = sA[buf];
         const unsigned char* B = sB[buf];
         i32x8 af[TN], bfr[TM];
+        int sa[TN], sb[TM];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) sa[j] = ((const unsigned char*)sAs[buf])[(arow + j * 16) * 4 + kblk];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+            sb[i] = BLK ? ((const unsigned char*)sBs[buf])[(brow + i * 16) * 4 + kblk] : 127;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
             const unsigned char* p = A + (arow + j * 16) * LDR + kofs;
-            const i32x4 x0 = *(const i32x4*)p, x1 = *(const i32x4*)(p + 16);
+            const i32x4 x0 = *(const i32x4*)p, x1 = *(const i32x4*)(p + 64);
             af[j] = i32x8{x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
         }
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
             const unsigned char* p = B + (brow + i * 16) * LDR + kofs;
-            const i32x4 x0 = *(const i32x4*)p, x1 = *(const i32x4*)(p + 16);
+            const i32x4 x0 = *(const i32x4*)p, x1 = *(const i32x4*)(p + 64);
             bfr[i] = i32x8{x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
         }
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[j], bfr[i], acc[i][j], 0, 0, 0, 127,
-                                                                             0, 127);
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[j], bfr[i], acc[i][j], 0, 0, 0,
+                                                                             sa[j], 0, sb[i]);
     };
 
     const int nk = a.K / BK;
-    load_chunk(0, ra2[0], rb2[0]);
-    load_chunk(1, ra2[1], rb2[1]);
-    store_chunk(0, ra2[0], rb2[0]);
-    load_chunk(2, ra2[0], rb2[0]);
+    load_chunk(0, ra2[0], rb2[0], rs2[0]);
+    load_chunk(1, ra2[1], rb2[1], rs2[1]);
+    store_chunk(0, ra2[0], rb2[0], rs2[0]);
+    load_chunk(2, ra2[0], rb2[0], rs2[0]);
     __syncthreads();
     auto iter = [&](int kc, auto cur_c) {
         constexpr int cur = decltype(cur_c)::value;
-        store_chunk(cur ^ 1, ra2[cur ^ 1], rb2[cur ^ 1]);
-        load_chunk(kc + 3, ra2[cur ^ 1], rb2[cur ^ 1]);
+        store_chunk(cur ^ 1, ra2[cur ^ 1], rb2[cur ^ 1], rs2[cur ^ 1]);
+        load_chunk(kc + 3, ra2[cur ^ 1], rb2[cur ^ 1], rs2[cur ^ 1]);
         compute(cur);
         __syncthreads();
     };
@@ -1737,12 +1806,15 @@ template <int C>
 static hipError_t launch_f8(const ConvArgs& a, hipStream_t s) {
     constexpr TileCfg8 t = kTiles8[C];
     dim3 grid(((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn));
-    conv_igemm_f8<t.bm, t.bn, t.wgm, t.wgn><<<grid, 256, 0, s>>>(a);
+    if (a.act_blocks)
+        conv_igemm_f8<t.bm, t.bn, t.wgm, t.wgn, true><<<grid, 256, 0, s>>>(a);
+    else
+        conv_igemm_f8<t.bm, t.bn, t.wgm, t.wgn, false><<<grid, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_conv_fp8(const ConvArgs& a, int c, hipStream_t s) {
-    if (!conv_fp8_ok(a) || !a.wscale || !(a.in_scale > 0.f)) return hipErrorInvalidValue;
+    if (!conv_fp8_ok(a) || !a.wscale || !a.wbscale || !(a.in_scale > 0.f)) return hipErrorInvalidValue;
     switch (c) {
         case 0: return launch_f8<0>(a, s);
         case 1: return launch_f8<1>(a, s);

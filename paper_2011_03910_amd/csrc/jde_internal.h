@@ -52,6 +52,7 @@ struct ConvArgs {
     const void* w;         // [Cout][k][k][Cin]
     const float* bias;     // [Cout]
     const float* wscale;   // FP8: per-output-channel weight dequantisation scale, else null
+    const unsigned char* wbscale;  // FP8: E8M0 exponent per output channel and 32-k block [Cout][K/32]
     const void* res;       // residual [M][Cout] (same type as out0), or null
     void* out0;            // [M][ld0], columns [0, n_split)
     float* out1;           // [M][ld1] FP32, columns [n_split, Cout) (linear), or null
@@ -67,7 +68,9 @@ struct ConvArgs {
     int ld0, ld1;
     int act;               // leaky ReLU 0.1 on out0 columns
     int out0_f32;          // out0 holds FP32 (head outputs) instead of the activation type
-    float in_scale;        // FP8: per-tensor scale of the input activations (x ~= in_scale * q)
+    float in_scale;        // FP8: per-tensor scale of the input activations (x ~= in_scale * q);
+                           // 1 with act_blocks
+    int act_blocks;        // FP8: input activations take an E8M0 scale per pixel and 32 channels
     int in_bytes, in2_bytes, w_bytes;  // sizes of the in / in2 / w buffers (< 2^31): loads past them read 0
     int n_major;           // tile order per XCD: 1 = pixel tiles of a channel range (weights dominate)
     unsigned* amax;        // calibration: max |out0| folded in with atomicMax on the float bits, or null

@@ -505,8 +505,14 @@ class JDE:
         """The largest batch of the context as frame sizes (for sizing buffers)."""
         return [(self.max_h, self.max_w)] * self.max_frames
 
+    def fp8_block_scales(self, on=True):
+        """FP8 contexts: per-pixel, per-32-channel E8M0 activation scales (on, the
+        default) or static per-tensor scales from ``calibrate`` (off)."""
+        check(self.lib.jde_fp8_block_scales(self.ctx, int(bool(on))), "jde_fp8_block_scales")
+
     def calibrate(self, frames, descs=None, heads=None, stream=None):
-        """FP8 contexts: set the static activation scales from one BF16 forward of this batch."""
+        """FP8 contexts: set the static per-tensor activation scales (used with block
+        scales off) from one BF16 forward of this batch."""
         if descs is None:
             n, _, H, W = frames.shape
             descs = [(H, W)] * n

@@ -109,20 +109,23 @@ def oracle_forward_rounded(cfg_name, k, n, fmt):
 
 
 def fp8_layer_set(cfg):
-    """Convs that run in FP8: backbone convs (after the stem) whose Cin % 128 == 0."""
+    """Convs that run in FP8: backbone 3x3 convs (after the stem) whose Cin % 128 == 0."""
     from jde_inputs import weight_specs
     n_backbone = 1 + 5 + 2 * sum(cfg.blocks)
     specs = weight_specs(cfg)
-    return {i for i in range(1, n_backbone) if specs[i][3] % 128 == 0}
+    return {i for i in range(1, n_backbone) if specs[i][2] == 3 and specs[i][3] % 128 == 0}
 
 
 @functools.lru_cache(maxsize=None)
-def oracle_forward_fp8(cfg_name, k, n):
-    """Oracle forward of the FP8 network: BF16 storage and weights, and for each FP8
-    conv per-channel e4m3 weights and an e4m3 input with a static scale (max |x|
-    of that input in the BF16 network on the same frames, / 448).
-    Returns (outputs, {conv index: input scale})."""
-    from oracle.network import forward, round_bf16, round_fp8, quantize_fp8_per_channel
+def oracle_forward_fp8(cfg_name, k, n, blocks=True):
+    """Oracle forward of the FP8 network (a diagnostic: no test bound comes from it):
+    BF16 storage and weights, and for each FP8 conv e4m3 weights with a per-channel
+    scale and a power-of-two scale per 32-k block, and an e4m3 input with
+    (blocks) a power-of-two scale per pixel and 32 channels or (not blocks) a
+    static scale (max |x| of that input in the BF16 network on the same frames,
+    / 448).  Returns (outputs, {conv index: static input scale})."""
+    from oracle.network import (forward, round_bf16, round_fp8, quantize_fp8_blocks,
+                                quantize_fp8_per_channel_blocks)
     cfg = TINY if cfg_name == "tiny" else FULL
     fr = frames(cfg_name, n)
     layers = weights(cfg_name, k)
@@ -137,9 +140,12 @@ def oracle_forward_fp8(cfg_name, k, n):
 
     forward(fr, lb, cfg.blocks, store=round_bf16, in_hook=record)
     scales = {i: (amax[i] / 448.0 if amax[i] > 0 else 1.0) for i in f8}
-    lq = [(quantize_fp8_per_channel(w)[0], b) if i in f8 else (w, b) for i, (w, b) in enumerate(lb)]
+    lq = [(quantize_fp8_per_channel_blocks(layers[i][0])[0], b) if i in f8 else (w, b)
+          for i, (w, b) in enumerate(lb)]
 
     def quant(i, x):
-        return round_fp8(x / scales[i]) * scales[i] if i in f8 else x
+        if i not in f8:
+            return x
+        return quantize_fp8_blocks(x) if blocks else round_fp8(x / scales[i]) * scales[i]
 
     return forward(fr, lq, cfg.blocks, store=round_bf16, in_hook=quant), scales

@@ -88,9 +88,13 @@ BF16_MISSES_BAR = pytest.mark.xfail(
     strict=True, raises=(HeadBarError, MatchBarError),
     reason="BF16 storage alone moves this network's heads 3.6e-2..1.1e-1 from FP64 (> 2e-2); the GPU measures "
            "3.7e-2..1.07e-1 and 81-93 % of detections matched")
+# e4m3 keeps 3 mantissa bits: the FP8-emulated oracle (e4m3 operands of the
+# backbone 3x3 convs, with per-32 block scales, else exact) already moves the heads
+# 0.18-0.51 from FP64 on this random-weight network, and the GPU measures the same.
 FP8_MISSES_BAR = pytest.mark.xfail(
     strict=True, raises=(HeadBarError, MatchBarError),
-    reason="the e4m3 backbone moves the heads 0.2-0.47 from FP64 and matches ~27 % of detections")
+    reason="e4m3 operands of the backbone 3x3 convs move the heads 0.16-0.48 from FP64 (the FP8-emulated oracle: "
+           "0.18-0.51); 3-57 % of detections matched, block or per-tensor activation scales alike")
 # FP16 meets the head half everywhere (5e-3 .. 1.44e-2) but single decisions
 # flip: a candidate whose margin lies within the FP16 error of the threshold, or
 # an overlapping pair whose NMS outcome changes.  With 8-70 detections per frame
@@ -427,21 +431,25 @@ def test_fp8_calibration_scales(torch, cfg_name, k):
 
 
 @pytest.mark.parametrize("cfg_name,k", [("tiny", 50), pytest.param("full", 40, marks=pytest.mark.slow)])
+@pytest.mark.parametrize("blocks", [True, False], ids=["block_scales", "per_tensor"])
 @FP8_MISSES_BAR
-def test_fp8_backbone_parity(torch, cfg_name, k):
-    """FP8 e4m3 backbone held to the reduced-precision bar (the FP8-emulated
+def test_fp8_backbone_parity(torch, cfg_name, k, blocks):
+    """FP8 e4m3 backbone held to the reduced-precision bar, with per-32-channel
+    activation exponents or static per-tensor activation scales (the FP8-emulated
     oracle's error is printed as a diagnostic)."""
     from tests.helpers import oracle_forward_fp8
     cfg = TINY if cfg_name == "tiny" else FULL
-    _say(f"case: {cfg_name} fp8 b1")
+    _say(f"case: {cfg_name} fp8 b1 {'block' if blocks else 'per-tensor'} scales")
     m = _model(cfg, "fp8", 1)
     m.load_weights(weights(cfg_name, k))
+    m.fp8_block_scales(blocks)
     x = torch.from_numpy(frames(cfg_name, 1)).cuda()
-    m.calibrate(x)
+    if not blocks:
+        m.calibrate(x)
     heads = m.forward(x)
     torch.cuda.synchronize()
     ref = oracle_forward(cfg_name, k, 1)
-    emul, _ = oracle_forward_fp8(cfg_name, k, 1)
+    emul, _ = oracle_forward_fp8(cfg_name, k, 1, blocks)
     v = head_views(heads, [(cfg.height, cfg.width)])
     d = gpu_dets(m.decode(heads, [(cfg.height, cfg.width)]), 0, m.cap)
     r = opost.detections(ref, anchors(cfg_name), 0.5, 0.4)
