@@ -457,8 +457,16 @@ ConvArgs conv_args(const jde_ctx* c, const Op& o, const jde_frame_desc* d, int n
         a.out0_f32 = 0;
     }
     if (o.emb_out >= 0) {
-        a.out1 = out->emb[o.emb_out];
-        a.ld1 = o.cout - o.n_split;
+        if (c->sparse_emb) {
+            // det3 alone: the emb rows of the weight block run later, at kept cells only
+            // (every launch of this op -- forward and autotuner -- must drop them: there
+            // is no dense emb output to write)
+            a.cout = o.n_split;
+            a.n_major = (double)a.cout * a.K > (double)a.M * a.cin ? 1 : 0;
+        } else {
+            a.out1 = out->emb[o.emb_out];
+            a.ld1 = o.cout - o.n_split;
+        }
     }
     if (runs_fp8(c, o)) {
         a.w = wb + o.dev_w8;
@@ -965,15 +973,8 @@ static jde_status forward_impl(jde_ctx* c, const float* frames, const jde_frame_
             a.nframes = n;
             a.uniform = 0;
             a.dyn = dynp;
-            a.n_major = (double)o.cout * a.K > (double)a.M * o.cin ? 1 : 0;
+            a.n_major = (double)a.cout * a.K > (double)a.M * o.cin ? 1 : 0;
             if (runs_fp8(c, o)) return fail(JDE_EUNSUPPORTED, "a graph for any batch does not run FP8 convs");
-        }
-        if (c->sparse_emb && o.emb_out >= 0) {
-            // det3 alone: the emb rows of the weight block run later, at kept cells only
-            a.cout = o.n_split;
-            a.out1 = nullptr;
-            a.ld1 = 0;
-            a.n_major = (double)a.cout * a.K > (double)a.M * a.cin ? 1 : 0;
         }
         int w3 = 0;  // pixel tiles of the window kernel, 0 = implicit GEMM
         if (c->window_convs && !dynamic && !runs_fp8(c, o) && conv3w_ok(a, c->et)) {

@@ -1528,8 +1528,14 @@ bool conv3w_ok(const ConvArgs& a, int et) {
            a.cout % 128 == 0 && a.cin1 == 0 && a.lvl_in == a.lvl_out && !a.wscale;
 }
 
+// Output columns at or past n_split go to out1: refuse a launch that would write
+// them through a null pointer (and outputs that are missing altogether).
+static bool conv_outputs_ok(const ConvArgs& a) {
+    return a.out0 && (a.n_split >= a.cout || a.out1);
+}
+
 hipError_t launch_conv3w(const ConvArgs& a, int et, int pixel_tiles, hipStream_t s) {
-    if (!conv3w_ok(a, et) || pixel_tiles <= 0) return hipErrorInvalidValue;
+    if (!conv_outputs_ok(a) || !conv3w_ok(a, et) || pixel_tiles <= 0) return hipErrorInvalidValue;
     const int ntc = a.cout / 128, total = pixel_tiles * ntc;
     dim3 grid(total), block(512);
     if (et == kBF16)
@@ -1814,7 +1820,8 @@ static hipError_t launch_f8(const ConvArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_conv_fp8(const ConvArgs& a, int c, hipStream_t s) {
-    if (!conv_fp8_ok(a) || !a.wscale || !a.wbscale || !(a.in_scale > 0.f)) return hipErrorInvalidValue;
+    if (!conv_outputs_ok(a) || !conv_fp8_ok(a) || !a.wscale || !a.wbscale || !(a.in_scale > 0.f))
+        return hipErrorInvalidValue;
     switch (c) {
         case 0: return launch_f8<0>(a, s);
         case 1: return launch_f8<1>(a, s);
@@ -2609,7 +2616,7 @@ static hipError_t launch_type(const ConvArgs& a, int c, bool aligned, hipStream_
 }
 
 hipError_t launch_conv(const ConvArgs& a, int et, int c, hipStream_t s) {
-    if (!conv_tile_ok(c, et, a)) return hipErrorInvalidValue;
+    if (!conv_outputs_ok(a) || !conv_tile_ok(c, et, a)) return hipErrorInvalidValue;
     if (kTiles[c].pw) return launch_pw(a, et, s);
     const bool aligned = aligned_cin(a, kTiles[c].bk);
     if (et == kF32) return launch_type<float>(a, c, aligned, s);

@@ -55,6 +55,28 @@ def test_tiny_batch_matches_single_frames_and_oracle(torch):
             assert rel_err(single[key][s][0], v[key][s][2]) <= 1e-5
 
 
+def test_autotune_with_sparse_emb_head(torch):
+    """With the embedding head at kept cells only there is no dense emb output: the
+    autotuner's trial launches of the det3 + emb3 convs must drop the emb rows as
+    the forward does (regression: they wrote those columns through the null emb
+    pointer).  The tuned forward's det heads equal the default tiles' ones."""
+    _say("case: tiny bf16 autotune with the sparse emb head")
+    m = _model(TINY, "bf16", 2)
+    m.load_weights(weights("tiny", 50))
+    m.sparse_emb(True)
+    descs = [(192, 320)] * 2
+    heads = m.head_buffers(descs, emb=False)
+    x = torch.from_numpy(frames("tiny", 2)).cuda()
+    m.forward(x, descs, heads=heads)
+    ref = [h.clone() for h in heads["det"]]
+    tiles = m.autotune(x, descs, heads=heads, reps=1)
+    _say(f"  tiles {tiles.tolist()}")
+    m.forward(x, descs, heads=heads)
+    torch.cuda.synchronize()
+    for s in range(3):
+        assert rel_err(heads["det"][s].float().cpu().numpy(), ref[s].float().cpu().numpy()) <= 3e-2
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_autotuned_tiles_match_default_tiles(torch, precision):
     _say(f"case: tiny {precision} autotune vs default")
