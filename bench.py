@@ -564,6 +564,30 @@ def ragged_bench(layers, tiles, big, torch, totals=(8, 16, 32, 64), steps=10, wa
     return out
 
 
+def tune_sweep(layers, torch, out_path):
+    """Autotuned tiles of the sweep configurations, keyed '<precision>_b<batch>' and
+    'bf16_mix64' (the 64-frame ragged mix of three resolutions), merged into the
+    stored choices."""
+    from jde_inputs import FULL, ragged_mix, mix_frames
+    cache = os.path.join(ROOT, "paper_2011_03910_amd", "tiles_mi355x.json")
+    saved = json.load(open(cache)) if os.path.exists(cache) else {}
+    big = make_inputs(32, torch)
+    for prec, b in (("bf16", 1), ("bf16", 4), ("bf16", 8), ("bf16", 32), ("fp16", 16)):
+        t0 = time.perf_counter()
+        pipe = Pipeline(prec, b, layers, torch, big[0][:b].contiguous(), None)
+        saved[f"{prec}_b{b}"] = pipe.tiles.tolist()
+        log(f"tuned {prec} b{b} in {time.perf_counter() - t0:.1f} s")
+        del pipe
+        torch.cuda.empty_cache()
+    descs = ragged_mix(FULL.seed, 64)
+    fr = torch.from_numpy(mix_frames(FULL.seed, descs)).cuda()
+    t0 = time.perf_counter()
+    pipe = Pipeline("bf16", len(descs), layers, torch, fr, None, descs=descs)
+    saved["bf16_mix64"] = pipe.tiles.tolist()
+    log(f"tuned the 64-frame ragged mix in {time.perf_counter() - t0:.1f} s")
+    json.dump(saved, open(out_path, "w"))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -581,6 +605,9 @@ def main():
     ap.add_argument("--save-tiles", help="write the tile choices to this JSON file")
     ap.add_argument("--load-tiles", help="use tile choices from this JSON file instead of tuning")
     ap.add_argument("--retune", action="store_true", help="run the autotuner instead of the stored tile choices")
+    ap.add_argument("--tune-sweep", metavar="OUT_JSON",
+                    help="autotune the sweep configurations (BF16 batch 1/4/8/32, FP16 batch 16, the 64-frame "
+                         "ragged mix), merge them into the stored tile choices, write OUT_JSON and exit")
     ap.add_argument("--eager", action="store_true",
                     help="time eager launches instead of replaying the step as a captured HIP graph")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"),
@@ -622,6 +649,9 @@ def main():
         log(f"copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
         del src, dst
     layers = model_weights(FULL, K_CAND)
+    if args.tune_sweep:
+        tune_sweep(layers, torch, args.tune_sweep)
+        return
     inputs_b = make_inputs(args.batch, torch)
 
     cache = os.path.join(ROOT, "paper_2011_03910_amd", "tiles_mi355x.json")
@@ -719,7 +749,7 @@ def main():
         bs = {}
         for b in (1, 4, 8, 16, 32):
             inp = tuple(x[:b * (1 if i == 0 else N_TRACKS)].contiguous() for i, x in enumerate(big))
-            r, p_ = quick_fps("bf16", b, layers, inp, torch, tiles16)
+            r, p_ = quick_fps("bf16", b, layers, inp, torch, saved.get(f"bf16_b{b}", tiles16))
             bs[str(b)] = r
             del p_
             torch.cuda.empty_cache()
@@ -742,7 +772,8 @@ def main():
         prec_heads8 = {}
         for pr in ("fp16", "fp8", "fp8_per_tensor"):
             base = "fp8" if pr.startswith("fp8") else pr
-            r, p_ = quick_fps(base, args.batch, layers, inputs_b, torch, tiles16 if pr == "fp16" else None,
+            r, p_ = quick_fps(base, args.batch, layers, inputs_b, torch,
+                              saved.get("fp16_b16", tiles16) if pr == "fp16" else None,
                               fp8_blocks=pr == "fp8")
             hd = ({k: [None if h is None else h.clone() for h in v] for k, v in p_.heads.items()}, frame0_dets(p_))
             if pr == "fp16":
@@ -754,7 +785,7 @@ def main():
             torch.cuda.empty_cache()
         sweeps["b16_precision"] = prec
         log(f"precision rows: {prec}")
-        sweeps["bf16_ragged_mix"] = ragged_bench(layers, tiles16, big, torch)
+        sweeps["bf16_ragged_mix"] = ragged_bench(layers, saved.get("bf16_mix64", tiles16), big, torch)
         log(f"ragged mixes: {sweeps['bf16_ragged_mix']}")
         del big
         torch.cuda.empty_cache()
