@@ -565,14 +565,14 @@ def ragged_bench(layers, tiles, big, torch, totals=(8, 16, 32, 64), steps=10, wa
 
 
 def tune_sweep(layers, torch, out_path):
-    """Autotuned tiles of the sweep configurations, keyed '<precision>_b<batch>' and
+    """Autotuned tiles of the headline and sweep configurations, keyed '<precision>_b<batch>' and
     'bf16_mix64' (the 64-frame ragged mix of three resolutions), merged into the
     stored choices."""
     from jde_inputs import FULL, ragged_mix, mix_frames
     cache = os.path.join(ROOT, "paper_2011_03910_amd", "tiles_mi355x.json")
     saved = json.load(open(cache)) if os.path.exists(cache) else {}
     big = make_inputs(32, torch)
-    for prec, b in (("bf16", 1), ("bf16", 4), ("bf16", 8), ("bf16", 32), ("fp16", 16)):
+    for prec, b in (("bf16", 16), ("bf16", 1), ("bf16", 4), ("bf16", 8), ("bf16", 32), ("fp16", 16)):
         t0 = time.perf_counter()
         pipe = Pipeline(prec, b, layers, torch, big[0][:b].contiguous(), None)
         saved[f"{prec}_b{b}"] = pipe.tiles.tolist()
@@ -606,7 +606,7 @@ def main():
     ap.add_argument("--load-tiles", help="use tile choices from this JSON file instead of tuning")
     ap.add_argument("--retune", action="store_true", help="run the autotuner instead of the stored tile choices")
     ap.add_argument("--tune-sweep", metavar="OUT_JSON",
-                    help="autotune the sweep configurations (BF16 batch 1/4/8/32, FP16 batch 16, the 64-frame "
+                    help="autotune the headline and sweep configurations (BF16 batch 16/1/4/8/32, FP16 batch 16, the 64-frame "
                          "ragged mix), merge them into the stored tile choices, write OUT_JSON and exit")
     ap.add_argument("--eager", action="store_true",
                     help="time eager launches instead of replaying the step as a captured HIP graph")
