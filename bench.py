@@ -417,6 +417,18 @@ def association_bench(pipe, inputs, torch, reps=20):
             "pairs_kept": int(out["kept"][:pipe.batch].sum().item()), "assign_single_frame": big}
 
 
+def footprint_mb(pipe):
+    """Device memory of one configuration (the Fig. 5 analogue): weights, the
+    library's workspace (activations, decode scratch), and head / detection / cost
+    buffers, in MB."""
+    nb = lambda t: 0 if t is None else t.numel() * t.element_size()
+    heads = sum(nb(h) for v in pipe.heads.values() for h in v)
+    rest = heads + sum(nb(t) for t in pipe.dets.values()) + nb(pipe.cost)
+    w, ws = nb(pipe.m.weights), nb(pipe.m.ws)
+    return {"weights": round(w / 1e6, 1), "workspace": round(ws / 1e6, 1), "heads_dets_cost": round(rest / 1e6, 1),
+            "total": round((w + ws + rest) / 1e6, 1)}
+
+
 def quick_fps(precision, batch, layers, inputs, torch, tiles, steps=10, warmup=3, descs=None, sparse_emb=True,
               fp8_blocks=True):
     """frames/s of the graph-replayed step for one configuration (no per-launch events)."""
@@ -427,7 +439,8 @@ def quick_fps(precision, batch, layers, inputs, torch, tiles, steps=10, warmup=3
     ncand = pipe.dets["n_cand"][:batch].cpu().numpy()
     counts = pipe.dets["count"][:batch].cpu().numpy()
     rec = {"fps": round(batch * steps / wall, 1), "step_p50_ms": round(pct(step_ms, 50), 3),
-           "candidates_per_frame": round(float(ncand.mean()), 1), "kept_per_frame": round(float(counts.mean()), 1)}
+           "candidates_per_frame": round(float(ncand.mean()), 1), "kept_per_frame": round(float(counts.mean()), 1),
+           "hbm_mb": footprint_mb(pipe)}
     return rec, pipe
 
 
@@ -723,6 +736,7 @@ def main():
         extra["ingest"] = ingest_bench(torch, args.batch)
         log(f"ingest: {extra['ingest']}")
     heads0 = {k: [None if h is None else h.clone() for h in v] for k, v in pipe.heads.items()}
+    hbm_main = footprint_mb(pipe)
     boxes0 = frame0_dets(pipe)
     del pipe
     torch.cuda.empty_cache()
@@ -733,7 +747,8 @@ def main():
         p32 = Pipeline("fp32", 1, layers, torch, None if args.no_tune else in1[0], saved.get("fp32_b1"))
         tiles_out["fp32_b1"] = None if p32.tiles is None else p32.tiles.tolist()
         w32, s32, _ = run(p32, in1, args.fp32_steps, 3, torch)
-        fp32 = {"fps": 1 * args.fp32_steps / w32, "p50_ms": pct(s32, 50), "p99_ms": pct(s32, 99)}
+        fp32 = {"fps": 1 * args.fp32_steps / w32, "p50_ms": pct(s32, 50), "p99_ms": pct(s32, 99),
+                "hbm_mb": footprint_mb(p32)}
         log(f"fp32 b1: {fp32['fps']:.1f} frames/s, p50 {fp32['p50_ms']:.2f} ms")
         del p32
         torch.cuda.empty_cache()
@@ -744,7 +759,8 @@ def main():
         t_sw = time.perf_counter()
         tiles16 = saved.get("bf16_b16")
         sweeps = {"note": "graph-replayed steps (forward + decode + NMS + normalise + 40-track cost), 10 timed "
-                          "steps each; every batch size uses the BF16 batch-16 tile choices"}
+                          "steps each; tile choices autotuned per batch size / precision / the 64-frame mix "
+                          "(tiles_mi355x.json); hbm_mb = weights + workspace + head, detection and cost buffers"}
         big = make_inputs(32, torch)
         bs = {}
         for b in (1, 4, 8, 16, 32):
@@ -844,7 +860,7 @@ def main():
         "frame_latency_note": "arrival -> tracks updated, 16 streams x 30 FPS through the serving loop",
         "step_p50_ms": round(pct(step_ms, 50), 3), "step_p99_ms": round(pct(step_ms, 99), 3),
         "candidates_per_frame": round(float(ncand.mean()), 1), "kept_per_frame": round(float(counts.mean()), 1),
-        "fp32_b1": None if fp32 is None else {k: round(v, 3) for k, v in fp32.items()},
+        "fp32_b1": None if fp32 is None else {k: v if isinstance(v, dict) else round(v, 3) for k, v in fp32.items()},
         "speedup_vs_fp32_b1": None if fp32 is None else round(fps / fp32["fps"], 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
@@ -852,6 +868,7 @@ def main():
                                f"{conv_flop / 1e9:.1f} GFLOP/step, mean {conv_ms / n_launch * 1e3:.1f} us/launch)"},
         "accuracy_frame0": acc,
         "post_processing": post,
+        "hbm_mb": hbm_main,
         **extra,
         "ablation_ladder": None if sweeps is None else {
             "fp32_b1_eager": None if fp32 is None else round(fp32["fps"], 1),

@@ -96,7 +96,7 @@ def test_autotuned_tiles_match_default_tiles(torch, precision):
     # every legal tile of one launch gives the same result (register-staged and
     # direct-to-LDS kernels alike; an index past the table is rejected)
     n_ops = len(tiles)
-    for t in range(40):
+    for t in range(48):
         forced = np.full(n_ops, -1, dtype=np.int32)
         forced[:] = t
         try:
