@@ -60,7 +60,7 @@ def test_tiny_fp32_forward_parity(torch):
             assert e <= 1e-4, (key, s, e)
 
 
-# The spec bar for the reduced-precision path: every head output within
+# The bar for the reduced-precision paths: every head output within
 # 2e-2 (normwise max relative error) of the FP64 oracle and >= 99 % of the
 # oracle's detections matched at IoU >= 0.9 (per frame, one-to-one greedy
 # matching in oracle-score order).  Both halves are asserted for every
