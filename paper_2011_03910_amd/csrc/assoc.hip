@@ -202,9 +202,9 @@ __global__ __launch_bounds__(kAssignThreads) void assign_kernel(const float* __r
                                                                 int* __restrict__ kept_out, double* __restrict__ total_out,
                                                                 int* __restrict__ status) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_n, s_m, s_tr, s_Tr, s_Dr, s_j0, s_j1, s_done, s_kept;
-    __shared__ double s_delta, s_red_v[kAssignThreads / 64];
-    __shared__ int s_red_j[kAssignThreads / 64];
+    __shared__ int s_n, s_m, s_tr, s_Tr, s_Dr;
+    __shared__ double s_red_v[2][kAssignThreads / 64];
+    __shared__ int s_red_j[2][kAssignThreads / 64];
     __shared__ double s_sum[kAssignThreads / 64];
     __shared__ int s_cnt[kAssignThreads / 64];
     const int f = blockIdx.x;
@@ -291,22 +291,25 @@ __global__ __launch_bounds__(kAssignThreads) void assign_kernel(const float* __r
             S.minv[j] = inf;
             S.used[j] = 0;
         }
-        if (tid == 0) {
-            S.p[0] = i;
-            s_j0 = 0;
-        }
+        if (tid == 0) S.p[0] = i;
         __syncthreads();
+        // One barrier per step.  Column j belongs to thread j % kAssignThreads, which
+        // alone reads and writes its used / minv / v / way entries; p does not change
+        // during a row's search, and u[i0] of the row being relaxed was last written
+        // before the row began (its column joins the tree only now), so only the
+        // wave minima need the barrier.  Every thread then finishes the block
+        // minimum itself (the same order of comparisons: ties to the lowest column);
+        // the minima alternate between two buffers, so a wave one step ahead cannot
+        // overwrite what a slower wave still reads.
+        int j0 = 0, par = 0;
         while (true) {
-            const int j0 = s_j0;
-            if (tid == 0) S.used[j0] = 1;
+            if (j0 % kAssignThreads == tid) S.used[j0] = 1;
             const int i0 = S.p[j0];
-            __syncthreads();
-            // relax the unused columns; the smallest minv (lowest j on ties)
+            const double ui = S.u[i0];
             double bv = inf;
             int bj = 0x7fffffff;
-            const double ui = S.u[i0];
-            for (int j = 1 + tid; j <= m; j += kAssignThreads) {
-                if (S.used[j]) continue;
+            for (int j = tid; j <= m; j += kAssignThreads) {
+                if (j == 0 || S.used[j]) continue;
                 const double cur = at(i0 - 1, j - 1) - ui - S.v[j];
                 if (cur < S.minv[j]) {
                     S.minv[j] = cur;
@@ -320,19 +323,13 @@ __global__ __launch_bounds__(kAssignThreads) void assign_kernel(const float* __r
                 argmin_pair(bv, bj, v2, j2);
             }
             if (lane == 0) {
-                s_red_v[wave] = bv;
-                s_red_j[wave] = bj;
+                s_red_v[par][wave] = bv;
+                s_red_j[par][wave] = bj;
             }
             __syncthreads();
-            if (tid == 0) {
-                double v0 = s_red_v[0];
-                int jj = s_red_j[0];
-                for (int w = 1; w < kAssignThreads / 64; ++w) argmin_pair(v0, jj, s_red_v[w], s_red_j[w]);
-                s_delta = v0;
-                s_j1 = jj;
-            }
-            __syncthreads();
-            const double delta = s_delta;
+            double delta = s_red_v[par][0];
+            int j1 = s_red_j[par][0];
+            for (int w = 1; w < kAssignThreads / 64; ++w) argmin_pair(delta, j1, s_red_v[par][w], s_red_j[par][w]);
             for (int j = tid; j <= m; j += kAssignThreads) {
                 if (S.used[j]) {
                     S.u[S.p[j]] += delta;
@@ -341,16 +338,12 @@ __global__ __launch_bounds__(kAssignThreads) void assign_kernel(const float* __r
                     S.minv[j] -= delta;
                 }
             }
-            __syncthreads();
-            if (tid == 0) {
-                s_j0 = s_j1;
-                s_done = S.p[s_j1] == 0;
-            }
-            __syncthreads();
-            if (s_done) break;
+            j0 = j1;
+            par ^= 1;
+            if (S.p[j1] == 0) break;
         }
+        __syncthreads();  // every thread's last potential update reads p before the path flips it
         if (tid == 0) {
-            int j0 = s_j0;
             do {
                 const int j1 = S.way[j0];
                 S.p[j0] = S.p[j1];
