@@ -115,43 +115,76 @@ def quantize_fp8_per_channel(w):
     return round_fp8(w / sb) * sb, s
 
 
-def e8m0_exponent(amax):
-    """Power-of-two block scale of FP8 with 32-value blocks (the E8M0 scale the
-    matrix cores apply): the smallest integer s with amax / 2^s <= 448, so that the
-    block's largest magnitude lands in e4m3's top binade without saturating; s = 0
-    for an all-zero block; s is kept within the E8M0 range [-127, 127]."""
+# The element formats of the block-scaled matrix-core operands (OCP microscaling):
+# mantissa bits M, smallest normal exponent emin (bias 1 - emin), largest value.
+# e4m3: 3 mantissa bits, exponent bias 7, max 1.75 * 2^8; FP6 E2M3: 3 mantissa bits,
+# bias 1, max 1.875 * 2^2; FP4 E2M1: 1 mantissa bit, bias 1, max 1.5 * 2^2.
+MINIFLOATS = {"fp8": (3, -6, 448.0), "fp6": (3, 0, 7.5), "fp4": (1, 0, 6.0)}
+
+
+def round_minifloat(x, fmt):
+    """Round to the nearest value of the element format ``fmt`` (ties to even),
+    saturating at its largest value; the spacing in binade e >= emin is 2^(e - M),
+    below 2^emin it stays 2^(emin - M) (subnormals).  Returned as FP64."""
+    mant, emin, top = MINIFLOATS[fmt]
+    x = np.asarray(x, dtype=np.float64)
+    a = np.minimum(np.abs(x), top)
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    e = np.maximum(e, float(emin))
+    q = np.exp2(e - mant)
+    r = np.minimum(np.round(a / q) * q, top)     # numpy rounds halves to even
+    return np.where(np.isnan(x), np.nan, np.sign(x) * r)
+
+
+def e8m0_exponent(amax, top=FP8_MAX):
+    """Power-of-two block scale with 32-value blocks (the E8M0 scale the matrix
+    cores apply): the smallest integer s with amax / 2^s <= top (the element
+    format's largest value, 448 for e4m3), so that the block's largest magnitude
+    lands in the format's top binade without saturating; s = 0 for an all-zero
+    block; s is kept within the E8M0 range [-127, 127]."""
     a = np.asarray(amax, dtype=np.float64)
     pos = a > 0
-    s = np.ceil(np.log2(np.where(pos, a, FP8_MAX) / FP8_MAX))
+    s = np.ceil(np.log2(np.where(pos, a, top) / top))
     # log2 is inexact near powers of two: settle s with exact power-of-two scalings
-    s = np.where(np.ldexp(np.where(pos, a, 0.0), -s.astype(np.int64)) > FP8_MAX, s + 1, s)
-    s = np.where(np.ldexp(np.where(pos, a, 0.0), -(s - 1).astype(np.int64)) <= FP8_MAX, s - 1, s)
+    s = np.where(np.ldexp(np.where(pos, a, 0.0), -s.astype(np.int64)) > top, s + 1, s)
+    s = np.where(np.ldexp(np.where(pos, a, 0.0), -(s - 1).astype(np.int64)) <= top, s - 1, s)
     s = np.where(pos, s, 0.0)
     return np.clip(s, -127, 127).astype(np.int64)
 
 
-def quantize_fp8_blocks(x, block=32):
-    """e4m3 with a power-of-two scale per block of ``block`` consecutive values
-    along the last axis: each block b becomes 2^s_b round_fp8(x / 2^s_b) with
-    s_b = e8m0_exponent(max |x_b|).  The last axis must be a multiple of block.
-    Returns the dequantised values (FP64)."""
+def quantize_blocks(x, fmt="fp8", block=32):
+    """Element format ``fmt`` with a power-of-two scale per block of ``block``
+    consecutive values along the last axis: each block b becomes
+    2^s_b round(x / 2^s_b) with s_b = e8m0_exponent(max |x_b|, top of fmt).  The
+    last axis must be a multiple of block.  Returns the dequantised values (FP64)."""
     x = np.asarray(x, dtype=np.float64)
     assert x.shape[-1] % block == 0, x.shape
     xb = x.reshape(x.shape[:-1] + (x.shape[-1] // block, block))
-    s = e8m0_exponent(np.abs(xb).max(axis=-1))[..., None]
-    return (np.ldexp(round_fp8(np.ldexp(xb, -s)), s)).reshape(x.shape)
+    s = e8m0_exponent(np.abs(xb).max(axis=-1), MINIFLOATS[fmt][2])[..., None]
+    return (np.ldexp(round_minifloat(np.ldexp(xb, -s), fmt), s)).reshape(x.shape)
+
+
+def quantize_fp8_blocks(x, block=32):
+    """e4m3 with a power-of-two scale per block (quantize_blocks with 'fp8')."""
+    return quantize_blocks(x, "fp8", block)
+
+
+def quantize_per_channel_blocks(w, fmt="fp8", block=32):
+    """Block-scaled weights with a per-output-channel scale and, inside it, a
+    power-of-two scale per block of 32 along the flattened (r, s, ci) axis of
+    w [Cout, k, k, Cin]: w ~= s_c * 2^s_cb * round(w / s_c / 2^s_cb),
+    s_c = max|w_c| / top of fmt.  Returns (dequantised weights, per-channel scales)."""
+    top = MINIFLOATS[fmt][2]
+    w = np.asarray(w, dtype=np.float64)
+    amax = np.abs(w.reshape(w.shape[0], -1)).max(axis=1)
+    s = np.where(amax > 0, amax / top, 1.0)
+    flat = w.reshape(w.shape[0], -1) / s[:, None]
+    return (quantize_blocks(flat, fmt, block) * s[:, None]).reshape(w.shape), s
 
 
 def quantize_fp8_per_channel_blocks(w, block=32):
-    """FP8 weights with a per-output-channel scale and, inside it, a power-of-two
-    scale per block of 32 along the flattened (r, s, ci) axis of w [Cout, k, k, Cin]:
-    w ~= s_c * 2^s_cb * round_fp8(w / s_c / 2^s_cb), s_c = max|w_c| / 448.
-    Returns (dequantised weights, per-channel scales)."""
-    w = np.asarray(w, dtype=np.float64)
-    amax = np.abs(w.reshape(w.shape[0], -1)).max(axis=1)
-    s = np.where(amax > 0, amax / FP8_MAX, 1.0)
-    flat = w.reshape(w.shape[0], -1) / s[:, None]
-    return (quantize_fp8_blocks(flat, block) * s[:, None]).reshape(w.shape), s
+    """quantize_per_channel_blocks with e4m3 elements."""
+    return quantize_per_channel_blocks(w, "fp8", block)
 
 
 class _Walker:

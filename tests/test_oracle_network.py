@@ -294,3 +294,58 @@ def test_fp8_weights_per_channel_and_block(rng):
     # with one scale per channel only, the same block would lose almost everything
     wq1, _ = net.quantize_fp8_per_channel(w)
     assert np.abs(wq1[2, 1, 1, :32] - blk).max() > 10 * np.abs(wq[2, 1, 1, :32] - blk).max()
+
+
+def _codes(e_bits, m_bits, bias):
+    """Every non-negative value of a sign / e_bits / m_bits minifloat with no inf or
+    NaN codes, from its definition: exponent field E = 0 is subnormal
+    (m / 2^M * 2^(1 - bias)), else (1 + m / 2^M) * 2^(E - bias); with the
+    mantissa's lowest bit (the tie-break parity)."""
+    out = []
+    for E in range(2 ** e_bits):
+        for m in range(2 ** m_bits):
+            v = (m / 2 ** m_bits) * 2.0 ** (1 - bias) if E == 0 else (1 + m / 2 ** m_bits) * 2.0 ** (E - bias)
+            out.append((v, m & 1))
+    return sorted(out)
+
+
+@pytest.mark.parametrize("fmt,e_bits,m_bits,bias", [("fp4", 2, 1, 1), ("fp6", 2, 3, 1)])
+def test_fp4_fp6_rounding_is_nearest_code_ties_to_even(rng, fmt, e_bits, m_bits, bias):
+    """round_minifloat against brute force over the format's codes: the nearest
+    representable value, ties to the code whose mantissa is even, saturating at the
+    largest code; exact at every code and at hand-picked ties."""
+    codes = _codes(e_bits, m_bits, bias)
+    vals = np.array([v for v, _ in codes])
+    assert vals.max() == net.MINIFLOATS[fmt][2]
+    x = np.concatenate([rng.uniform(-9, 9, 4000), vals, -vals, (vals[1:] + vals[:-1]) / 2])
+    want = []
+    for xi in x:
+        a = min(abs(xi), vals.max())
+        d = np.abs(vals - a)
+        best = np.flatnonzero(d == d.min())
+        if len(best) > 1:                      # a tie: the even-mantissa code
+            best = [b for b in best if codes[b][1] == 0]
+        want.append(np.sign(xi) * vals[best[0]])
+    np.testing.assert_array_equal(net.round_minifloat(x, fmt), np.array(want))
+    if fmt == "fp4":
+        got = net.round_minifloat(np.array([0.25, 0.75, 1.25, 1.75, 2.5, 3.5, 5.0, 7.0]), "fp4")
+        np.testing.assert_array_equal(got, [0.0, 1.0, 1.0, 2.0, 2.0, 4.0, 4.0, 6.0])
+
+
+def test_fp4_fp6_block_exponents_and_blocks(rng):
+    """Block exponents against each format's largest value (6 for FP4, 7.5 for FP6
+    E2M3), and block quantisation that scales each 32-value block on its own."""
+    e = net.e8m0_exponent
+    assert e(6.0, 6.0) == 0 and e(6.0001, 6.0) == 1 and e(3.0, 6.0) == -1 and e(3.1, 6.0) == 0
+    assert e(7.5, 7.5) == 0 and e(1.0, 7.5) == -2      # 1 / 2^-2 = 4 <= 7.5 < 8 = 1 / 2^-3
+    for fmt in ("fp4", "fp6"):
+        top = net.MINIFLOATS[fmt][2]
+        x = rng.standard_normal((4, 64)) * 10.0 ** rng.uniform(-3, 3, (4, 1))
+        q = net.quantize_blocks(x, fmt)
+        xb, qb = x.reshape(4, 2, 32), q.reshape(4, 2, 32)
+        s = net.e8m0_exponent(np.abs(xb).max(-1), top)
+        t = np.ldexp(np.abs(xb).max(-1), -s)
+        assert np.all((t > top / 2) & (t <= top))
+        np.testing.assert_array_equal(net.quantize_blocks(x[1, 32:], fmt), q[1, 32:])
+        # every quantised value is 2^s times a code of the format
+        np.testing.assert_array_equal(net.round_minifloat(np.ldexp(qb, -s[..., None]), fmt), np.ldexp(qb, -s[..., None]))
