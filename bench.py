@@ -22,7 +22,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "frames/s at 1088x608 (BF16 batched vs FP32 batch-1) + p99 frame latency"
-PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3, "fp8": 5000.0}
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3, "fp8": 5000.0, "fp6": 10100.0, "fp4": 10100.0}
 N_TRACKS = 40
 K_CAND = 40
 CONF, NMS_IOU = 0.5, 0.4
@@ -607,7 +607,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32", "fp8"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32", "fp8", "fp6", "fp4"])
     ap.add_argument("--fp32-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 batch-1 plain form")
@@ -786,7 +786,7 @@ def main():
         torch.cuda.empty_cache()
         prec = {}
         prec_heads8 = {}
-        for pr in ("fp16", "fp8", "fp8_per_tensor"):
+        for pr in ("fp16", "fp8", "fp8_per_tensor", "fp6", "fp4"):
             base = "fp8" if pr.startswith("fp8") else pr
             r, p_ = quick_fps(base, args.batch, layers, inputs_b, torch,
                               saved.get("fp16_b16", tiles16) if pr == "fp16" else None,

@@ -54,8 +54,11 @@ typedef enum {
  * Accumulation is FP32 in every mode; head outputs, decode and normalisation
  * stay FP32.  JDE_FP8 runs the backbone 3x3 convolutions in OCP FP8 e4m3 with
  * per-channel and per-32-k-block weight scales and per-32-channel activation
- * scales (see jde_fp8_block_scales), and the rest in BF16. */
-typedef enum { JDE_FP32 = 0, JDE_BF16 = 1, JDE_FP16 = 2, JDE_FP8 = 3 } jde_precision;
+ * scales (see jde_fp8_block_scales), and the rest in BF16.  JDE_FP6 and JDE_FP4
+ * do the same with OCP microscaling elements FP6 E2M3 (largest value 7.5) and
+ * FP4 E2M1 (largest value 6), always with block scales (a precision study
+ * beyond the paper). */
+typedef enum { JDE_FP32 = 0, JDE_BF16 = 1, JDE_FP16 = 2, JDE_FP8 = 3, JDE_FP6 = 4, JDE_FP4 = 5 } jde_precision;
 
 typedef struct {
     int base_ch;             /* stem width c0 (32 for Darknet-53)                       */
@@ -257,6 +260,11 @@ jde_status jde_sparse_emb(jde_ctx* ctx, int on);
 /* Host helper: x (host, n floats) -> OCP e4m3 codes (host, n bytes), round to
  * nearest even, saturating at +-448, NaN -> 0x7f; the encoding of the weights. */
 void jde_fp8_encode(const float* x, uint8_t* out, size_t n);
+/* Host helper: x (host, n floats) -> codes of FP6 E2M3 (fmt 2) or FP4 E2M1
+ * (fmt 4), one code per byte in its low 6 / 4 bits (sign in the top one), round
+ * to nearest even, saturating at +-7.5 / +-6; the encoding of those weights.
+ * Any other fmt leaves out unchanged. */
+void jde_mx_encode(int fmt, const float* x, uint8_t* out, size_t n);
 
 /* Post-processing of Appendix A items 1-3 plus embedding normalisation, for
  * every frame of the batch: anchor decode, keep iff score >= conf_thr

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libjde.so")
 
 JDE_OK, JDE_EINVAL, JDE_ENOMEM, JDE_EDEVICE, JDE_ECAPACITY, JDE_EUNSUPPORTED, JDE_ESTATE, JDE_EBUDGET = \
     0, -1, -2, -3, -4, -5, -6, -7
-JDE_FP32, JDE_BF16, JDE_FP16, JDE_FP8 = 0, 1, 2, 3
+JDE_FP32, JDE_BF16, JDE_FP16, JDE_FP8, JDE_FP6, JDE_FP4 = 0, 1, 2, 3, 4, 5
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
 c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -112,6 +112,8 @@ SIGNATURES = {
     "jde_window_convs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_sparse_emb": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_fp8_encode": (None, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t]),
+    "jde_mx_encode": (None, [ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint8),
+                             ctypes.c_size_t]),
     "jde_profile_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p, c_int_p, c_int_p,
                                            c_int_p]),
@@ -155,7 +157,7 @@ def load():
 
 _host = None
 HOST_CALLS = ("jde_kf_initiate", "jde_kf_initiate_n", "jde_kf_predict", "jde_kf_update", "jde_kf_update_n",
-              "jde_assign", "jde_fp8_encode", "jde_box_to_z")
+              "jde_assign", "jde_fp8_encode", "jde_mx_encode", "jde_box_to_z")
 
 
 def load_host():

@@ -93,6 +93,7 @@ struct jde_ctx {
     int n_backbone_ops = 0;
     bool fp8 = false, fp8_ready = false, calibrating = false;
     bool fp8_blocks = true;   // FP8 activations with an E8M0 scale per pixel and 32 channels
+    int mx_fmt = 0;           // element format of the FP8-class convs: 0 e4m3, 2 FP6 E2M3, 4 FP4 E2M1
     // The stem and the first downsample conv run as one launch (16-bit storage),
     // and so do the two convs of each 64- and 128-channel residual block.
     // launch_kind[i] records how op i ran in the latest forward: 0 = its own
@@ -411,8 +412,11 @@ GeomParams geom_params(const jde_frame_desc* d, int n) {
 // An FP8 op runs on e4m3 operands once its activation scales are known: always
 // with per-block activation scales, after calibration with per-tensor ones.
 bool runs_fp8(const jde_ctx* c, const Op& o) {
-    return o.fp8 && !c->calibrating && (c->fp8_blocks || c->fp8_ready);
+    return o.fp8 && !c->calibrating && (c->fp8_blocks || c->mx_fmt != 0 || c->fp8_ready);
 }
+
+// Bits per element of the block-scaled formats (mx_fmt 0 e4m3, 2 FP6 E2M3, 4 FP4 E2M1).
+static int mx_bits(int fmt) { return fmt == 0 ? 8 : (fmt == 2 ? 6 : 4); }
 
 // Arguments of conv op `o` for a batch (d, n) with workspace W and head outputs `out`.
 ConvArgs conv_args(const jde_ctx* c, const Op& o, const jde_frame_desc* d, int n, bool uniform, char* W,
@@ -472,9 +476,11 @@ ConvArgs conv_args(const jde_ctx* c, const Op& o, const jde_frame_desc* d, int n
         a.w = wb + o.dev_w8;
         a.wscale = (const float*)(wb + o.dev_ws);
         a.wbscale = (const unsigned char*)(wb + o.dev_wbs);
-        a.act_blocks = c->fp8_blocks ? 1 : 0;
-        a.in_scale = c->fp8_blocks ? 1.f : o.in_scale;
-        a.w_bytes = o.cout * a.K;
+        a.mx_fmt = c->mx_fmt;
+        const bool blocks = c->fp8_blocks || c->mx_fmt != 0;
+        a.act_blocks = blocks ? 1 : 0;
+        a.in_scale = blocks ? 1.f : o.in_scale;
+        a.w_bytes = o.cout * (a.K / 8 * mx_bits(c->mx_fmt));
     }
     if (c->calibrating && op_index >= 0) a.amax = (unsigned*)(W + c->ws_amax) + op_index;
     return a;
@@ -557,14 +563,40 @@ uint16_t f32_to_bf16_rne(float x) {
 }
 // OCP FP8 e4m3 (bias 7, 3 mantissa bits, no infinities, max 448), round to
 // nearest even, saturating at +-448; NaN -> 0x7f.
-// E8M0 exponent byte (127 + s) of the smallest 2^s with m / 2^s <= 448 (m >= 0,
+// Largest value of the element format (mx_fmt 0 e4m3, 2 FP6 E2M3, 4 FP4 E2M1).
+static float mx_top(int fmt) { return fmt == 0 ? 448.f : (fmt == 2 ? 7.5f : 6.f); }
+
+// E8M0 exponent byte (127 + s) of the smallest 2^s with m / 2^s <= top (m >= 0,
 // 127 for m = 0); the device conversion of activation blocks computes the same.
-int e8m0_for_amax_host(float m) {
+int e8m0_for_amax_host(float m, float top) {
     if (!(m > 0.f)) return 127;
-    int E;
-    const float f = 2.f * frexpf(m, &E);   // m = f * 2^(E - 1), f in [1, 2)
-    const int e = 127 + (E - 1) - 8 + (f > 1.75f ? 1 : 0);
+    int E, Et;
+    const float f = 2.f * frexpf(m, &E);     // m = f * 2^(E - 1), f in [1, 2)
+    const float ft = 2.f * frexpf(top, &Et);  // top = ft * 2^(Et - 1)
+    const int e = 127 + (E - 1) - (Et - 1) + (f > ft ? 1 : 0);
     return e < 0 ? 0 : (e > 254 ? 254 : e);
+}
+
+// FP6 E2M3 (fmt 2) / FP4 E2M1 (fmt 4) code of the value nearest x, ties to even,
+// saturating: in binade e >= emin = 0 the spacing is 2^(e - M), below 1 it stays
+// 2^-M (subnormals); n = the significand in units of the spacing.
+unsigned mx_code_host(int fmt, float x) {
+    const int M = fmt == 2 ? 3 : 1, bits = fmt == 2 ? 6 : 4;
+    const unsigned sign = std::signbit(x) ? 1u : 0u;
+    const float a = std::min(fabsf(x), mx_top(fmt));
+    if (!(a > 0.f)) return sign << (bits - 1);
+    int E;
+    frexpf(a, &E);                         // a in [2^(E-1), 2^E)
+    const int e = std::max(E - 1, 0);
+    const int n = (int)nearbyintf(ldexpf(a, M - e));   // the default rounding mode is to nearest even
+    unsigned code;
+    if (n < (1 << M)) {
+        code = (unsigned)n;
+    } else {
+        const int up = n >> (M + 1);
+        code = ((unsigned)(e + up + 1) << M) | (up ? 0u : (unsigned)(n - (1 << M)));
+    }
+    return code | (sign << (bits - 1));
 }
 
 uint8_t f32_to_e4m3(float x) {
@@ -667,7 +699,7 @@ jde_status jde_create(const jde_config* cfg, jde_ctx** out) {
         if (g.blocks[i] < 0 || g.blocks[i] > 64) return fail(JDE_EINVAL, "blocks[%d] out of range", i);
     if (g.num_anchors != 4) return fail(JDE_EUNSUPPORTED, "num_anchors must be 4");
     if (g.emb_dim <= 0 || g.emb_dim % 64) return fail(JDE_EINVAL, "emb_dim must be a positive multiple of 64");
-    if (g.precision != JDE_FP32 && g.precision != JDE_BF16 && g.precision != JDE_FP16 && g.precision != JDE_FP8)
+    if (g.precision < JDE_FP32 || g.precision > JDE_FP4)
         return fail(JDE_EUNSUPPORTED, "precision %d not implemented", g.precision);
     if (g.max_frames <= 0 || g.max_frames > kMaxFrames) return fail(JDE_EINVAL, "max_frames must be 1..%d", kMaxFrames);
     if (g.max_h <= 0 || g.max_w <= 0 || g.max_h % 32 || g.max_w % 32)
@@ -693,7 +725,8 @@ jde_status jde_create(const jde_config* cfg, jde_ctx** out) {
     c->cfg = g;
     c->cap_pix = cap_pix;
     c->et = g.precision == JDE_FP32 ? kF32 : (g.precision == JDE_FP16 ? kF16 : kBF16);
-    c->fp8 = g.precision == JDE_FP8;
+    c->fp8 = g.precision == JDE_FP8 || g.precision == JDE_FP6 || g.precision == JDE_FP4;
+    c->mx_fmt = g.precision == JDE_FP6 ? 2 : (g.precision == JDE_FP4 ? 4 : 0);
     build_plan(c);
     plan_fp8(c);
     plan_arena(c);
@@ -845,18 +878,34 @@ jde_status jde_load_weights(jde_ctx* c, const float* blob, size_t nf, void* d_we
                     // 32-k block b the E8M0 exponent e_b that brings the block's max |w / sc|
                     // to at most 448 (e_b <= 127: blocks below the channel's range are
                     // scaled up into e4m3's normal range).
+                    // FP6 / FP4: the same with the format's largest value, codes packed
+                    // EB bits each, value k of the row at bit EB k (little-endian).
+                    const int fmt = c->mx_fmt, eb_bits = mx_bits(fmt);
+                    const float top = mx_top(fmt);
                     float amax = 0.f;
                     for (int k = 0; k < K; ++k) amax = std::max(amax, fabsf(w[(size_t)co * K + k]));
-                    const float sc = amax > 0.f ? amax / 448.f : 1.f;
+                    const float sc = amax > 0.f ? amax / top : 1.f;
                     memcpy(host.data() + o.dev_ws + row * 4, &sc, 4);
+                    unsigned char* wrow = host.data() + o.dev_w8 + row * (size_t)(K / 8 * eb_bits);
                     for (int kb = 0; kb < K / 32; ++kb) {
                         float bm = 0.f;
                         for (int k = 32 * kb; k < 32 * kb + 32; ++k)
                             bm = std::max(bm, fabsf(w[(size_t)co * K + k] / sc));
-                        const int e = e8m0_for_amax_host(bm);
+                        const int e = e8m0_for_amax_host(bm, top);
                         host[o.dev_wbs + row * (K / 32) + kb] = (unsigned char)e;
-                        for (int k = 32 * kb; k < 32 * kb + 32; ++k)
-                            host[o.dev_w8 + row * K + k] = f32_to_e4m3(ldexpf(w[(size_t)co * K + k] / sc, 127 - e));
+                        for (int k = 32 * kb; k < 32 * kb + 32; ++k) {
+                            const float v = ldexpf(w[(size_t)co * K + k] / sc, 127 - e);
+                            if (fmt == 0) {
+                                wrow[k] = f32_to_e4m3(v);
+                            } else {
+                                const unsigned code = mx_code_host(fmt, v);
+                                for (int bb = 0; bb < eb_bits; ++bb)
+                                    if ((code >> bb) & 1) {
+                                        const size_t bit = (size_t)k * eb_bits + bb;
+                                        wrow[bit / 8] |= (unsigned char)(1u << (bit % 8));
+                                    }
+                            }
+                        }
                     }
                 }
             }
@@ -1442,6 +1491,7 @@ jde_status jde_calibrate(jde_ctx* c, const float* frames, const jde_frame_desc* 
 jde_status jde_fp8_block_scales(jde_ctx* c, int on) {
     if (!c) return fail(JDE_EINVAL, "null context");
     if (!c->fp8) return fail(JDE_EUNSUPPORTED, "block scales apply to FP8 contexts");
+    if (c->mx_fmt != 0 && !on) return fail(JDE_EUNSUPPORTED, "FP6 / FP4 activations always take block scales");
     c->fp8_blocks = on != 0;
     return JDE_OK;
 }
@@ -1479,6 +1529,11 @@ jde_status jde_fp8_scales(const jde_ctx* c, float* in_scales, int n_ops) {
 
 void jde_fp8_encode(const float* x, uint8_t* out, size_t n) {
     for (size_t i = 0; i < n; ++i) out[i] = f32_to_e4m3(x[i]);
+}
+
+void jde_mx_encode(int fmt, const float* x, uint8_t* out, size_t n) {
+    if (fmt != 2 && fmt != 4) return;
+    for (size_t i = 0; i < n; ++i) out[i] = (uint8_t)mx_code_host(fmt, x[i]);
 }
 
 struct jde_graph {

@@ -1566,26 +1566,62 @@ hipError_t launch_conv3w(const ConvArgs& a, int et, int pixel_tiles, hipStream_t
 //   is 1 with block scales).  Requires Cin % 128 == 0 (every chunk lies within
 //   one tap) and no concat input.
 // ---------------------------------------------------------------------------
-// E8M0 exponent byte (127 + s) of the smallest power of two 2^s with m / 2^s <= 448
-// (the largest e4m3 value, 1.75 * 2^8), for m = max |x| >= 0 of a block: with
-// m = f * 2^E, f in [1, 2), s = E - 8 when f <= 1.75, else E - 7.  0 for m = 0.
+// Element formats of the block-scaled MFMA operands (the instruction's format code):
+// 0 = e4m3 (8 bits), 2 = FP6 E2M3 (6 bits), 4 = FP4 E2M1 (4 bits).
+template <int FMT> struct MxFmt;
+template <> struct MxFmt<0> { static constexpr int bits = 8, mant = 3, emin = -6, top_e = 8; static constexpr unsigned top_m = 0x600000; };
+template <> struct MxFmt<2> { static constexpr int bits = 6, mant = 3, emin = 0, top_e = 2; static constexpr unsigned top_m = 0x700000; };
+template <> struct MxFmt<4> { static constexpr int bits = 4, mant = 1, emin = 0, top_e = 2; static constexpr unsigned top_m = 0x400000; };
+
+// E8M0 exponent byte (127 + s) of the smallest power of two 2^s with m / 2^s <= top,
+// the format's largest value f_t * 2^top_e (e4m3: 1.75 * 2^8, E2M3: 1.875 * 2^2,
+// E2M1: 1.5 * 2^2), for m = max |x| >= 0 of a block: with m = f * 2^E, f in [1, 2),
+// s = E - top_e when f <= f_t, else E - top_e + 1.  127 (s = 0) for m = 0.
+template <int FMT>
 __device__ __forceinline__ int e8m0_for_amax(float m) {
     const unsigned b = __float_as_uint(m);
     if (m == 0.f) return 127;
     const int eb = (int)(b >> 23) & 0xff;   // biased exponent (m is finite and >= 0)
-    const int mant = (int)(b & 0x7fffff);
-    const int e = eb - 8 + (mant > 0x600000 ? 1 : 0);
+    const unsigned mant = b & 0x7fffff;
+    const int e = eb - MxFmt<FMT>::top_e + (mant > MxFmt<FMT>::top_m ? 1 : 0);
     return e < 0 ? 0 : (e > 254 ? 254 : e);
 }
 
-template <int BM, int BN, int WGM, int WGN, bool BLK>
+// Code of the FP6 E2M3 / FP4 E2M1 value nearest x (ties to even), x already within
+// the format's range: in binade e >= emin the spacing is 2^(e - M), below 2^emin it
+// stays 2^(emin - M); n = rint(|x| / spacing) is the significand in units of the
+// spacing (2^M <= n <= 2^(M+1) for a normal result, n < 2^M for a subnormal one).
+template <int FMT>
+__device__ __forceinline__ unsigned mx_code(float x) {
+    constexpr int M = MxFmt<FMT>::mant, EMIN = MxFmt<FMT>::emin, BITS = MxFmt<FMT>::bits;
+    const unsigned sign = __float_as_uint(x) >> 31;
+    const float a = fabsf(x);
+    int e = (int)((__float_as_uint(a) >> 23) & 0xff) - 127;
+    e = e < EMIN ? EMIN : e;
+    const int n = (int)rintf(__builtin_amdgcn_ldexpf(a, M - e));
+    unsigned code;
+    if (n < (1 << M)) {                      // subnormal (e == EMIN) or zero
+        code = (unsigned)n;
+    } else {
+        const int up = n >> (M + 1);          // rounded up into the next binade
+        const unsigned mm = up ? 0u : (unsigned)(n - (1 << M));
+        code = ((unsigned)(e + up - EMIN + 1) << M) | mm;
+    }
+    return code | (sign << (BITS - 1));
+}
+
+template <int BM, int BN, int WGM, int WGN, bool BLK, int FMT = 0>
 __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
-    constexpr int BK = 128;                  // fp8 elements (bytes) per chunk
-    constexpr int LDR = BK + 16;             // padded LDS row, bytes
+    constexpr int BK = 128;                  // elements per chunk (one MFMA's K)
+    constexpr int EB = MxFmt<FMT>::bits;     // bits per element
+    constexpr int RB = BK * EB / 8;          // bytes of a row's chunk: 128 / 96 / 64
+    constexpr int LDR = RB + 16;             // padded LDS row, bytes
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
     constexpr int TM = WTM / 16, TN = WTN / 16;
     constexpr int VRB = BK / 8;              // 16-byte BF16 loads per pixel row and chunk
-    constexpr int VRA = BK / 16;             // 16-byte FP8 loads per weight row and chunk
+    constexpr int VRA = RB / 16;             // 16-byte loads per weight row and chunk
+    constexpr float TOP = FMT == 0 ? 448.f : (FMT == 2 ? 7.5f : 6.f);   // largest element value
+    static_assert(FMT == 0 || BLK, "FP6 / FP4 operands take block scales");
     constexpr int BVEC = BM * VRB, AVEC = BN * VRA;
     constexpr int BPT = (BVEC + 255) / 256, APT = (AVEC + 255) / 256;
     static_assert(WGM * WGN == 4 && TM >= 1 && TN >= 1, "tile");
@@ -1646,19 +1682,19 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
             b_hw[i] = (h << 16) | w;
         }
     }
-    int a_off[APT];
+    int a_off[APT];   // byte offsets into the packed weight rows (K EB / 8 bytes per row)
 #pragma unroll
     for (int i = 0; i < APT; ++i) {
         const int v = tid + i * 256;
         const int row = v / VRA, kv = v % VRA;
-        a_off[i] = (v < AVEC && n0 + row < a.cout) ? (n0 + row) * a.K + kv * 16 : -1;
+        a_off[i] = (v < AVEC && n0 + row < a.cout) ? (n0 + row) * (a.K / 8 * EB) + kv * 16 : -1;
     }
 
     int ld_ci = 0, ld_r = 0, ld_s = 0;
     i32x4 ra2[2][APT], rb2[2][BPT];
     unsigned rs2[2];
-    auto load_chunk = [&](int kc, i32x4 (&ra)[APT], i32x4 (&rb)[BPT], unsigned& rs) {
-        const int k0 = kc * BK;
+    auto load_chunk = [&](int kc, i32x4 (&ra)[APT], i32x4 (&rb)[BPT], unsigned& rs) __attribute__((always_inline)) {
+        const int k0 = kc * RB;
 #pragma unroll
         for (int i = 0; i < APT; ++i)
             ra[i] = __builtin_amdgcn_raw_buffer_load_b128(r_w, a_off[i] >= 0 ? a_off[i] + k0 : kOOB, 0, 0);
@@ -1679,10 +1715,12 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
         ld_s = wrap2 ? 0 : ld_s;
         ld_r += wrap2;
     };
-    // 8 BF16 values -> 8 e4m3 bytes (two dwords), scaled and saturated.  BLK: every
-    // lane of the quad that holds one pixel's 32-channel block computes the block's
-    // exponent (returned in *e8) and scales by it exactly.
-    auto to_fp8 = [&](i32x4 v, int* e8) {
+    // 8 BF16 values -> 8 elements (e4m3: two dwords; E2M3: 48 bits, low dword then
+    // the high 16 bits; E2M1: one dword), scaled and saturated; element q of the 8
+    // sits at bits EB q.  BLK: every lane of the quad that holds one pixel's
+    // 32-channel block computes the block's exponent (returned in *e8) and scales by
+    // it exactly.
+    auto to_fp8 = [&](i32x4 v, int* e8) __attribute__((always_inline)) {
         float f[8];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -1696,23 +1734,30 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
             // max over the quad (lanes 4j .. 4j+3 of the wave hold one block)
             m = fmaxf(m, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(m), 0xB1, 0xF, 0xF, true)));
             m = fmaxf(m, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(m), 0x4E, 0xF, 0xF, true)));
-            const int e = e8m0_for_amax(m);
+            const int e = e8m0_for_amax<FMT>(m);
             *e8 = e;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) f[q] = fminf(fmaxf(__builtin_amdgcn_ldexpf(f[q], 127 - e), -448.f), 448.f);
+            for (int q = 0; q < 8; ++q) f[q] = fminf(fmaxf(__builtin_amdgcn_ldexpf(f[q], 127 - e), -TOP), TOP);
         } else {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) f[q] = fminf(fmaxf(f[q] * inv_scale, -448.f), 448.f);
+            for (int q = 0; q < 8; ++q) f[q] = fminf(fmaxf(f[q] * inv_scale, -TOP), TOP);
         }
-        int lo = 0, hi = 0;
-        lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[0], f[1], lo, false);
-        lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[2], f[3], lo, true);
-        hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[4], f[5], hi, false);
-        hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[6], f[7], hi, true);
-        return i32x2{lo, hi};
+        if constexpr (FMT == 0) {
+            int lo = 0, hi = 0;
+            lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[0], f[1], lo, false);
+            lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[2], f[3], lo, true);
+            hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[4], f[5], hi, false);
+            hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[6], f[7], hi, true);
+            return i32x2{lo, hi};
+        } else {
+            unsigned long long bits = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) bits |= (unsigned long long)mx_code<FMT>(f[q]) << (EB * q);
+            return i32x2{(int)(unsigned)bits, (int)(unsigned)(bits >> 32)};
+        }
     };
     static_assert(BVEC % 256 == 0, "every lane converts: the quad exchange needs all four lanes");
-    auto store_chunk = [&](int buf, const i32x4 (&ra)[APT], const i32x4 (&rb)[BPT], unsigned rs) {
+    auto store_chunk = [&](int buf, const i32x4 (&ra)[APT], const i32x4 (&rb)[BPT], unsigned rs) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < APT; ++i) {
             const int v = tid + i * 256;
@@ -1724,7 +1769,16 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
             const int v = tid + i * 256;
             int e8 = 127;
             const i32x2 q = to_fp8(rb[i], &e8);
-            *(i32x2*)(&sB[buf][(v / VRB) * LDR + (v % VRB) * 8]) = q;
+            unsigned char* dst = &sB[buf][(v / VRB) * LDR + (v % VRB) * EB];
+            if constexpr (FMT == 0) {
+                *(i32x2*)dst = q;
+            } else if constexpr (FMT == 4) {
+                *(int*)dst = q[0];
+            } else {  // 6 bytes at a 2-byte-aligned offset
+                ((unsigned short*)dst)[0] = (unsigned short)((unsigned)q[0] & 0xffff);
+                ((unsigned short*)dst)[1] = (unsigned short)((unsigned)q[0] >> 16);
+                ((unsigned short*)dst)[2] = (unsigned short)((unsigned)q[1] & 0xffff);
+            }
             if constexpr (BLK) {
                 // lane 4j of the quad writes the block's exponent: row v / VRB, block (v % VRB) / 4
                 if ((v & 3) == 0) ((unsigned char*)sBs[buf])[(v / VRB) * 4 + (v % VRB) / 4] = (unsigned char)e8;
@@ -1738,15 +1792,29 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int arow = wn * WTN + (lane & 15), brow = wm * WTM + (lane & 15);
-    // The matrix core takes a lane's 32 bytes as two 16-value halves: lane group g
-    // (lane / 16) supplies k = 16 g .. 16 g + 15 in bytes 0-15 and k = 64 + 16 g ..
-    // in bytes 16-31, and the block scale of lane group b covers k = 32 b .. 32 b +
-    // 31 (groups 2 (b % 2) and 2 (b % 2) + 1, half b / 2).  Reading the chunk's
-    // bytes 16 g and 64 + 16 g puts chunk k = 32 b .. 32 b + 31 -- one weight or
-    // activation scale block -- exactly where lane group b's scale applies.
-    const int kofs = (lane >> 4) * 16;
+    // e4m3: the matrix core takes a lane's 32 bytes as two 16-value halves: lane
+    // group g (lane / 16) supplies k = 16 g .. 16 g + 15 in bytes 0-15 and k = 64 +
+    // 16 g .. in bytes 16-31, and the block scale of lane group b covers k = 32 b ..
+    // 32 b + 31 (groups 2 (b % 2) and 2 (b % 2) + 1, half b / 2).  Reading the
+    // chunk's bytes 16 g and 64 + 16 g puts chunk k = 32 b .. 32 b + 31 -- one weight
+    // or activation scale block -- exactly where lane group b's scale applies.
+    // FP6 / FP4: lane group g's 32 packed values (24 / 16 bytes) are all of block g,
+    // so it reads the chunk's values 32 g .. 32 g + 31 as they lie.
+    const int kofs = (lane >> 4) * (FMT == 0 ? 16 : 32 * EB / 8);
     const int kblk = lane >> 4;   // the 32-k block this lane feeds
-    auto compute = [&](int buf) {
+    auto operand = [&](const unsigned char* p) __attribute__((always_inline)) -> i32x8 {
+        if constexpr (FMT == 0) {
+            const i32x4 x0 = *(const i32x4*)p, x1 = *(const i32x4*)(p + 64);
+            return i32x8{x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
+        } else if constexpr (FMT == 4) {
+            const i32x4 x0 = *(const i32x4*)p;
+            return i32x8{x0[0], x0[1], x0[2], x0[3], 0, 0, 0, 0};
+        } else {  // 24 bytes at an 8-byte-aligned offset
+            const i32x2 x0 = *(const i32x2*)p, x1 = *(const i32x2*)(p + 8), x2 = *(const i32x2*)(p + 16);
+            return i32x8{x0[0], x0[1], x1[0], x1[1], x2[0], x2[1], 0, 0};
+        }
+    };
+    auto compute = [&](int buf) __attribute__((always_inline)) {
         const unsigned char* A = sA[buf];
         const unsigned char* B = sB[buf];
         i32x8 af[TN], bfr[TM];
@@ -1757,23 +1825,15 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
         for (int i = 0; i < TM; ++i)
             sb[i] = BLK ? ((const unsigned char*)sBs[buf])[(brow + i * 16) * 4 + kblk] : 127;
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const unsigned char* p = A + (arow + j * 16) * LDR + kofs;
-            const i32x4 x0 = *(const i32x4*)p, x1 = *(const i32x4*)(p + 64);
-            af[j] = i32x8{x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
-        }
+        for (int j = 0; j < TN; ++j) af[j] = operand(A + (arow + j * 16) * LDR + kofs);
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const unsigned char* p = B + (brow + i * 16) * LDR + kofs;
-            const i32x4 x0 = *(const i32x4*)p, x1 = *(const i32x4*)(p + 64);
-            bfr[i] = i32x8{x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
-        }
+        for (int i = 0; i < TM; ++i) bfr[i] = operand(B + (brow + i * 16) * LDR + kofs);
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[j], bfr[i], acc[i][j], 0, 0, 0,
-                                                                             sa[j], 0, sb[i]);
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[j], bfr[i], acc[i][j], FMT, FMT,
+                                                                             0, sa[j], 0, sb[i]);
     };
 
     const int nk = a.K / BK;
@@ -1782,7 +1842,7 @@ __global__ __launch_bounds__(256) void conv_igemm_f8(ConvArgs a) {
     store_chunk(0, ra2[0], rb2[0], rs2[0]);
     load_chunk(2, ra2[0], rb2[0], rs2[0]);
     __syncthreads();
-    auto iter = [&](int kc, auto cur_c) {
+    auto iter = [&](int kc, auto cur_c) __attribute__((always_inline)) {
         constexpr int cur = decltype(cur_c)::value;
         store_chunk(cur ^ 1, ra2[cur ^ 1], rb2[cur ^ 1], rs2[cur ^ 1]);
         load_chunk(kc + 3, ra2[cur ^ 1], rb2[cur ^ 1], rs2[cur ^ 1]);
@@ -1812,7 +1872,13 @@ template <int C>
 static hipError_t launch_f8(const ConvArgs& a, hipStream_t s) {
     constexpr TileCfg8 t = kTiles8[C];
     dim3 grid(((a.M + t.bm - 1) / t.bm) * ((a.cout + t.bn - 1) / t.bn));
-    if (a.act_blocks)
+    if (a.mx_fmt == 4 && a.act_blocks)
+        conv_igemm_f8<t.bm, t.bn, t.wgm, t.wgn, true, 4><<<grid, 256, 0, s>>>(a);
+    else if (a.mx_fmt == 2 && a.act_blocks)
+        conv_igemm_f8<t.bm, t.bn, t.wgm, t.wgn, true, 2><<<grid, 256, 0, s>>>(a);
+    else if (a.mx_fmt != 0)
+        return hipErrorInvalidValue;   // FP6 / FP4 activations take block scales
+    else if (a.act_blocks)
         conv_igemm_f8<t.bm, t.bn, t.wgm, t.wgn, true><<<grid, 256, 0, s>>>(a);
     else
         conv_igemm_f8<t.bm, t.bn, t.wgm, t.wgn, false><<<grid, 256, 0, s>>>(a);

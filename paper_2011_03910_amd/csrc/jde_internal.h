@@ -71,6 +71,7 @@ struct ConvArgs {
     float in_scale;        // FP8: per-tensor scale of the input activations (x ~= in_scale * q);
                            // 1 with act_blocks
     int act_blocks;        // FP8: input activations take an E8M0 scale per pixel and 32 channels
+    int mx_fmt;            // element format of the block-scaled operands: 0 e4m3, 2 FP6 E2M3, 4 FP4 E2M1
     int in_bytes, in2_bytes, w_bytes;  // sizes of the in / in2 / w buffers (< 2^31): loads past them read 0
     int n_major;           // tile order per XCD: 1 = pixel tiles of a channel range (weights dominate)
     unsigned* amax;        // calibration: max |out0| folded in with atomicMax on the float bits, or null

@@ -11,9 +11,10 @@ import numpy as np
 
 from . import _lib
 from ._lib import (JdeConfig, JdeFrameDesc, JdeHeadOut, JdeDets, check, load, load_host,  # noqa: F401
-                   JDE_FP32, JDE_BF16, JDE_FP16, JDE_FP8)
+                   JDE_FP32, JDE_BF16, JDE_FP16, JDE_FP8, JDE_FP6, JDE_FP4)
 
-PRECISIONS = {"fp32": JDE_FP32, "bf16": JDE_BF16, "fp16": JDE_FP16, "fp8": JDE_FP8}
+PRECISIONS = {"fp32": JDE_FP32, "bf16": JDE_BF16, "fp16": JDE_FP16, "fp8": JDE_FP8, "fp6": JDE_FP6,
+              "fp4": JDE_FP4}
 
 
 def _torch():
@@ -269,6 +270,17 @@ def jde_fp8_encode(x):
     out = np.zeros(x.shape, dtype=np.uint8)
     load_host().jde_fp8_encode(x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), x.size)
+    return out
+
+
+def jde_mx_encode(fmt, x):
+    """Host FP6 E2M3 (fmt 'fp6') / FP4 E2M1 (fmt 'fp4') encoding (RNE, saturating)
+    of a float array -> one code per uint8."""
+    f = {"fp6": 2, "fp4": 4}[fmt]
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.zeros(x.shape, dtype=np.uint8)
+    load_host().jde_mx_encode(f, x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), x.size)
     return out
 
 

@@ -117,6 +117,23 @@ def fp8_layer_set(cfg):
 
 
 @functools.lru_cache(maxsize=None)
+def oracle_forward_mx(cfg_name, k, n, fmt):
+    """Oracle forward of the FP6 / FP4 network (a diagnostic: no test bound comes
+    from it): as oracle_forward_fp8 with block scales, elements of ``fmt``."""
+    from oracle.network import forward, round_bf16, quantize_blocks, quantize_per_channel_blocks
+    cfg = TINY if cfg_name == "tiny" else FULL
+    layers = weights(cfg_name, k)
+    f8 = fp8_layer_set(cfg)
+    lq = [layers[0]] + [(quantize_per_channel_blocks(w, fmt)[0] if i in f8 else round_bf16(w), b)
+                        for i, (w, b) in enumerate(layers[1:], 1)]
+
+    def quant(i, x):
+        return quantize_blocks(x, fmt) if i in f8 else x
+
+    return forward(frames(cfg_name, n), lq, cfg.blocks, store=round_bf16, in_hook=quant)
+
+
+@functools.lru_cache(maxsize=None)
 def oracle_forward_fp8(cfg_name, k, n, blocks=True):
     """Oracle forward of the FP8 network (a diagnostic: no test bound comes from it):
     BF16 storage and weights, and for each FP8 conv e4m3 weights with a per-channel

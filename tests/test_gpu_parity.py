@@ -456,6 +456,37 @@ def test_fp8_backbone_parity(torch, cfg_name, k, blocks):
     check_bar(v, ref, d, r, emul=emul)
 
 
+# OCP microscaling FP6 E2M3 and FP4 E2M1 (3 and 1 mantissa bits) on the same convs,
+# a precision study beyond the paper: further from the bar than e4m3.
+MX_MISSES_BAR = pytest.mark.xfail(
+    strict=True, raises=(HeadBarError, MatchBarError),
+    reason="FP6 E2M3 operands move the heads 0.17-0.45 from FP64 (emulated oracle 0.19-0.45), 17-45 % matched; "
+           "FP4 E2M1 0.32-0.92 (emulated 0.36-0.95), 0-2 % matched")
+
+
+@pytest.mark.parametrize("cfg_name,k", [("tiny", 50), pytest.param("full", 40, marks=pytest.mark.slow)])
+@pytest.mark.parametrize("fmt", ["fp6", "fp4"])
+@MX_MISSES_BAR
+def test_mx_backbone_parity(torch, cfg_name, k, fmt):
+    """FP6 E2M3 / FP4 E2M1 backbone 3x3 convs (block scales per 32 on the matrix
+    cores) held to the reduced-precision bar; the emulated oracle's error is printed
+    as a diagnostic."""
+    from tests.helpers import oracle_forward_mx
+    cfg = TINY if cfg_name == "tiny" else FULL
+    _say(f"case: {cfg_name} {fmt} b1 block scales")
+    m = _model(cfg, fmt, 1)
+    m.load_weights(weights(cfg_name, k))
+    x = torch.from_numpy(frames(cfg_name, 1)).cuda()
+    heads = m.forward(x)
+    torch.cuda.synchronize()
+    ref = oracle_forward(cfg_name, k, 1)
+    emul = oracle_forward_mx(cfg_name, k, 1, fmt)
+    v = head_views(heads, [(cfg.height, cfg.width)])
+    d = gpu_dets(m.decode(heads, [(cfg.height, cfg.width)]), 0, m.cap)
+    r = opost.detections(ref, anchors(cfg_name), 0.5, 0.4)
+    check_bar(v, ref, d, r, emul=emul)
+
+
 @pytest.mark.slow
 def test_decode_on_gpu_full_heads_dense_overflow_and_global_sort(torch):
     """Decode, sort, NMS and normalisation of the GPU's own full-frame FP32 heads

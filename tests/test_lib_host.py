@@ -226,6 +226,28 @@ def test_fp8_encoder_matches_library_cast():
     np.testing.assert_array_equal(jde_fp8_encode(big), [0x7E, 0x7E, 0xFE, 0x7F])
 
 
+@pytest.mark.parametrize("fmt,e_bits,m_bits", [("fp6", 2, 3), ("fp4", 2, 1)])
+def test_fp6_fp4_encoder_matches_the_oracle_rounding(fmt, e_bits, m_bits):
+    """The FP6 E2M3 / FP4 E2M1 weight encoder (host, product): its codes, decoded
+    by the format's definition (bias 1: E = 0 is m / 2^M, else (1 + m / 2^M)
+    2^(E - 1)), equal the oracle's nearest-even rounding with saturation, on random
+    values, every tie point between neighbouring codes and out-of-range values."""
+    from oracle.network import round_minifloat
+    from paper_2011_03910_amd.jde import jde_mx_encode
+    r = np.random.Generator(np.random.PCG64(89))
+    x = (r.standard_normal(20000) * 10.0 ** r.uniform(-3, 1.2, 20000)).astype(np.float32)
+    grid = np.unique(np.abs(round_minifloat(np.linspace(0, 8, 4001), fmt)))
+    x = np.concatenate([x, grid, -grid, (grid[1:] + grid[:-1]) / 2, [9.0, -1e6, 0.0, -0.0]]).astype(np.float32)
+    codes = jde_mx_encode(fmt, x).astype(np.int64)
+    bits = 1 + e_bits + m_bits
+    sign = np.where((codes >> (bits - 1)) & 1, -1.0, 1.0)
+    E = (codes >> m_bits) & ((1 << e_bits) - 1)
+    m = codes & ((1 << m_bits) - 1)
+    val = np.where(E == 0, m / 2.0 ** m_bits, (1 + m / 2.0 ** m_bits) * 2.0 ** (E - 1.0)) * sign
+    assert codes.max() < (1 << bits)
+    np.testing.assert_array_equal(val, round_minifloat(x.astype(np.float64), fmt))
+
+
 def test_nms_noalloc_rejects_lists_beyond_its_scratch(lib):
     """The static-scratch NMS refuses K > 8192 before any device work."""
     from paper_2011_03910_amd import _lib
