@@ -121,7 +121,7 @@ def head_errors(v, ref, frame=0, ref_frame=0, emul=None):
 
 
 def check_format_fidelity(v, ref, emul, frame=0):
-    """The block-scaled paths miss the bar by the format's own rounding; this
+    """The reduced-precision paths miss the bar by the format's own rounding; this
     checks, beside the bar, that the kernels implement the format: every head's
     error against FP64 lies within 2x (+0.05) of the error of the oracle that
     rounds the same operands to the same format (a kernel mistake -- a scale on
@@ -186,6 +186,7 @@ def test_tiny_reduced_precision_parity(torch, precision):
     v = head_views(heads, [(192, 320)])
     d = gpu_dets(m.decode(heads, [(192, 320)]), 0, m.cap)
     r = opost.detections(ref, anchors("tiny"), 0.5, 0.4)
+    check_format_fidelity(v, ref, emul)
     check_bar(v, ref, d, r, emul=emul)
 
 
@@ -336,7 +337,9 @@ def test_full_bf16_parity(torch):
     v = head_views(heads, [(608, 1088)])
     d = gpu_dets(m.decode(heads, [(608, 1088)]), 0, m.cap)
     r = opost.detections(ref, anchors("full"), 0.5, 0.4)
-    check_bar(v, ref, d, r, emul=oracle_forward_rounded("full", 40, 1, "bf16"))
+    emul = oracle_forward_rounded("full", 40, 1, "bf16")
+    check_format_fidelity(v, ref, emul)
+    check_bar(v, ref, d, r, emul=emul)
 
 
 def _stored_tiles(name):
