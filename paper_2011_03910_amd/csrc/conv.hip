@@ -667,9 +667,15 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
 // Cout (both are multiples of 4).  With a.amax set, the largest |value| stored
 // to out0 is folded into *a.amax (float bits as unsigned, non-negative).
 // ---------------------------------------------------------------------------
+// Residual tile of a 128 x 128 conv_dma tile staged in LDS (see conv_dma): pixels
+// 0-63 of the tile in half[0], 64-127 in half[1], 256 bytes (128 channels) per
+// pixel row, 16-byte slot c of row r at slot c ^ (r % 16) (16 rows of a column
+// read by 16 lanes hit 16 different slots).  m_tile, n_tile: the tile's origin.
+struct ResLds { const char* h0; const char* h1; int m_tile, n_tile; };
+
 template <typename T, int TM, int TN, int WTM, int WTN, bool NT = false>
 __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)[TM][TN], int m_base, int n_base,
-                                           int lane, const float* __restrict__ dq) {
+                                           int lane, const float* __restrict__ dq, const ResLds* rl = nullptr) {
     typedef T T4 __attribute__((ext_vector_type(4)));
     // Every load of the epilogue (bias, scales, residual) is issued before the
     // first store, so a tile pays one memory latency rather than one per 16x16
@@ -692,7 +698,13 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)
         for (int j = 0; j < TN; ++j) {
             const int cb = n_base + j * 16 + (lane >> 4) * 4;
             rv[i][j] = T4{};
-            if (res_t && m < a.M && cb < a.n_split) rv[i][j] = *(const T4*)((const T*)a.res + (size_t)m * a.ld0 + cb);
+            if (res_t && rl) {
+                const int p = m - rl->m_tile, cl = cb - rl->n_tile, r = p & 63;
+                const char* base = (p >> 6) ? rl->h1 : rl->h0;
+                rv[i][j] = *(const T4*)(base + r * 256 + (((cl >> 3) ^ (r & 15)) << 4) + (cl & 7) * 2);
+            } else if (res_t && m < a.M && cb < a.n_split) {
+                rv[i][j] = *(const T4*)((const T*)a.res + (size_t)m * a.ld0 + cb);
+            }
         }
     }
     float amax = 0.f;
@@ -1129,7 +1141,7 @@ __device__ __forceinline__ int lds_swizzle(int r) {
     else return (((r >> 1) & 1) << 2) | (((r >> 2) & 1) << 1);
 }
 
-template <typename T, int BM, int BN, int WGM, int WGN, int S, bool NT, int BK, bool DYN = false>
+template <typename T, int BM, int BN, int WGM, int WGN, int S, bool NT, int BK, bool DYN = false, bool RL = false>
 __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
     constexpr int NW = WGM * WGN;                  // waves (4 or 8)
     constexpr int WTM = BM / WGM, WTN = BN / WGN;
@@ -1305,11 +1317,44 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
     // outstanding) and this wave's operand reads of chunk k are done; barrier (so
     // for every wave; chunk k's stage is then free); issue chunk k+S into it; read
     // chunk k+1's operands; run chunk k's MFMAs.
+    // The residual of a 128 x 128 tile (32 KB of the storage type: two stages)
+    // comes into LDS by DMA during the last steps, in place of the loads of chunks
+    // past the end that those steps would issue (a wave issues the same NPW = 4
+    // instructions, so every wait count stays as it is); the epilogue then reads it
+    // from LDS instead of waiting on 16 global loads per lane.  Step nk - S writes
+    // pixels 0-63 into chunk nk - S's stage, step nk - S + 1 pixels 64-127 into the
+    // next one: both stages' operands are in registers by then.
+    // RL: launches with a residual of the storage type on an eligible tile (the
+    // launcher picks the form, so convs without a residual keep the plain kernel)
+    static_assert(!RL || (BM == 128 && BN == 128 && BK == 32 && NW == 4 && sizeof(T) == 2), "residual in LDS");
+    const bool res_lds = RL && a.res && !a.out0_f32 && nk >= S + 1;
+    int res_st0 = 0, res_st1 = 1;   // stage of each half
+    auto res_issue = [&](auto st_c, auto h_c) {
+        constexpr int st = decltype(st_c)::value, h = decltype(h_c)::value;
+        const char* sp = st == 0 ? st0 : st == 1 ? st1 : st == 2 ? st2 : st3;
+        const __amdgpu_buffer_rsrc_t r_res = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)a.res, 0, (int)((size_t)a.M * a.ld0 * sizeof(T) < 0x7fffffff ? (size_t)a.M * a.ld0 * sizeof(T)
+                                                                                    : 0x7fffffff), kBufFlags);
+#pragma unroll
+        for (int i = 0; i < NPW; ++i) {
+            const int q = NW * i + wave;                 // 1-KB instruction: pixel rows 4q .. 4q + 3 of the half
+            const int r = 4 * q + (lane >> 4), c = (lane & 15) ^ (r & 15);
+            const int m = m0 + 64 * h + r, ch = n0 + 8 * c;
+            const bool ok = m < a.M && ch < a.n_split;
+            dma16(r_res, sp + q * 1024, ok ? (int)(((size_t)m * a.ld0 + ch) * sizeof(T)) : kOOB);
+        }
+        if constexpr (h == 0) res_st0 = st; else res_st1 = st;
+    };
     auto step = [&](auto u_c, int k) {
         constexpr int u = decltype(u_c)::value;
         __builtin_amdgcn_s_waitcnt(waitcnt_imm((S - 2) * NPW, 0));
         __builtin_amdgcn_s_barrier();
-        issue(std::integral_constant<int, u % S>{});
+        if (res_lds && k == nk - S)
+            res_issue(std::integral_constant<int, u % S>{}, std::integral_constant<int, 0>{});
+        else if (res_lds && k == nk - S + 1)
+            res_issue(std::integral_constant<int, u % S>{}, std::integral_constant<int, 1>{});
+        else
+            issue(std::integral_constant<int, u % S>{});
         if (k + 1 < nk) read(std::integral_constant<int, (u + 1) % S>{}, std::integral_constant<int, (u + 1) & 1>{});
         mma(std::integral_constant<int, u & 1>{});
     };
@@ -1333,7 +1378,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
     // no DMA may still be writing LDS when the workgroup ends (or starts its next tile)
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
 
-    store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
+    if (res_lds) {
+        __syncthreads();   // every wave's share of the residual has landed
+        auto stp = [&](int st) -> const char* { return st == 0 ? st0 : st == 1 ? st1 : st == 2 ? st2 : st3; };
+        const ResLds rl{stp(res_st0), stp(res_st1), m0, n0};
+        store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr, &rl);
+    } else {
+        store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
+    }
     if constexpr (!DYN) break;
     // every wave is done reading this tile's stages before the next tile's DMAs refill them
     __syncthreads();
@@ -2593,6 +2645,17 @@ int conv_default_tile(int et, const ConvArgs& a) {
     return best;
 }
 
+// conv_dma tiles that take a residual through LDS (128 x 128, 32-channel chunks, 4 waves)
+template <typename T, int C>
+constexpr bool res_lds_tile() {
+    return kTiles[C].st > 0 && kTiles[C].bm == 128 && kTiles[C].bn == 128 && kTiles[C].bk == 32 &&
+           kTiles[C].wgm * kTiles[C].wgn == 4 && sizeof(T) == 2;
+}
+template <typename T, int C>
+static bool res_lds_launch(const ConvArgs& a) {
+    return res_lds_tile<T, C>() && a.res && !a.out0_f32;
+}
+
 template <typename T, int C>
 static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
     if constexpr (!tile_built<T>(C) || kTiles[C].pw) {  // pointwise tiles: launch_pw
@@ -2612,7 +2675,9 @@ static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
                     return hipGetLastError();
                 };
                 if constexpr (t.st > 0)
-                    return go(conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk, true>);
+                    return res_lds_launch<T, C>(a) ? go(conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk, true,
+                                                              res_lds_tile<T, C>()>)
+                                                   : go(conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk, true>);
                 else if (aligned)
                     return go(conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, true, true>);
                 else if constexpr (C == 5)
@@ -2625,7 +2690,11 @@ static hipError_t launch_t(const ConvArgs& a, bool aligned, hipStream_t s) {
         }
         dim3 grid(tiles);
         if constexpr (t.st > 0)
-            conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk><<<grid, block, 0, s>>>(a);
+            if (res_lds_launch<T, C>(a))
+                conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk, false, res_lds_tile<T, C>()>
+                    <<<grid, block, 0, s>>>(a);
+            else
+                conv_dma<T, t.bm, t.bn, t.wgm, t.wgn, t.st, t.nt != 0, t.bk><<<grid, block, 0, s>>>(a);
         else if (aligned)
             conv_igemm<T, t.bm, t.bn, t.wgm, t.wgn, t.bk, true><<<grid, block, 0, s>>>(a);
         else if constexpr (C == 5)
