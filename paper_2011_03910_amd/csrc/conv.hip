@@ -667,11 +667,12 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
 // Cout (both are multiples of 4).  With a.amax set, the largest |value| stored
 // to out0 is folded into *a.amax (float bits as unsigned, non-negative).
 // ---------------------------------------------------------------------------
-// Residual tile of a 128 x 128 conv_dma tile staged in LDS (see conv_dma): pixels
-// 0-63 of the tile in half[0], 64-127 in half[1], 256 bytes (128 channels) per
-// pixel row, 16-byte slot c of row r at slot c ^ (r % 16) (16 rows of a column
-// read by 16 lanes hit 16 different slots).  m_tile, n_tile: the tile's origin.
-struct ResLds { const char* h0; const char* h1; int m_tile, n_tile; };
+// Residual tile of a conv_dma tile staged in LDS (see conv_dma): the first half of
+// the tile's pixels in h0, the second in h1, row_bytes (2 x the tile's channels,
+// 256 or 512) per pixel row, 16-byte slot c of row r at slot c ^ (r % 16) (16
+// rows of a column read by 16 lanes hit 16 different slots).  m_tile, n_tile: the
+// tile's origin; half_rows: pixels per half.
+struct ResLds { const char* h0; const char* h1; int m_tile, n_tile, half_rows, row_bytes; };
 
 template <typename T, int TM, int TN, int WTM, int WTN, bool NT = false>
 __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)[TM][TN], int m_base, int n_base,
@@ -699,9 +700,11 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)
             const int cb = n_base + j * 16 + (lane >> 4) * 4;
             rv[i][j] = T4{};
             if (res_t && rl) {
-                const int p = m - rl->m_tile, cl = cb - rl->n_tile, r = p & 63;
-                const char* base = (p >> 6) ? rl->h1 : rl->h0;
-                rv[i][j] = *(const T4*)(base + r * 256 + (((cl >> 3) ^ (r & 15)) << 4) + (cl & 7) * 2);
+                const int p = m - rl->m_tile, cl = cb - rl->n_tile;
+                const bool second = p >= rl->half_rows;
+                const int r = second ? p - rl->half_rows : p;
+                const char* base = second ? rl->h1 : rl->h0;
+                rv[i][j] = *(const T4*)(base + r * rl->row_bytes + (((cl >> 3) ^ (r & 15)) << 4) + (cl & 7) * 2);
             } else if (res_t && m < a.M && cb < a.n_split) {
                 rv[i][j] = *(const T4*)((const T*)a.res + (size_t)m * a.ld0 + cb);
             }
@@ -1317,16 +1320,21 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
     // outstanding) and this wave's operand reads of chunk k are done; barrier (so
     // for every wave; chunk k's stage is then free); issue chunk k+S into it; read
     // chunk k+1's operands; run chunk k's MFMAs.
-    // The residual of a 128 x 128 tile (32 KB of the storage type: two stages)
-    // comes into LDS by DMA during the last steps, in place of the loads of chunks
-    // past the end that those steps would issue (a wave issues the same NPW = 4
-    // instructions, so every wait count stays as it is); the epilogue then reads it
-    // from LDS instead of waiting on 16 global loads per lane.  Step nk - S writes
-    // pixels 0-63 into chunk nk - S's stage, step nk - S + 1 pixels 64-127 into the
-    // next one: both stages' operands are in registers by then.
-    // RL: launches with a residual of the storage type on an eligible tile (the
-    // launcher picks the form, so convs without a residual keep the plain kernel)
-    static_assert(!RL || (BM == 128 && BN == 128 && BK == 32 && NW == 4 && sizeof(T) == 2), "residual in LDS");
+    // RL: the tile's residual (BM x BN of the storage type, two halves of BM / 2
+    // pixels, each no larger than a stage) comes into LDS by DMA during the last
+    // steps, in place of the loads of chunks past the end that those steps would
+    // issue; a wave still issues NPW instructions per step (the half's
+    // instructions, then out-of-range ones into the rest of the stage), so every
+    // wait count stays as it is.  The epilogue then reads the residual from LDS
+    // instead of waiting on TM x TN global loads per lane.  Step nk - S writes the
+    // first half into chunk nk - S's stage, step nk - S + 1 the second into the
+    // next one: both stages' operands are in registers by then.  The launcher
+    // picks this form for convs with a residual only.
+    constexpr int RROW = BN * 2;                      // bytes per pixel row of the residual
+    constexpr int RIPR = 1024 / RROW;                  // pixel rows per 1-KB instruction
+    constexpr int RINS = BM * BN / 1024 / NW;          // a wave's instructions per half
+    static_assert(!RL || (sizeof(T) == 2 && (BN == 128 || BN == 256) && BM * BN <= SB &&
+                          (BM * BN / 1024) % NW == 0 && RINS <= NPW), "residual in LDS");
     const bool res_lds = RL && a.res && !a.out0_f32 && nk >= S + 1;
     int res_st0 = 0, res_st1 = 1;   // stage of each half
     auto res_issue = [&](auto st_c, auto h_c) {
@@ -1337,10 +1345,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
                                                                                     : 0x7fffffff), kBufFlags);
 #pragma unroll
         for (int i = 0; i < NPW; ++i) {
-            const int q = NW * i + wave;                 // 1-KB instruction: pixel rows 4q .. 4q + 3 of the half
-            const int r = 4 * q + (lane >> 4), c = (lane & 15) ^ (r & 15);
-            const int m = m0 + 64 * h + r, ch = n0 + 8 * c;
-            const bool ok = m < a.M && ch < a.n_split;
+            const int q = NW * i + wave;                 // 1-KB instruction: pixel rows RIPR q .. of the half
+            const int r = RIPR * q + lane / (RROW / 16), c = (lane % (RROW / 16)) ^ (r & 15);
+            const int m = m0 + (BM / 2) * h + r, ch = n0 + 8 * c;
+            const bool ok = i < RINS && m < a.M && ch < a.n_split;
             dma16(r_res, sp + q * 1024, ok ? (int)(((size_t)m * a.ld0 + ch) * sizeof(T)) : kOOB);
         }
         if constexpr (h == 0) res_st0 = st; else res_st1 = st;
@@ -1381,7 +1389,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
     if (res_lds) {
         __syncthreads();   // every wave's share of the residual has landed
         auto stp = [&](int st) -> const char* { return st == 0 ? st0 : st == 1 ? st1 : st == 2 ? st2 : st3; };
-        const ResLds rl{stp(res_st0), stp(res_st1), m0, n0};
+        const ResLds rl{stp(res_st0), stp(res_st1), m0, n0, BM / 2, RROW};
         store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr, &rl);
     } else {
         store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
@@ -2645,11 +2653,15 @@ int conv_default_tile(int et, const ConvArgs& a) {
     return best;
 }
 
-// conv_dma tiles that take a residual through LDS (128 x 128, 32-channel chunks, 4 waves)
+// conv_dma tiles that take a residual through LDS: a half tile (BM / 2 pixels x BN
+// channels) fits one stage, its 1-KB instructions split evenly over the waves, no
+// more of them than a chunk's, and 128 or 256 channels (rows of 256 or 512 bytes)
 template <typename T, int C>
 constexpr bool res_lds_tile() {
-    return kTiles[C].st > 0 && kTiles[C].bm == 128 && kTiles[C].bn == 128 && kTiles[C].bk == 32 &&
-           kTiles[C].wgm * kTiles[C].wgn == 4 && sizeof(T) == 2;
+    constexpr TileCfg t = kTiles[C];
+    constexpr int nw = t.wgm * t.wgn, npw = (t.bm + t.bn) / ((1024 / (t.bk * 2)) * (nw > 0 ? nw : 1));
+    return t.st > 0 && sizeof(T) == 2 && (t.bn == 128 || t.bn == 256) && t.bm * t.bn <= (t.bm + t.bn) * t.bk * 2 &&
+           (t.bm * t.bn / 1024) % nw == 0 && t.bm * t.bn / 1024 / nw <= npw;
 }
 template <typename T, int C>
 static bool res_lds_launch(const ConvArgs& a) {
