@@ -236,6 +236,18 @@ jde_status jde_fuse_stem(jde_ctx* ctx, int on);
  * 4 at the block's first conv and the second conv is kind 5 with no time or
  * FLOPs of its own. */
 jde_status jde_fuse_blocks(jde_ctx* ctx, int on);
+/* With on != 0 (the default), 16-bit contexts run each head's det 1x1 (Sec. 3.1
+ * heads: det 3x3 F -> 2F with leaky, then a linear 1x1 2F -> 6A) in the det 3x3's
+ * launch, where that launch runs on a direct-to-LDS tile whose activated output
+ * tile fits two of its stages: the 2F-channel output never goes to memory.  The
+ * 1x1 multiplies the same storage-rounded values; a 3x3 tile covering part of the
+ * 2F channels adds its FP32 partial sums to a workspace buffer, and the last of a
+ * pixel range's tiles sums them in channel order, so the result is deterministic
+ * but rounds differently from the unfused 1x1 (FP32 sums in another order).  FP8
+ * launches and calibration forwards always run unfused; on = 0 runs the 1x1 as its
+ * own launch.  In jde_profile_collect the 3x3 launch is then kind 7 (its FLOPs
+ * include the 1x1's) and the 1x1 kind 8 with no time or FLOPs of its own. */
+jde_status jde_fold_det(jde_ctx* ctx, int on);
 /* With on != 0 (default off), 16-bit contexts run each 3x3 stride-1 conv with
  * Cin % 64 == 0 and Cout % 128 == 0 (Sec. 3.1: the residual blocks of the deep
  * stages and the head convs) from an LDS window loaded once per 32-channel input
@@ -439,7 +451,7 @@ jde_status jde_profile_begin(jde_ctx* ctx, int on);
  * the profiled forwards (op_ms), FLOPs of one launch for the last batch
  * (op_flop: 2*M*N*K), kind (op_kind: 0 = stem, 1 = MFMA conv; 2-5 = fused
  * launches, see jde_fuse_stem and jde_fuse_blocks; 6 = MFMA conv run by the
- * persistent pointwise kernel, tile 37 of jde_tiles).  *n_fwd gets
+ * persistent pointwise kernel, tile 37 of jde_tiles; 7-8 see jde_fold_det).  *n_fwd gets
  * the number of forwards summed.  All arrays host. */
 jde_status jde_profile_collect(jde_ctx* ctx, int max_ops, double* op_ms, double* op_flop, int* op_kind,
                                int* n_ops, int* n_fwd);

@@ -99,8 +99,15 @@ struct jde_ctx {
     // launch_kind[i] records how op i ran in the latest forward: 0 = its own
     // launch, 2 / 4 = head of a fused stem / residual-block launch, 3 / 5 = run
     // inside the previous op's fused launch, 6 = its own launch of the persistent
-    // pointwise kernel.
+    // pointwise kernel, 7 = a det 3x3 launch that also runs the det 1x1, 8 = that
+    // det 1x1 (no launch of its own).
     bool fuse_stem = true, fuse_blocks = true;
+    // The det 1x1 of each head runs in its det 3x3's epilogue (16-bit storage, the
+    // 3x3 on a conv_tile_folds_det tile); its partial sums and per-pixel-tile
+    // counters live in the workspace.
+    bool fold_det = true;
+    size_t ws_det_part = 0, ws_det_cnt = 0;
+    int det_cnt_n = 0;
     // 3x3 stride-1 convs run from an LDS window (conv3_win) where they qualify;
     // off by default: measured slower than the implicit GEMM on MI355X.
     bool window_convs = false;
@@ -370,6 +377,18 @@ void plan_decode_scratch(jde_ctx* c) {
     c->ws_work = off;   off = align256(off + (size_t)3 * n * c->cap * 3 * 4);
     c->ws_work_count = off; off = align256(off + 3 * 4);
     c->ws_dyn = off;    off = align256(off + kDynInts * 4);
+    // det 1x1 folded into the det 3x3: partials [M][2F / 64][nout] of the largest
+    // head, and a counter per 64-pixel tile
+    size_t part = 0, tiles = 0;
+    for (const Op& o : c->ops)
+        if (o.det_out >= 0) {
+            const size_t m = c->cap_pix >> (2 * o.lvl_out);
+            part = std::max(part, m * (size_t)(o.cin / 64) * o.cout * 4);
+            tiles = std::max(tiles, (m + 63) / 64);
+        }
+    c->det_cnt_n = (int)tiles;
+    c->ws_det_part = off; off = align256(off + part);
+    c->ws_det_cnt = off;  off = align256(off + tiles * 4);
     c->ws_total = off;
 }
 
@@ -541,15 +560,16 @@ hipError_t launch_setup(const GeomParams& p, int* geom, int* counters, int ncoun
 }
 
 __global__ void setup_dyn_kernel(GeomParams p, DynHeader h, int* geom, int* dyn, int* counters, int ncount,
-                                 int* counters2, int ncount2) {
+                                 int* counters2, int ncount2, int* counters3, int ncount3) {
     setup_kernel_body(p, geom, counters, ncount);
     const int t = threadIdx.x;
     if (t < kDynInts) dyn[t] = h.v[t];
     for (int i = t; i < ncount2; i += blockDim.x) counters2[i] = 0;
+    for (int i = t; i < ncount3; i += blockDim.x) counters3[i] = 0;
 }
 hipError_t launch_setup_dyn(const GeomParams& p, const DynHeader& h, int* geom, int* dyn, int* counters, int ncount,
-                            int* counters2, int ncount2, hipStream_t s) {
-    setup_dyn_kernel<<<1, 256, 0, s>>>(p, h, geom, dyn, counters, ncount, counters2, ncount2);
+                            int* counters2, int ncount2, int* counters3, int ncount3, hipStream_t s) {
+    setup_dyn_kernel<<<1, 256, 0, s>>>(p, h, geom, dyn, counters, ncount, counters2, ncount2, counters3, ncount3);
     return hipGetLastError();
 }
 
@@ -920,6 +940,27 @@ jde_status jde_load_weights(jde_ctx* c, const float* blob, size_t nf, void* d_we
     return JDE_OK;
 }
 
+// Op i is a head's det 3x3 whose det 1x1 (op i + 1) can run in its epilogue:
+// 16-bit storage, neither in FP8, no calibration pass (which records the 3x3's
+// output range), a 1x1 over exactly the 3x3's det channels with at most 32
+// outputs.  The 3x3's tile decides the rest (conv_tile_folds_det).
+static bool det_foldable(const jde_ctx* c, size_t i) {
+    if (!c->fold_det || c->calibrating || (c->et != kBF16 && c->et != kF16) || i + 1 >= c->ops.size()) return false;
+    const Op& o = c->ops[i];
+    const Op& o1 = c->ops[i + 1];
+    return o.kind == OP_CONV && o.emb_out >= 0 && o1.kind == OP_CONV && o1.det_out >= 0 && o1.in_t == o.out_t &&
+           o1.ksz == 1 && o1.cin == o.n_split && o1.cin % 64 == 0 && o1.cout % 4 == 0 && o1.cout <= 32 &&
+           o1.cin1 == 0 && o1.in2_t < 0 && o1.res_t < 0 && !o1.act && !runs_fp8(c, o) && !runs_fp8(c, o1);
+}
+static void set_det_fold(const jde_ctx* c, const Op& o1, char* W, const jde_head_out* out, ConvArgs& a) {
+    a.det_w = c->d_weights + o1.dev_w;
+    a.det_b = (const float*)(c->d_weights + o1.dev_b);
+    a.det_out = out->det[o1.det_out];
+    a.det_part = (float*)(W + c->ws_det_part);
+    a.det_cnt = (unsigned*)(W + c->ws_det_cnt);
+    a.det_n = o1.cout;
+}
+
 // The forward's launches.  dynamic: for a batch described by the header in the
 // workspace (written before each replay of a graph, see jde_graph_capture_any):
 // grids are sized for the capacity and every launch reads the batch's pixels,
@@ -944,7 +985,8 @@ static jde_status forward_impl(jde_ctx* c, const float* frames, const jde_frame_
     int* geom = (int*)(W + c->ws_geom);
     const int* dynp = dynamic ? (const int*)(W + c->ws_dyn) : nullptr;
     auto cap_m = [&](int lvl) { return c->cap_pix >> (2 * lvl); };
-    if (!dynamic) HIP_TRY(launch_setup(geom_params(d, n), geom, nullptr, 0, s));
+    // (the det 1x1 counters start at 0; every launch that uses them leaves them at 0)
+    if (!dynamic) HIP_TRY(launch_setup(geom_params(d, n), geom, (int*)(W + c->ws_det_cnt), c->det_cnt_n, s));
     auto tptr = [&](int t) -> void* { return t < 0 ? nullptr : (void*)(W + c->tens[t].off); };
     hipEvent_t* pev = nullptr;
     if (c->prof) {
@@ -1036,18 +1078,33 @@ static jde_status forward_impl(jde_ctx* c, const float* frames, const jde_frame_
                 w3 += t;
             }
         }
+        bool folded = false;
         if (w3 > 0) {
             HIP_TRY(launch_conv3w(a, c->et, w3, s));
         } else if (runs_fp8(c, o)) {
             HIP_TRY(launch_conv_fp8(a, o.tile8, s));
         } else {
             const int tile = (o.tile >= 0 && conv_tile_ok(o.tile, c->et, a)) ? o.tile : conv_default_tile(c->et, a);
+            folded = det_foldable(c, oi) && conv_tile_folds_det(tile, c->et, a.n_split);
+            if (folded) set_det_fold(c, c->ops[oi + 1], W, out, a);
             HIP_TRY(launch_conv(a, c->et, tile, s));
             if (conv_tile_pw(tile)) c->launch_kind[oi] = 6;
         }
         if (pev) {
             HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));
             c->op_flop[oi] = 2.0 * a.M * (double)a.cout * a.K;
+        }
+        if (folded) {
+            const Op& o1 = c->ops[oi + 1];
+            if (pev) {
+                HIP_TRY(hipEventRecord(pev[2 * oi + 2], s));
+                HIP_TRY(hipEventRecord(pev[2 * oi + 3], s));
+                c->op_flop[oi] += 2.0 * a.M * (double)o1.cout * o1.cin;
+                c->op_flop[oi + 1] = 0.0;
+            }
+            c->launch_kind[oi] = 7;
+            c->launch_kind[oi + 1] = 8;
+            ++oi;
         }
     }
     return JDE_OK;
@@ -1073,14 +1130,32 @@ jde_status jde_autotune(jde_ctx* c, const float* frames, const jde_frame_desc* d
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     jde_status st = JDE_OK;
-    for (Op& o : c->ops) {
+    for (size_t oi = 0; oi < c->ops.size(); ++oi) {
+        Op& o = c->ops[oi];
         if (o.kind != OP_CONV) continue;
         const ConvArgs a = conv_args(c, o, d, n, uniform, W, geom, out);
         const bool f8 = runs_fp8(c, o);
         float best = 1e30f;
         int best_t = -1;
         const int nt = f8 ? conv_fp8_num_tiles() : conv_num_tile_cfgs();
-        auto go = [&](int t) { return f8 ? launch_conv_fp8(a, t, s) : launch_conv(a, c->et, t, s); };
+        // a det 3x3 whose det 1x1 can fold: a tile that folds is timed with the 1x1 in
+        // its epilogue, any other followed by the 1x1's own launch (what the forward runs)
+        const bool fold = det_foldable(c, oi);
+        ConvArgs af = a, a1{};
+        int tile1 = -1;
+        if (fold) {
+            set_det_fold(c, c->ops[oi + 1], W, out, af);
+            a1 = conv_args(c, c->ops[oi + 1], d, n, uniform, W, geom, out);
+            const Op& o1 = c->ops[oi + 1];
+            tile1 = (o1.tile >= 0 && conv_tile_ok(o1.tile, c->et, a1)) ? o1.tile : conv_default_tile(c->et, a1);
+        }
+        auto go = [&](int t) {
+            if (f8) return launch_conv_fp8(a, t, s);
+            if (!fold) return launch_conv(a, c->et, t, s);
+            if (conv_tile_folds_det(t, c->et, a.n_split)) return launch_conv(af, c->et, t, s);
+            const hipError_t e = launch_conv(a, c->et, t, s);
+            return e != hipSuccess ? e : launch_conv(a1, c->et, tile1, s);
+        };
         for (int t = 0; t < nt && st == JDE_OK; ++t) {
             if (!f8 && !conv_tile_ok(t, c->et, a)) continue;
             hipError_t e = go(t);
@@ -1514,6 +1589,12 @@ jde_status jde_sparse_emb(jde_ctx* c, int on) {
     return JDE_OK;
 }
 
+jde_status jde_fold_det(jde_ctx* c, int on) {
+    if (!c) return fail(JDE_EINVAL, "null context");
+    c->fold_det = on != 0;
+    return JDE_OK;
+}
+
 jde_status jde_window_convs(jde_ctx* c, int on) {
     if (!c) return fail(JDE_EINVAL, "null context");
     c->window_convs = on != 0;
@@ -1626,7 +1707,7 @@ jde_status jde_graph_launch_batch(jde_graph* g, const jde_frame_desc* d, int n, 
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_setup_dyn(geom_params(d, n), h, (int*)(g->ws + c->ws_geom), (int*)(g->ws + c->ws_dyn),
                              (int*)(g->ws + c->ws_counts), c->cfg.max_frames, (int*)(g->ws + c->ws_work_count), 3,
-                             s));
+                             (int*)(g->ws + c->ws_det_cnt), c->det_cnt_n, s));
     HIP_TRY(hipGraphLaunch(g->e, s));
     return JDE_OK;
 }

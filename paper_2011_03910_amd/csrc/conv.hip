@@ -772,6 +772,149 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Det head's 1x1 folded into the det 3x3's epilogue (Sec. 3.1 heads: the det 3x3
+// F -> 2F with leaky ReLU, then a linear 1x1 2F -> 6A).  The 3x3 tile (BM pixels
+// x BN of the 2F channels) never goes to memory: after bias and leaky each wave
+// rounds its values to the storage type -- what the unfused conv stores -- into
+// LDS (pixels 0 .. BM/2 - 1 in h0, the rest in h1, 2 BN bytes per pixel row,
+// 16-byte slot c of row r at c ^ (r % min(16, BN / 8))), and the workgroup
+// multiplies the tile by the 1x1 weights of its BN channels on MFMA, wave w
+// taking pixel rows w BM/NW ...  A tile that covers all 2F channels writes the
+// head output (+ the 1x1 bias).  Otherwise each channel tile writes its FP32
+// partial sums to det_part[m][tile][o], and the last of the nN channel tiles of
+// a pixel range to finish (a per-range counter, incremented after the partials
+// are visible device-wide, reset to 0 by that last tile) adds them in channel-
+// tile order, then the bias: the sum does not depend on which tile finished last.
+// All threads of the workgroup call this (it has barriers); flag: 4 bytes of LDS
+// not in h0 or h1.
+// ---------------------------------------------------------------------------
+template <typename T, int BM, int BN, int NW, int TM, int TN, int WTM, int WTN>
+__device__ __forceinline__ void det_fold(const ConvArgs& a, const f32x4 (&acc)[TM][TN], int m0, int n0, int wm,
+                                         int wn, int wave, int lane, int tid, char* h0, char* h1, int* flag) {
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    typedef typename V16<T>::type V;
+    constexpr int RROW = BN * 2, SW = (BN / 8 < 16 ? BN / 8 : 16) - 1;
+    constexpr int RW = BM / NW, MB = RW / 16, KS = BN / 32;
+    static_assert(RW % 16 == 0 && BN % 32 == 0, "det fold");
+    auto slot = [&](int r, int cl) { return r * RROW + (((cl >> 3) ^ (r & SW)) << 4) + (cl & 7) * 2; };
+    f32x4 bv[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) bv[j] = *(const f32x4*)(a.bias + n0 + wn * WTN + j * 16 + (lane >> 4) * 4);
+    __syncthreads();  // every wave is done reading the stages h0 / h1 overlay
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int p = wm * WTM + i * 16 + (lane & 15);
+        const bool second = p >= BM / 2;
+        const int r = second ? p - BM / 2 : p;
+        char* base = second ? h1 : h0;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int cl = wn * WTN + j * 16 + (lane >> 4) * 4;
+            T4 pk;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                float v = acc[i][j][t] + bv[j][t];
+                if (a.act) v = leaky01(v);
+                pk[t] = cvt_out<T>(v);
+            }
+            *(T4*)(base + slot(r, cl)) = pk;
+        }
+    }
+    // 1x1 weights of this tile's channels: operand rows o = 16 ob + lane % 16 (zero past det_n)
+    V wa[KS][2];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob) {
+            const int o = ob * 16 + (lane & 15);
+            wa[ks][ob] = o < a.det_n
+                             ? *(const V*)((const T*)a.det_w + (size_t)o * a.n_split + n0 + ks * 32 + (lane >> 4) * 8)
+                             : V{};
+        }
+    __syncthreads();
+    f32x4 d[MB][2];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob) d[mb][ob] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int p = wave * RW + mb * 16 + (lane & 15);
+            const bool second = p >= BM / 2;
+            const int r = second ? p - BM / 2 : p;
+            const V xb = *(const V*)((second ? h1 : h0) + slot(r, ks * 32 + (lane >> 4) * 8));
+#pragma unroll
+            for (int ob = 0; ob < 2; ++ob) {
+                if constexpr (__is_same(T, bf16))
+                    d[mb][ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ks][ob], xb, d[mb][ob], 0, 0, 0);
+                else
+                    d[mb][ob] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[ks][ob], xb, d[mb][ob], 0, 0, 0);
+            }
+        }
+    // lane holds outputs o = 16 ob + 4 (lane / 16) + t of pixel m0 + wave RW + 16 mb + lane % 16
+    const int nN = a.n_split / BN;
+    if (nN == 1) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int m = m0 + wave * RW + mb * 16 + (lane & 15);
+#pragma unroll
+            for (int ob = 0; ob < 2; ++ob) {
+                const int o = ob * 16 + (lane >> 4) * 4;
+                if (m < a.M && o < a.det_n)
+                    *(f32x4*)(a.det_out + (size_t)m * a.det_n + o) = d[mb][ob] + *(const f32x4*)(a.det_b + o);
+            }
+        }
+        return;
+    }
+    // The partials travel through device-coherent accesses (16-byte stores and
+    // agent-scope atomic loads with the device-coherence bit, which the compute
+    // unit's caches and this XCD's L2 neither hold back nor serve stale): a partial
+    // is at the coherence point once its store has completed, which the wait below
+    // ensures before the barrier and the count.  A release fence does the same with
+    // a write-back of this XCD's whole L2 per workgroup (measured: the stride-8 det
+    // 3x3 launch 3.4x slower), an acquire fence with an invalidation of it, and
+    // per-float coherent stores add three times what the 16-byte ones add.
+    const int nt = n0 / BN;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+        const int m = m0 + wave * RW + mb * 16 + (lane & 15);
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob) {
+            const int o = ob * 16 + (lane >> 4) * 4;
+            if (m < a.M && o < a.det_n) {
+                float* pp = a.det_part + ((size_t)m * nN + nt) * a.det_n + o;
+                asm volatile("global_store_dwordx4 %0, %1, off sc1" : : "v"(pp), "v"(d[mb][ob]) : "memory");
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));  // this wave's partials have landed
+    __syncthreads();
+    unsigned* cnt = a.det_cnt + m0 / BM;
+    if (tid == 0) *flag = atomicAdd(cnt, 1u) == (unsigned)(nN - 1);
+    __syncthreads();
+    if (*flag) {
+        const int q4 = a.det_n / 4;
+        for (int e = tid; e < BM * q4; e += 64 * NW) {
+            const int m = m0 + e / q4, o = (e % q4) * 4;
+            if (m >= a.M) continue;
+            const float* pp = a.det_part + (size_t)m * nN * a.det_n + o;
+            f32x4 sum;
+            for (int t = 0; t < nN; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float v = __hip_atomic_load(pp + (size_t)t * a.det_n + c, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                    sum[c] = t == 0 ? v : sum[c] + v;
+                }
+            *(f32x4*)(a.det_out + (size_t)m * a.det_n + o) = sum + *(const f32x4*)(a.det_b + o);
+        }
+        if (tid == 0) atomicExch(cnt, 0u);
+    }
+}
+
 // XCD-aware tile order: workgroup L runs on XCD L % 8.  Every XCD gets a
 // contiguous range of logical tiles (a bijection on [0, tiles)), ordered so that
 // the tiles of one XCD share the larger operand in its L2: all channel tiles of
@@ -1336,6 +1479,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
     static_assert(!RL || (sizeof(T) == 2 && (BN == 128 || BN == 256) && BM * BN <= SB &&
                           (BM * BN / 1024) % NW == 0 && RINS <= NPW), "residual in LDS");
     const bool res_lds = RL && a.res && !a.out0_f32 && nk >= S + 1;
+    // det 1x1 in the epilogue: the activated tile (BM x BN of the storage type) in two
+    // stages, the last-tile flag in a third (not in the residual form: a det 3x3 has
+    // no residual)
+    constexpr bool kFoldDet = !RL && sizeof(T) == 2 && BM * BN <= SB;
     int res_st0 = 0, res_st1 = 1;   // stage of each half
     auto res_issue = [&](auto st_c, auto h_c) {
         constexpr int st = decltype(st_c)::value, h = decltype(h_c)::value;
@@ -1391,6 +1538,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
         auto stp = [&](int st) -> const char* { return st == 0 ? st0 : st == 1 ? st1 : st == 2 ? st2 : st3; };
         const ResLds rl{stp(res_st0), stp(res_st1), m0, n0, BM / 2, RROW};
         store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr, &rl);
+    } else if (kFoldDet && a.det_w && n0 < a.n_split) {
+        det_fold<T, BM, BN, NW, TM, TN, WTM, WTN>(a, acc, m0, n0, wm, wn, wave, lane, tid, st0, st1, (int*)st2);
     } else {
         store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
     }
@@ -2602,6 +2751,11 @@ constexpr bool tile_built(int c) {
 }
 
 int conv_num_tile_cfgs() { return kNumTiles; }
+bool conv_tile_folds_det(int c, int et, int n_split) {
+    if (c < 0 || c >= kNumTiles || (et != kBF16 && et != kF16)) return false;
+    const TileCfg& t = kTiles[c];
+    return t.st > 0 && !t.pw && t.bm * t.bn <= (t.bm + t.bn) * t.bk * 2 && n_split > 0 && n_split % t.bn == 0;
+}
 bool conv_tile_pw(int c) { return c >= 0 && c < kNumTiles && kTiles[c].pw; }
 void conv_tile_shape(int c, int* bm, int* bn) {
     *bm = kTiles[c].bm;

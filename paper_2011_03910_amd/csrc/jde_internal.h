@@ -77,6 +77,15 @@ struct ConvArgs {
     unsigned* amax;        // calibration: max |out0| folded in with atomicMax on the float bits, or null
     const int* dyn;        // batch header (kDyn*): M, nframes, uniform read from it; M above is then the
                            // capacity the grid was sized for; null = the values above
+    // Det 1x1 folded into this conv's epilogue (conv_tile_folds_det tiles only), or
+    // det_w null: the 1x1 (det_n x n_split, linear) runs on the activated, storage-
+    // rounded columns [0, n_split) in place of storing them to out0.
+    const void* det_w;     // [det_n][n_split], storage type
+    const float* det_b;    // [det_n]
+    float* det_out;        // [M][det_n] FP32 head output
+    float* det_part;       // [M][n_split / BN][det_n] FP32 partial sums of the channel tiles
+    unsigned* det_cnt;     // per pixel tile: channel tiles finished; 0 between launches
+    int det_n;             // det_n % 4 == 0, <= 32
 };
 
 // Launchers (conv.hip).
@@ -84,6 +93,9 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
                        int M, const float* w, const float* bias, int cout, void* out, int out_type,
                        hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, int elem_type, int tile_cfg, hipStream_t s);
+// Tiles whose launches can take the det 1x1 in their epilogue (ConvArgs::det_w)
+// for a det 3x3 of n_split det channels (whole channel tiles only).
+bool conv_tile_folds_det(int tile_cfg, int elem_type, int n_split);
 // Stem fused with the first 3x3 stride-2 conv (c0 = 32 -> 64, 16-bit storage):
 // frames -> stride-2 level output; `tiles` = sum over frames of stem_down_tiles(h, w).
 hipError_t launch_stem_down(const float* frames, const int* geom, int nframes, int tiles, const float* w0,
@@ -135,10 +147,11 @@ hipError_t launch_decode(const DecodeArgs& a, int max_anchors, hipStream_t s);
 // Writes the batch geometry table and zeroes `ncount` ints (graph-safe: a kernel, no memset).
 struct GeomParams { int n; int hw[kMaxFrames][2]; };
 hipError_t launch_setup(const GeomParams& p, int* geom, int* counters, int ncount, hipStream_t s);
-// The same plus the batch header (host-computed, kDynInts ints) written to dyn.
+// The same plus the batch header (host-computed, kDynInts ints) written to dyn,
+// zeroing three counter ranges.
 struct DynHeader { int v[kDynInts]; };
 hipError_t launch_setup_dyn(const GeomParams& p, const DynHeader& h, int* geom, int* dyn, int* counters,
-                            int ncount, int* counters2, int ncount2, hipStream_t s);
+                            int ncount, int* counters2, int ncount2, int* counters3, int ncount3, hipStream_t s);
 hipError_t launch_sort(unsigned long long* keys, int* vals, const int* counts, int keycap, int n,
                        hipStream_t s);
 struct GatherArgs {

@@ -549,6 +549,10 @@ class JDE:
         """Run each 64- and 128-channel residual block as one launch (16-bit only)."""
         check(self.lib.jde_fuse_blocks(self.ctx, 1 if on else 0), "jde_fuse_blocks")
 
+    def fold_det(self, on=True):
+        """Run each head's det 1x1 in its det 3x3's epilogue (16-bit only)."""
+        check(self.lib.jde_fold_det(self.ctx, 1 if on else 0), "jde_fold_det")
+
     def window_convs(self, on=True):
         """Run qualifying 3x3 stride-1 convs from an LDS window (16-bit only)."""
         check(self.lib.jde_window_convs(self.ctx, 1 if on else 0), "jde_window_convs")

@@ -275,6 +275,52 @@ def test_fused_blocks_tiny_partial_tiles(torch, precision):
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
 @pytest.mark.parametrize("cfg_name", ["tiny", "full"])
+def test_det_fold_equals_unfused(torch, precision, cfg_name):
+    """The det 1x1 run in the det 3x3's epilogue gives the det head output of the
+    two launches, to the rounding of another FP32 summation order, for tiles whose
+    channel width splits the 2F det channels into 1, 2, 4, 8 or 16 parts (partial
+    sums combined by the last tile of each pixel range), on a ragged batch whose
+    level sizes end in partial pixel tiles; the dense emb columns of the same GEMM
+    are unchanged; a second forward (counters back at 0) is bitwise the same."""
+    _say(f"case: det fold {cfg_name} {precision}")
+    cfg = TINY if cfg_name == "tiny" else FULL
+    sizes = ([(192, 320), (128, 256), (192, 320)] if cfg_name == "tiny"
+             else [(608, 1088), (320, 576), (480, 864)])
+    m = _model(cfg, precision, len(sizes))
+    m.load_weights(weights(cfg_name, 50 if cfg_name == "tiny" else 40))
+    frs = [frames(cfg_name, 1, 0, h, w)[0] for h, w in sizes]
+    packed = torch.from_numpy(np.concatenate([f.ravel() for f in frs])).cuda()
+    n_ops = len(m.tiles())
+    two_f = [cfg.c0 * 2 ** lvl // 2 * 2 for lvl in (5, 4, 3)]   # 2F of the stride-32, 16, 8 heads
+    # 128x128, 64x64, 128x256 (64-channel chunks), 64x128, 256x64, 128x64 direct-to-LDS tiles
+    for t, bn in ((16, 128), (28, 64), (35, 256), (21, 128), (19, 64), (26, 64)):
+        m.set_tiles(np.full(n_ops, t, dtype=np.int32))
+        m.fold_det(True)
+        m.profile_begin(True)
+        fold = head_views(m.forward(packed, sizes), sizes)
+        _, _, kind, _ = m.profile_collect()
+        m.profile_begin(False)
+        again = head_views(m.forward(packed, sizes), sizes)
+        m.fold_det(False)
+        plain = head_views(m.forward(packed, sizes), sizes)
+        m.fold_det(True)
+        torch.cuda.synchronize()
+        n7, n8 = int((kind == 7).sum()), int((kind == 8).sum())
+        worst = max(rel_err(fold["det"][s][i], plain["det"][s][i]) for s in range(3) for i in range(len(sizes)))
+        same = all(np.array_equal(fold[k][s][i], again[k][s][i]) for k in ("det", "emb")
+                   for s in range(3) for i in range(len(sizes)))
+        emb_same = all(np.array_equal(fold["emb"][s][i], plain["emb"][s][i])
+                       for s in range(3) for i in range(len(sizes)))
+        _say(f"  tile {t}: {n7} folded det heads; det rel err vs unfused {worst:.2e}; "
+             f"repeat bitwise {same}; emb unchanged {emb_same}")
+        assert n7 == n8 == sum(1 for f2 in two_f if f2 % bn == 0), (t, n7, n8)
+        assert n7 > 0
+        assert worst <= 1e-5, (t, worst)
+        assert same and emb_same, t
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("cfg_name", ["tiny", "full"])
 def test_window_convs_match_implicit_gemm(torch, precision, cfg_name):
     """The LDS-window 3x3 convolutions (deep residual blocks and head convs)
     compute what the implicit GEMM computes, to the rounding of a different FP32
