@@ -773,11 +773,37 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)
 }
 
 // ---------------------------------------------------------------------------
+// Where the det fold (below) keeps a conv_dma tile in LDS: rows of 2 BN bytes,
+// `rows` pixel rows (a multiple of 16, as many as fit) per pipeline stage of
+// `stage` bytes, `parts` stages in use, and the 4-byte last-tile flag at byte
+// `flag` of stage `flag_stage` (after the rows of the last part, or in the next
+// stage).  ok: the tile fits the S stages.
+struct FoldLayout { bool ok; int rows, parts, flag_stage, flag; };
+constexpr FoldLayout fold_layout(int bm, int bn, int bk, int st) {
+    const int stage = (bm + bn) * bk * 2, row = bn * 2;
+    const int rows = (stage / row) / 16 * 16 < bm ? (stage / row) / 16 * 16 : bm;
+    if (rows < 16 || st < 1) return {false, 0, 0, 0, 0};
+    const int parts = (bm + rows - 1) / rows;
+    const int used = (bm - (parts - 1) * rows) * row;
+    if (used + 4 <= stage) return {parts <= st, rows, parts, parts - 1, used};
+    return {parts + 1 <= st, rows, parts, parts, 0};
+}
+
+// conv_dma tiles that carry the det fold: the tile fits the stages; not the
+// 4-wave tiles of 32 K elements, whose walking form (graphs for any batch) the
+// fold pushes past 256 registers (one workgroup per CU instead of two) -- and a
+// tile folds in every form or in none, so that a graph for any batch computes
+// what the eager forward computes, bit for bit.
+constexpr bool fold_det_tile(int bm, int bn, int bk, int st, int nw) {
+    return fold_layout(bm, bn, bk, st).ok && !(nw == 4 && bm * bn >= 32768);
+}
+
+// ---------------------------------------------------------------------------
 // Det head's 1x1 folded into the det 3x3's epilogue (Sec. 3.1 heads: the det 3x3
 // F -> 2F with leaky ReLU, then a linear 1x1 2F -> 6A).  The 3x3 tile (BM pixels
 // x BN of the 2F channels) never goes to memory: after bias and leaky each wave
 // rounds its values to the storage type -- what the unfused conv stores -- into
-// LDS (pixels 0 .. BM/2 - 1 in h0, the rest in h1, 2 BN bytes per pixel row,
+// LDS (fold_layout: pixel p in stage p / rows, row p % rows, 2 BN bytes per row,
 // 16-byte slot c of row r at c ^ (r % min(16, BN / 8))), and the workgroup
 // multiplies the tile by the 1x1 weights of its BN channels on MFMA, wave w
 // taking pixel rows w BM/NW ...  A tile that covers all 2F channels writes the
@@ -786,39 +812,42 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f32x4 (&acc)
 // a pixel range to finish (a per-range counter, incremented after the partials
 // are visible device-wide, reset to 0 by that last tile) adds them in channel-
 // tile order, then the bias: the sum does not depend on which tile finished last.
-// All threads of the workgroup call this (it has barriers); flag: 4 bytes of LDS
-// not in h0 or h1.
+// All threads of the workgroup call this (it has barriers); st0 .. st3: the
+// pipeline stages.
 // ---------------------------------------------------------------------------
-template <typename T, int BM, int BN, int NW, int TM, int TN, int WTM, int WTN>
+template <typename T, int BM, int BN, int NW, int TM, int TN, int WTM, int WTN, int BK, int S>
 __device__ __forceinline__ void det_fold(const ConvArgs& a, const f32x4 (&acc)[TM][TN], int m0, int n0, int wm,
-                                         int wn, int wave, int lane, int tid, char* h0, char* h1, int* flag) {
+                                         int wn, int wave, int lane, int tid, char* st0, char* st1, char* st2,
+                                         char* st3) {
     typedef T T4 __attribute__((ext_vector_type(4)));
     typedef typename V16<T>::type V;
+    constexpr FoldLayout L = fold_layout(BM, BN, BK, S);
     constexpr int RROW = BN * 2, SW = (BN / 8 < 16 ? BN / 8 : 16) - 1;
     constexpr int RW = BM / NW, MB = RW / 16, KS = BN / 32;
-    static_assert(RW % 16 == 0 && BN % 32 == 0, "det fold");
-    auto slot = [&](int r, int cl) { return r * RROW + (((cl >> 3) ^ (r & SW)) << 4) + (cl & 7) * 2; };
-    f32x4 bv[TN];
+    static_assert(L.ok && RW % 16 == 0 && BN % 32 == 0 && L.rows % 16 == 0, "det fold");
+    auto stage = [&](int q) { return q == 0 ? st0 : q == 1 ? st1 : q == 2 ? st2 : st3; };
+    // LDS address of channel cl of tile pixel p (a 16-pixel group never straddles stages)
+    auto at = [&](int p, int cl) {
+        const int r = p % L.rows;
+        return stage(p / L.rows) + r * RROW + (((cl >> 3) ^ (r & SW)) << 4) + (cl & 7) * 2;
+    };
+    int* flag = (int*)(stage(L.flag_stage) + L.flag);
+    __syncthreads();  // every wave is done reading the stages the tile overlays
 #pragma unroll
-    for (int j = 0; j < TN; ++j) bv[j] = *(const f32x4*)(a.bias + n0 + wn * WTN + j * 16 + (lane >> 4) * 4);
-    __syncthreads();  // every wave is done reading the stages h0 / h1 overlay
+    for (int j = 0; j < TN; ++j) {
+        const int cl = wn * WTN + j * 16 + (lane >> 4) * 4;
+        const f32x4 bv = *(const f32x4*)(a.bias + n0 + cl);
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        const int p = wm * WTM + i * 16 + (lane & 15);
-        const bool second = p >= BM / 2;
-        const int r = second ? p - BM / 2 : p;
-        char* base = second ? h1 : h0;
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int cl = wn * WTN + j * 16 + (lane >> 4) * 4;
+        for (int i = 0; i < TM; ++i) {
+            const int p = wm * WTM + i * 16 + (lane & 15);
             T4 pk;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                float v = acc[i][j][t] + bv[j][t];
+                float v = acc[i][j][t] + bv[t];
                 if (a.act) v = leaky01(v);
                 pk[t] = cvt_out<T>(v);
             }
-            *(T4*)(base + slot(r, cl)) = pk;
+            *(T4*)at(p, cl) = pk;
         }
     }
     // 1x1 weights of this tile's channels: operand rows o = 16 ob + lane % 16 (zero past det_n)
@@ -843,9 +872,7 @@ __device__ __forceinline__ void det_fold(const ConvArgs& a, const f32x4 (&acc)[T
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             const int p = wave * RW + mb * 16 + (lane & 15);
-            const bool second = p >= BM / 2;
-            const int r = second ? p - BM / 2 : p;
-            const V xb = *(const V*)((second ? h1 : h0) + slot(r, ks * 32 + (lane >> 4) * 8));
+            const V xb = *(const V*)at(p, ks * 32 + (lane >> 4) * 8);
 #pragma unroll
             for (int ob = 0; ob < 2; ++ob) {
                 if constexpr (__is_same(T, bf16))
@@ -1479,10 +1506,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
     static_assert(!RL || (sizeof(T) == 2 && (BN == 128 || BN == 256) && BM * BN <= SB &&
                           (BM * BN / 1024) % NW == 0 && RINS <= NPW), "residual in LDS");
     const bool res_lds = RL && a.res && !a.out0_f32 && nk >= S + 1;
-    // det 1x1 in the epilogue: the activated tile (BM x BN of the storage type) in two
-    // stages, the last-tile flag in a third (not in the residual form: a det 3x3 has
-    // no residual)
-    constexpr bool kFoldDet = !RL && sizeof(T) == 2 && BM * BN <= SB;
+    // det 1x1 in the epilogue: the activated tile (BM x BN of the storage type) over
+    // the stages (not in the residual form: a det 3x3 has no residual)
+    constexpr bool kFoldDet = !RL && sizeof(T) == 2 && fold_det_tile(BM, BN, BK, S, NW);
     int res_st0 = 0, res_st1 = 1;   // stage of each half
     auto res_issue = [&](auto st_c, auto h_c) {
         constexpr int st = decltype(st_c)::value, h = decltype(h_c)::value;
@@ -1539,7 +1565,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
         const ResLds rl{stp(res_st0), stp(res_st1), m0, n0, BM / 2, RROW};
         store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr, &rl);
     } else if (kFoldDet && a.det_w && n0 < a.n_split) {
-        det_fold<T, BM, BN, NW, TM, TN, WTM, WTN>(a, acc, m0, n0, wm, wn, wave, lane, tid, st0, st1, (int*)st2);
+        if constexpr (kFoldDet) {
+            // the arguments read afresh here, so that the walking form holds none of the
+            // fold's through the K loop
+            const ConvArgs af = tile_args<DYN>(a0, db);
+            det_fold<T, BM, BN, NW, TM, TN, WTM, WTN, BK, S>(af, acc, m0, n0, wm, wn, wave, lane, tid, st0, st1,
+                                                              st2, st3);
+        }
     } else {
         store_tile<T, TM, TN, WTM, WTN, NT>(a, acc, m0 + wm * WTM, n0 + wn * WTN, lane, nullptr);
     }
@@ -2754,7 +2786,8 @@ int conv_num_tile_cfgs() { return kNumTiles; }
 bool conv_tile_folds_det(int c, int et, int n_split) {
     if (c < 0 || c >= kNumTiles || (et != kBF16 && et != kF16)) return false;
     const TileCfg& t = kTiles[c];
-    return t.st > 0 && !t.pw && t.bm * t.bn <= (t.bm + t.bn) * t.bk * 2 && n_split > 0 && n_split % t.bn == 0;
+    return t.st > 0 && !t.pw && fold_det_tile(t.bm, t.bn, t.bk, t.st, t.wgm * t.wgn) && n_split > 0 &&
+           n_split % t.bn == 0;
 }
 bool conv_tile_pw(int c) { return c >= 0 && c < kNumTiles && kTiles[c].pw; }
 void conv_tile_shape(int c, int* bm, int* bn) {

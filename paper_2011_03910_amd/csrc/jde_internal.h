@@ -94,7 +94,8 @@ hipError_t launch_stem(const float* frames, const int* geom, int nframes, int un
                        hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, int elem_type, int tile_cfg, hipStream_t s);
 // Tiles whose launches can take the det 1x1 in their epilogue (ConvArgs::det_w)
-// for a det 3x3 of n_split det channels (whole channel tiles only).
+// for a det 3x3 of n_split det channels (whole channel tiles only), in eager
+// launches and graphs for any batch alike.
 bool conv_tile_folds_det(int tile_cfg, int elem_type, int n_split);
 // Stem fused with the first 3x3 stride-2 conv (c0 = 32 -> 64, 16-bit storage):
 // frames -> stride-2 level output; `tiles` = sum over frames of stem_down_tiles(h, w).

@@ -279,7 +279,8 @@ def test_det_fold_equals_unfused(torch, precision, cfg_name):
     """The det 1x1 run in the det 3x3's epilogue gives the det head output of the
     two launches, to the rounding of another FP32 summation order, for tiles whose
     channel width splits the 2F det channels into 1, 2, 4, 8 or 16 parts (partial
-    sums combined by the last tile of each pixel range), on a ragged batch whose
+    sums combined by the last tile of each pixel range) and whose activated tile
+    takes one, two or three pipeline stages of LDS, on a ragged batch whose
     level sizes end in partial pixel tiles; the dense emb columns of the same GEMM
     are unchanged; a second forward (counters back at 0) is bitwise the same."""
     _say(f"case: det fold {cfg_name} {precision}")
@@ -292,8 +293,10 @@ def test_det_fold_equals_unfused(torch, precision, cfg_name):
     packed = torch.from_numpy(np.concatenate([f.ravel() for f in frs])).cuda()
     n_ops = len(m.tiles())
     two_f = [cfg.c0 * 2 ** lvl // 2 * 2 for lvl in (5, 4, 3)]   # 2F of the stride-32, 16, 8 heads
-    # 128x128, 64x64, 128x256 (64-channel chunks), 64x128, 256x64, 128x64 direct-to-LDS tiles
-    for t, bn in ((16, 128), (28, 64), (35, 256), (21, 128), (19, 64), (26, 64)):
+    # 128x128, 64x64, 128x256 (64-channel chunks), 64x128, 256x64, 128x64 direct-to-LDS
+    # tiles, and three whose activated tile spans all three stages or one whole stage:
+    # 256x128 and 128x256 (8 waves), 128x128 (64-channel chunks)
+    for t, bn in ((16, 128), (28, 64), (35, 256), (21, 128), (19, 64), (26, 64), (29, 128), (30, 256), (36, 128)):
         m.set_tiles(np.full(n_ops, t, dtype=np.int32))
         m.fold_det(True)
         m.profile_begin(True)
