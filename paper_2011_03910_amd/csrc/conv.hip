@@ -33,8 +33,14 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // leaky ReLU 0.1: max(x, 0.1 x) equals (x > 0 ? x : 0.1 x) for every x (signed
-// zeros included) in two vector instructions instead of three
-__device__ __forceinline__ float leaky01(float x) { return __builtin_fmaxf(x, 0.1f * x); }
+// zeros included).  Written as the median of (x, 0.1 x, FLT_MAX), the same value
+// for every finite x: the median instruction takes its operands as they are,
+// where fmax first quiets a possible signalling NaN in x with an extra
+// instruction whenever x comes from a matrix-core accumulator (two instructions,
+// not three; with +inf as the bound the compiler turns the median back into fmax).
+__device__ __forceinline__ float leaky01(float x) {
+    return __builtin_amdgcn_fmed3f(x, 0.1f * x, 3.40282347e38f);
+}
 
 template <typename T> struct V16;
 template <> struct V16<float> { typedef f32x4 type; };
@@ -174,11 +180,14 @@ __device__ __forceinline__ void stem_wfrag(const float* __restrict__ w, int co, 
 }
 
 // B operand of k-step m for a pixel whose 3x3 window starts at position `pos`
-// (row 0, column 0 of the receptive field) in a window of row stride `ws`.
+// (row 0, column 0 of the receptive field) in a window of row stride `ws`.  The
+// lane groups of kernel row 3 (k-step 1, kg >= 2) meet zero weights (stem_wfrag):
+// they read row 2 again -- finite frame values, so the products are zeros --
+// rather than branch, which would keep the compiler from overlapping one
+// block's LDS reads with another's matrix-core work.
 __device__ __forceinline__ f16x8 stem_bfrag(const f16x4* __restrict__ win, int pos, int ws, int m, int kg) {
     const int r = 2 * m + (kg >> 1);
-    if (r > 2) return f16x8{};
-    const f16x4* q = win + pos + r * ws + 2 * (kg & 1);
+    const f16x4* q = win + pos + (r > 2 ? 2 : r) * ws + 2 * (kg & 1);
     const f16x4 a = q[0], b = q[1];
     return f16x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
 }
@@ -519,8 +528,42 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
         // batches of SB blocks per wave, unrolled so that the blocks' LDS reads,
         // MFMAs and epilogues overlap; slots past the last block recompute it
         // without storing
+        // (all SB blocks' operand reads first, then their MFMAs -- per accumulator in
+        // stem_block's order -- then their epilogues)
         constexpr int SB = 4;
         for (int b0 = 0; b0 < (NSB + 3) / 4; b0 += SB) {
+            f16x8 fbh[SB][2], fbl[SB][2];
+            f32x4 accs[SB][2];
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+                const int bi = wave + 4 * (b0 + b);
+                const int q = (bi < NSB ? bi : NSB - 1) * 16 + p;
+                const int R = q / WC, C = q - R * WC;
+                const int pos = q < WR * WC ? R * FS + C : 0;
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    fbh[b][m] = stem_bfrag(fwh, pos, FS, m, kg);
+                    fbl[b][m] = split ? stem_bfrag(fwl, pos, FS, m, kg) : f16x8{};
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+#pragma unroll
+                for (int cg = 0; cg < 2; ++cg) accs[b][cg] = f32x4{bv[cg][0], bv[cg][1], bv[cg][2], bv[cg][3]};
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int cg = 0; cg < 2; ++cg) {
+                        if constexpr (split) {
+                            accs[b][cg] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl[cg][m], fbh[b][m], accs[b][cg], 0,
+                                                                                 0, 0);
+                            accs[b][cg] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg][m], fbl[b][m], accs[b][cg], 0,
+                                                                                 0, 0);
+                        }
+                        accs[b][cg] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wa[cg][m], fbh[b][m], accs[b][cg], 0, 0,
+                                                                             0);
+                    }
+            }
 #pragma unroll
             for (int b = 0; b < SB; ++b) {
                 const int bi = wave + 4 * (b0 + b);
@@ -528,8 +571,7 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
                 const int q = (live ? bi : NSB - 1) * 16 + p;
                 const int R = q / WC, C = q - R * WC;
                 const bool valid = live && q < WR * WC;
-                f32x4 acc[2];
-                stem_block<2, split>(fwh, fwl, q < WR * WC ? R * FS + C : 0, FS, kg, wa, wl, bv, acc);
+                const f32x4 (&acc)[2] = accs[b];
                 const int sy = 2 * t.ty0 - 1 + R, sx = 2 * t.tx0 - 1 + C;
                 const bool inside = (unsigned)sy < (unsigned)h && (unsigned)sx < (unsigned)wd;
 #pragma unroll
