@@ -586,6 +586,9 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
             }
         }
         __syncthreads();  // stem window complete; the frame window is free
+        // the next tile's frame window into LDS now (its loads were issued before the
+        // stem), so that one barrier per tile -- the one below -- covers both buffers
+        if (Pn < total) park();
         const int obase1 = g[2 + 1];  // first level-1 pixel of the frame
         // the 3x3 stride-2 conv from LDS: 8 blocks of 16 pixels (2 rows x 64 columns)
         f32x4 acc[8];
@@ -608,8 +611,8 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
         // 128-byte pixel row); the frame's base pixel is read before the stores (a
         // scalar load after vector stores to memory it may alias waits for them)
         // Buffer stores, issued by every lane (outside the frame: an out-of-range
-        // offset, dropped), so the wait for the next window's loads before the
-        // park below can leave this wave's 8 stores in flight.
+        // offset, dropped): a fixed count per wave, which the compiler's wait for
+        // the next tile's window loads counts exactly.
         typedef TO T4 __attribute__((ext_vector_type(4)));
         typedef unsigned U2 __attribute__((ext_vector_type(2)));
 #pragma unroll
@@ -625,9 +628,7 @@ __global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict_
                                 : kOOB;
             __builtin_amdgcn_raw_buffer_store_b64(u2, r_out, off, 0, 0);
         }
-        __syncthreads();  // every wave is done with the stem window
-        if (Pn < total) park();
-        __syncthreads();
+        __syncthreads();  // every wave is done with the stem window; the next frame window is parked
         t = tn;
     }
 }
