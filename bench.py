@@ -504,11 +504,16 @@ def summarize_pmc(fetch_dir, write_dir, key, tiles, out_json, commands, probe_mi
     nbytes = probe_mib << 20
     fscale = nbytes / (probe_f * 1024)
     wscale = nbytes / (probe_w * 1024)
-    conv_f = [v for _, n, v in fetch if any(k in n for k in CONV_KERNELS)]
-    conv_w = [v for _, n, v in write if any(k in n for k in CONV_KERNELS)]
-    nl = 67                               # conv launches of one forward
-    lf = [round(v * 1024 * fscale) for v in conv_f[-nl:]]
-    lw = [round(v * 1024 * wscale) for v in conv_w[-nl:]]
+    def last_forward(rows):
+        # the conv launches of the last forward: those after its stem launch
+        start = max(i for i, n, _ in rows if "stem" in n)
+        return [v for i, n, v in rows if i > start and any(k in n for k in CONV_KERNELS)]
+
+    conv_f, conv_w = last_forward(fetch), last_forward(write)
+    nl = len(conv_f)                      # conv launches of one forward
+    assert nl == len(conv_w) and nl > 0, (nl, len(conv_w))
+    lf = [round(v * 1024 * fscale) for v in conv_f]
+    lw = [round(v * 1024 * wscale) for v in conv_w]
     rec = {"workload": key, "source_sha256": conv_source_hash(key, tiles), "launches": nl,
            "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
            "fetch_bytes_per_forward": sum(lf), "write_bytes_per_forward": sum(lw),
