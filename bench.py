@@ -73,7 +73,7 @@ class Pipeline:
     """Preallocated buffers and one step of the hot path for a fixed batch."""
 
     def __init__(self, precision, batch, layers, torch, tune_frames=None, tiles=None, calib_frames=None,
-                 descs=None, sparse_emb=True, fp8_blocks=True, fold_det=True):
+                 descs=None, sparse_emb=True, fp8_blocks=True, fold_det=True, window_down=True):
         from jde_inputs import FULL, anchors_px
         from paper_2011_03910_amd import JDE
         self.torch = torch
@@ -87,6 +87,8 @@ class Pipeline:
         self.m.sparse_emb(sparse_emb)
         # each head's det 1x1 in its det 3x3's epilogue (16-bit storage)
         self.m.fold_det(fold_det)
+        # the stride-4 downsample conv from an LDS window (16-bit storage)
+        self.m.window_down(window_down)
         self.heads = self.m.head_buffers(self.descs, emb=not sparse_emb)
         self.dets = self.m.dets_buffers(batch)
         self.track_begin = [N_TRACKS * f for f in range(batch + 1)]
@@ -629,6 +631,8 @@ def main():
                     help="autotune the headline and sweep configurations (BF16 batch 16/1/4/8/32, FP16 batch 16, the 64-frame "
                          "ragged mix), merge them into the stored tile choices, write OUT_JSON and exit")
     ap.add_argument("--no-fold-det", action="store_true", help="run each det 1x1 as its own launch")
+    ap.add_argument("--no-window-down", action="store_true",
+                    help="run the stride-4 downsample conv as an implicit GEMM")
     ap.add_argument("--eager", action="store_true",
                     help="time eager launches instead of replaying the step as a captured HIP graph")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DIR", "OUT_MD", "COMMAND"),
@@ -684,7 +688,8 @@ def main():
         saved = {}
     key = f"{args.precision}_b{args.batch}"
     pipe = Pipeline(args.precision, args.batch, layers, torch, None if args.no_tune else inputs_b[0],
-                    saved.get(key), calib_frames=inputs_b[0], fold_det=not args.no_fold_det)
+                    saved.get(key), calib_frames=inputs_b[0], fold_det=not args.no_fold_det,
+                    window_down=not args.no_window_down)
     tiles_out = {key: None if pipe.tiles is None else pipe.tiles.tolist()}
     traffic = measured_traffic(key, tiles_out[key])
     # Throughput and latency from a timed pass with no per-launch events; the
@@ -703,7 +708,8 @@ def main():
         f"p99 {pct(step_ms, 99):.2f} ms; candidates/frame {ncand.mean():.1f}, kept {counts.mean():.1f}")
 
     ms, fl, kind, nfwd = prof
-    conv = (kind == 1) | (kind == 6) | (kind == 7)  # implicit-GEMM (7: with the det 1x1) and pointwise launches
+    # implicit-GEMM (7: with the det 1x1), pointwise and window-downsample (9) conv launches
+    conv = (kind == 1) | (kind == 6) | (kind == 7) | (kind == 9)
     conv_ms = ms[conv].sum() / nfwd
     conv_flop = fl[conv].sum()
     n_launch = int(conv.sum())

@@ -248,6 +248,15 @@ jde_status jde_fuse_blocks(jde_ctx* ctx, int on);
  * own launch.  In jde_profile_collect the 3x3 launch is then kind 7 (its FLOPs
  * include the 1x1's) and the 1x1 kind 8 with no time or FLOPs of its own. */
 jde_status jde_fold_det(jde_ctx* ctx, int on);
+/* With on != 0 (the default), 16-bit contexts run the backbone's 3x3 stride-2
+ * downsample convs with Cin 64 (Sec. 3.1: into the stride-4 level) with a
+ * persistent window kernel: each workgroup keeps 128 output
+ * channels' weights in registers and loads each tile's input window once into
+ * on-chip memory, instead of gathering every input pixel 2.25 times through the
+ * implicit GEMM's short K loop.  Same sums in the same order: bitwise equal.
+ * FP8 launches and calibration forwards always run the implicit GEMM; on = 0
+ * runs it everywhere.  In jde_profile_collect such a launch is kind 9. */
+jde_status jde_window_down(jde_ctx* ctx, int on);
 /* With on != 0 (default off), 16-bit contexts run each 3x3 stride-1 conv with
  * Cin % 64 == 0 and Cout % 128 == 0 (Sec. 3.1: the residual blocks of the deep
  * stages and the head convs) from an LDS window loaded once per 32-channel input
@@ -451,7 +460,8 @@ jde_status jde_profile_begin(jde_ctx* ctx, int on);
  * the profiled forwards (op_ms), FLOPs of one launch for the last batch
  * (op_flop: 2*M*N*K), kind (op_kind: 0 = stem, 1 = MFMA conv; 2-5 = fused
  * launches, see jde_fuse_stem and jde_fuse_blocks; 6 = MFMA conv run by the
- * persistent pointwise kernel, tile 37 of jde_tiles; 7-8 see jde_fold_det).  *n_fwd gets
+ * persistent pointwise kernel, tile 37 of jde_tiles; 7-8 see jde_fold_det; 9
+ * see jde_window_down).  *n_fwd gets
  * the number of forwards summed.  All arrays host. */
 jde_status jde_profile_collect(jde_ctx* ctx, int max_ops, double* op_ms, double* op_flop, int* op_kind,
                                int* n_ops, int* n_fwd);

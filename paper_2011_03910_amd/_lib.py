@@ -111,6 +111,7 @@ SIGNATURES = {
     "jde_fuse_blocks": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_window_convs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_fold_det": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "jde_window_down": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_sparse_emb": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "jde_fp8_encode": (None, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t]),
     "jde_mx_encode": (None, [ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint8),

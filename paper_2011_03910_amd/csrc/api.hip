@@ -100,12 +100,16 @@ struct jde_ctx {
     // launch, 2 / 4 = head of a fused stem / residual-block launch, 3 / 5 = run
     // inside the previous op's fused launch, 6 = its own launch of the persistent
     // pointwise kernel, 7 = a det 3x3 launch that also runs the det 1x1, 8 = that
-    // det 1x1 (no launch of its own).
+    // det 1x1 (no launch of its own), 9 = a downsample conv run by the window
+    // kernel (window_down).
     bool fuse_stem = true, fuse_blocks = true;
     // The det 1x1 of each head runs in its det 3x3's epilogue (16-bit storage, the
     // 3x3 on a conv_tile_folds_det tile); its partial sums and per-pixel-tile
     // counters live in the workspace.
     bool fold_det = true;
+    // The 3x3 stride-2 downsample convs with Cin 64 (16-bit storage) run
+    // from an LDS window (down_win_kernel) instead of the implicit GEMM.
+    bool window_down = true;
     size_t ws_det_part = 0, ws_det_cnt = 0;
     int det_cnt_n = 0;
     // 3x3 stride-1 convs run from an LDS window (conv3_win) where they qualify;
@@ -940,6 +944,16 @@ jde_status jde_load_weights(jde_ctx* c, const float* blob, size_t nf, void* d_we
     return JDE_OK;
 }
 
+// A backbone downsample conv that the window kernel runs: 3x3 stride 2 into the
+// next level, Cin 64, nothing but bias + leaky in the epilogue (no concat, no
+// residual, no head output), 16-bit storage, not in FP8 and not in a calibration
+// pass (which records conv output ranges through the implicit GEMM's epilogue).
+static bool window_down_op(const jde_ctx* c, const Op& o) {
+    return c->window_down && !c->calibrating && down_win_ok(o.cin, o.cout, o.ksz, o.stride, c->et) &&
+           o.lvl_out == o.lvl_in + 1 && o.cin1 == 0 && o.in2_t < 0 && o.res_t < 0 && o.act && o.n_split == o.cout &&
+           o.det_out < 0 && o.emb_out < 0 && o.layer2 < 0 && !runs_fp8(c, o);
+}
+
 // Op i is a head's det 3x3 whose det 1x1 (op i + 1) can run in its epilogue:
 // 16-bit storage, neither in FP8, no calibration pass (which records the 3x3's
 // output range), a 1x1 over exactly the 3x3's det channels with at most 32
@@ -1055,6 +1069,17 @@ static jde_status forward_impl(jde_ctx* c, const float* frames, const jde_frame_
                 HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));
                 c->op_flop[oi] = 2.0 * M * o.cout * 27;
             }
+            continue;
+        }
+        if (o.kind == OP_CONV && window_down_op(c, o)) {
+            HIP_TRY(launch_down_win(tptr(o.in_t), tptr(o.out_t), wb + o.dev_w, (const float*)(wb + o.dev_b), geom, n,
+                                    o.lvl_in, o.cin, o.cout, c->et, s, dynp));
+            if (pev) {
+                HIP_TRY(hipEventRecord(pev[2 * oi + 1], s));
+                const double M = dynamic ? (double)cap_m(o.lvl_out) : (double)level_pixels(d, n, o.lvl_out);
+                c->op_flop[oi] = 2.0 * M * o.cout * 9.0 * o.cin;
+            }
+            c->launch_kind[oi] = 9;
             continue;
         }
         ConvArgs a = conv_args(c, o, d, dynamic ? 0 : n, uniform, W, geom, out, (int)oi);
@@ -1586,6 +1611,12 @@ jde_status jde_fuse_blocks(jde_ctx* c, int on) {
 jde_status jde_sparse_emb(jde_ctx* c, int on) {
     if (!c) return fail(JDE_EINVAL, "null context");
     c->sparse_emb = on != 0;
+    return JDE_OK;
+}
+
+jde_status jde_window_down(jde_ctx* c, int on) {
+    if (!c) return fail(JDE_EINVAL, "null context");
+    c->window_down = on != 0;
     return JDE_OK;
 }
 

@@ -651,6 +651,187 @@ hipError_t launch_stem_down(const float* frames, const int* geom, int nframes, i
 }
 int stem_down_tiles(int h, int w) { return ((h / 2 + kSdTY - 1) / kSdTY) * ((w / 2 + kSdTX - 1) / kSdTX); }
 
+// ---------------------------------------------------------------------------
+// 3x3 stride-2 convolution from an LDS window (16-bit storage; Cin = 64, Cout a
+// multiple of 128, bias + leaky, no concat input, no residual): the backbone's
+// downsample conv into the stride-4 level (Sec. 3.1).  Its K (576) is short, so
+// the implicit GEMM pays a pipeline fill and drain per tile and gathers each
+// input pixel 2.25 times through the load path.
+// Here a persistent workgroup (8 waves) owns 128 output channels -- wave w's 16
+// channels' weights for all nine taps stay in registers for the workgroup's life
+// -- and walks output tiles of one row x kDwTX pixels.  A tile's input window (3
+// rows x 2 kDwTX + 1 columns x Cin) is loaded once, into registers during the
+// previous tile's MFMAs, then parked in LDS with even and odd columns in separate
+// planes and 16-byte-padded pixel slots (Cin + 16 elements: 160 bytes, full-rate
+// operand reads), so the stride-2 reads are unit-stride.  Per pixel
+// block and channel block the MFMAs run tap-major, 32 channels per k-step: the
+// implicit GEMM's order, so the result is bitwise the same.
+// ---------------------------------------------------------------------------
+constexpr int kDwTX = 64;
+
+template <typename T, int CIN>
+__global__ __launch_bounds__(512) void down_win_kernel(const T* __restrict__ in, const T* __restrict__ w,
+                                                       const float* __restrict__ bias, T* __restrict__ out,
+                                                       const int* __restrict__ geom, int nframes, int lvl_in,
+                                                       int cout, const int* __restrict__ dyn) {
+    if (dyn) nframes = dyn[kDynN];
+    constexpr int TX = kDwTX, WC = 2 * TX + 1, NE = TX + 1;
+    constexpr int PS = CIN + 16;              // elements per pixel slot
+    constexpr int KS = CIN / 32;              // MFMA k-steps per tap
+    constexpr int CH = CIN / 8;               // 16-byte chunks per input pixel
+    constexpr int NCHUNK = 3 * WC * CH;       // chunks of a window
+    constexpr int LPT = (NCHUNK + 511) / 512; // window loads per thread
+    typedef typename V16<T>::type V;
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    __shared__ __attribute__((aligned(16))) T win[3 * 2 * NE * PS];
+
+    const int lvl_out = lvl_in + 1;
+    const int ncg = cout / 128;                       // channel groups of 128
+    const int cg = blockIdx.x % ncg, walker = blockIdx.x / ncg, stride = gridDim.x / ncg;
+    // output tiles of the batch: per frame, ho rows x ceil(wo / TX) column tiles
+    int total = 0;
+    for (int f = 0; f < nframes; ++f)
+        total += (geom[f * kGeomInts] >> lvl_out) * (((geom[f * kGeomInts + 1] >> lvl_out) + TX - 1) / TX);
+    struct Tile { int f, oy, ox0; };
+    auto locate = [&](int item) {
+        Tile t{0, 0, 0};
+        for (;; ++t.f) {
+            const int n = (geom[t.f * kGeomInts] >> lvl_out) * (((geom[t.f * kGeomInts + 1] >> lvl_out) + TX - 1) / TX);
+            if (item < n || t.f + 1 >= nframes) break;
+            item -= n;
+        }
+        const int tw = ((geom[t.f * kGeomInts + 1] >> lvl_out) + TX - 1) / TX;
+        t.oy = item / tw;
+        t.ox0 = (item - t.oy * tw) * TX;
+        return t;
+    };
+    // window chunks of this thread: chunk e = tid + 512 j -> row r, window column c, 16-byte slot k
+    V fv[LPT];
+    auto load = [&](const Tile& t) {
+        const int* g = geom + t.f * kGeomInts;
+        const int hi = g[0] >> lvl_in, wi = g[1] >> lvl_in;
+        const T* src = in + (size_t)g[2 + lvl_in] * CIN;
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int e = threadIdx.x + 512 * j;
+            const int r = e / (WC * CH), rem = e - r * (WC * CH), c = rem / CH, k = rem - c * CH;
+            const int iy = 2 * t.oy - 1 + r, ix = 2 * t.ox0 - 1 + c;
+            const bool ok = e < NCHUNK && (unsigned)iy < (unsigned)hi && (unsigned)ix < (unsigned)wi;
+            fv[j] = ok ? *(const V*)(src + ((size_t)iy * wi + ix) * CIN + 8 * k) : V{};
+        }
+    };
+    auto park = [&]() {
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int e = threadIdx.x + 512 * j;
+            if (e < NCHUNK) {
+                const int r = e / (WC * CH), rem = e - r * (WC * CH), c = rem / CH, k = rem - c * CH;
+                *(V*)&win[((r * 2 + (c & 1)) * NE + (c >> 1)) * PS + 8 * k] = fv[j];
+            }
+        }
+    };
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p = lane & 15, kg = lane >> 4;
+    const int cbase = cg * 128 + wave * 16;
+    // this wave's weights, all taps and k-steps: lane = (channel p, k-slot kg)
+    V af[9][KS];
+#pragma unroll
+    for (int tp = 0; tp < 9; ++tp)
+#pragma unroll
+        for (int h = 0; h < KS; ++h)
+            af[tp][h] = *(const V*)(w + (size_t)(cbase + p) * (9 * CIN) + tp * CIN + h * 32 + kg * 8);
+    f32x4 bv = *(const f32x4*)(bias + cbase + kg * 4);
+    touch_regs(af, bv);  // the weight loads complete here, not inside the tile loop
+
+    if (walker >= total) return;  // uniform over the workgroup
+    Tile t = locate(walker);
+    load(t);
+    park();
+    __syncthreads();
+    for (int P = walker; P < total; P += stride) {
+        const int Pn = P + stride;
+        Tile tn = t;
+        if (Pn < total) {
+            tn = locate(Pn);
+            load(tn);  // in flight during this tile's MFMAs
+        }
+        f32x4 acc[TX / 16];
+#pragma unroll
+        for (int i = 0; i < TX / 16; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // pixel operands of a tap, read one tap ahead into a second register set so
+        // that the LDS latency hides behind the previous tap's MFMAs
+        V bfr[2][KS][TX / 16];
+        auto rd = [&](auto tp_c, auto set_c) {
+            constexpr int tp = decltype(tp_c)::value, st = decltype(set_c)::value;
+            constexpr int r = tp / 3, s = tp % 3;
+#pragma unroll
+            for (int h = 0; h < KS; ++h)
+#pragma unroll
+                for (int i = 0; i < TX / 16; ++i)
+                    bfr[st][h][i] = *(const V*)&win[((r * 2 + (s & 1)) * NE + i * 16 + p + (s >> 1)) * PS + h * 32 + kg * 8];
+        };
+        rd(std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{});
+        static_for<0, 9>([&](auto tp_c) {
+            constexpr int tp = decltype(tp_c)::value;
+            if constexpr (tp + 1 < 9) rd(std::integral_constant<int, tp + 1>{}, std::integral_constant<int, (tp + 1) & 1>{});
+            __builtin_amdgcn_sched_barrier(0);  // (the scheduler would otherwise pull them just in time)
+#pragma unroll
+            for (int h = 0; h < KS; ++h)
+#pragma unroll
+                for (int i = 0; i < TX / 16; ++i) {
+                    if constexpr (__is_same(T, bf16))
+                        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[tp][h], bfr[tp & 1][h][i], acc[i], 0, 0, 0);
+                    else
+                        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[tp][h], bfr[tp & 1][h][i], acc[i], 0, 0, 0);
+                }
+        });
+        __syncthreads();  // every wave is done with this window
+        if (Pn < total) park();
+        // epilogue: bias, leaky, this wave's 16 channels (8 bytes per lane and pixel)
+        const int* g = geom + t.f * kGeomInts;
+        const int wo = g[1] >> lvl_out;
+        const size_t orow = (size_t)g[2 + lvl_out] + (size_t)t.oy * wo;
+#pragma unroll
+        for (int i = 0; i < TX / 16; ++i) {
+            const int ox = t.ox0 + i * 16 + p;
+            T4 pk;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pk[q] = cvt_out<T>(leaky01(acc[i][q] + bv[q]));
+            if (ox < wo) *(T4*)(out + (orow + ox) * cout + cbase + kg * 4) = pk;
+        }
+        __syncthreads();  // the next window is parked
+        t = tn;
+    }
+}
+
+// Cin 64 only: with Cin 128 the weights (144 VGPRs) and the window prefetch do not
+// fit a wave's 256 registers.
+bool down_win_ok(int cin, int cout, int ksz, int stride, int et) {
+    return (et == kBF16 || et == kF16) && ksz == 3 && stride == 2 && cin == 64 && cout % 128 == 0;
+}
+
+static int resident_grid(const void* fn, int threads);
+
+hipError_t launch_down_win(const void* in, void* out, const void* w, const float* bias, const int* geom, int nframes,
+                           int lvl_in, int cin, int cout, int et, hipStream_t s, const int* dyn) {
+    if (!down_win_ok(cin, cout, 3, 2, et)) return hipErrorInvalidValue;
+    auto go = [&](auto kern, auto tag) {
+        typedef decltype(tag) T;
+        // persistent: the workgroups the device holds at once, a multiple of the
+        // channel groups and of the 8 XCDs
+        const int ncg = cout / 128;
+        int g = resident_grid(reinterpret_cast<const void*>(kern), 512);
+        g -= g % (8 * ncg);
+        if (g < 8 * ncg) g = 8 * ncg;
+        kern<<<dim3(g), dim3(512), 0, s>>>((const T*)in, (const T*)w, bias, (T*)out, geom, nframes, lvl_in, cout,
+                                           dyn);
+        return hipGetLastError();
+    };
+    if (et == kBF16) return go(down_win_kernel<bf16, 64>, bf16{});
+    return go(down_win_kernel<f16, 64>, f16{});
+}
+
 hipError_t launch_stem(const float* frames, const int* geom, int nframes, int uniform, int rows, int max_w,
                        int M, const float* w, const float* bias, int cout, void* out, int out_type,
                        hipStream_t s) {

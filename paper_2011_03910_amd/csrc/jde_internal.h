@@ -117,6 +117,12 @@ constexpr int kW3MaxW = 190;
 bool conv3w_ok(const ConvArgs& a, int et);
 int conv3w_tiles(int h, int w);
 hipError_t launch_conv3w(const ConvArgs& a, int et, int pixel_tiles, hipStream_t s);
+// 3x3 stride-2 convolution from an LDS window (16-bit storage, bias + leaky, no
+// concat, no residual) where down_win_ok: level lvl_in -> lvl_in + 1 of every
+// frame, bitwise equal to the implicit GEMM.
+bool down_win_ok(int cin, int cout, int ksz, int stride, int et);
+hipError_t launch_down_win(const void* in, void* out, const void* w, const float* bias, const int* geom, int nframes,
+                           int lvl_in, int cin, int cout, int et, hipStream_t s, const int* dyn = nullptr);
 // FP8 e4m3 convolution: BF16 activations quantised on load with in_scale, FP8
 // weights with per-channel wscale; needs cin % 128 == 0 and no concat.
 hipError_t launch_conv_fp8(const ConvArgs& a, int tile_cfg, hipStream_t s);

@@ -553,6 +553,10 @@ class JDE:
         """Run each head's det 1x1 in its det 3x3's epilogue (16-bit only)."""
         check(self.lib.jde_fold_det(self.ctx, 1 if on else 0), "jde_fold_det")
 
+    def window_down(self, on=True):
+        """Run the 3x3 stride-2 downsample convs with Cin 64 from an LDS window (16-bit only)."""
+        check(self.lib.jde_window_down(self.ctx, 1 if on else 0), "jde_window_down")
+
     def window_convs(self, on=True):
         """Run qualifying 3x3 stride-1 convs from an LDS window (16-bit only)."""
         check(self.lib.jde_window_convs(self.ctx, 1 if on else 0), "jde_window_convs")

@@ -275,6 +275,28 @@ def test_fused_blocks_tiny_partial_tiles(torch, precision):
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
 @pytest.mark.parametrize("cfg_name", ["tiny", "full"])
+def test_window_downsample_equals_implicit_gemm(torch, precision, cfg_name):
+    """The 3x3 stride-2 downsample conv with 64 input channels run by the window
+    kernel gives bitwise the heads of the implicit GEMM (same MFMA order), on a
+    ragged batch whose output rows end in partial 64-pixel tiles; the launch kinds
+    show the one launch that took it."""
+    _say(f"case: window downsample {cfg_name} {precision}")
+    cfg = TINY if cfg_name == "tiny" else FULL
+    sizes = ([(192, 320), (128, 256), (192, 320)] if cfg_name == "tiny"
+             else [(608, 1088), (320, 576), (480, 864)])
+    m = _model(cfg, precision, len(sizes))
+    m.load_weights(weights(cfg_name, 50 if cfg_name == "tiny" else 40))
+    frs = [frames(cfg_name, 1, 0, h, w)[0] for h, w in sizes]
+    packed = torch.from_numpy(np.concatenate([f.ravel() for f in frs])).cuda()
+    worst, same, kind = _fused_vs_plain(m, packed, sizes, m.window_down)
+    n_win = int((np.asarray(kind) == 9).sum())
+    _say(f"  window downsample launches: {n_win}; vs implicit GEMM: rel err {worst:.2e}, bitwise equal {same}")
+    assert n_win == 1
+    assert same
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("cfg_name", ["tiny", "full"])
 def test_det_fold_equals_unfused(torch, precision, cfg_name):
     """The det 1x1 run in the det 3x3's epilogue gives the det head output of the
     two launches, to the rounding of another FP32 summation order, for tiles whose
