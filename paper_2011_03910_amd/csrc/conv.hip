@@ -661,7 +661,8 @@ int stem_down_tiles(int h, int w) { return ((h / 2 + kSdTY - 1) / kSdTY) * ((w /
 // channels' weights for all nine taps stay in registers for the workgroup's life
 // -- and walks output tiles of one row x kDwTX pixels.  A tile's input window (3
 // rows x 2 kDwTX + 1 columns x Cin) is loaded once, into registers during the
-// previous tile's MFMAs, then parked in LDS with even and odd columns in separate
+// previous tile's MFMAs, then parked in the second of two LDS windows (one
+// barrier per tile) with even and odd columns in separate
 // planes and 16-byte-padded pixel slots (Cin + 16 elements: 160 bytes, full-rate
 // operand reads), so the stride-2 reads are unit-stride.  Per pixel
 // block and channel block the MFMAs run tap-major, 32 channels per k-step: the
@@ -683,7 +684,8 @@ __global__ __launch_bounds__(512) void down_win_kernel(const T* __restrict__ in,
     constexpr int LPT = (NCHUNK + 511) / 512; // window loads per thread
     typedef typename V16<T>::type V;
     typedef T T4 __attribute__((ext_vector_type(4)));
-    __shared__ __attribute__((aligned(16))) T win[3 * 2 * NE * PS];
+    constexpr int WE = 3 * 2 * NE * PS;       // elements of one window
+    __shared__ __attribute__((aligned(16))) T win2[2 * WE];  // two windows: this tile's, the next one's
 
     const int lvl_out = lvl_in + 1;
     const int ncg = cout / 128;                       // channel groups of 128
@@ -720,7 +722,7 @@ __global__ __launch_bounds__(512) void down_win_kernel(const T* __restrict__ in,
             fv[j] = ok ? *(const V*)(src + ((size_t)iy * wi + ix) * CIN + 8 * k) : V{};
         }
     };
-    auto park = [&]() {
+    auto park = [&](T* win) {
 #pragma unroll
         for (int j = 0; j < LPT; ++j) {
             const int e = threadIdx.x + 512 * j;
@@ -747,9 +749,11 @@ __global__ __launch_bounds__(512) void down_win_kernel(const T* __restrict__ in,
     if (walker >= total) return;  // uniform over the workgroup
     Tile t = locate(walker);
     load(t);
-    park();
+    park(win2);
     __syncthreads();
+    int cur = 0;
     for (int P = walker; P < total; P += stride) {
+        const T* win = win2 + cur * WE;
         const int Pn = P + stride;
         Tile tn = t;
         if (Pn < total) {
@@ -786,8 +790,9 @@ __global__ __launch_bounds__(512) void down_win_kernel(const T* __restrict__ in,
                         acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[tp][h], bfr[tp & 1][h][i], acc[i], 0, 0, 0);
                 }
         });
-        __syncthreads();  // every wave is done with this window
-        if (Pn < total) park();
+        // the next window into the other buffer (whose last reader, the previous
+        // tile, every wave finished before the barrier that ended it)
+        if (Pn < total) park(win2 + (cur ^ 1) * WE);
         // epilogue: bias, leaky, this wave's 16 channels (8 bytes per lane and pixel)
         const int* g = geom + t.f * kGeomInts;
         const int wo = g[1] >> lvl_out;
@@ -800,7 +805,8 @@ __global__ __launch_bounds__(512) void down_win_kernel(const T* __restrict__ in,
             for (int q = 0; q < 4; ++q) pk[q] = cvt_out<T>(leaky01(acc[i][q] + bv[q]));
             if (ox < wo) *(T4*)(out + (orow + ox) * cout + cbase + kg * 4) = pk;
         }
-        __syncthreads();  // the next window is parked
+        __syncthreads();  // the next window is parked; every wave is done with this one
+        cur ^= 1;
         t = tn;
     }
 }
