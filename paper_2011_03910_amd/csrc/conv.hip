@@ -1576,6 +1576,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
     tile_origin_at(a, BM, BN, tl, W, m0, n0);
     const __amdgpu_buffer_rsrc_t r_in = __builtin_amdgcn_make_buffer_rsrc((void*)a.in, 0, a.in_bytes, kBufFlags);
     const __amdgpu_buffer_rsrc_t r_w = __builtin_amdgcn_make_buffer_rsrc((void*)a.w, 0, a.w_bytes, kBufFlags);
+    // FPN concat (1x1 convs only): channels [0, cin1) from `in` at the next level
+    // (nearest x2 upsample: pixel (y / 2, x / 2)), the rest from in2 at this level
+    // (never in the residual form: no concat conv has a residual)
+    const bool concat = !RL && a.cin1 > 0;
+    const __amdgpu_buffer_rsrc_t r_in2 =
+        concat ? __builtin_amdgcn_make_buffer_rsrc((void*)a.in2, 0, a.in2_bytes, kBufFlags) : r_in;
 
     // Row descriptors of this lane's DMA instructions (instruction i of this
     // wave fills rows RPI q .. RPI q + RPI - 1 of a stage, q = NW i + wave):
@@ -1584,6 +1590,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
     //           k x Cin for a weight row);
     //   d_mask: bit r * k + s set iff tap (r, s) lies inside the image (every tap of
     //           a weight row; none for a row past M or Cout).
+    // With concat a pixel row's d_off addresses `in` and d_wc (unused by a 1x1)
+    // the row's origin in in2.
     int d_off[NPW], d_wc[NPW], d_mask[NPW];
     const int rloc = lane / (RB / 16);
     // (rows of a 128-byte-row instruction start at multiples of 8: rloc carries
@@ -1614,12 +1622,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
                 const int h = g[0] >> a.lvl_in, w = g[1] >> a.lvl_in;
                 d_off[i] = (g[2 + a.lvl_in] + iy0 * w + ix0) * a.cin + kslot;
                 d_wc[i] = w * a.cin;
+                if (concat) {
+                    const int l1 = a.lvl_out + 1;
+                    d_off[i] = (g[2 + l1] + (y >> 1) * (g[1] >> l1) + (x >> 1)) * a.cin1 + kslot;
+                    d_wc[i] = (g[2 + a.lvl_out] + y * (g[1] >> a.lvl_out) + x) * (a.cin - a.cin1) + kslot;
+                }
                 int mk = 0;
                 for (int r = 0; r < a.ksz; ++r)
                     for (int t = 0; t < a.ksz; ++t)
                         if ((unsigned)(iy0 + r) < (unsigned)h && (unsigned)(ix0 + t) < (unsigned)w)
                             mk |= 1 << (r * a.ksz + t);
-                d_mask[i] = mk;
+                d_mask[i] = concat ? 1 : mk;  // concat: its one tap, every pixel of the level
             }
         }
     }
@@ -1632,13 +1645,17 @@ __global__ __launch_bounds__(64 * WGM * WGN) void conv_dma(ConvArgs a0) {
         constexpr int u = decltype(u_c)::value;
         const int tap = issued < nk ? ld_r * a.ksz + ld_s : 31;  // bit 31 is never set
         const int sc = ld_s * a.cin + ld_ci;
+        const bool first = !concat || ld_ci < a.cin1;  // concat: this chunk's source
 #pragma unroll
         for (int i = 0; i < NPW; ++i) {
             const int q = NW * i + wave;
             const bool ok = (d_mask[i] >> tap) & 1;
-            const int off = ok ? (d_off[i] + ld_r * d_wc[i] + sc) * (int)sizeof(T) : kOOB;
+            const bool wrow = RPI * NW * i < BN;  // weight row (static per i)
+            const int e = (wrow || !concat) ? d_off[i] + ld_r * d_wc[i] + sc
+                                            : (first ? d_off[i] + ld_ci : d_wc[i] + (ld_ci - a.cin1));
+            const int off = ok ? e * (int)sizeof(T) : kOOB;
             const char* sp = u == 0 ? st0 : u == 1 ? st1 : u == 2 ? st2 : st3;
-            dma16(RPI * NW * i < BN ? r_w : r_in, sp + q * 1024, off);
+            dma16(wrow ? r_w : (first ? r_in : r_in2), sp + q * 1024, off);
         }
         ++issued;
         ld_ci += BK;
@@ -3041,7 +3058,12 @@ bool conv_tile_ok(int c, int et, const ConvArgs& a) {
     if (et != kF32 && et != kBF16 && et != kF16) return false;
     if (!built(c, et)) return false;
     if (kTiles[c].pw) return conv_pw_ok(a, et);
-    if (kTiles[c].st) return a.cin % kTiles[c].bk == 0 && a.cin1 == 0;
+    if (kTiles[c].st) {
+        const int bk = kTiles[c].bk;
+        if (a.cin1 > 0)  // concat: 1x1 stride 1, both sources in whole K chunks
+            return a.ksz == 1 && a.stride == 1 && a.cin1 % bk == 0 && (a.cin - a.cin1) % bk == 0;
+        return a.cin % bk == 0;
+    }
     if (!aligned_cin(a, kTiles[c].bk)) return c == 5 && a.cin1 == 0 && a.cin % (et == kF32 ? 4 : 8) == 0;
     return true;
 }

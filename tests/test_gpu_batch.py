@@ -274,6 +274,40 @@ def test_fused_blocks_tiny_partial_tiles(torch, precision):
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_every_tile_bitwise_equal_unfolded(torch, precision):
+    """With the det 1x1 as its own launch, every legal tile forced on every conv
+    -- register-staged, direct-to-LDS with 32- or 64-channel chunks, with the FPN
+    concat as a second source, with the residual through LDS, the pointwise
+    stream -- gives bitwise the heads of the built-in choice: the K order and the
+    epilogue are the same.  Ragged batch: level sizes end in partial tiles."""
+    _say(f"case: every tile bitwise, tiny {precision}")
+    sizes = [(192, 320), (128, 256)]
+    m = _model(TINY, precision, len(sizes))
+    m.load_weights(weights("tiny", 50))
+    frs = [frames("tiny", 1, 0, h, w)[0] for h, w in sizes]
+    packed = torch.from_numpy(np.concatenate([f.ravel() for f in frs])).cuda()
+    m.fold_det(False)
+    n_ops = len(m.tiles())
+    m.set_tiles(np.full(n_ops, -1, dtype=np.int32))
+    base = head_views(m.forward(packed, sizes), sizes)
+    tried = 0
+    for t in range(48):
+        try:
+            m.set_tiles(np.full(n_ops, t, dtype=np.int32))
+        except Exception:
+            continue
+        out = head_views(m.forward(packed, sizes), sizes)
+        torch.cuda.synchronize()
+        diff = [(k, s, i) for k in ("det", "emb") for s in range(3) for i in range(len(sizes))
+                if not np.array_equal(out[k][s][i], base[k][s][i])]
+        _say(f"  tile {t}: {'bitwise equal' if not diff else f'differs at {diff[:3]}'}")
+        assert not diff, (t, diff[:3])
+        tried += 1
+    assert tried >= 30
+    m.fold_det(True)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
 @pytest.mark.parametrize("cfg_name", ["tiny", "full"])
 def test_window_downsample_equals_implicit_gemm(torch, precision, cfg_name):
     """The 3x3 stride-2 downsample conv with 64 input channels run by the window
