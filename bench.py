@@ -450,7 +450,7 @@ def quick_fps(precision, batch, layers, inputs, torch, tiles, steps=10, warmup=3
 
 # ---- summaries of rocprofv3 output (CPU only; they write the files under profiles/) ----
 
-CONV_KERNELS = ("conv_dma", "conv_igemm", "conv_pw_stream")
+CONV_KERNELS = ("conv_dma", "conv_igemm", "conv_pw_stream", "down_win_kernel")
 
 
 def _read_csv(path):
