@@ -878,7 +878,7 @@ def main():
         "speedup_vs_fp32_b1": None if fp32 is None else round(fps / fp32["fps"], 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "kernel": f"conv launches conv_dma/conv_igemm/conv_pw_stream ({n_launch} launches/step, "
+                     "kernel": f"conv launches conv_dma/conv_igemm/conv_pw_stream/down_win_kernel ({n_launch} launches/step, "
                                f"{conv_flop / 1e9:.1f} GFLOP/step, mean {conv_ms / n_launch * 1e3:.1f} us/launch)"},
         "accuracy_frame0": acc,
         "post_processing": post,
