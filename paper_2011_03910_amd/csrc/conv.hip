@@ -2763,12 +2763,14 @@ hipError_t launch_resblock(const void* x, void* out, const void* w1, const float
 template <int CIN, int COUT> struct PwCfg;
 template <> struct PwCfg<256, 128> { static constexpr int BN = 32, G = 1, NBUF = 4; };
 template <> struct PwCfg<512, 256> { static constexpr int BN = 16, G = 2, NBUF = 4; };
+// 1024 -> 512 in four workgroups of 128 output channels (ngroups = 4)
+template <> struct PwCfg<1024, 128> { static constexpr int BN = 16, G = 1, NBUF = 4; };
 
 template <typename T, int CIN, int COUT>
 __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T* __restrict__ out,
                                                       const T* __restrict__ w, const float* __restrict__ bias, int M,
                                                       int ld, int act, int x_bytes, int out_bytes,
-                                                      const int* __restrict__ dyn_m) {
+                                                      const int* __restrict__ dyn_m, int ngroups) {
     constexpr int NW = 8, BN = PwCfg<CIN, COUT>::BN, G = PwCfg<CIN, COUT>::G;
     static_assert(NW * G * 16 == COUT, "one wave per 16 G output channels");
     constexpr int KA = CIN / 32, NB = BN / 16;
@@ -2789,11 +2791,18 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
     const __amdgpu_buffer_rsrc_t r_x = __builtin_amdgcn_make_buffer_rsrc((void*)x, 0, x_bytes, kBufFlags);
     const __amdgpu_buffer_rsrc_t r_out = __builtin_amdgcn_make_buffer_rsrc((void*)out, 0, out_bytes, kBufFlags);
 
+    // ngroups > 1: output channels c0 .. c0 + COUT of ngroups x COUT; the ngroups
+    // workgroups of one pixel range run on one XCD (workgroup b on XCD b % 8; the
+    // grid is a multiple of 8 ngroups), so that its L2 fetches the range once
+    const int ng = ngroups > 1 ? (int)(blockIdx.x / 8) % ngroups : 0;
+    const int walker = ngroups > 1 ? (int)(blockIdx.x % 8) + 8 * (int)(blockIdx.x / (8 * ngroups)) : (int)blockIdx.x;
+    const int nwalk = (int)gridDim.x / ngroups;
+    const int c0 = ng * COUT;
     V a[G][KA];
     float bb[G][4];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int ch = (wave * G + g) * 16;
+        const int ch = c0 + (wave * G + g) * 16;
 #pragma unroll
         for (int kk = 0; kk < KA; ++kk) a[g][kk] = *(const V*)(w + (size_t)(ch + p) * CIN + kk * 32 + kg * 8);
 #pragma unroll
@@ -2816,8 +2825,8 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
     // this workgroup's pixels [lo, hi) and tiles (with a batch header, M is this
     // batch's and the grid the capacity's: a workgroup may get no pixels)
     if (dyn_m) M = *dyn_m;
-    const int lo = (int)((long long)blockIdx.x * M / gridDim.x);
-    const int hi = (int)((long long)(blockIdx.x + 1) * M / gridDim.x);
+    const int lo = (int)((long long)walker * M / nwalk);
+    const int hi = (int)((long long)(walker + 1) * M / nwalk);
     if (hi <= lo) return;  // uniform over the workgroup, before any load or barrier
     const int nt = (hi - lo + BN - 1) / BN;
     // Load i of tile j into ring slot buf (tile j >= nt: zeros, so that the count
@@ -2838,7 +2847,7 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
     };
     const bool full = wave + NW * (DPW - 1) < NDMA;
 
-    // gridDim.x <= ceil(M / BN): every workgroup has at least one pixel
+    // nwalk <= ceil(M / BN): every pixel range has at least one pixel
     static_for<0, NBUF - 1>([&](auto j_c) {
 #pragma unroll
         for (int i = 0; i < DPW; ++i) issue_one(decltype(j_c)::value, decltype(j_c)::value, i);
@@ -2908,7 +2917,7 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
                 }
                 U2 u2;
                 __builtin_memcpy(&u2, &pk, 8);
-                const int ob = (mo * ld + (wave * G + g) * 16 + kg * 4) * (int)sizeof(T);
+                const int ob = (mo * ld + c0 + (wave * G + g) * 16 + kg * 4) * (int)sizeof(T);
                 __builtin_amdgcn_raw_buffer_store_b64(u2, r_out, m < hi ? ob : kOOB, 0, 0);
             }
         }
@@ -2925,27 +2934,35 @@ static bool conv_pw_ok(const ConvArgs& a, int et) {
     if (et != kBF16 && et != kF16) return false;
     if (a.ksz != 1 || a.stride != 1 || a.pad != 0 || a.cin1 != 0 || a.lvl_in != a.lvl_out) return false;
     if (a.res || a.out1 || a.n_split != a.cout || a.out0_f32 || a.wscale || a.amax) return false;
-    if (!((a.cin == 256 && a.cout == 128) || (a.cin == 512 && a.cout == 256))) return false;
+    if (!((a.cin == 256 && a.cout == 128) || (a.cin == 512 && a.cout == 256) || (a.cin == 1024 && a.cout == 512)))
+        return false;
     if (a.ld0 < a.cout || a.ld0 % 4 || a.M <= 0) return false;
     return (size_t)a.M * a.cin * 2 <= (size_t)a.in_bytes && (size_t)a.M * a.ld0 * 2 < ((size_t)1 << 31);
 }
 
 template <typename T, int CIN, int COUT>
-static hipError_t launch_pw_t(const ConvArgs& a, hipStream_t s) {
+static hipError_t launch_pw_t(const ConvArgs& a, hipStream_t s, int ngroups = 1) {
     constexpr int BN = PwCfg<CIN, COUT>::BN;
     const int ntiles = (a.M + BN - 1) / BN;
-    const int g = ntiles < 256 ? ntiles : 256;  // one workgroup per compute unit (68 KB of LDS)
-    conv_pw_stream<T, CIN, COUT><<<dim3(g), dim3(512), 0, s>>>((const T*)a.in, (T*)a.out0, (const T*)a.w, a.bias,
-                                                                a.M, a.ld0, a.act, a.in_bytes, a.M * a.ld0 * 2,
-                                                                a.dyn ? a.dyn + kDynM + a.lvl_out : nullptr);
+    // one workgroup per compute unit (68-132 KB of LDS); with channel groups, a
+    // multiple of 8 ngroups of them (pixel ranges in whole XCD rounds)
+    int walkers = ntiles < 256 / ngroups ? ntiles : 256 / ngroups;
+    if (ngroups > 1) walkers = walkers >= 8 ? walkers - walkers % 8 : 8;
+    conv_pw_stream<T, CIN, COUT><<<dim3(walkers * ngroups), dim3(512), 0, s>>>(
+        (const T*)a.in, (T*)a.out0, (const T*)a.w, a.bias, a.M, a.ld0, a.act, a.in_bytes, a.M * a.ld0 * 2,
+        a.dyn ? a.dyn + kDynM + a.lvl_out : nullptr, ngroups);
     return hipGetLastError();
 }
 
 static hipError_t launch_pw(const ConvArgs& a, int et, hipStream_t s) {
     if (!conv_pw_ok(a, et)) return hipErrorInvalidValue;
     if (et == kBF16)
-        return a.cin == 256 ? launch_pw_t<bf16, 256, 128>(a, s) : launch_pw_t<bf16, 512, 256>(a, s);
-    return a.cin == 256 ? launch_pw_t<f16, 256, 128>(a, s) : launch_pw_t<f16, 512, 256>(a, s);
+        return a.cin == 256   ? launch_pw_t<bf16, 256, 128>(a, s)
+               : a.cin == 512 ? launch_pw_t<bf16, 512, 256>(a, s)
+                              : launch_pw_t<bf16, 1024, 128>(a, s, 4);
+    return a.cin == 256   ? launch_pw_t<f16, 256, 128>(a, s)
+           : a.cin == 512 ? launch_pw_t<f16, 512, 256>(a, s)
+                          : launch_pw_t<f16, 1024, 128>(a, s, 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -2953,8 +2970,8 @@ static hipError_t launch_pw(const ConvArgs& a, int et, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // st = 0: register-staged conv_igemm; st = S >= 3: conv_dma with S stages;
 // nt = 1: streaming (non-temporal) output stores.
-// pw = 1: the persistent pointwise kernel (conv_pw_stream; 1x1 convs of 256 -> 128
-// and 512 -> 256 channels only, the other fields unused).
+// pw = 1: the persistent pointwise kernel (conv_pw_stream; 1x1 convs of 256 -> 128,
+// 512 -> 256 and 1024 -> 512 channels only, the other fields unused).
 struct TileCfg { int bm, bn, wgm, wgn, bk, st, nt, pw = 0; };
 constexpr int kDynConvGrid = 1024;  // fallback grid of a conv launch in a graph for any batch
 

@@ -274,17 +274,20 @@ def test_fused_blocks_tiny_partial_tiles(torch, precision):
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
-def test_every_tile_bitwise_equal_unfolded(torch, precision):
+@pytest.mark.parametrize("cfg_name", ["tiny", "full"])
+def test_every_tile_bitwise_equal_unfolded(torch, precision, cfg_name):
     """With the det 1x1 as its own launch, every legal tile forced on every conv
     -- register-staged, direct-to-LDS with 32- or 64-channel chunks, with the FPN
     concat as a second source, with the residual through LDS, the pointwise
-    stream -- gives bitwise the heads of the built-in choice: the K order and the
-    epilogue are the same.  Ragged batch: level sizes end in partial tiles."""
-    _say(f"case: every tile bitwise, tiny {precision}")
-    sizes = [(192, 320), (128, 256)]
-    m = _model(TINY, precision, len(sizes))
-    m.load_weights(weights("tiny", 50))
-    frs = [frames("tiny", 1, 0, h, w)[0] for h, w in sizes]
+    stream (the full network's 1024 -> 512 convs in four channel groups) -- gives
+    bitwise the heads of the built-in choice: the K order and the epilogue are the
+    same.  Ragged batch: level sizes end in partial tiles."""
+    _say(f"case: every tile bitwise, {cfg_name} {precision}")
+    cfg = TINY if cfg_name == "tiny" else FULL
+    sizes = [(192, 320), (128, 256)] if cfg_name == "tiny" else [(608, 1088), (320, 576)]
+    m = _model(cfg, precision, len(sizes))
+    m.load_weights(weights(cfg_name, 50 if cfg_name == "tiny" else 40))
+    frs = [frames(cfg_name, 1, 0, h, w)[0] for h, w in sizes]
     packed = torch.from_numpy(np.concatenate([f.ravel() for f in frs])).cuda()
     m.fold_det(False)
     n_ops = len(m.tiles())
