@@ -237,13 +237,15 @@ jde_status jde_fuse_stem(jde_ctx* ctx, int on);
  * FLOPs of its own. */
 jde_status jde_fuse_blocks(jde_ctx* ctx, int on);
 /* With on != 0 (the default), 16-bit contexts run each head's det 1x1 (Sec. 3.1
- * heads: det 3x3 F -> 2F with leaky, then a linear 1x1 2F -> 6A) in the det 3x3's
- * launch, where that launch runs on a direct-to-LDS tile whose activated output
- * tile fits two of its stages: the 2F-channel output never goes to memory.  The
- * 1x1 multiplies the same storage-rounded values; a 3x3 tile covering part of the
- * 2F channels adds its FP32 partial sums to a workspace buffer, and the last of a
- * pixel range's tiles sums them in channel order, so the result is deterministic
- * but rounds differently from the unfused 1x1 (FP32 sums in another order).  FP8
+ * heads: det 3x3 F -> 2F with leaky, then a linear 1x1 2F -> 6A, 6A <= 32) in the
+ * det 3x3's launch, where that launch runs on a direct-to-LDS tile whose
+ * activated output tile fits its pipeline stages (not the 4-wave tiles of 32 K
+ * elements) and whose channel width divides 2F: the 2F-channel output never goes
+ * to memory.  The 1x1 multiplies the same storage-rounded values; a 3x3 tile
+ * covering part of the 2F channels writes its FP32 partial sums to a workspace
+ * buffer, and the last of a pixel range's tiles sums them in channel order, so
+ * the result is deterministic (the same in a graph for any batch) but rounds
+ * differently from the unfused 1x1 (FP32 sums in another order).  FP8
  * launches and calibration forwards always run unfused; on = 0 runs the 1x1 as its
  * own launch.  In jde_profile_collect the 3x3 launch is then kind 7 (its FLOPs
  * include the 1x1's) and the 1x1 kind 8 with no time or FLOPs of its own. */
