@@ -2798,13 +2798,40 @@ __global__ __launch_bounds__(512) void conv_pw_stream(const T* __restrict__ x, T
     const int walker = ngroups > 1 ? (int)(blockIdx.x % 8) + 8 * (int)(blockIdx.x / (8 * ngroups)) : (int)blockIdx.x;
     const int nwalk = (int)gridDim.x / ngroups;
     const int c0 = ng * COUT;
+    // Weights: the MFMA operand of k-step kk wants lane (p, kg) to hold W[ch + p]
+    // [32 kk + 8 kg, +8): loaded that way, an instruction reads 16 rows x 64 bytes,
+    // at half the load path's rate.  Instead two instructions read rows ch .. ch + 7
+    // and ch + 8 .. ch + 15 in 128-byte segments (lane L: row L / 8, 16-byte unit
+    // L % 8 of k-steps 2 kp and 2 kp + 1), and a cross-lane permute hands each lane
+    // its 16 bytes: unit 4 h + kg of row p, from lane 8 (p % 8) + 4 h + kg of
+    // instruction p / 8.
     V a[G][KA];
     float bb[G][4];
+    static_assert(KA % 2 == 0, "k-steps in pairs");
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int ch = c0 + (wave * G + g) * 16;
 #pragma unroll
-        for (int kk = 0; kk < KA; ++kk) a[g][kk] = *(const V*)(w + (size_t)(ch + p) * CIN + kk * 32 + kg * 8);
+        for (int kp = 0; kp < KA / 2; ++kp) {
+            int src[2][4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const V v = *(const V*)(w + (size_t)(ch + 8 * i + (lane >> 3)) * CIN + kp * 64 + (lane & 7) * 8);
+                __builtin_memcpy(src[i], &v, 16);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int from = ((p & 7) * 8 + 4 * h + kg) * 4;  // source lane, as a byte address
+                int dst[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int lo8 = __builtin_amdgcn_ds_bpermute(from, src[0][d]);
+                    const int hi8 = __builtin_amdgcn_ds_bpermute(from, src[1][d]);
+                    dst[d] = p < 8 ? lo8 : hi8;
+                }
+                __builtin_memcpy(&a[g][2 * kp + h], dst, 16);
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) bb[g][q] = bias[ch + kg * 4 + q];
     }
