@@ -398,8 +398,11 @@ __global__ __launch_bounds__(256) void stem_mfma_kernel(const float* __restrict_
 // ---------------------------------------------------------------------------
 constexpr int kSdTY = 2, kSdTX = 64;  // output tile (stride-2 level)
 
+// (two waves per SIMD: two workgroups per CU, as the persistent grid assumes;
+// the FP16 form, which also holds the low parts, spills 10 registers for it --
+// 488 -> 372 us measured -- the BF16 form fits in 226)
 template <typename TO>
-__global__ __launch_bounds__(256) void stem_down_kernel(const float* __restrict__ frames,
+__global__ __launch_bounds__(256, 2) void stem_down_kernel(const float* __restrict__ frames,
                                                         const int* __restrict__ geom, int nframes, int total,
                                                         const float* __restrict__ w0, const float* __restrict__ b0,
                                                         const TO* __restrict__ w1, const float* __restrict__ b1,
